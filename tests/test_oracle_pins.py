@@ -1,0 +1,238 @@
+"""Pins of the oracle against what the paper and the mathematics fix.
+
+None of these compare the oracle with itself: each check is a closed form,
+brute force on a tiny input, an identity of Section 2, a special case that
+reduces to a numpy/LAPACK routine, or the Lemma of Section 3.1.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import fastsum, graph, krylov
+import synth
+
+
+# ---- Oracle A: the graph of Section 2 ----------------------------------------
+
+def test_closed_form_three_points():
+    """Three points at distances sigma, 2 sigma, sqrt(5) sigma: W = e^-1, e^-4, e^-5
+    (eq. W_gaussian), zero diagonal; degrees are row sums (Section 2)."""
+    s = 0.05
+    v = np.array([[0.0, 0.0], [s, 0.0], [0.0, 2 * s]])
+    e1, e4, e5 = math.exp(-1), math.exp(-4), math.exp(-5)
+    Wref = np.array([[0, e1, e4], [e1, 0, e5], [e4, e5, 0]])
+    x = np.array([1.0, -2.0, 0.5])
+    np.testing.assert_allclose(graph.apply_W(v, s, x), Wref @ x, rtol=1e-14)
+    np.testing.assert_allclose(graph.degree(v, s), Wref.sum(axis=1), rtol=1e-14)
+    np.testing.assert_allclose(graph.dense_W(v, s), Wref, rtol=1e-14)
+
+
+def test_duplicates_and_diagonal():
+    """Only the diagonal is zero: duplicate points j != i have weight exp(0) = 1."""
+    v = np.array([[0.1, 0.2, 0.0], [0.1, 0.2, 0.0], [0.5, 0.5, 0.5]])
+    W = graph.dense_W(v, 0.01)
+    assert W[0, 1] == 1.0 and W[0, 0] == 0.0 and W[1, 1] == 0.0
+    np.testing.assert_allclose(graph.degree(v, 0.01)[:2], [1.0, 1.0], atol=1e-300)
+
+
+def test_direct_sums_match_dense_matrix():
+    """The C loops and the explicitly formed matrix are two independent paths."""
+    v = synth.gmm(57, d=3, k=3, seed=4)
+    x = synth.normal_vectors(57, nvec=3, seed=1).astype(np.float64)
+    W = graph.dense_W(v, 0.07)
+    np.testing.assert_allclose(graph.apply_W(v, 0.07, x), x @ W.T, rtol=1e-13, atol=1e-13)
+    rows = np.array([0, 13, 56])
+    np.testing.assert_allclose(graph.w_rows(v, 0.07, x, rows), (x @ W.T)[:, rows], rtol=1e-13, atol=1e-13)
+
+
+def test_laplacian_identities():
+    """u^T L u = 1/2 sum W_ji (u_j - u_i)^2, L 1 = 0 (Section 2), L_s D^{1/2} 1 = 0,
+    symmetry of L_s (eq. nomlap), spec(L_s) in [0, 2] with smallest eigenvalue 0."""
+    v = synth.gmm(40, d=2, k=2, seed=2)
+    s = 0.06
+    rng = np.random.default_rng(0)
+    u, y = rng.standard_normal(40), rng.standard_normal(40)
+    quad = 0.0
+    for j in range(40):                       # brute force double loop
+        for i in range(40):
+            if i != j:
+                dist2 = float(((v[j].astype(np.float64) - v[i]) ** 2).sum())
+                quad += math.exp(-dist2 / s**2) * (u[j] - u[i]) ** 2
+    assert abs(u @ graph.apply_L(v, s, u) - 0.5 * quad) <= 1e-12 * abs(quad)
+    np.testing.assert_allclose(graph.apply_L(v, s, np.ones(40)), 0.0, atol=1e-12)
+    d = graph.degree(v, s)
+    np.testing.assert_allclose(graph.apply_Ls(v, s, np.sqrt(d)), 0.0, atol=1e-12)
+    assert abs(y @ graph.apply_Ls(v, s, u) - u @ graph.apply_Ls(v, s, y)) < 1e-12
+    lam = np.linalg.eigvalsh(graph.dense_Ls(v, s))
+    assert lam[0] > -1e-12 and lam[-1] < 2 + 1e-12 and abs(lam[0]) < 1e-12
+
+
+# ---- the regularised kernel and its coefficients (Section 3) ----------------
+
+def test_gaussian_derivatives_against_finite_differences():
+    """Radial derivatives of the Gaussian against central differences of the
+    next-lower derivative (step 1e-5, truncation error ~ (h/sigma)^2)."""
+    s, r0, p = 0.07, 0.06, 6
+    D = fastsum.gaussian_radial_derivs(r0, s, p)
+    h = 1e-5
+    assert abs(D[0] - math.exp(-(r0 / s) ** 2)) < 1e-16
+    for k in range(1, p):
+        lo = fastsum.gaussian_radial_derivs(r0 - h, s, k)[k - 1]
+        hi = fastsum.gaussian_radial_derivs(r0 + h, s, k)[k - 1]
+        fd = (hi - lo) / (2 * h)
+        assert abs(D[k] - fd) <= 1e-6 * max(abs(D[k]), abs(D[k - 1]) / s), k
+
+
+@pytest.mark.parametrize("p", [2, 4, 6])
+def test_two_point_taylor_conditions(p):
+    """T_B matches K and p-1 derivatives at 1/2 - eps_B; value K(1/2) and zero
+    derivatives at 1/2 (so the constant continuation is C^{p-1})."""
+    s, eps = 0.25, 1.0 / 8
+    K = fastsum.RegKernel(s, eps, p)
+    poly = np.polynomial.Polynomial(K.coef)
+    h = 0.5 - K.r0
+    A = fastsum.gaussian_radial_derivs(K.r0, s, p)
+    for k in range(p):
+        dk = poly.deriv(k) if k else poly
+        # rounding scale of the k-th derivative at t = 1
+        scale = sum(abs(c) * q**k for q, c in enumerate(K.coef)) / h**k
+        assert abs(dk(0.0) / h**k - A[k]) <= 1e-12 * scale + 1e-14
+        want = math.exp(-(0.5 / s) ** 2) if k == 0 else 0.0
+        assert abs(dk(1.0) / h**k - want) <= 1e-12 * scale + 1e-14
+    # K_R continuous across both junctions
+    r = np.array([K.r0 - 1e-12, K.r0 + 1e-12, 0.5 - 1e-12, 0.5 + 1e-12])
+    vals = K(r)
+    assert abs(vals[0] - vals[1]) < 1e-9 and abs(vals[2] - vals[3]) < 1e-9
+
+
+@pytest.mark.parametrize("d,N,eps", [(1, 16, 0.0), (2, 16, 1.0 / 8), (3, 8, 1.0 / 4)])
+def test_coefficients_interpolate_samples(d, N, eps):
+    """With the N^{-d} normalisation, K_RF(j/N) = K_R(j/N) on all nodes of I_N^d
+    (the defining property of the trapezoidal coefficients, eq. b_l::K_RF)."""
+    s = 0.2
+    b = fastsum.coefficients(s, N, d, eps, 3)
+    j = fastsum.index_set(N)
+    nodes = np.stack(np.meshgrid(*([j / N] * d), indexing="ij"), axis=-1).reshape(-1, d)
+    K = fastsum.RegKernel(s, eps, 3)
+    got = fastsum.K_RF(nodes, b, N)
+    np.testing.assert_allclose(got.real, K(np.linalg.norm(nodes, axis=1)), atol=1e-13)
+    assert np.abs(got.imag).max() < 1e-13
+
+
+def test_coefficients_closed_form_small_sigma():
+    """For a narrow Gaussian the regularisation is inert and the trapezoidal
+    coefficients are, by Poisson summation, sum_r c(l + rN) with the
+    continuous transform c(xi) = (sqrt(pi) sigma)^d exp(-pi^2 sigma^2 |xi|^2)
+    (the analytic coefficients Section 3 mentions for small sigma)."""
+    s, N, d = 0.05, 32, 2
+    b = fastsum.coefficients(s, N, d, 0.0, 4)
+    l = fastsum.index_set(N)
+    L1, L2 = np.meshgrid(l, l, indexing="ij")
+    ref = np.zeros_like(b)
+    for r1 in range(-3, 4):
+        for r2 in range(-3, 4):
+            xi2 = (L1 + r1 * N) ** 2 + (L2 + r2 * N) ** 2
+            ref += (math.sqrt(math.pi) * s) ** d * np.exp(-(math.pi * s) ** 2 * xi2)
+    np.testing.assert_allclose(b, ref, atol=1e-15)
+
+
+# ---- Oracle B: the exact trigonometric operator -----------------------------
+
+def test_trig_operator_on_grid_nodes_is_the_direct_sum():
+    """On nodes lying on the lattice j/N inside the ball of radius 1/4 - eps_B/2,
+    every difference v_j - v_i is a lattice node with norm <= 1/2 - eps_B, where
+    K_RF interpolates K_R = K exactly; so the trigonometric operator equals the
+    direct sum sum_i x_i K(v_j - v_i) = (W x)_j + x_j."""
+    N, d, s = 32, 2, 0.09
+    j = fastsum.index_set(N)
+    g = np.stack(np.meshgrid(j / N, j / N, indexing="ij"), axis=-1).reshape(-1, 2)
+    g = g[np.linalg.norm(g, axis=1) <= 0.25 - 1.0 / 16]
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal(g.shape[0])
+    b = fastsum.coefficients(s, N, d, 1.0 / 8, 4)
+    f = fastsum.trig_operator(g, x, b, N)
+    np.testing.assert_allclose(f, graph.apply_W(g, s, x) + x, atol=1e-12)
+
+
+def test_trig_operator_matches_matrix_and_kerr_bound():
+    """Two code paths for the same operator agree; and |f - f_RF| <=
+    ||x||_1 ||K_ERR||_inf (eq. KERR_estimate) against the direct sum."""
+    v = synth.gmm(300, d=3, k=3, seed=7)
+    s, N, eps = 0.05, 16, 0.0
+    c, rho, vt = fastsum.scaling(v, eps)
+    b = fastsum.coefficients(s * rho, N, 3, eps, 4)
+    x = np.random.default_rng(1).standard_normal(300)
+    f = fastsum.trig_operator(vt, x, b, N)
+    M = fastsum.trig_matrix(vt, b, N)
+    np.testing.assert_allclose(f, M @ x, atol=1e-11)
+    kerr = fastsum.kerr_sampled(b, N, s * rho, eps, 3, samples=40000)
+    err = np.abs(f - (graph.apply_W(v, s, x) + x)).max()
+    # the sampled maximum under-estimates the true sup slightly: allow 2x
+    assert err <= 2.0 * np.abs(x).sum() * kerr
+    assert err > 0.0
+
+
+def test_scaling_puts_nodes_in_ball_and_preserves_weights():
+    v = synth.gmm(200, d=3, seed=1)
+    eps = 6.0 / 64
+    c, rho, vt = fastsum.scaling(v, eps)
+    assert abs(np.linalg.norm(vt, axis=1).max() - (0.25 - eps / 2)) < 1e-15
+    W1 = graph.dense_W(v, 0.04)
+    W2 = graph.dense_W(vt, 0.04 * rho)
+    np.testing.assert_allclose(W1, W2, rtol=1e-12, atol=1e-300)
+
+
+def test_lemma_bound_holds():
+    """Lemma normalization_propagation with the exact eps, eta and ||A - A_E||_inf
+    computed from the full matrices (eq. epsilon_norm_aposteriori)."""
+    v = synth.blobs2d(240, seed=5)
+    s, N, eps_B = 0.05, 32, 0.0
+    c, rho, vt = fastsum.scaling(v, eps_B)
+    b = fastsum.coefficients(s * rho, N, 2, eps_B, 4)
+    Wt_E = fastsum.trig_matrix(vt, b, N)          # W~_E = W + I + E
+    W = graph.dense_W(v, s)
+    E = Wt_E - W - np.eye(W.shape[0])
+    Wn = np.abs(W).sum(axis=1).max()
+    eps = np.abs(E).sum(axis=1).max() / Wn
+    d = W.sum(axis=1)
+    eta = d.min() / Wn
+    assert 0 < eps < eta
+    W_E = W + E
+    dE = W_E.sum(axis=1)
+    A = W / np.sqrt(np.outer(d, d))
+    A_E = W_E / np.sqrt(np.outer(dE, dE))
+    err = np.abs(A - A_E).sum(axis=1).max()
+    assert err <= fastsum.lemma_bound(eps, eta)
+    # and the bound is not vacuous here
+    assert fastsum.lemma_bound(eps, eta) < 1.0
+
+
+# ---- Krylov solvers (Section 4) -----------------------------------------------
+
+def test_lanczos_matches_lapack_and_top_eigenpair():
+    """Largest eigenvalue of A is 1 with eigenvector D^{1/2} 1 (Section 2);
+    the k largest Ritz values match LAPACK's eigh."""
+    v = synth.blobs2d(400, seed=2)
+    s = 0.05
+    A = graph.dense_A(v, s)
+    theta, V, res, steps = krylov.lanczos_largest(lambda q: A @ q, 400, 6, tol=1e-11)
+    ref = np.linalg.eigvalsh(A)[::-1][:6]
+    np.testing.assert_allclose(theta, ref, atol=1e-10)
+    assert abs(theta[0] - 1.0) < 1e-12
+    d = graph.degree(v, s)
+    u = np.sqrt(d) / np.linalg.norm(np.sqrt(d))
+    assert abs(abs(V[:, 0] @ u) - 1.0) < 1e-9
+    for i in range(6):
+        assert np.linalg.norm(A @ V[:, i] - theta[i] * V[:, i]) < 1e-9
+
+
+def test_cg_matches_dense_solve():
+    """CG on (I + tau L_s) u = f (eq. ssl::system) against LAPACK's solve."""
+    v, lab = synth.moons_and_roll(600, seed=3)
+    s, tau = 0.04, 10.0
+    M = np.eye(600) + tau * graph.dense_Ls(v, s)
+    f = synth.ssl_rhs(lab, 0, frac=0.05, seed=1)
+    u, it, rel = krylov.cg(lambda p: M @ p, f, tol=1e-10, maxit=500)
+    np.testing.assert_allclose(u, np.linalg.solve(M, f), atol=1e-8)
+    assert rel <= 1e-10 and it < 200
