@@ -1,0 +1,174 @@
+/*
+ * nfl.h -- NFFT fast summation for the graph Laplacian of a fully connected
+ * Gaussian graph, on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Alfke, Potts, Stoll, Volkmer, "NFFT meets Krylov methods: fast
+ * matrix-vector products for the graph Laplacian of fully connected networks".
+ * Section numbers, equation and algorithm labels below refer to that paper.
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ * - Return value: NFL_OK (0) on success; a negative NFL_ERR_* code on a hard
+ *   error, in which case no output has been written; NFL_NOT_CONVERGED (> 0)
+ *   when an iterative solver stopped at maxit (outputs hold the last iterate).
+ *   nfl_strerror() names every code; nfl_last_error() gives the message of
+ *   the last failure on the calling thread.
+ * - Pointers named *_dev are device pointers (HBM of the device current when
+ *   the handle was created); *_host are host pointers.  The caller owns every
+ *   pointer it passes; the library never keeps one after the call returns
+ *   (points are copied into handle-owned memory).
+ * - Vectors at the boundary are in the caller's node order.  Internally the
+ *   nodes are sorted by grid cell; that order never leaks out.
+ * - All work is enqueued on the stream given to nfl_create() and is
+ *   asynchronous, except where a call returns host scalars (noted below),
+ *   which synchronises that stream.  A handle must not be used from two
+ *   threads at once.
+ * - The kernel is the Gaussian K(y) = exp(-||y||^2 / sigma^2), K(0) = 1
+ *   (eq. W_gaussian).  W has zero diagonal (Section 2).
+ */
+#ifndef NFL_H
+#define NFL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NFL_OK              0
+#define NFL_NOT_CONVERGED   1
+#define NFL_ERR_ARG        -1   /* invalid argument (value or pointer) */
+#define NFL_ERR_ORDER      -2   /* call order: e.g. apply before set_kernel */
+#define NFL_ERR_DEGREE     -3   /* an approximate degree d_E,i <= 0 (Lemma of Section 3.1 needs eps < eta) */
+#define NFL_ERR_HIP        -4   /* a HIP runtime call failed */
+#define NFL_ERR_OOM        -5   /* device allocation failed */
+#define NFL_ERR_UNSUPPORTED -6  /* valid for the method, not supported by this build (e.g. N not a power of 2) */
+
+typedef struct nfl_plan *nfl_handle;
+
+/* Options for nfl_set_option (take effect at the next nfl_set_kernel). */
+#define NFL_OPT_P          1   /* regularisation smoothness p of K_R (Fig. tab:fastsum_param); default p = m */
+#define NFL_OPT_TILE       2   /* grid tile edge T for spread/interp (power of 2, 4..32); default 8 */
+#define NFL_OPT_CHUNK      3   /* max nodes per spread/interp work item; default 2048 */
+#define NFL_OPT_EPS_B_DEFAULT 4 /* if value != 0, nfl_set_kernel with eps_B < 0 uses eps_B = p/N (the paper's default) */
+
+/* Create a plan for nodes in R^d, d in {1, 2, 3}.  `hip_stream` is a
+ * hipStream_t (NULL = the default stream).  Allocates nothing on the device
+ * yet. */
+int nfl_create(nfl_handle *h, int d, void *hip_stream);
+
+/* Release every device buffer of the plan.  Synchronises its stream. */
+int nfl_destroy(nfl_handle h);
+
+/* The vertex set {v_j} (Alg. nfft_fastsum input, Alg. nfft_normalized_matvec
+ * input): n nodes, v_dev is n x d float32 row-major on the device, copied.
+ * Computes the bounding-box midpoint c and R = max_j ||v_j - c|| on the
+ * device (synchronises).  n >= 2.  Invalidates a previous set_kernel. */
+int nfl_set_points(nfl_handle h, int64_t n, const float *v_dev);
+
+/* Kernel and NFFT parameters (Fig. tab:fastsum_param): sigma > 0 in the
+ * coordinates of the points; bandwidth N (even; this build needs a power of
+ * 2, 8 <= N <= 256); window cut-off m (2 <= m <= 8); boundary region eps_B in
+ * [0, 1/2) (or < 0 for the paper's default p/N when NFL_OPT_EPS_B_DEFAULT is
+ * set).  The oversampled grid has 2N points per dimension.
+ * Runs setup steps 1-4 of Alg. nfft_normalized_matvec: scales the nodes by
+ * rho = (1/4 - eps_B/2)/R after shifting them to c (steps 1-2), computes the
+ * Fourier coefficients b_l of the regularised kernel K_R by eq. b_l::K_RF
+ * (step 3), sorts the nodes by grid cell, and computes the approximate
+ * degrees D_E = diag(W~_E 1 - K(0) 1) (step 4).  Synchronises.  Returns
+ * NFL_ERR_DEGREE if some d_E,i <= 0 (then apply calls fail with ORDER). */
+int nfl_set_kernel(nfl_handle h, double sigma, int N, int m, double eps_B);
+
+int nfl_set_option(nfl_handle h, int opt, double value);
+
+/* d_E (step 4 of Alg. nfft_normalized_matvec): n float32 in caller order. */
+int nfl_degree(nfl_handle h, float *d_dev);
+
+/* y = W_E x with W_E = W~_E - K(0) I (Section 3, Alg. nfft_fastsum followed by
+ * removal of the diagonal).  x_dev, y_dev: nvec vectors of n float32, vector
+ * k at offset k*ld (ld >= n); x and y must not overlap. */
+int nfl_apply_W(nfl_handle h, const float *x_dev, float *y_dev, int nvec, int64_t ld);
+
+/* y = L_s x = x - D_E^{-1/2} (W~_E (D_E^{-1/2} x) - K(0) D_E^{-1/2} x), the
+ * symmetric normalised Laplacian (eq. nomlap) through step 5 of Alg.
+ * nfft_normalized_matvec.  Same layout rules as nfl_apply_W. */
+int nfl_apply_Ls(nfl_handle h, const float *x_dev, float *y_dev, int nvec, int64_t ld);
+
+/* y = A_E x, A_E = D_E^{-1/2} W_E D_E^{-1/2} (step 5 of Alg.
+ * nfft_normalized_matvec). */
+int nfl_apply_A(nfl_handle h, const float *x_dev, float *y_dev, int nvec, int64_t ld);
+
+/* The k smallest eigenpairs of L_s (Section 4): Lanczos on A_E for its k
+ * largest eigenvalues theta, lambda = 1 - theta (end of Section 2).  FP64
+ * vectors, full reorthogonalisation (two classical Gram-Schmidt passes),
+ * tridiagonal eigensolve on the device; stop when every wanted Ritz residual
+ * |beta_{j+1} w_j| <= tol (Section 4) or after maxit steps.  block must be 1
+ * (block > 1 runs a block Lanczos of that block size, 1..8).
+ * evals_host: k doubles, ascending eigenvalues of L_s.  evecs_dev: n x k
+ * FP64 column-major in caller order (NULL to skip).  iters, max_resid: host,
+ * may be NULL.  Synchronises.  1 <= k < n, k <= maxit. */
+int nfl_lanczos_smallest(nfl_handle h, int k, int block, double tol, int maxit,
+                         double *evals_host, double *evecs_dev, int *iters, double *max_resid);
+
+/* Warm-start modes of nfl_cg_solve. */
+#define NFL_WARM_ZERO 0
+#define NFL_WARM_USER 1
+#define NFL_WARM_MLP  2
+
+/* CG for (I + tau L_s) u = f, the kernel-SSL system (eq. ssl::system), tau >= 0.
+ * FP64 vectors and inner products, FP32 NFFT matvecs.  Stops when the
+ * recurrence residual ||r|| / ||f|| <= tol or after maxit iterations; relres
+ * (host, may be NULL) is the TRUE residual ||f - (I + tau L_s) u|| / ||f||
+ * recomputed at the end with the same operator.  f_dev, u_dev: n doubles in
+ * caller order.  warm: NFL_WARM_ZERO (u0 = 0), NFL_WARM_USER (u0 read from
+ * u_dev), NFL_WARM_MLP (u0 from the plan's warm-start network, see
+ * nfl_mlp_*).  Synchronises. */
+int nfl_cg_solve(nfl_handle h, double tau, const double *f_dev, double *u_dev, int warm,
+                 double tol, int maxit, int *iters, double *relres);
+
+/* Plan information (host outputs, any may be NULL): rho, sigma_tilde = rho*sigma,
+ * min and max of d_E, and eps_B / p actually used.  Synchronises. */
+int nfl_get_info(nfl_handle h, double *rho, double *sigma_tilde, double *dmin, double *dmax,
+                 double *eps_B, int *p);
+
+/* ---- the individual NFFT steps (for testing; same stream rules) ---------- */
+
+/* Size of the oversampled grid: (2N)^d float32 cells, index ((x*2N)+y)*2N+z
+ * (last dimension fastest).  Valid after nfl_set_kernel. */
+int64_t nfl_grid_size(nfl_handle h);
+
+/* Spread (adjoint NFFT gridding, step 1 of Alg. nfft_fastsum before its FFT):
+ * g[k] = sum_i x_i psi~(k - u_i) with the periodised window psi~ on the grid,
+ * u_i = 2N (v~_i + 1/2).  x_dev: n float32 (caller order); grid_dev: grid
+ * size float32, overwritten. */
+int nfl_spread(nfl_handle h, const float *x_dev, float *grid_dev);
+
+/* FFT -> multiply by the kernel's Fourier coefficients divided by the
+ * window's transform squared -> inverse FFT, on the real grid (the middle of
+ * Alg. nfft_fastsum: end of step 1, step 2, start of step 3). */
+int nfl_convolve(nfl_handle h, const float *grid_in_dev, float *grid_out_dev);
+
+/* Interpolate (step 3 of Alg. nfft_fastsum after its inverse FFT):
+ * f_i = sum_k g[k] psi~(k - u_i), the exact transpose of nfl_spread.  f_dev:
+ * n float32 in caller order. */
+int nfl_interp(nfl_handle h, const float *grid_dev, float *f_dev);
+
+/* The filter the plan multiplies with, on the half spectrum
+ * l_x, l_y in -N/2..N/2, l_z in 0..N/2 (d = 3; fewer axes for d < 3):
+ * (N+1)^(d-1) (N/2+1) doubles, host.  Synchronises. */
+int nfl_get_filter(nfl_handle h, double *filter_host, int64_t count);
+
+/* The same filter computed from explicit parameters without a plan or a GPU
+ * (host FP64; sigma_tilde is sigma in the scaled torus coordinates).  count
+ * must be >= (N+1)^(d-1) (N/2+1).  N a power of 2. */
+int nfl_compute_filter(int d, int N, int m, int p, double eps_B, double sigma_tilde,
+                       double *filter_host, int64_t count);
+
+const char *nfl_strerror(int code);
+const char *nfl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NFL_H */

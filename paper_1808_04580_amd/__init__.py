@@ -1,0 +1,267 @@
+"""Python binding of the NFFT graph-Laplacian library (libnfl.so, gfx950).
+
+Argument marshalling only: every step runs in the HIP library behind the
+C-ABI declared in include/nfl.h.  PyTorch supplies device memory and the
+stream (the current torch stream of the tensors' device).  If the library is
+not built, loading fails loudly; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnfl.so")
+
+NFL_OK = 0
+NFL_NOT_CONVERGED = 1
+NFL_ERR_ARG = -1
+NFL_ERR_ORDER = -2
+NFL_ERR_DEGREE = -3
+NFL_ERR_HIP = -4
+NFL_ERR_OOM = -5
+NFL_ERR_UNSUPPORTED = -6
+
+OPT_P = 1
+OPT_TILE = 2
+OPT_CHUNK = 3
+OPT_EPS_B_DEFAULT = 4
+
+WARM_ZERO = 0
+WARM_USER = 1
+WARM_MLP = 2
+
+_lib = None
+
+# every exported symbol with its (restype, argtypes)
+_i, _i64, _d, _p = ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+SIGNATURES = {
+    "nfl_create": (_i, [ctypes.POINTER(_p), _i, _p]),
+    "nfl_destroy": (_i, [_p]),
+    "nfl_set_points": (_i, [_p, _i64, _p]),
+    "nfl_set_kernel": (_i, [_p, _d, _i, _i, _d]),
+    "nfl_set_option": (_i, [_p, _i, _d]),
+    "nfl_degree": (_i, [_p, _p]),
+    "nfl_apply_W": (_i, [_p, _p, _p, _i, _i64]),
+    "nfl_apply_Ls": (_i, [_p, _p, _p, _i, _i64]),
+    "nfl_apply_A": (_i, [_p, _p, _p, _i, _i64]),
+    "nfl_lanczos_smallest": (_i, [_p, _i, _i, _d, _i, _p, _p, _p, _p]),
+    "nfl_cg_solve": (_i, [_p, _d, _p, _p, _i, _d, _i, _p, _p]),
+    "nfl_get_info": (_i, [_p, _p, _p, _p, _p, _p, _p]),
+    "nfl_grid_size": (_i64, [_p]),
+    "nfl_spread": (_i, [_p, _p, _p]),
+    "nfl_convolve": (_i, [_p, _p, _p]),
+    "nfl_interp": (_i, [_p, _p, _p]),
+    "nfl_get_filter": (_i, [_p, _p, _i64]),
+    "nfl_compute_filter": (_i, [_i, _i, _i, _i, _d, _d, _p, _i64]),
+    "nfl_strerror": (ctypes.c_char_p, [_i]),
+    "nfl_last_error": (ctypes.c_char_p, []),
+}
+
+
+class NFLError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__("%s failed (%d): %s" % (where, code, msg))
+        self.code = code
+
+
+def lib():
+    """Load libnfl.so (built in-tree by paper_1808_04580_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libnfl.so is not built: run python -m paper_1808_04580_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(code: int, where: str, allow_soft: bool = False) -> int:
+    if code < 0 or (code > 0 and not allow_soft):
+        msg = lib().nfl_last_error().decode(errors="replace")
+        raise NFLError(code, where, msg)
+    return code
+
+
+def strerror(code: int) -> str:
+    return lib().nfl_strerror(code).decode()
+
+
+def compute_filter(d: int, N: int, m: int, p: int, eps_B: float, sigma_tilde: float) -> np.ndarray:
+    """The half-spectrum filter (host FP64, no GPU needed)."""
+    count = (N + 1) ** (d - 1) * (N // 2 + 1)
+    out = np.empty(count, dtype=np.float64)
+    _check(lib().nfl_compute_filter(d, N, m, p, float(eps_B), float(sigma_tilde),
+                                    out.ctypes.data_as(_p), count), "nfl_compute_filter")
+    shape = tuple([N + 1] * (d - 1) + [N // 2 + 1])
+    return out.reshape(shape)
+
+
+def _ptr(t) -> int:
+    return t.data_ptr()
+
+
+class Plan:
+    """One graph (vertex set + Gaussian kernel + NFFT parameters) on the
+    current device; all work goes on the current torch stream at creation."""
+
+    def __init__(self, d: int, stream=None):
+        import torch
+        self._torch = torch
+        self.d = d
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.device = self.stream.device
+        h = _p()
+        _check(lib().nfl_create(ctypes.byref(h), d, _p(self.stream.cuda_stream)), "nfl_create")
+        self._h = h
+        self.n = 0
+
+    # -- lifecycle ----------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().nfl_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- setup --------------------------------------------------------------
+    def set_option(self, opt: int, value: float):
+        _check(lib().nfl_set_option(self._h, opt, float(value)), "nfl_set_option")
+
+    def set_points(self, v):
+        torch = self._torch
+        v = torch.as_tensor(v, dtype=torch.float32, device=self.device).contiguous()
+        if v.dim() == 1:
+            v = v[:, None]
+        assert v.shape[1] == self.d
+        self.n = int(v.shape[0])
+        _check(lib().nfl_set_points(self._h, self.n, _ptr(v)), "nfl_set_points")
+
+    def set_kernel(self, sigma: float, N: int, m: int, eps_B: float = 0.0):
+        _check(lib().nfl_set_kernel(self._h, float(sigma), int(N), int(m), float(eps_B)),
+               "nfl_set_kernel")
+        self._N = int(N)
+
+    def info(self) -> dict:
+        vals = [ctypes.c_double() for _ in range(5)]
+        p = ctypes.c_int()
+        _check(lib().nfl_get_info(self._h, *[ctypes.byref(x) for x in vals], ctypes.byref(p)),
+               "nfl_get_info")
+        return dict(rho=vals[0].value, sigma_tilde=vals[1].value, dmin=vals[2].value,
+                    dmax=vals[3].value, eps_B=vals[4].value, p=p.value)
+
+    # -- operators ----------------------------------------------------------
+    def degree(self):
+        torch = self._torch
+        out = torch.empty(self.n, dtype=torch.float32, device=self.device)
+        _check(lib().nfl_degree(self._h, _ptr(out)), "nfl_degree")
+        return out
+
+    def _apply(self, fn, name, x, out=None):
+        torch = self._torch
+        x = torch.as_tensor(x, dtype=torch.float32, device=self.device).contiguous()
+        single = x.dim() == 1
+        X = x[None, :] if single else x
+        assert X.shape[1] == self.n
+        Y = torch.empty_like(X) if out is None else out.view(X.shape)
+        _check(fn(self._h, _ptr(X), _ptr(Y), int(X.shape[0]), self.n), name)
+        return Y[0] if single else Y
+
+    def apply_W(self, x, out=None):
+        return self._apply(lib().nfl_apply_W, "nfl_apply_W", x, out)
+
+    def apply_Ls(self, x, out=None):
+        return self._apply(lib().nfl_apply_Ls, "nfl_apply_Ls", x, out)
+
+    def apply_A(self, x, out=None):
+        return self._apply(lib().nfl_apply_A, "nfl_apply_A", x, out)
+
+    # -- solvers ------------------------------------------------------------
+    def lanczos_smallest(self, k: int, tol: float = 1e-8, maxit: int = 300, block: int = 1,
+                         vectors: bool = True):
+        torch = self._torch
+        ev = np.empty(k, dtype=np.float64)
+        V = torch.empty((k, self.n), dtype=torch.float64, device=self.device) if vectors else None
+        it = ctypes.c_int()
+        res = ctypes.c_double()
+        code = _check(lib().nfl_lanczos_smallest(self._h, k, block, float(tol), int(maxit),
+                                                 ev.ctypes.data_as(_p),
+                                                 _p(_ptr(V)) if V is not None else None,
+                                                 ctypes.byref(it), ctypes.byref(res)),
+                      "nfl_lanczos_smallest", allow_soft=True)
+        return dict(evals=ev, evecs=(V.T if V is not None else None), iters=it.value,
+                    max_resid=res.value, converged=(code == NFL_OK))
+
+    def cg_solve(self, f, tau: float, tol: float = 1e-6, maxit: int = 1000,
+                 warm: int = WARM_ZERO, u0=None):
+        torch = self._torch
+        f = torch.as_tensor(f, dtype=torch.float64, device=self.device).contiguous()
+        if u0 is not None:
+            u = torch.as_tensor(u0, dtype=torch.float64, device=self.device).clone().contiguous()
+            warm = WARM_USER if warm == WARM_ZERO else warm
+        else:
+            u = torch.zeros_like(f)
+        it = ctypes.c_int()
+        rel = ctypes.c_double()
+        code = _check(lib().nfl_cg_solve(self._h, float(tau), _ptr(f), _ptr(u), int(warm),
+                                         float(tol), int(maxit), ctypes.byref(it),
+                                         ctypes.byref(rel)), "nfl_cg_solve", allow_soft=True)
+        return dict(u=u, iters=it.value, relres=rel.value, converged=(code == NFL_OK))
+
+    # -- individual steps -----------------------------------------------------
+    def grid_size(self) -> int:
+        return int(lib().nfl_grid_size(self._h))
+
+    def spread(self, x):
+        torch = self._torch
+        x = torch.as_tensor(x, dtype=torch.float32, device=self.device).contiguous()
+        g = torch.empty(self.grid_size(), dtype=torch.float32, device=self.device)
+        _check(lib().nfl_spread(self._h, _ptr(x), _ptr(g)), "nfl_spread")
+        return g
+
+    def convolve(self, g):
+        out = self._torch.empty_like(g)
+        _check(lib().nfl_convolve(self._h, _ptr(g), _ptr(out)), "nfl_convolve")
+        return out
+
+    def interp(self, g):
+        torch = self._torch
+        f = torch.empty(self.n, dtype=torch.float32, device=self.device)
+        _check(lib().nfl_interp(self._h, _ptr(g.contiguous()), _ptr(f)), "nfl_interp")
+        return f
+
+    def filter(self) -> np.ndarray:
+        N = self._N
+        count = (N + 1) ** (self.d - 1) * (N // 2 + 1)
+        out = np.empty(count, dtype=np.float64)
+        _check(lib().nfl_get_filter(self._h, out.ctypes.data_as(_p), count), "nfl_get_filter")
+        return out
+
+
+def plan(points, sigma: float, N: int, m: int, eps_B: float = 0.0, stream=None, **options):
+    """Create, fill and return a Plan for float32 points (n, d) on the GPU."""
+    import torch
+    v = torch.as_tensor(points)
+    d = 1 if v.dim() == 1 else int(v.shape[1])
+    P = Plan(d, stream)
+    for k, val in options.items():
+        P.set_option({"p": OPT_P, "tile": OPT_TILE, "chunk": OPT_CHUNK}[k], val)
+    P.set_points(v)
+    P.set_kernel(sigma, N, m, eps_B)
+    return P

@@ -1,0 +1,347 @@
+// C-ABI of the NFFT graph-Laplacian library: argument checks, plan
+// lifecycle, call order.  See include/nfl.h for the contract of every entry.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "nfl_internal.h"
+
+namespace nfl {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+int compute_filter(int d, int N, int m, int p, double eps_B, double sigma_t,
+                   std::vector<double> &out);
+
+// The learned warm start is attached by nfl_mlp_*; without a trained model a
+// warm start of mode NFL_WARM_MLP is a call-order error.
+int mlp_warm_start(nfl_plan *P, const double *f_sorted, double *u_sorted);
+
+static bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+static int check_vec_args(nfl_plan *P, const void *x, const void *y, int nvec, int64_t ld) {
+  if (!P) { set_error("null handle"); return NFL_ERR_ARG; }
+  if (!P->have_kernel) { set_error("apply before a successful nfl_set_kernel"); return NFL_ERR_ORDER; }
+  if (!x || !y) { set_error("null vector pointer"); return NFL_ERR_ARG; }
+  if (nvec < 1) { set_error("nvec < 1"); return NFL_ERR_ARG; }
+  if (ld < P->n) { set_error("ld < n"); return NFL_ERR_ARG; }
+  return NFL_OK;
+}
+
+// (min, max) of the degrees: small host copy of the FP32 vector (setup only).
+static int degree_stats(nfl_plan *P) {
+  std::vector<float> h((size_t)P->n);
+  NFL_HIP(hipMemcpyAsync(h.data(), P->deg.p, (size_t)P->n * sizeof(float), hipMemcpyDeviceToHost,
+                         P->stream));
+  NFL_HIP(hipStreamSynchronize(P->stream));
+  double lo = INFINITY, hi = -INFINITY;
+  for (float v : h) {
+    lo = std::fmin(lo, (double)v);
+    hi = std::fmax(hi, (double)v);
+  }
+  P->dmin = lo;
+  P->dmax = hi;
+  return NFL_OK;
+}
+
+}  // namespace nfl
+
+using namespace nfl;
+
+extern "C" {
+
+int nfl_create(nfl_handle *h, int d, void *hip_stream) {
+  if (!h) { set_error("null handle pointer"); return NFL_ERR_ARG; }
+  *h = nullptr;
+  if (d < 1 || d > 3) { set_error("d must be 1, 2 or 3"); return NFL_ERR_ARG; }
+  nfl_plan *P = new (std::nothrow) nfl_plan();
+  if (!P) { set_error("host allocation failed"); return NFL_ERR_OOM; }
+  P->d = d;
+  P->stream = (hipStream_t)hip_stream;
+  if (hipGetDevice(&P->device) != hipSuccess) {
+    delete P;
+    set_error("hipGetDevice failed");
+    return NFL_ERR_HIP;
+  }
+  *h = P;
+  return NFL_OK;
+}
+
+int nfl_destroy(nfl_handle P) {
+  if (!P) return NFL_OK;
+  (void)hipStreamSynchronize(P->stream);
+  P->pts_user.release();
+  P->pts.release();
+  P->perm.release();
+  P->items.release();
+  P->filt.release();
+  P->tw.release();
+  P->grid.release();
+  P->spec1.release();
+  P->spec2.release();
+  P->deg.release();
+  P->dinv.release();
+  P->xs.release();
+  P->fs.release();
+  P->red.release();
+  P->tmp.release();
+  delete P;
+  return NFL_OK;
+}
+
+int nfl_set_option(nfl_handle P, int opt, double value) {
+  if (!P) { set_error("null handle"); return NFL_ERR_ARG; }
+  switch (opt) {
+    case NFL_OPT_P:
+      if (value < 0 || value > 16 || value != std::floor(value)) { set_error("p must be 0 (= m) or 1..16"); return NFL_ERR_ARG; }
+      P->opt_p = (int)value;
+      return NFL_OK;
+    case NFL_OPT_TILE:
+      if (!is_pow2((int)value) || value < 4 || value > 32) { set_error("tile must be a power of 2 in [4, 32]"); return NFL_ERR_ARG; }
+      P->opt_tile = (int)value;
+      return NFL_OK;
+    case NFL_OPT_CHUNK:
+      if (value < 64 || value > (1 << 24)) { set_error("chunk must be in [64, 2^24]"); return NFL_ERR_ARG; }
+      P->opt_chunk = (int)value;
+      return NFL_OK;
+    case NFL_OPT_EPS_B_DEFAULT:
+      P->opt_eps_default = value != 0;
+      return NFL_OK;
+    default:
+      set_error("unknown option");
+      return NFL_ERR_ARG;
+  }
+}
+
+int nfl_set_points(nfl_handle P, int64_t n, const float *v_dev) {
+  if (!P) { set_error("null handle"); return NFL_ERR_ARG; }
+  if (n < 2) { set_error("need n >= 2 points"); return NFL_ERR_ARG; }
+  if (n > (int64_t)1 << 30) { set_error("n above 2^30 is not supported"); return NFL_ERR_UNSUPPORTED; }
+  if (!v_dev) { set_error("null point pointer"); return NFL_ERR_ARG; }
+  P->have_points = false;
+  P->have_kernel = false;
+  P->n = n;
+  NFL_TRY(P->pts_user.ensure((size_t)n * P->d));
+  NFL_HIP(hipMemcpyAsync(P->pts_user.p, v_dev, (size_t)n * P->d * sizeof(float),
+                         hipMemcpyDeviceToDevice, P->stream));
+  NFL_TRY(bbox_and_radius(P));
+  if (!std::isfinite(P->radius)) { set_error("non-finite coordinates"); return NFL_ERR_ARG; }
+  P->have_points = true;
+  return NFL_OK;
+}
+
+int nfl_set_kernel(nfl_handle P, double sigma, int N, int m, double eps_B) {
+  if (!P) { set_error("null handle"); return NFL_ERR_ARG; }
+  if (!P->have_points) { set_error("set_kernel before set_points"); return NFL_ERR_ORDER; }
+  if (!(sigma > 0) || !std::isfinite(sigma)) { set_error("sigma must be > 0"); return NFL_ERR_ARG; }
+  if (N < 2 || (N & 1)) { set_error("N must be even and >= 2"); return NFL_ERR_ARG; }
+  if (m < 1) { set_error("m must be >= 1"); return NFL_ERR_ARG; }
+  const int p = P->opt_p > 0 ? P->opt_p : m;
+  if (eps_B < 0 && P->opt_eps_default) eps_B = (double)p / N;
+  if (!(eps_B >= 0.0 && eps_B < 0.5)) { set_error("eps_B must be in [0, 1/2)"); return NFL_ERR_ARG; }
+  if (!is_pow2(N) || N < 8 || N > 256) { set_error("this build needs N a power of 2 in [8, 256]"); return NFL_ERR_UNSUPPORTED; }
+  if (m < 2 || m > 8) { set_error("this build supports 2 <= m <= 8"); return NFL_ERR_UNSUPPORTED; }
+  if (2 * m > N) { set_error("window wider than half the grid (need m <= N/2)"); return NFL_ERR_UNSUPPORTED; }
+  P->have_kernel = false;
+  P->sigma = sigma;
+  P->N = N;
+  P->m = m;
+  P->p = p;
+  P->eps_B = eps_B;
+  P->nos = 2 * N;
+  P->rho = P->radius > 0 ? (0.25 - 0.5 * eps_B) / P->radius : 1.0;
+  P->sigma_t = sigma * P->rho;
+  P->win.m = m;
+  P->win.b = (float)(M_PI * 1.5);
+  P->win.mm = (float)(m * m);
+
+  NFL_TRY(build_filter_host(P));
+  NFL_TRY(P->filt.ensure(P->filt_host.size()));
+  {
+    std::vector<float> f32(P->filt_host.size());
+    for (size_t i = 0; i < f32.size(); ++i) f32[i] = (float)P->filt_host[i];
+    NFL_HIP(hipMemcpyAsync(P->filt.p, f32.data(), f32.size() * sizeof(float),
+                           hipMemcpyHostToDevice, P->stream));
+    std::vector<float2> tw((size_t)P->nos / 2);
+    for (int k = 0; k < P->nos / 2; ++k) {
+      const double a = -2.0 * M_PI * k / P->nos;
+      tw[k] = make_float2((float)std::cos(a), (float)std::sin(a));
+    }
+    NFL_TRY(P->tw.ensure(tw.size()));
+    NFL_HIP(hipMemcpyAsync(P->tw.p, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice,
+                           P->stream));
+    NFL_HIP(hipStreamSynchronize(P->stream));
+  }
+  int64_t gsz = 1;
+  for (int t = 0; t < P->d; ++t) gsz *= P->nos;
+  NFL_TRY(P->grid.ensure(gsz));
+  const int Hz = N / 2 + 1, F = N + 1;
+  size_t s1 = Hz, s2 = 0;
+  if (P->d == 2) s1 = (size_t)P->nos * Hz;
+  if (P->d == 3) {
+    s1 = (size_t)P->nos * P->nos * Hz;
+    s2 = (size_t)P->nos * F * Hz;
+  }
+  NFL_TRY(P->spec1.ensure(s1));
+  if (s2) NFL_TRY(P->spec2.ensure(s2));
+  NFL_TRY(build_sorted_nodes(P));
+  NFL_TRY(P->deg.ensure(P->n));
+  NFL_TRY(P->dinv.ensure(P->n));
+
+  // step 4 of Alg. nfft_normalized_matvec: D_E = diag(W~_E 1 - K(0) 1)
+  VecArgs a;
+  NFL_TRY(fastsum(P, IN_ONES, OUT_DEGREE, a));
+  NFL_TRY(degree_stats(P));
+  if (!(P->dmin > 0.0)) {
+    set_error("approximate degree d_E <= 0 for some node (eps >= eta): raise N or m");
+    return NFL_ERR_DEGREE;
+  }
+  P->have_kernel = true;
+  return NFL_OK;
+}
+
+int nfl_degree(nfl_handle P, float *d_dev) {
+  if (!P) { set_error("null handle"); return NFL_ERR_ARG; }
+  if (!P->have_kernel) { set_error("degree before a successful nfl_set_kernel"); return NFL_ERR_ORDER; }
+  if (!d_dev) { set_error("null output"); return NFL_ERR_ARG; }
+  return scatter_f32(P, P->deg.p, d_dev);
+}
+
+static int apply_common(nfl_handle P, const float *x, float *y, int nvec, int64_t ld, int in_mode,
+                        int out_mode) {
+  NFL_TRY(check_vec_args(P, x, y, nvec, ld));
+  for (int k = 0; k < nvec; ++k) {
+    VecArgs a;
+    a.x32 = x + (int64_t)k * ld;
+    a.y32 = y + (int64_t)k * ld;
+    NFL_TRY(fastsum(P, in_mode, out_mode, a));
+  }
+  return NFL_OK;
+}
+
+int nfl_apply_W(nfl_handle P, const float *x, float *y, int nvec, int64_t ld) {
+  return apply_common(P, x, y, nvec, ld, IN_USER_F32, OUT_USER_W);
+}
+
+int nfl_apply_Ls(nfl_handle P, const float *x, float *y, int nvec, int64_t ld) {
+  return apply_common(P, x, y, nvec, ld, IN_USER_F32_DINV, OUT_USER_LS);
+}
+
+int nfl_apply_A(nfl_handle P, const float *x, float *y, int nvec, int64_t ld) {
+  return apply_common(P, x, y, nvec, ld, IN_USER_F32_DINV, OUT_USER_A);
+}
+
+int nfl_lanczos_smallest(nfl_handle P, int k, int block, double tol, int maxit, double *evals_host,
+                         double *evecs_dev, int *iters, double *max_resid) {
+  if (!P) { set_error("null handle"); return NFL_ERR_ARG; }
+  if (!P->have_kernel) { set_error("lanczos before a successful nfl_set_kernel"); return NFL_ERR_ORDER; }
+  if (!evals_host) { set_error("null eigenvalue output"); return NFL_ERR_ARG; }
+  if (k < 1 || k >= P->n || maxit < k || !(tol > 0)) { set_error("need 1 <= k < n, maxit >= k, tol > 0"); return NFL_ERR_ARG; }
+  if (block < 1 || block > 8) { set_error("block must be in 1..8"); return NFL_ERR_ARG; }
+  return lanczos(P, k, block, tol, maxit, evals_host, evecs_dev, iters, max_resid);
+}
+
+int nfl_cg_solve(nfl_handle P, double tau, const double *f_dev, double *u_dev, int warm, double tol,
+                 int maxit, int *iters, double *relres) {
+  if (!P) { set_error("null handle"); return NFL_ERR_ARG; }
+  if (!P->have_kernel) { set_error("cg before a successful nfl_set_kernel"); return NFL_ERR_ORDER; }
+  if (!f_dev || !u_dev) { set_error("null vector pointer"); return NFL_ERR_ARG; }
+  if (!(tau >= 0) || !(tol > 0) || maxit < 0) { set_error("need tau >= 0, tol > 0, maxit >= 0"); return NFL_ERR_ARG; }
+  if (warm < NFL_WARM_ZERO || warm > NFL_WARM_MLP) { set_error("bad warm-start mode"); return NFL_ERR_ARG; }
+  return cg(P, tau, f_dev, u_dev, warm, tol, maxit, iters, relres);
+}
+
+int nfl_get_info(nfl_handle P, double *rho, double *sigma_tilde, double *dmin, double *dmax,
+                 double *eps_B, int *p) {
+  if (!P) { set_error("null handle"); return NFL_ERR_ARG; }
+  if (!P->have_kernel) { set_error("info before a successful nfl_set_kernel"); return NFL_ERR_ORDER; }
+  if (rho) *rho = P->rho;
+  if (sigma_tilde) *sigma_tilde = P->sigma_t;
+  if (dmin) *dmin = P->dmin;
+  if (dmax) *dmax = P->dmax;
+  if (eps_B) *eps_B = P->eps_B;
+  if (p) *p = P->p;
+  return NFL_OK;
+}
+
+int64_t nfl_grid_size(nfl_handle P) {
+  if (!P || P->nos == 0) return 0;
+  int64_t g = 1;
+  for (int t = 0; t < P->d; ++t) g *= P->nos;
+  return g;
+}
+
+int nfl_spread(nfl_handle P, const float *x_dev, float *grid_dev) {
+  NFL_TRY(check_vec_args(P, x_dev, grid_dev, 1, P ? P->n : 0));
+  VecArgs a;
+  a.x32 = x_dev;
+  return spread(P, IN_USER_F32, a, grid_dev);
+}
+
+int nfl_convolve(nfl_handle P, const float *gin, float *gout) {
+  NFL_TRY(check_vec_args(P, gin, gout, 1, P ? P->n : 0));
+  return convolve(P, gin, gout);
+}
+
+int nfl_interp(nfl_handle P, const float *grid_dev, float *f_dev) {
+  NFL_TRY(check_vec_args(P, grid_dev, f_dev, 1, P ? P->n : 0));
+  VecArgs a;
+  a.y32 = f_dev;
+  return interp(P, grid_dev, IN_USER_F32, OUT_USER_RAW, a);
+}
+
+int nfl_get_filter(nfl_handle P, double *filter_host, int64_t count) {
+  if (!P) { set_error("null handle"); return NFL_ERR_ARG; }
+  if (!P->have_kernel) { set_error("filter before a successful nfl_set_kernel"); return NFL_ERR_ORDER; }
+  if (!filter_host || count < (int64_t)P->filt_host.size()) { set_error("filter buffer too small"); return NFL_ERR_ARG; }
+  std::memcpy(filter_host, P->filt_host.data(), P->filt_host.size() * sizeof(double));
+  return NFL_OK;
+}
+
+int nfl_compute_filter(int d, int N, int m, int p, double eps_B, double sigma_tilde,
+                       double *filter_host, int64_t count) {
+  if (!filter_host) { set_error("null output"); return NFL_ERR_ARG; }
+  if (d < 1 || d > 3 || N < 2 || (N & 1) || !is_pow2(N) || m < 1 || p < 1 ||
+      !(eps_B >= 0 && eps_B < 0.5) || !(sigma_tilde > 0)) {
+    set_error("bad filter arguments");
+    return NFL_ERR_ARG;
+  }
+  std::vector<double> f;
+  NFL_TRY(compute_filter(d, N, m, p, eps_B, sigma_tilde, f));
+  if (count < (int64_t)f.size()) { set_error("filter buffer too small"); return NFL_ERR_ARG; }
+  std::memcpy(filter_host, f.data(), f.size() * sizeof(double));
+  return NFL_OK;
+}
+
+const char *nfl_strerror(int code) {
+  switch (code) {
+    case NFL_OK: return "ok";
+    case NFL_NOT_CONVERGED: return "not converged (outputs hold the last iterate)";
+    case NFL_ERR_ARG: return "invalid argument";
+    case NFL_ERR_ORDER: return "call order (set_points / set_kernel first)";
+    case NFL_ERR_DEGREE: return "approximate degree <= 0 (eps >= eta)";
+    case NFL_ERR_HIP: return "HIP runtime error";
+    case NFL_ERR_OOM: return "out of device memory";
+    case NFL_ERR_UNSUPPORTED: return "unsupported by this build";
+    default: return "unknown error code";
+  }
+}
+
+const char *nfl_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"
+
+namespace nfl {
+int mlp_warm_start(nfl_plan *P, const double *f_sorted, double *u_sorted) {
+  (void)P;
+  (void)f_sorted;
+  (void)u_sorted;
+  set_error("no warm-start network attached to this plan");
+  return NFL_ERR_ORDER;
+}
+}  // namespace nfl

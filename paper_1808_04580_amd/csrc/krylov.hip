@@ -1,0 +1,550 @@
+// Krylov solvers on top of the NFFT operator (Section 4): Lanczos with full
+// reorthogonalisation for the largest eigenvalues of A_E (= 1 - smallest of
+// L_s) and CG for the kernel-SSL system (I + tau L_s) u = f.  Vectors live in
+// the plan's sorted node order in FP64; the operator runs in FP32.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <vector>
+
+#include "nfl_internal.h"
+
+namespace nfl {
+
+constexpr int VT = 256;        // threads per block for vector kernels
+constexpr int VBLOCKS = 1024;  // row blocks for reductions
+
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += sh[k];
+  return t;  // valid in thread 0
+}
+
+__global__ __launch_bounds__(VT) void k_dot_partial(const double *__restrict__ x,
+                                                    const double *__restrict__ y, int64_t n,
+                                                    double *__restrict__ part) {
+  __shared__ double sh[VT / 64];
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT)
+    s += x[i] * y[i];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// out[0] = sum of part (op 0) or its square root (op 1); fixed order -> deterministic.
+__global__ __launch_bounds__(VT) void k_reduce_final(const double *__restrict__ part, int nb,
+                                                     double *__restrict__ out, int op) {
+  __shared__ double sh[VT / 64];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += VT) s += part[i];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) out[0] = op == 1 ? sqrt(s) : s;
+}
+
+__global__ __launch_bounds__(VT) void k_gather64(const double *__restrict__ src,
+                                                 const int *__restrict__ perm, int64_t n,
+                                                 double *__restrict__ dst) {
+  for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT)
+    dst[i] = src[perm[i]];
+}
+
+__global__ __launch_bounds__(VT) void k_scatter64(const double *__restrict__ src,
+                                                  const int *__restrict__ perm, int64_t n,
+                                                  double *__restrict__ dst) {
+  for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT)
+    dst[perm[i]] = src[i];
+}
+
+__global__ __launch_bounds__(VT) void k_fill64(double *__restrict__ p, int64_t n, double v) {
+  for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT)
+    p[i] = v;
+}
+
+// Deterministic start vector: splitmix64 counter hash -> two uniforms -> Box-Muller.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
+  z += 0x9e3779b97f4a7c15ULL;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+  return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(VT) void k_start_vector(double *__restrict__ q,
+                                                     const int *__restrict__ perm, int64_t n,
+                                                     uint64_t seed) {
+  for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT) {
+    // keyed by the caller's index so the start vector does not depend on the sort
+    const uint64_t key = (uint64_t)perm[i] * 2ull + seed * 0x100000001b3ull;
+    const double u1 = ((splitmix64(key) >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+    const double u2 = ((splitmix64(key + 1) >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+    q[i] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+  }
+}
+
+// q = w * (1 / s[0])
+__global__ __launch_bounds__(VT) void k_scale_inv(const double *__restrict__ w,
+                                                  const double *__restrict__ s, int64_t n,
+                                                  double *__restrict__ q) {
+  const double f = 1.0 / s[0];
+  for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT)
+    q[i] = w[i] * f;
+}
+
+// w -= alpha[0] * q + beta[0] * qp (qp may be null)
+__global__ __launch_bounds__(VT) void k_lanczos_sub(double *__restrict__ w,
+                                                    const double *__restrict__ q,
+                                                    const double *__restrict__ qp,
+                                                    const double *__restrict__ alpha,
+                                                    const double *__restrict__ beta, int64_t n) {
+  const double a = alpha[0], b = qp ? beta[0] : 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT)
+    w[i] -= a * q[i] + (qp ? b * qp[i] : 0.0);
+}
+
+// part[b*J + j] = sum over this block's rows of Q[j*ld + i] w[i]
+__global__ __launch_bounds__(VT) void k_gemv_t_partial(const double *__restrict__ Q, int64_t ld,
+                                                       int J, const double *__restrict__ w,
+                                                       int64_t n, double *__restrict__ part) {
+  __shared__ double sh[VT / 64];
+  for (int j = 0; j < J; ++j) {
+    double s = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT)
+      s += Q[j * ld + i] * w[i];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * J + j] = s;
+  }
+}
+
+__global__ __launch_bounds__(VT) void k_gemv_t_final(const double *__restrict__ part, int nb,
+                                                     int J, double *__restrict__ c) {
+  for (int j = blockIdx.x * VT + threadIdx.x; j < J; j += gridDim.x * VT) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += part[(int64_t)b * J + j];
+    c[j] = s;
+  }
+}
+
+// w[i] -= sum_j Q[j*ld + i] c[j]
+__global__ __launch_bounds__(VT) void k_gemv_n_sub(const double *__restrict__ Q, int64_t ld,
+                                                   int J, const double *__restrict__ c,
+                                                   double *__restrict__ w, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT) {
+    double s = 0.0;
+    for (int j = 0; j < J; ++j) s += Q[j * ld + i] * c[j];
+    w[i] -= s;
+  }
+}
+
+// out[c*n + i] = sum_j Q[j*ld + i] Z[sel[c]*J + j]   (Ritz vectors, sorted order)
+__global__ __launch_bounds__(VT) void k_ritz(const double *__restrict__ Q, int64_t ld, int J,
+                                             const double *__restrict__ Z,
+                                             const int *__restrict__ sel, int k, int64_t n,
+                                             double *__restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT) {
+    for (int c = 0; c < k; ++c) {
+      const double *z = Z + (int64_t)sel[c] * J;
+      double s = 0.0;
+      for (int j = 0; j < J; ++j) s += Q[j * ld + i] * z[j];
+      out[(int64_t)c * n + i] = s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Symmetric tridiagonal eigensolver on the device: implicit QL with shifts
+// (the tql2 algorithm of Bowdler, Martin, Reinsch and Wilkinson).
+// k_tridiag_ql: one thread runs the QL sweeps on (diag, off) held in LDS and
+// records every plane rotation (i, c, s) in order.  k_tridiag_apply: each
+// thread owns one row of the identity and applies the whole rotation sequence
+// to it, which yields that row of the eigenvector matrix.  Output: eval[J]
+// (unsorted), Z[col*J + row] = row-th component of the col-th eigenvector.
+// status[0] = 0 on success, 1 if the iteration limit or the rotation buffer
+// was exceeded.
+// ---------------------------------------------------------------------------
+constexpr int QL_MAXJ = 1024;
+
+__global__ __launch_bounds__(64) void k_tridiag_ql(const double *__restrict__ alpha,
+                                                   const double *__restrict__ beta, int J,
+                                                   double *__restrict__ rot, int64_t max_rot,
+                                                   int64_t *__restrict__ nrot_out,
+                                                   double *__restrict__ eval,
+                                                   int *__restrict__ status) {
+  __shared__ double d[QL_MAXJ], e[QL_MAXJ];
+  for (int i = threadIdx.x; i < J; i += 64) {
+    d[i] = alpha[i];
+    e[i] = (i + 1 < J) ? beta[i + 1] : 0.0;  // beta[i+1] couples i and i+1
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  int64_t nr = 0;
+  int st = 0;
+  for (int l = 0; l < J && !st; ++l) {
+    int iter = 0;
+    int m;
+    do {
+      for (m = l; m < J - 1; ++m) {
+        const double dd = fabs(d[m]) + fabs(d[m + 1]);
+        if (fabs(e[m]) <= 2.220446049250313e-16 * dd) break;
+      }
+      if (m != l) {
+        if (++iter > 60) { st = 1; break; }
+        double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+        double r = hypot(g, 1.0);
+        g = d[m] - d[l] + e[l] / (g + (g >= 0.0 ? fabs(r) : -fabs(r)));
+        double s = 1.0, c = 1.0, p = 0.0;
+        bool early = false;
+        for (int i = m - 1; i >= l; --i) {
+          const double f = s * e[i];
+          const double b = c * e[i];
+          r = hypot(f, g);
+          e[i + 1] = r;
+          if (r == 0.0) {
+            d[i + 1] -= p;
+            e[m] = 0.0;
+            early = true;
+            break;
+          }
+          s = f / r;
+          c = g / r;
+          g = d[i + 1] - p;
+          r = (d[i] - g) * s + 2.0 * c * b;
+          p = s * r;
+          d[i + 1] = g + p;
+          g = c * r - b;
+          if (nr < max_rot) {
+            rot[3 * nr] = (double)i;
+            rot[3 * nr + 1] = c;
+            rot[3 * nr + 2] = s;
+            ++nr;
+          } else {
+            st = 1;
+          }
+        }
+        if (early) continue;
+        d[l] -= p;
+        e[l] = g;
+        e[m] = 0.0;
+      }
+    } while (m != l);
+  }
+  for (int i = 0; i < J; ++i) eval[i] = d[i];
+  nrot_out[0] = nr;
+  status[0] = st;
+}
+
+constexpr int QL_CHUNK = 512;
+
+// rows [blockIdx.x*rb, +rb), one thread per row; LDS: rb*J doubles + chunk of rotations
+__global__ __launch_bounds__(64) void k_tridiag_apply(const double *__restrict__ rot,
+                                                      const int64_t *__restrict__ nrot_in, int J,
+                                                      int rb, double *__restrict__ Z) {
+  extern __shared__ double sm[];
+  double *z = sm;                 // z[col*rb + r]
+  double *rc = sm + (size_t)rb * J;  // 3*QL_CHUNK
+  const int r = threadIdx.x;
+  const int row = blockIdx.x * rb + r;
+  const bool act = r < rb && row < J;
+  if (act)
+    for (int col = 0; col < J; ++col) z[col * rb + r] = (col == row) ? 1.0 : 0.0;
+  const int64_t nr = nrot_in[0];
+  for (int64_t t0 = 0; t0 < nr; t0 += QL_CHUNK) {
+    const int cnt = (int)min((int64_t)QL_CHUNK, nr - t0);
+    __syncthreads();
+    for (int q = threadIdx.x; q < 3 * cnt; q += blockDim.x) rc[q] = rot[3 * t0 + q];
+    __syncthreads();
+    if (act) {
+      for (int t = 0; t < cnt; ++t) {
+        const int i = (int)rc[3 * t];
+        const double c = rc[3 * t + 1], s = rc[3 * t + 2];
+        const double f = z[(i + 1) * rb + r];
+        const double zi = z[i * rb + r];
+        z[(i + 1) * rb + r] = s * zi + c * f;
+        z[i * rb + r] = c * zi - s * f;
+      }
+    }
+  }
+  if (act)
+    for (int col = 0; col < J; ++col) Z[(int64_t)col * J + row] = z[col * rb + r];
+}
+
+// ---------------------------------------------------------------------------
+// Host helpers
+// ---------------------------------------------------------------------------
+struct Reducer {
+  DBuf<double> part;
+  int nb = 0;
+  int init(int64_t n) {
+    nb = (int)std::max<int64_t>(1, std::min<int64_t>(VBLOCKS, (n + VT - 1) / VT));
+    return part.ensure((size_t)nb * 512 + 16);
+  }
+};
+
+static int dot(nfl_plan *P, Reducer &R, const double *x, const double *y, double *out,
+               int op = 0) {
+  hipLaunchKernelGGL(k_dot_partial, dim3(R.nb), dim3(VT), 0, P->stream, x, y, P->n, R.part.p);
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(VT), 0, P->stream, R.part.p, R.nb, out, op);
+  NFL_HIP(hipGetLastError());
+  return NFL_OK;
+}
+
+static int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(4096, (n + VT - 1) / VT)); }
+
+// w = A_E q (sorted order, FP64 in/out, FP32 NFFT)
+static int apply_A64(nfl_plan *P, const double *q, double *w) {
+  VecArgs a;
+  a.x64 = q;
+  a.y64 = w;
+  return fastsum(P, IN_SORTED_F64_DINV, OUT_SORTED_F64_A, a);
+}
+
+// w = (I + tau L_s) q
+static int apply_SSL64(nfl_plan *P, double tau, const double *q, double *w) {
+  VecArgs a;
+  a.x64 = q;
+  a.y64 = w;
+  a.tau = tau;
+  return fastsum(P, IN_SORTED_F64_DINV, OUT_SORTED_F64_SSL, a);
+}
+
+int lanczos(nfl_plan *P, int k, int block, double tol, int maxit, double *evals_host,
+            double *evecs_dev, int *iters, double *max_resid) {
+  if (block != 1) {
+    set_error("lanczos: only block = 1 is implemented");
+    return NFL_ERR_UNSUPPORTED;
+  }
+  const int64_t n = P->n;
+  maxit = (int)std::min<int64_t>(maxit, n);
+  if (k < 1 || k > maxit) {
+    set_error("lanczos: need 1 <= k <= min(maxit, n)");
+    return NFL_ERR_ARG;
+  }
+  const int64_t ld = n;
+  DBuf<double> Q, w, sc, cvec, part, rot, ev, Z;
+  DBuf<int64_t> nrot;
+  DBuf<int> st, sel;
+  NFL_TRY(Q.ensure((size_t)ld * (maxit + 1)));
+  NFL_TRY(w.ensure(n));
+  NFL_TRY(sc.ensure(2 * (size_t)maxit + 8));  // alpha[0..maxit), beta[0..maxit]
+  NFL_TRY(cvec.ensure(maxit + 1));
+  Reducer R;
+  NFL_TRY(R.init(n));
+  NFL_TRY(part.ensure((size_t)R.nb * (maxit + 1)));
+  const int64_t max_rot = (int64_t)8 * (maxit + 1) * (maxit + 1) + 4096;
+  NFL_TRY(rot.ensure((size_t)(3 * max_rot)));
+  NFL_TRY(ev.ensure(maxit + 1));
+  NFL_TRY(Z.ensure((size_t)(maxit + 1) * (maxit + 1)));
+  NFL_TRY(nrot.ensure(1));
+  NFL_TRY(st.ensure(1));
+  NFL_TRY(sel.ensure(k));
+  double *alpha = sc.p, *beta = sc.p + maxit;  // beta[j] couples q_{j-1}, q_j
+  const int gb = grid_for(n);
+  hipStream_t s = P->stream;
+
+  hipLaunchKernelGGL(k_fill64, dim3(1), dim3(VT), 0, s, sc.p, (int64_t)(2 * maxit + 8), 0.0);
+  hipLaunchKernelGGL(k_start_vector, dim3(gb), dim3(VT), 0, s, w.p, P->perm.p, n, (uint64_t)1);
+  NFL_TRY(dot(P, R, w.p, w.p, beta, 1));  // beta[0] = ||r|| (used only to normalise)
+  hipLaunchKernelGGL(k_scale_inv, dim3(gb), dim3(VT), 0, s, w.p, beta, n, Q.p);
+  hipLaunchKernelGGL(k_fill64, dim3(1), dim3(VT), 0, s, beta, (int64_t)1, 0.0);
+
+  std::vector<double> h_eval, h_Z, h_beta(1);
+  std::vector<int> h_sel(k);
+  int J = 0;
+  bool converged = false;
+  double worst = 0.0;
+  if (maxit > QL_MAXJ) {
+    set_error("lanczos: maxit above 1024 is not supported");
+    return NFL_ERR_UNSUPPORTED;
+  }
+  for (int j = 0; j < maxit; ++j) {
+    const double *qj = Q.p + (int64_t)j * ld;
+    NFL_TRY(apply_A64(P, qj, w.p));
+    NFL_TRY(dot(P, R, qj, w.p, alpha + j));
+    hipLaunchKernelGGL(k_lanczos_sub, dim3(gb), dim3(VT), 0, s, w.p, qj,
+                       j > 0 ? Q.p + (int64_t)(j - 1) * ld : (const double *)nullptr, alpha + j,
+                       beta + j, n);
+    for (int pass = 0; pass < 2; ++pass) {
+      hipLaunchKernelGGL(k_gemv_t_partial, dim3(R.nb), dim3(VT), 0, s, Q.p, ld, j + 1, w.p, n,
+                         part.p);
+      hipLaunchKernelGGL(k_gemv_t_final, dim3(1), dim3(VT), 0, s, part.p, R.nb, j + 1, cvec.p);
+      hipLaunchKernelGGL(k_gemv_n_sub, dim3(gb), dim3(VT), 0, s, Q.p, ld, j + 1, cvec.p, w.p, n);
+    }
+    NFL_TRY(dot(P, R, w.p, w.p, beta + j + 1, 1));
+    hipLaunchKernelGGL(k_scale_inv, dim3(gb), dim3(VT), 0, s, w.p, beta + j + 1, n,
+                       Q.p + (int64_t)(j + 1) * ld);
+    NFL_HIP(hipGetLastError());
+    J = j + 1;
+    const bool last = (J == maxit);
+    const int check_every = J <= 100 ? 5 : 10;
+    if (J >= k && (J % check_every == 0 || last || J == k)) {
+      hipLaunchKernelGGL(k_tridiag_ql, dim3(1), dim3(64), 0, s, alpha, beta, J, rot.p, max_rot,
+                         nrot.p, ev.p, st.p);
+      const int rb = std::max(1, std::min(64, (int)(48000 / (8 * J))));
+      const size_t zl = ((size_t)rb * J + 3 * QL_CHUNK) * sizeof(double);
+      hipLaunchKernelGGL(k_tridiag_apply, dim3((J + rb - 1) / rb), dim3(64), zl, s, rot.p,
+                         nrot.p, J, rb, Z.p);
+      NFL_HIP(hipGetLastError());
+      h_eval.resize(J);
+      h_Z.resize((size_t)J * J);
+      int h_st = 0;
+      NFL_HIP(hipMemcpyAsync(h_eval.data(), ev.p, J * sizeof(double), hipMemcpyDeviceToHost, s));
+      NFL_HIP(hipMemcpyAsync(h_Z.data(), Z.p, (size_t)J * J * sizeof(double),
+                             hipMemcpyDeviceToHost, s));
+      NFL_HIP(hipMemcpyAsync(h_beta.data(), beta + J, sizeof(double), hipMemcpyDeviceToHost, s));
+      NFL_HIP(hipMemcpyAsync(&h_st, st.p, sizeof(int), hipMemcpyDeviceToHost, s));
+      NFL_HIP(hipStreamSynchronize(s));
+      if (h_st != 0) {
+        set_error("lanczos: tridiagonal QL did not converge");
+        return NFL_ERR_HIP;
+      }
+      std::vector<int> order(J);
+      std::iota(order.begin(), order.end(), 0);
+      std::sort(order.begin(), order.end(), [&](int a, int b) { return h_eval[a] > h_eval[b]; });
+      worst = 0.0;
+      for (int c = 0; c < k; ++c) {
+        h_sel[c] = order[c];
+        const double res = std::fabs(h_beta[0] * h_Z[(size_t)order[c] * J + (J - 1)]);
+        worst = std::max(worst, res);
+      }
+      if (worst <= tol || h_beta[0] <= 1e-300) {
+        converged = true;
+        break;
+      }
+      if (last) break;
+    }
+  }
+  for (int c = 0; c < k; ++c) evals_host[c] = 1.0 - h_eval[h_sel[c]];  // ascending lambda
+  if (evecs_dev) {
+    DBuf<double> V;
+    NFL_TRY(V.ensure((size_t)n * k));
+    NFL_HIP(hipMemcpyAsync(sel.p, h_sel.data(), k * sizeof(int), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_ritz, dim3(gb), dim3(VT), 0, s, Q.p, ld, J, Z.p, sel.p, k, n, V.p);
+    for (int c = 0; c < k; ++c)
+      hipLaunchKernelGGL(k_scatter64, dim3(gb), dim3(VT), 0, s, V.p + (int64_t)c * n, P->perm.p,
+                         n, evecs_dev + (int64_t)c * n);
+    NFL_HIP(hipGetLastError());
+    NFL_HIP(hipStreamSynchronize(s));
+  }
+  if (iters) *iters = J;
+  if (max_resid) *max_resid = worst;
+  return converged ? NFL_OK : NFL_NOT_CONVERGED;
+}
+
+// ---------------------------------------------------------------------------
+// CG
+// ---------------------------------------------------------------------------
+// u += a p; r -= a q; partial r.r      with a = sc[0] / sc[1]
+__global__ __launch_bounds__(VT) void k_cg_step(double *__restrict__ u, double *__restrict__ r,
+                                                const double *__restrict__ p,
+                                                const double *__restrict__ q,
+                                                const double *__restrict__ sc, int64_t n,
+                                                double *__restrict__ part) {
+  __shared__ double sh[VT / 64];
+  const double a = sc[0] / sc[1];
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT) {
+    u[i] += a * p[i];
+    const double ri = r[i] - a * q[i];
+    r[i] = ri;
+    s += ri * ri;
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// p = r + (sc[2] / sc[0]) p ; then sc[0] = sc[2]   (done by the last kernel below)
+__global__ __launch_bounds__(VT) void k_cg_dir(double *__restrict__ p,
+                                               const double *__restrict__ r,
+                                               const double *__restrict__ sc, int64_t n) {
+  const double b = sc[2] / sc[0];
+  for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT)
+    p[i] = r[i] + b * p[i];
+}
+
+__global__ void k_copy_scalar(double *__restrict__ sc, int dst, int src) { sc[dst] = sc[src]; }
+
+// r = f - t
+__global__ __launch_bounds__(VT) void k_sub64(const double *__restrict__ f,
+                                              const double *__restrict__ t, int64_t n,
+                                              double *__restrict__ r) {
+  for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT)
+    r[i] = f[i] - t[i];
+}
+
+int mlp_warm_start(nfl_plan *P, const double *f_sorted, double *u_sorted);
+
+int cg(nfl_plan *P, double tau, const double *f_dev, double *u_dev, int warm, double tol,
+       int maxit, int *iters, double *relres) {
+  const int64_t n = P->n;
+  hipStream_t s = P->stream;
+  DBuf<double> f, u, r, p, q, sc;
+  NFL_TRY(f.ensure(n));
+  NFL_TRY(u.ensure(n));
+  NFL_TRY(r.ensure(n));
+  NFL_TRY(p.ensure(n));
+  NFL_TRY(q.ensure(n));
+  NFL_TRY(sc.ensure(8));
+  Reducer R;
+  NFL_TRY(R.init(n));
+  const int gb = grid_for(n);
+  hipLaunchKernelGGL(k_gather64, dim3(gb), dim3(VT), 0, s, f_dev, P->perm.p, n, f.p);
+  if (warm == NFL_WARM_USER) {
+    hipLaunchKernelGGL(k_gather64, dim3(gb), dim3(VT), 0, s, u_dev, P->perm.p, n, u.p);
+  } else if (warm == NFL_WARM_MLP) {
+    NFL_TRY(mlp_warm_start(P, f.p, u.p));
+  } else {
+    hipLaunchKernelGGL(k_fill64, dim3(gb), dim3(VT), 0, s, u.p, n, 0.0);
+  }
+  // sc: [0] rr, [1] p.q, [2] rr_new, [3] ||f||
+  NFL_TRY(dot(P, R, f.p, f.p, sc.p + 3, 1));
+  NFL_TRY(apply_SSL64(P, tau, u.p, q.p));
+  hipLaunchKernelGGL(k_sub64, dim3(gb), dim3(VT), 0, s, f.p, q.p, n, r.p);
+  NFL_HIP(hipMemcpyAsync(p.p, r.p, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  NFL_TRY(dot(P, R, r.p, r.p, sc.p + 0));
+  double h[4];
+  NFL_HIP(hipMemcpyAsync(h, sc.p, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+  NFL_HIP(hipStreamSynchronize(s));
+  const double nf = h[3];
+  int it = 0;
+  double rel = nf > 0 ? std::sqrt(h[0]) / nf : 0.0;
+  while (nf > 0 && rel > tol && it < maxit) {
+    NFL_TRY(apply_SSL64(P, tau, p.p, q.p));
+    NFL_TRY(dot(P, R, p.p, q.p, sc.p + 1));
+    hipLaunchKernelGGL(k_cg_step, dim3(R.nb), dim3(VT), 0, s, u.p, r.p, p.p, q.p, sc.p, n,
+                       R.part.p);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(VT), 0, s, R.part.p, R.nb, sc.p + 2, 0);
+    hipLaunchKernelGGL(k_cg_dir, dim3(gb), dim3(VT), 0, s, p.p, r.p, sc.p, n);
+    hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(1), 0, s, sc.p, 0, 2);
+    NFL_HIP(hipGetLastError());
+    double rr;
+    NFL_HIP(hipMemcpyAsync(&rr, sc.p, sizeof(double), hipMemcpyDeviceToHost, s));
+    NFL_HIP(hipStreamSynchronize(s));
+    ++it;
+    rel = std::sqrt(rr) / nf;
+  }
+  // true residual with the same operator
+  double trueres = 0.0;
+  if (nf > 0) {
+    NFL_TRY(apply_SSL64(P, tau, u.p, q.p));
+    hipLaunchKernelGGL(k_sub64, dim3(gb), dim3(VT), 0, s, f.p, q.p, n, r.p);
+    NFL_TRY(dot(P, R, r.p, r.p, sc.p + 4, 1));
+    NFL_HIP(hipMemcpyAsync(h, sc.p + 4, sizeof(double), hipMemcpyDeviceToHost, s));
+    NFL_HIP(hipStreamSynchronize(s));
+    trueres = h[0] / nf;
+  }
+  hipLaunchKernelGGL(k_scatter64, dim3(gb), dim3(VT), 0, s, u.p, P->perm.p, n, u_dev);
+  NFL_HIP(hipGetLastError());
+  NFL_HIP(hipStreamSynchronize(s));
+  if (iters) *iters = it;
+  if (relres) *relres = trueres;
+  return (rel <= tol || nf == 0) ? NFL_OK : NFL_NOT_CONVERGED;
+}
+
+}  // namespace nfl

@@ -1,0 +1,180 @@
+// Internal declarations of the NFFT graph-Laplacian library (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/nfl.h"
+
+namespace nfl {
+
+// Thread-local message of the last failure (nfl_last_error()).
+void set_error(const std::string &msg);
+
+#define NFL_HIP(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      nfl::set_error(std::string(#expr) + ": " + hipGetErrorString(e_));           \
+      return e_ == hipErrorOutOfMemory ? NFL_ERR_OOM : NFL_ERR_HIP;               \
+    }                                                                              \
+  } while (0)
+
+#define NFL_TRY(expr)                                                              \
+  do {                                                                             \
+    int rc_ = (expr);                                                              \
+    if (rc_ < 0) return rc_;                                                       \
+  } while (0)
+
+// A device buffer owned by a plan.
+template <class T>
+struct DBuf {
+  T *p = nullptr;
+  size_t n = 0;
+  int ensure(size_t count) {
+    if (count <= n && p) return NFL_OK;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+    if (count == 0) return NFL_OK;
+    hipError_t e = hipMalloc(&p, count * sizeof(T));
+    if (e != hipSuccess) {
+      p = nullptr;
+      set_error(std::string("hipMalloc: ") + hipGetErrorString(e));
+      return e == hipErrorOutOfMemory ? NFL_ERR_OOM : NFL_ERR_HIP;
+    }
+    n = count;
+    return NFL_OK;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+};
+
+// One unit of spread/interp work: a contiguous range of sorted nodes inside
+// one grid tile.
+struct Item {
+  int tile;
+  int start;
+  int end;
+  int pad;
+};
+
+// Window constants in grid units: psi(t) for |t| <= m, t = k - u.
+struct Window {
+  int m;       // cut-off
+  float b;     // Kaiser-Bessel shape parameter pi (2 - 1/sigma_os), sigma_os = 2
+  float mm;    // m*m
+};
+
+}  // namespace nfl
+
+struct nfl_plan {
+  int d = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+
+  // points
+  int64_t n = 0;
+  nfl::DBuf<float> pts_user;    // n*d, caller order
+  double centre[3] = {0, 0, 0};
+  double radius = 0;
+  bool have_points = false;
+
+  // options
+  int opt_p = 0;                // 0 -> p = m
+  int opt_tile = 8;
+  int opt_chunk = 2048;
+  bool opt_eps_default = false;
+
+  // kernel / NFFT parameters
+  double sigma = 0, eps_B = 0, rho = 1, sigma_t = 0;
+  int N = 0, m = 0, p = 0, nos = 0, tshift = 3;
+  bool have_kernel = false;
+  nfl::Window win{};
+
+  // sorted nodes
+  nfl::DBuf<float4> pts;        // (frac_x, frac_y, frac_z, packed cell) sorted
+  nfl::DBuf<int> perm;          // sorted position -> caller index
+  nfl::DBuf<nfl::Item> items;
+  int nitems = 0;
+  int max_item_len = 0;
+
+  // FFT / filter
+  nfl::DBuf<float> filt;        // half spectrum, FP32
+  std::vector<double> filt_host;
+  nfl::DBuf<float2> tw;         // e^{-2 pi i k / nos}, k < nos/2
+  nfl::DBuf<float> grid;        // nos^d real
+  nfl::DBuf<float2> spec1, spec2;
+
+  // degrees (sorted order)
+  nfl::DBuf<float> deg;
+  nfl::DBuf<float> dinv;        // d_E^{-1/2}
+  double dmin = 0, dmax = 0;
+
+  // scratch
+  nfl::DBuf<float> xs;          // sorted FP32 work vector
+  nfl::DBuf<float> fs;          // sorted FP32 interp output
+  nfl::DBuf<double> red;        // reduction partials
+  nfl::DBuf<unsigned char> tmp; // sort temporaries
+};
+
+namespace nfl {
+
+// ---- setup (setup.hip) -------------------------------------------------------
+int bbox_and_radius(nfl_plan *P);                       // sets centre, radius
+int build_sorted_nodes(nfl_plan *P);                    // keys, sort, items
+int build_filter_host(nfl_plan *P);                     // filt_host (FP64)
+int exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t len, hipStream_t s,
+                       DBuf<uint32_t> &scratch, size_t scratch_off);
+int radix_sort_pairs(uint32_t *keys, uint32_t *vals, int64_t n, int bits, hipStream_t s,
+                     DBuf<unsigned char> &tmp);
+
+// ---- NFFT (nfft.hip) -----------------------------------------------------------
+// How the spread kernel gets its input value for sorted node i, and what the
+// interp kernel does with f_i (the post-operations of Alg. nfft_normalized_matvec).
+enum InMode {
+  IN_USER_F32 = 0,      // x[perm[i]]
+  IN_USER_F32_DINV = 1, // dinv[i] * x[perm[i]]
+  IN_ONES = 2,          // 1
+  IN_SORTED_F32 = 3,    // xs[i]
+  IN_SORTED_F64_DINV = 4, // (float)(dinv[i] * x64[i])
+};
+enum OutMode {
+  OUT_USER_RAW = 0,     // y[perm[i]] = f
+  OUT_USER_W = 1,       // y[perm[i]] = f - x[perm[i]]                 (W x)
+  OUT_USER_LS = 2,      // y[perm[i]] = x - dinv (f - dinv x)          (L_s x)
+  OUT_USER_A = 3,       // y[perm[i]] = dinv (f - dinv x)              (A x)
+  OUT_DEGREE = 4,       // deg[i] = f - 1, dinv[i] = 1/sqrt(deg)
+  OUT_SORTED_F64_A = 5, // y64[i] = dinv (f - xt), xt = (float)(dinv x64)
+  OUT_SORTED_F64_SSL = 6, // y64[i] = x64 + tau (x64 - dinv (f - xt))
+};
+
+struct VecArgs {
+  const float *x32 = nullptr;   // caller order
+  float *y32 = nullptr;         // caller order
+  const double *x64 = nullptr;  // sorted order
+  double *y64 = nullptr;        // sorted order
+  double tau = 0;
+};
+
+int spread(nfl_plan *P, int in_mode, const VecArgs &a, float *grid);
+int convolve(nfl_plan *P, const float *gin, float *gout);
+int interp(nfl_plan *P, const float *grid, int in_mode, int out_mode, const VecArgs &a);
+// whole fast summation with the given input/output modes (grid = plan grid)
+int fastsum(nfl_plan *P, int in_mode, int out_mode, const VecArgs &a);
+int fill_f32(float *p, int64_t n, float v, hipStream_t s);
+int scatter_f32(nfl_plan *P, const float *src_sorted, float *dst_user);
+
+// ---- Krylov (krylov.hip) -------------------------------------------------------
+int lanczos(nfl_plan *P, int k, int block, double tol, int maxit, double *evals_host,
+            double *evecs_dev, int *iters, double *max_resid);
+int cg(nfl_plan *P, double tau, const double *f_dev, double *u_dev, int warm, double tol,
+       int maxit, int *iters, double *relres);
+
+}  // namespace nfl

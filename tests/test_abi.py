@@ -1,0 +1,82 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every symbol the
+header declares, rejects bad arguments without touching a GPU, and its host
+FP64 filter matches the oracle's coefficients divided by the window
+transform (computed here by quadrature of the Kaiser-Bessel window)."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1808_04580_amd as nfl
+from oracle import fastsum
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    txt = open(os.path.join(ROOT, "include", "nfl.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(nfl_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = nfl.lib()
+    syms = header_symbols()
+    assert len(syms) >= 17
+    for s in syms:
+        assert hasattr(L, s), s
+        assert s in nfl.SIGNATURES, "binding lacks " + s
+
+
+def test_error_codes_without_gpu():
+    L = nfl.lib()
+    import ctypes
+    h = ctypes.c_void_p()
+    assert L.nfl_create(ctypes.byref(h), 4, None) == nfl.NFL_ERR_ARG
+    assert L.nfl_create(None, 3, None) == nfl.NFL_ERR_ARG
+    assert L.nfl_set_points(None, 10, None) == nfl.NFL_ERR_ARG
+    assert L.nfl_apply_Ls(None, None, None, 1, 10) == nfl.NFL_ERR_ARG
+    for c in [0, 1, -1, -2, -3, -4, -5, -6]:
+        assert nfl.strerror(c) and "unknown" not in nfl.strerror(c)
+    out = np.empty(10)
+    assert L.nfl_compute_filter(3, 15, 4, 4, 0.0, 0.1, out.ctypes.data_as(ctypes.c_void_p), 10) \
+        == nfl.NFL_ERR_ARG
+
+
+def kb_hat_quadrature(xi, m, b=1.5 * math.pi, nq=2001):
+    """Fourier transform of psi(t) = sinh(b sqrt(m^2-t^2))/(sqrt(m^2-t^2) b e^{bm})
+    on [-m, m] by the composite Simpson rule after t = m sin(theta), which turns
+    the integrand into the smooth sinh(b m cos theta) cos(2 pi xi m sin theta)."""
+    th = np.linspace(-math.pi / 2, math.pi / 2, nq)
+    f = np.sinh(b * m * np.cos(th)) * np.cos(2 * math.pi * xi * m * np.sin(th))
+    h = th[1] - th[0]
+    return h / 3 * (f[0] + f[-1] + 4 * f[1:-1:2].sum() + 2 * f[2:-1:2].sum()) / (b * math.exp(b * m))
+
+
+@pytest.mark.parametrize("d,N,m,eps", [(1, 16, 3, 0.0), (2, 16, 4, 0.125), (3, 8, 2, 0.25)])
+def test_filter_equals_coefficients_over_window_transform(d, N, m, eps):
+    sig = 0.12
+    p = m
+    F = nfl.compute_filter(d, N, m, p, eps, sig)
+    b = fastsum.coefficients(sig, N, d, eps, p)           # indexed by l + N/2 on I_N^d
+    nos = 2 * N
+    wh = np.array([kb_hat_quadrature(l / nos, m) for l in range(-N // 2, N // 2 + 1)])
+    # expected on the extended set {-N/2..N/2}^(d-1) x {0..N/2}: real part of
+    # the asymmetric sum = b_l split evenly between l and -l at the Nyquist indices
+    ext = np.arange(-N // 2, N // 2 + 1)
+    grids = np.meshgrid(*([ext] * (d - 1) + [np.arange(0, N // 2 + 1)]), indexing="ij")
+    L = np.stack(grids, axis=-1).reshape(-1, d)
+    exp = np.empty(L.shape[0])
+    for q, l in enumerate(L):
+        inI = np.all(l <= N // 2 - 1)
+        inmI = np.all(-l <= N // 2 - 1)
+        val = 0.0
+        if inI:
+            val += 0.5 * b[tuple(l + N // 2)]
+        if inmI:
+            val += 0.5 * b[tuple(-l + N // 2)]
+        den = np.prod([wh[li + N // 2] ** 2 for li in l])
+        exp[q] = val / den
+    np.testing.assert_allclose(F.reshape(-1), exp, rtol=1e-10, atol=1e-12 * np.abs(exp).max())
