@@ -48,9 +48,10 @@ typedef struct nfl_plan *nfl_handle;
 
 /* Options for nfl_set_option (take effect at the next nfl_set_kernel). */
 #define NFL_OPT_P          1   /* regularisation smoothness p of K_R (Fig. tab:fastsum_param); default p = m */
-#define NFL_OPT_TILE       2   /* grid tile edge T for spread/interp (power of 2, 4..32); default 8 */
-#define NFL_OPT_CHUNK      3   /* max nodes per spread/interp work item; default 2048 */
+#define NFL_OPT_TILE       2   /* grid tile edge T for spread/interp (power of 2, 4..32); default 4 */
+#define NFL_OPT_CHUNK      3   /* max nodes per spread/interp work item; default 512 */
 #define NFL_OPT_EPS_B_DEFAULT 4 /* if value != 0, nfl_set_kernel with eps_B < 0 uses eps_B = p/N (the paper's default) */
+#define NFL_OPT_KERNEL     5   /* d = 3 spread/interp: 0 = matrix-core (MFMA) kernels (default), 1 = vector-ALU kernels; takes effect immediately */
 
 /* Create a plan for nodes in R^d, d in {1, 2, 3}.  `hip_stream` is a
  * hipStream_t (NULL = the default stream).  Allocates nothing on the device
@@ -158,11 +159,29 @@ int nfl_interp(nfl_handle h, const float *grid_dev, float *f_dev);
  * (N+1)^(d-1) (N/2+1) doubles, host.  Synchronises. */
 int nfl_get_filter(nfl_handle h, double *filter_host, int64_t count);
 
+/* Runs nrep products y = L_s x (as nfl_apply_Ls, one vector) with HIP
+ * events recorded on the plan's stream between the stages, and returns the
+ * average milliseconds per product of each stage in stage_ms[5]: grid
+ * clear, spread, FFT + filter + inverse FFT, interpolation, whole product.
+ * Synchronises. */
+int nfl_profile_stages(nfl_handle h, const float *x_dev, float *y_dev, int nrep,
+                       double *stage_ms);
+
 /* The same filter computed from explicit parameters without a plan or a GPU
  * (host FP64; sigma_tilde is sigma in the scaled torus coordinates).  count
  * must be >= (N+1)^(d-1) (N/2+1).  N a power of 2. */
 int nfl_compute_filter(int d, int N, int m, int p, double eps_B, double sigma_tilde,
                        double *filter_host, int64_t count);
+
+/* The window the kernels apply (host, no GPU): for each of the 2m grid
+ * offsets c of a node's window, NFL_WIN_NC float32 coefficients of the
+ * polynomial in g = 2f - 1 (f = the node's fraction inside its cell) that
+ * approximates the Kaiser-Bessel window psi(c - (m-1) - f),
+ *   psi(t) = sinh(b sqrt(m^2 - t^2)) / (sqrt(m^2 - t^2) b e^{bm}), b = 3 pi / 2,
+ * row-major [c][k], count >= 2m * NFL_WIN_NC.  The filter deconvolves with the
+ * exact transform of this piecewise polynomial. */
+#define NFL_WIN_NC 10
+int nfl_window_coefficients(int m, float *coef_host, int64_t count);
 
 const char *nfl_strerror(int code);
 const char *nfl_last_error(void);

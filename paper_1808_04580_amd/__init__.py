@@ -28,6 +28,7 @@ OPT_P = 1
 OPT_TILE = 2
 OPT_CHUNK = 3
 OPT_EPS_B_DEFAULT = 4
+OPT_KERNEL = 5
 
 WARM_ZERO = 0
 WARM_USER = 1
@@ -56,6 +57,8 @@ SIGNATURES = {
     "nfl_interp": (_i, [_p, _p, _p]),
     "nfl_get_filter": (_i, [_p, _p, _i64]),
     "nfl_compute_filter": (_i, [_i, _i, _i, _i, _d, _d, _p, _i64]),
+    "nfl_profile_stages": (_i, [_p, _p, _p, _i, _p]),
+    "nfl_window_coefficients": (_i, [_i, _p, _i64]),
     "nfl_strerror": (ctypes.c_char_p, [_i]),
     "nfl_last_error": (ctypes.c_char_p, []),
 }
@@ -101,6 +104,17 @@ def compute_filter(d: int, N: int, m: int, p: int, eps_B: float, sigma_tilde: fl
                                     out.ctypes.data_as(_p), count), "nfl_compute_filter")
     shape = tuple([N + 1] * (d - 1) + [N // 2 + 1])
     return out.reshape(shape)
+
+
+WIN_NC = 10
+
+
+def window_coefficients(m: int) -> np.ndarray:
+    """(2m, WIN_NC) float32 window polynomial coefficients (host, no GPU)."""
+    out = np.empty(2 * m * WIN_NC, dtype=np.float32)
+    _check(lib().nfl_window_coefficients(m, out.ctypes.data_as(_p), out.size),
+           "nfl_window_coefficients")
+    return out.reshape(2 * m, WIN_NC)
 
 
 def _ptr(t) -> int:
@@ -224,6 +238,16 @@ class Plan:
                                          ctypes.byref(rel)), "nfl_cg_solve", allow_soft=True)
         return dict(u=u, iters=it.value, relres=rel.value, converged=(code == NFL_OK))
 
+    def profile_stages(self, x, nrep: int = 20) -> dict:
+        """Average ms per L_s product of: grid clear, spread, convolution, interp, total."""
+        torch = self._torch
+        x = torch.as_tensor(x, dtype=torch.float32, device=self.device).contiguous()
+        y = torch.empty_like(x)
+        out = np.zeros(5)
+        _check(lib().nfl_profile_stages(self._h, _ptr(x), _ptr(y), int(nrep),
+                                        out.ctypes.data_as(_p)), "nfl_profile_stages")
+        return dict(zip(["clear", "spread", "convolve", "interp", "total"], out.tolist()))
+
     # -- individual steps -----------------------------------------------------
     def grid_size(self) -> int:
         return int(lib().nfl_grid_size(self._h))
@@ -261,7 +285,8 @@ def plan(points, sigma: float, N: int, m: int, eps_B: float = 0.0, stream=None, 
     d = 1 if v.dim() == 1 else int(v.shape[1])
     P = Plan(d, stream)
     for k, val in options.items():
-        P.set_option({"p": OPT_P, "tile": OPT_TILE, "chunk": OPT_CHUNK}[k], val)
+        P.set_option({"p": OPT_P, "tile": OPT_TILE, "chunk": OPT_CHUNK, "kernel": OPT_KERNEL}[k],
+                     val)
     P.set_points(v)
     P.set_kernel(sigma, N, m, eps_B)
     return P

@@ -80,6 +80,7 @@ int nfl_destroy(nfl_handle P) {
   P->perm.release();
   P->items.release();
   P->filt.release();
+  P->wcoef.release();
   P->tw.release();
   P->grid.release();
   P->spec1.release();
@@ -111,6 +112,10 @@ int nfl_set_option(nfl_handle P, int opt, double value) {
       return NFL_OK;
     case NFL_OPT_EPS_B_DEFAULT:
       P->opt_eps_default = value != 0;
+      return NFL_OK;
+    case NFL_OPT_KERNEL:
+      if (value != 0 && value != 1) { set_error("kernel must be 0 (matrix cores) or 1 (vector ALU)"); return NFL_ERR_ARG; }
+      P->opt_kernel = (int)value;
       return NFL_OK;
     default:
       set_error("unknown option");
@@ -160,6 +165,13 @@ int nfl_set_kernel(nfl_handle P, double sigma, int N, int m, double eps_B) {
   P->win.b = (float)(M_PI * 1.5);
   P->win.mm = (float)(m * m);
 
+  {
+    std::vector<float> wc;
+    NFL_TRY(window_coefficients(m, wc));
+    NFL_TRY(P->wcoef.ensure(wc.size()));
+    NFL_HIP(hipMemcpyAsync(P->wcoef.p, wc.data(), wc.size() * sizeof(float),
+                           hipMemcpyHostToDevice, P->stream));
+  }
   NFL_TRY(build_filter_host(P));
   NFL_TRY(P->filt.ensure(P->filt_host.size()));
   {
@@ -315,6 +327,50 @@ int nfl_compute_filter(int d, int N, int m, int p, double eps_B, double sigma_ti
   NFL_TRY(compute_filter(d, N, m, p, eps_B, sigma_tilde, f));
   if (count < (int64_t)f.size()) { set_error("filter buffer too small"); return NFL_ERR_ARG; }
   std::memcpy(filter_host, f.data(), f.size() * sizeof(double));
+  return NFL_OK;
+}
+
+int nfl_profile_stages(nfl_handle P, const float *x_dev, float *y_dev, int nrep,
+                       double *stage_ms) {
+  NFL_TRY(check_vec_args(P, x_dev, y_dev, 1, P ? P->n : 0));
+  if (nrep < 1 || !stage_ms) { set_error("need nrep >= 1 and an output array"); return NFL_ERR_ARG; }
+  std::vector<hipEvent_t> ev((size_t)nrep * 5);
+  for (auto &e : ev) NFL_HIP(hipEventCreate(&e));
+  int rc = NFL_OK;
+  for (int r = 0; r < nrep && rc == NFL_OK; ++r) {
+    P->prof_ev = ev.data() + (size_t)r * 5;
+    VecArgs a;
+    a.x32 = x_dev;
+    a.y32 = y_dev;
+    rc = fastsum(P, IN_USER_F32_DINV, OUT_USER_LS, a);
+  }
+  P->prof_ev = nullptr;
+  if (rc == NFL_OK && hipStreamSynchronize(P->stream) != hipSuccess) rc = NFL_ERR_HIP;
+  double acc[5] = {0, 0, 0, 0, 0};
+  for (int r = 0; r < nrep && rc == NFL_OK; ++r) {
+    hipEvent_t *e = ev.data() + (size_t)r * 5;
+    for (int s = 0; s < 4; ++s) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, e[s], e[s + 1]) != hipSuccess) { rc = NFL_ERR_HIP; break; }
+      acc[s] += ms;
+    }
+    float tot = 0.f;
+    if (hipEventElapsedTime(&tot, e[0], e[4]) != hipSuccess) rc = NFL_ERR_HIP;
+    acc[4] += tot;
+  }
+  for (auto &e : ev) (void)hipEventDestroy(e);
+  if (rc != NFL_OK) { set_error("nfl_profile_stages: event timing failed"); return rc; }
+  for (int s = 0; s < 5; ++s) stage_ms[s] = acc[s] / nrep;
+  return NFL_OK;
+}
+
+int nfl_window_coefficients(int m, float *coef_host, int64_t count) {
+  if (!coef_host || m < 1 || 2 * m > WIN_MAXW) { set_error("need 1 <= m <= 8 and an output"); return NFL_ERR_ARG; }
+  std::vector<float> wc;
+  NFL_TRY(window_coefficients(m, wc));
+  const int64_t need = (int64_t)2 * m * WIN_NC;
+  if (count < need) { set_error("coefficient buffer too small"); return NFL_ERR_ARG; }
+  std::memcpy(coef_host, wc.data(), need * sizeof(float));
   return NFL_OK;
 }
 

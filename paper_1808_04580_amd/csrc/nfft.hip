@@ -12,23 +12,26 @@
 namespace nfl {
 
 // ---------------------------------------------------------------------------
-// Kaiser-Bessel window in grid units, normalised as
-//   psi(t) = sinh(b s) / (s b e^{bm}),  s = sqrt(m^2 - t^2),  |t| <= m,
-// evaluated as e^{-b t^2/(s+m)} (1 - e^{-2bs}) / (2bs): the exponent is never
-// positive and the only cancellation happens where psi is ~e^{-bm} small.
-// Its transform is pi I_0(m sqrt(b^2 - 4 pi^2 xi^2)) / (b e^{bm}) (host side).
+// Window.  The Kaiser-Bessel window psi(t) = sinh(b s)/(s b e^{bm}),
+// s = sqrt(m^2 - t^2), t in (-m, m] (grid units), is applied as 2m
+// polynomials, one per grid offset c of a node's window:
+//   psi(c - (m-1) - f) = sum_k coef[c][k] g^k,  g = 2f - 1,
+// where f in [0, 1) is the node's fraction inside its cell.  The host fits the
+// coefficients (FP64, rounded to float32) and deconvolves with the exact
+// transform of this piecewise polynomial.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float kb_window(float t, float m, float b) {
-  const float t2 = t * t;
-  const float s = __builtin_sqrtf(fmaxf(fmaf(-t, t, m * m), 0.f));
-  const float e1 = __expf(-b * t2 / (s + m));
-  const float x = 2.f * b * s;
-  float h;
-  if (x < 0.25f)
-    h = fmaf(x, fmaf(x, fmaf(x, fmaf(x, 1.f / 120.f, -1.f / 24.f), 1.f / 6.f), -0.5f), 1.f);
-  else
-    h = (1.f - __expf(-x)) / x;
-  return e1 * h;
+template <int NC>
+__device__ __forceinline__ float win_poly(const float (&cf)[NC], float f) {
+  const float g = fmaf(2.f, f, -1.f);
+  float p = cf[NC - 1];
+#pragma unroll
+  for (int k = NC - 2; k >= 0; --k) p = fmaf(p, g, cf[k]);
+  return p;
+}
+
+__device__ __forceinline__ void load_coef(const float *__restrict__ wcoef, int c, float (&cf)[WIN_NC]) {
+#pragma unroll
+  for (int k = 0; k < WIN_NC; ++k) cf[k] = wcoef[c * WIN_NC + k];
 }
 
 struct KArgs {
@@ -103,7 +106,7 @@ template <int W, int IN>
 __global__ __launch_bounds__(256) void k_spread3(const Item *__restrict__ items,
                                                  const float4 *__restrict__ pts, KArgs ka,
                                                  float *__restrict__ grid, int nos, int tshift,
-                                                 float b) {
+                                                 const float *__restrict__ wcoef) {
   constexpr int M = W / 2, R = (W * W + 63) / 64;
   extern __shared__ float lds[];
   const int T = 1 << tshift, P = T + W - 1, PP = P * P, P3 = PP * P;
@@ -129,7 +132,8 @@ __global__ __launch_bounds__(256) void k_spread3(const Item *__restrict__ items,
     paz[r] = pv[r] ? p % W : 0;
   }
   const int wdim = lane / W;
-  const float toff = (float)(lane - wdim * W - (M - 1));
+  float cf[WIN_NC];
+  load_coef(wcoef, min(lane - wdim * W, WIN_MAXW - 1), cf);
 
   float acc[R][W];
 #pragma unroll
@@ -155,26 +159,37 @@ __global__ __launch_bounds__(256) void k_spread3(const Item *__restrict__ items,
     }
   };
 
-  for (int i = s; i < e; ++i) {
-    const float4 q = pts[i];
-    const uint32_t cell = __float_as_uint(q.w);
-    const float xv = load_in<IN>(ka, i);
-    if (cell != cur) {
-      if (cur != 0xffffffffu) flush(cur);
-      cur = cell;
+  // Nodes are fetched 64 at a time (one per lane, coalesced) and walked one
+  // by one from registers, so no per-node global-load latency is exposed.
+  for (int i0 = s; i0 < e; i0 += 64) {
+    const int cnt = min(64, e - i0);
+    float4 qb = make_float4(0.f, 0.f, 0.f, 0.f);
+    float xb = 0.f;
+    if (lane < cnt) {
+      qb = pts[i0 + lane];
+      xb = load_in<IN>(ka, i0 + lane);
     }
-    const float fr = wdim == 0 ? q.x : (wdim == 1 ? q.y : q.z);
-    const float wgt = kb_window(toff - fr, (float)M, b);
-    float wx[W];
+    for (int j = 0; j < cnt; ++j) {
+      const uint32_t cell = (uint32_t)__builtin_amdgcn_readlane((int)__float_as_uint(qb.w), j);
+      const float xv = readlane_f(xb, j);
+      if (cell != cur) {
+        if (cur != 0xffffffffu) flush(cur);
+        cur = cell;
+      }
+      const float qx = readlane_f(qb.x, j), qy = readlane_f(qb.y, j), qz = readlane_f(qb.z, j);
+      const float fr = wdim == 0 ? qx : (wdim == 1 ? qy : qz);
+      const float wgt = win_poly(cf, fr);
+      float wx[W];
 #pragma unroll
-    for (int a = 0; a < W; ++a) wx[a] = readlane_f(wgt, a);
+      for (int a = 0; a < W; ++a) wx[a] = readlane_f(wgt, a);
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const float wy = __shfl(wgt, W + pay[r]);
-      const float wz = __shfl(wgt, 2 * W + paz[r]);
-      const float sy = pv[r] ? xv * wy * wz : 0.f;
+      for (int r = 0; r < R; ++r) {
+        const float wy = __shfl(wgt, W + pay[r]);
+        const float wz = __shfl(wgt, 2 * W + paz[r]);
+        const float sy = pv[r] ? xv * wy * wz : 0.f;
 #pragma unroll
-      for (int a = 0; a < W; ++a) acc[r][a] = fmaf(sy, wx[a], acc[r][a]);
+        for (int a = 0; a < W; ++a) acc[r][a] = fmaf(sy, wx[a], acc[r][a]);
+      }
     }
   }
   if (cur != 0xffffffffu) flush(cur);
@@ -208,7 +223,7 @@ template <int W, int IN, int OUT>
 __global__ __launch_bounds__(256) void k_interp3(const Item *__restrict__ items,
                                                  const float4 *__restrict__ pts, KArgs ka,
                                                  const float *__restrict__ grid, int nos,
-                                                 int tshift, float b) {
+                                                 int tshift, const float *__restrict__ wcoef) {
   constexpr int M = W / 2, R = (W * W + 63) / 64;
   extern __shared__ float lds[];
   const int T = 1 << tshift, P = T + W - 1, PP = P * P, P3 = PP * P;
@@ -240,41 +255,313 @@ __global__ __launch_bounds__(256) void k_interp3(const Item *__restrict__ items,
     paz[r] = pv[r] ? p % W : 0;
   }
   const int wdim = lane / W;
-  const float toff = (float)(lane - wdim * W - (M - 1));
+  float cf[WIN_NC];
+  load_coef(wcoef, min(lane - wdim * W, WIN_MAXW - 1), cf);
 
   float g[R][W];
   uint32_t cur = 0xffffffffu;
-  for (int i = s; i < e; ++i) {
-    const float4 q = pts[i];
-    const uint32_t cell = __float_as_uint(q.w);
-    if (cell != cur) {
-      cur = cell;
-      const int lx = (int)(cell & 1023u) - ox, ly = (int)((cell >> 10) & 1023u) - oy,
-                lz = (int)(cell >> 20) - oz;
+  for (int i0 = s; i0 < e; i0 += 64) {
+    const int cnt = min(64, e - i0);
+    float4 qb = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (lane < cnt) qb = pts[i0 + lane];
+    float res = 0.f;
+    for (int j = 0; j < cnt; ++j) {
+      const uint32_t cell = (uint32_t)__builtin_amdgcn_readlane((int)__float_as_uint(qb.w), j);
+      if (cell != cur) {
+        cur = cell;
+        const int lx = (int)(cell & 1023u) - ox, ly = (int)((cell >> 10) & 1023u) - oy,
+                  lz = (int)(cell >> 20) - oz;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const float *base = lds + (lx * P + ly + pay[r]) * P + lz + paz[r];
+#pragma unroll
+          for (int a = 0; a < W; ++a) g[r][a] = pv[r] ? base[a * PP] : 0.f;
+        }
+      }
+      const float qx = readlane_f(qb.x, j), qy = readlane_f(qb.y, j), qz = readlane_f(qb.z, j);
+      const float fr = wdim == 0 ? qx : (wdim == 1 ? qy : qz);
+      const float wgt = win_poly(cf, fr);
+      float wx[W];
+#pragma unroll
+      for (int a = 0; a < W; ++a) wx[a] = readlane_f(wgt, a);
+      float part = 0.f;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const float *base = lds + (lx * P + ly + pay[r]) * P + lz + paz[r];
+        const float wy = __shfl(wgt, W + pay[r]);
+        const float wz = __shfl(wgt, 2 * W + paz[r]);
+        float t = 0.f;
 #pragma unroll
-        for (int a = 0; a < W; ++a) g[r][a] = pv[r] ? base[a * PP] : 0.f;
+        for (int a = 0; a < W; ++a) t = fmaf(wx[a], g[r][a], t);
+        part = fmaf(wy * wz, t, part);
+      }
+      part = wave_sum(part);
+      if (lane == j) res = part;
+    }
+    if (lane < cnt) store_out<OUT>(ka, i0 + lane, res);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// d = 3 spread and interpolation on the matrix cores.
+//
+// Nodes are processed in sub-batches of 16.  Per sub-batch each lane l
+// evaluates, for node l%16, the window polynomials of the offsets
+// 4 (l/16) .. 4 (l/16) + 3 on all three axes (12 Horner evaluations) and writes
+// them to a per-wave weight table wt[node][axis][offset] in LDS (the x value
+// of the node rides along in wt[node][3][0]).  The matrix-core loop then reads
+// its operands from the table with independent broadcast loads.
+// ---------------------------------------------------------------------------
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr int WT_STRIDE = 4 * 16;  // floats per node in the weight table
+
+// Fill the weight table for nodes i0 .. i0 + cnt - 1 (cnt <= 16); returns, in
+// every lane, the packed cell of node (lane % 16) (0xffffffff past cnt).
+template <int W, int IN, bool WITH_X>
+__device__ __forceinline__ uint32_t fill_weights(const float4 *__restrict__ pts, const KArgs &ka,
+                                                 int i0, int cnt, int lane,
+                                                 const float (&cf)[4][WIN_NC], float *wt) {
+  const int node = lane & 15, part = lane >> 4;
+  float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
+  uint32_t cell = 0xffffffffu;
+  float xv = 0.f;
+  if (node < cnt) {
+    q = pts[i0 + node];
+    cell = __float_as_uint(q.w);
+    if (WITH_X && part == 0) xv = load_in<IN>(ka, i0 + node);
+  }
+  float *w = wt + node * WT_STRIDE;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int o = 4 * part + u;
+    w[0 * 16 + o] = win_poly(cf[u], q.x);
+    w[1 * 16 + o] = win_poly(cf[u], q.y);
+    w[2 * 16 + o] = win_poly(cf[u], q.z);
+  }
+  if (WITH_X && part == 0) w[3 * 16] = xv;
+  return cell;
+}
+
+// Spread: for the nodes p of one grid cell
+//   G[ax][ay][az] += sum_p (x_p wx_p[ax]) (wy_p[ay] wz_p[az])
+// with v_mfma_f32_16x16x4_f32: rows = x-offsets ax (W of 16 used), K = 4
+// nodes of the cell, columns = S y-offsets times WP z-offsets (WP = W rounded
+// up to 4, 8 or 16, S = 16/WP), NB = W/S column blocks.  Lane l (node slot
+// l/16, column l%16) accumulates D[ax = 4 (l/16) + r][column l%16], r < 4, in
+// registers over the run of the cell, then adds it into its wave's PRIVATE
+// copy of the padded tile (plain read-add-write: every lane of a flush owns a
+// distinct cell, and LDS operations of one wave are ordered).  At the end the
+// four private tiles are summed and added into the grid.
+template <int W>
+struct SpreadShape {
+  static constexpr int WP = W <= 4 ? 4 : (W <= 8 ? 8 : 16);
+  static constexpr int S = 16 / WP;
+  static constexpr int NB = (W + S - 1) / S;
+};
+
+template <int W, int IN>
+__global__ __launch_bounds__(256) void k_spread3_mfma(const Item *__restrict__ items,
+                                                      const float4 *__restrict__ pts, KArgs ka,
+                                                      float *__restrict__ grid, int nos,
+                                                      int tshift,
+                                                      const float *__restrict__ wcoef) {
+  constexpr int M = W / 2;
+  constexpr int WP = SpreadShape<W>::WP, S = SpreadShape<W>::S, NB = SpreadShape<W>::NB;
+  extern __shared__ float lds[];
+  const int T = 1 << tshift, P = T + W - 1, PP = P * P, P3 = PP * P;
+  const Item it = items[blockIdx.x];
+  const int ntd = nos >> tshift;
+  const int tz = it.tile % ntd, ty = (it.tile / ntd) % ntd, tx = it.tile / (ntd * ntd);
+  const int ox = tx * T, oy = ty * T, oz = tz * T;
+  for (int c = threadIdx.x; c < 4 * P3; c += 256) lds[c] = 0.f;
+  __syncthreads();
+
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int c16 = lane & 15, p4 = lane >> 4;
+  const int sub = c16 / WP, az = c16 % WP;
+  float *tile = lds + wave * P3;
+  float *wt = lds + 4 * P3 + wave * (16 * WT_STRIDE);
+  const int len = it.end - it.start, per = (len + 3) >> 2;
+  const int s = it.start + min(len, wave * per), e = it.start + min(len, (wave + 1) * per);
+
+  float cf[4][WIN_NC];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int o = 4 * p4 + u;
+#pragma unroll
+    for (int k = 0; k < WIN_NC; ++k) cf[u][k] = o < W ? wcoef[o * WIN_NC + k] : 0.f;
+  }
+  f32x4 acc[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  uint32_t cur = 0xffffffffu;
+
+  auto flush = [&](uint32_t cell) {
+    const int lx = (int)(cell & 1023u) - ox, ly = (int)((cell >> 10) & 1023u) - oy,
+              lz = (int)(cell >> 20) - oz;
+    float old[NB][4];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int ay = S * nb + sub;
+      const float *base = tile + (lx * P + ly + ay) * P + lz + az;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ax = 4 * p4 + r;
+        old[nb][r] = (az < W && ay < W && ax < W) ? base[ax * PP] : 0.f;
       }
     }
-    const float fr = wdim == 0 ? q.x : (wdim == 1 ? q.y : q.z);
-    const float wgt = kb_window(toff - fr, (float)M, b);
-    float wx[W];
 #pragma unroll
-    for (int a = 0; a < W; ++a) wx[a] = readlane_f(wgt, a);
-    float part = 0.f;
+    for (int nb = 0; nb < NB; ++nb) {
+      const int ay = S * nb + sub;
+      float *base = tile + (lx * P + ly + ay) * P + lz + az;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const float wy = __shfl(wgt, W + pay[r]);
-      const float wz = __shfl(wgt, 2 * W + paz[r]);
-      float t = 0.f;
-#pragma unroll
-      for (int a = 0; a < W; ++a) t = fmaf(wx[a], g[r][a], t);
-      part = fmaf(wy * wz, t, part);
+      for (int r = 0; r < 4; ++r) {
+        const int ax = 4 * p4 + r;
+        if (az < W && ay < W && ax < W) base[ax * PP] = old[nb][r] + acc[nb][r];
+      }
+      acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
-    part = wave_sum(part);
-    if (lane == 0) store_out<OUT>(ka, i, part);
+  };
+
+  for (int i0 = s; i0 < e; i0 += 16) {
+    const int cnt = min(16, e - i0);
+    const int cellv = (int)fill_weights<W, IN, true>(pts, ka, i0, cnt, lane, cf, wt);
+    wave_sync_lds();
+    int j = 0;
+    while (j < cnt) {
+      const uint32_t cell = (uint32_t)__builtin_amdgcn_readlane(cellv, j);
+      if (cell != cur) {
+        if (cur != 0xffffffffu) flush(cur);
+        cur = cell;
+      }
+      int k = 1;
+      while (k < 4 && j + k < cnt && (uint32_t)__builtin_amdgcn_readlane(cellv, j + k) == cell) ++k;
+      const float *w = wt + (j + min(p4, k - 1)) * WT_STRIDE;
+      const float xv = p4 < k ? w[3 * 16] : 0.f;
+      const float a = xv * w[c16 & 15];
+      const float wz = w[2 * 16 + (az & 15)];
+      float by[NB];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) by[nb] = w[16 + S * nb + sub];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, by[nb] * wz, acc[nb], 0, 0, 0);
+      j += k;
+    }
+    wave_sync_lds();
+  }
+  if (cur != 0xffffffffu) flush(cur);
+  __syncthreads();
+
+  const int mask = nos - 1;
+  for (int c = threadIdx.x; c < P3; c += 256) {
+    const float v = (lds[c] + lds[P3 + c]) + (lds[2 * P3 + c] + lds[3 * P3 + c]);
+    if (v != 0.f) {
+      const int px = c / PP, rem = c - px * PP, py = rem / P, pz = rem - py * P;
+      const int gx = (ox - (M - 1) + px) & mask, gy = (oy - (M - 1) + py) & mask,
+                gz = (oz - (M - 1) + pz) & mask;
+      unsafeAtomicAdd(&grid[((size_t)gx * nos + gy) * nos + gz], v);
+    }
+  }
+}
+
+// Interpolation, the transpose of the spread: for up to 16 nodes p of one cell
+//   D[ax][p] = sum_ay wy_p[ay] sum_az G[ax][ay][az] wz_p[az],  f_p = sum_ax wx_p[ax] D[ax][p],
+// rows = x-offsets, columns = nodes, K over (ay, 4 consecutive az) in W * KZ
+// steps (KZ = ceil(W/4)).  The cell's window G, read from the workgroup's
+// shared LDS copy of the padded tile, is the register-resident A operand:
+// lane l holds G[ax = l%16][ay][4 t + l/16].
+template <int W, int IN, int OUT>
+__global__ __launch_bounds__(256) void k_interp3_mfma(const Item *__restrict__ items,
+                                                      const float4 *__restrict__ pts, KArgs ka,
+                                                      const float *__restrict__ grid, int nos,
+                                                      int tshift,
+                                                      const float *__restrict__ wcoef) {
+  constexpr int M = W / 2, KZ = (W + 3) / 4, NQ = W * KZ;
+  extern __shared__ float lds[];
+  const int T = 1 << tshift, P = T + W - 1, PP = P * P, P3 = PP * P;
+  const Item it = items[blockIdx.x];
+  const int ntd = nos >> tshift;
+  const int tz = it.tile % ntd, ty = (it.tile / ntd) % ntd, tx = it.tile / (ntd * ntd);
+  const int ox = tx * T, oy = ty * T, oz = tz * T;
+  const int mask = nos - 1;
+  for (int c = threadIdx.x; c < P3; c += 256) {
+    const int px = c / PP, rem = c - px * PP, py = rem / P, pz = rem - py * P;
+    const int gx = (ox - (M - 1) + px) & mask, gy = (oy - (M - 1) + py) & mask,
+              gz = (oz - (M - 1) + pz) & mask;
+    lds[c] = grid[((size_t)gx * nos + gy) * nos + gz];
+  }
+  __syncthreads();
+
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int c16 = lane & 15, k4 = lane >> 4;
+  float *wt = lds + P3 + wave * (16 * WT_STRIDE);
+  const int len = it.end - it.start, per = (len + 3) >> 2;
+  const int s = it.start + min(len, wave * per), e = it.start + min(len, (wave + 1) * per);
+
+  float cf[4][WIN_NC];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int o = 4 * k4 + u;
+#pragma unroll
+    for (int k = 0; k < WIN_NC; ++k) cf[u][k] = o < W ? wcoef[o * WIN_NC + k] : 0.f;
+  }
+  float g[NQ];
+  uint32_t cur = 0xffffffffu;
+  for (int i0 = s; i0 < e; i0 += 16) {
+    const int cnt = min(16, e - i0);
+    const int cellv = (int)fill_weights<W, IN, false>(pts, ka, i0, cnt, lane, cf, wt);
+    wave_sync_lds();
+    int j = 0;
+    while (j < cnt) {
+      const uint32_t cell = (uint32_t)__builtin_amdgcn_readlane(cellv, j);
+      if (cell != cur) {
+        cur = cell;
+        const int lx = (int)(cell & 1023u) - ox, ly = (int)((cell >> 10) & 1023u) - oy,
+                  lz = (int)(cell >> 20) - oz;
+        const float *base = lds + (lx + c16) * PP + ly * P + lz;
+#pragma unroll
+        for (int ay = 0; ay < W; ++ay)
+#pragma unroll
+          for (int t = 0; t < KZ; ++t) {
+            const int zz = 4 * t + k4;
+            g[ay * KZ + t] = (c16 < W && zz < W) ? base[ay * P + zz] : 0.f;
+          }
+      }
+      int k = 1;
+      while (k < 16 && j + k < cnt && (uint32_t)__builtin_amdgcn_readlane(cellv, j + k) == cell) ++k;
+      const float *w = wt + (j + min(c16, k - 1)) * WT_STRIDE;
+      float wyv[W], wzv[KZ], wxv[4];
+#pragma unroll
+      for (int ay = 0; ay < W; ++ay) wyv[ay] = w[16 + ay];
+#pragma unroll
+      for (int t = 0; t < KZ; ++t) wzv[t] = w[32 + ((4 * t + k4) & 15)];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) wxv[r] = w[(4 * k4 + r) & 15];
+      f32x4 d = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ay = 0; ay < W; ++ay)
+#pragma unroll
+        for (int t = 0; t < KZ; ++t)
+          d = __builtin_amdgcn_mfma_f32_16x16x4f32(g[ay * KZ + t], wyv[ay] * wzv[t], d, 0, 0, 0);
+      float part = 0.f;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (4 * k4 + r < W) part = fmaf(wxv[r], d[r], part);
+      part += __shfl_xor(part, 16);
+      part += __shfl_xor(part, 32);
+      if (k4 == 0 && c16 < k) store_out<OUT>(ka, i0 + j + c16, part);
+      j += k;
+    }
+    wave_sync_lds();
   }
 }
 
@@ -284,7 +571,10 @@ __global__ __launch_bounds__(256) void k_interp3(const Item *__restrict__ items,
 template <int IN>
 __global__ __launch_bounds__(256) void k_spread12(const float4 *__restrict__ pts, int n, KArgs ka,
                                                   float *__restrict__ grid, int d, int nos,
-                                                  int m, float b) {
+                                                  int m, const float *__restrict__ wcoef) {
+  __shared__ float sc[WIN_MAXW * WIN_NC];
+  for (int q = threadIdx.x; q < WIN_MAXW * WIN_NC; q += 256) sc[q] = wcoef[q];
+  __syncthreads();
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
   const float4 q = pts[i];
@@ -292,10 +582,16 @@ __global__ __launch_bounds__(256) void k_spread12(const float4 *__restrict__ pts
   const int cx = cell & 1023u, cy = (cell >> 10) & 1023u;
   const float xv = load_in<IN>(ka, i);
   const int W = 2 * m, mask = nos - 1;
-  float wx[16], wy[16];
+  float wx[WIN_MAXW], wy[WIN_MAXW];
+  const float gx0 = fmaf(2.f, q.x, -1.f), gy0 = fmaf(2.f, q.y, -1.f);
   for (int a = 0; a < W; ++a) {
-    wx[a] = kb_window((float)(a - (m - 1)) - q.x, (float)m, b);
-    wy[a] = d == 2 ? kb_window((float)(a - (m - 1)) - q.y, (float)m, b) : 1.f;
+    float px = sc[a * WIN_NC + WIN_NC - 1], py = px;
+    for (int k = WIN_NC - 2; k >= 0; --k) {
+      px = fmaf(px, gx0, sc[a * WIN_NC + k]);
+      py = fmaf(py, gy0, sc[a * WIN_NC + k]);
+    }
+    wx[a] = px;
+    wy[a] = d == 2 ? py : 1.f;
   }
   for (int a = 0; a < W; ++a) {
     const int gx = (cx - (m - 1) + a) & mask;
@@ -313,17 +609,26 @@ __global__ __launch_bounds__(256) void k_spread12(const float4 *__restrict__ pts
 template <int IN, int OUT>
 __global__ __launch_bounds__(256) void k_interp12(const float4 *__restrict__ pts, int n, KArgs ka,
                                                   const float *__restrict__ grid, int d, int nos,
-                                                  int m, float b) {
+                                                  int m, const float *__restrict__ wcoef) {
+  __shared__ float sc[WIN_MAXW * WIN_NC];
+  for (int q = threadIdx.x; q < WIN_MAXW * WIN_NC; q += 256) sc[q] = wcoef[q];
+  __syncthreads();
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
   const float4 q = pts[i];
   const uint32_t cell = __float_as_uint(q.w);
   const int cx = cell & 1023u, cy = (cell >> 10) & 1023u;
   const int W = 2 * m, mask = nos - 1;
-  float wx[16], wy[16];
+  float wx[WIN_MAXW], wy[WIN_MAXW];
+  const float gx0 = fmaf(2.f, q.x, -1.f), gy0 = fmaf(2.f, q.y, -1.f);
   for (int a = 0; a < W; ++a) {
-    wx[a] = kb_window((float)(a - (m - 1)) - q.x, (float)m, b);
-    wy[a] = d == 2 ? kb_window((float)(a - (m - 1)) - q.y, (float)m, b) : 1.f;
+    float px = sc[a * WIN_NC + WIN_NC - 1], py = px;
+    for (int k = WIN_NC - 2; k >= 0; --k) {
+      px = fmaf(px, gx0, sc[a * WIN_NC + k]);
+      py = fmaf(py, gy0, sc[a * WIN_NC + k]);
+    }
+    wx[a] = px;
+    wy[a] = d == 2 ? py : 1.f;
   }
   float f = 0.f;
   for (int a = 0; a < W; ++a) {
@@ -559,26 +864,44 @@ static size_t tile_lds_bytes(const nfl_plan *P) {
   return (size_t)Pd * Pd * Pd * sizeof(float);
 }
 
+template <class K>
+static int set_lds(K kern, size_t lds) {
+  if (lds > 65536)
+    NFL_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds));
+  return NFL_OK;
+}
+
 template <int W, int IN>
 static int launch_spread3(nfl_plan *P, const KArgs &k, float *grid) {
   const size_t lds = tile_lds_bytes(P);
-  if (lds > 65536)
-    NFL_HIP(hipFuncSetAttribute((const void *)k_spread3<W, IN>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL((k_spread3<W, IN>), dim3(P->nitems), dim3(256), lds, P->stream, P->items.p,
-                     P->pts.p, k, grid, P->nos, P->tshift, P->win.b);
+  if (P->opt_kernel == 0) {
+    const size_t ldsm = 4 * lds + 4 * 16 * WT_STRIDE * sizeof(float);
+    NFL_TRY(set_lds(k_spread3_mfma<W, IN>, ldsm));
+    hipLaunchKernelGGL((k_spread3_mfma<W, IN>), dim3(P->nitems), dim3(256), ldsm, P->stream,
+                       P->items.p, P->pts.p, k, grid, P->nos, P->tshift, P->wcoef.p);
+  } else {
+    NFL_TRY(set_lds(k_spread3<W, IN>, lds));
+    hipLaunchKernelGGL((k_spread3<W, IN>), dim3(P->nitems), dim3(256), lds, P->stream, P->items.p,
+                       P->pts.p, k, grid, P->nos, P->tshift, P->wcoef.p);
+  }
   NFL_HIP(hipGetLastError());
   return NFL_OK;
 }
 
 template <int W, int IN, int OUT>
 static int launch_interp3(nfl_plan *P, const KArgs &k, const float *grid) {
-  const size_t lds = tile_lds_bytes(P);
-  if (lds > 65536)
-    NFL_HIP(hipFuncSetAttribute((const void *)k_interp3<W, IN, OUT>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL((k_interp3<W, IN, OUT>), dim3(P->nitems), dim3(256), lds, P->stream,
-                     P->items.p, P->pts.p, k, grid, P->nos, P->tshift, P->win.b);
+  if (P->opt_kernel == 0) {
+    const size_t lds = tile_lds_bytes(P) + 4 * 16 * WT_STRIDE * sizeof(float);
+    NFL_TRY(set_lds(k_interp3_mfma<W, IN, OUT>, lds));
+    hipLaunchKernelGGL((k_interp3_mfma<W, IN, OUT>), dim3(P->nitems), dim3(256), lds, P->stream,
+                       P->items.p, P->pts.p, k, grid, P->nos, P->tshift, P->wcoef.p);
+  } else {
+    const size_t lds = tile_lds_bytes(P);
+    NFL_TRY(set_lds(k_interp3<W, IN, OUT>, lds));
+    hipLaunchKernelGGL((k_interp3<W, IN, OUT>), dim3(P->nitems), dim3(256), lds, P->stream,
+                       P->items.p, P->pts.p, k, grid, P->nos, P->tshift, P->wcoef.p);
+  }
   NFL_HIP(hipGetLastError());
   return NFL_OK;
 }
@@ -599,7 +922,7 @@ static int spread_in(nfl_plan *P, const KArgs &k, float *grid) {
   }
   const int nb = (int)((P->n + 255) / 256);
   hipLaunchKernelGGL((k_spread12<IN>), dim3(nb), dim3(256), 0, P->stream, P->pts.p, (int)P->n, k,
-                     grid, P->d, P->nos, P->m, P->win.b);
+                     grid, P->d, P->nos, P->m, P->wcoef.p);
   NFL_HIP(hipGetLastError());
   return NFL_OK;
 }
@@ -608,6 +931,7 @@ int spread(nfl_plan *P, int in_mode, const VecArgs &a, float *grid) {
   int64_t gsz = 1;
   for (int t = 0; t < P->d; ++t) gsz *= P->nos;
   NFL_TRY(fill_f32(grid, gsz, 0.f, P->stream));
+  if (P->prof_ev) NFL_HIP(hipEventRecord(P->prof_ev[1], P->stream));
   const KArgs k = make_kargs(P, a);
   switch (in_mode) {
     case IN_USER_F32: return spread_in<IN_USER_F32>(P, k, grid);
@@ -634,7 +958,7 @@ static int interp_io(nfl_plan *P, const KArgs &k, const float *grid) {
   }
   const int nb = (int)((P->n + 255) / 256);
   hipLaunchKernelGGL((k_interp12<IN, OUT>), dim3(nb), dim3(256), 0, P->stream, P->pts.p,
-                     (int)P->n, k, grid, P->d, P->nos, P->m, P->win.b);
+                     (int)P->n, k, grid, P->d, P->nos, P->m, P->wcoef.p);
   NFL_HIP(hipGetLastError());
   return NFL_OK;
 }
@@ -700,9 +1024,14 @@ int convolve(nfl_plan *P, const float *gin, float *gout) {
 }
 
 int fastsum(nfl_plan *P, int in_mode, int out_mode, const VecArgs &a) {
+  if (P->prof_ev) NFL_HIP(hipEventRecord(P->prof_ev[0], P->stream));
   NFL_TRY(spread(P, in_mode, a, P->grid.p));
+  if (P->prof_ev) NFL_HIP(hipEventRecord(P->prof_ev[2], P->stream));
   NFL_TRY(convolve(P, P->grid.p, P->grid.p));
-  return interp(P, P->grid.p, in_mode, out_mode, a);
+  if (P->prof_ev) NFL_HIP(hipEventRecord(P->prof_ev[3], P->stream));
+  NFL_TRY(interp(P, P->grid.p, in_mode, out_mode, a));
+  if (P->prof_ev) NFL_HIP(hipEventRecord(P->prof_ev[4], P->stream));
+  return NFL_OK;
 }
 
 }  // namespace nfl

@@ -65,6 +65,11 @@ struct Item {
   int pad;
 };
 
+// Window polynomials: WIN_NC coefficients for each of up to WIN_MAXW offsets.
+constexpr int WIN_NC = 10;
+constexpr int WIN_MAXW = 16;
+int window_coefficients(int m, std::vector<float> &coef);
+
 // Window constants in grid units: psi(t) for |t| <= m, t = k - u.
 struct Window {
   int m;       // cut-off
@@ -88,8 +93,8 @@ struct nfl_plan {
 
   // options
   int opt_p = 0;                // 0 -> p = m
-  int opt_tile = 8;
-  int opt_chunk = 2048;
+  int opt_tile = 4;
+  int opt_chunk = 512;
   bool opt_eps_default = false;
 
   // kernel / NFFT parameters
@@ -106,6 +111,8 @@ struct nfl_plan {
   int max_item_len = 0;
 
   // FFT / filter
+  nfl::DBuf<float> wcoef;       // window polynomials, WIN_MAXW x WIN_NC
+  int opt_kernel = 0;           // 0: MFMA spread/interp (d = 3), 1: VALU
   nfl::DBuf<float> filt;        // half spectrum, FP32
   std::vector<double> filt_host;
   nfl::DBuf<float2> tw;         // e^{-2 pi i k / nos}, k < nos/2
@@ -116,6 +123,10 @@ struct nfl_plan {
   nfl::DBuf<float> deg;
   nfl::DBuf<float> dinv;        // d_E^{-1/2}
   double dmin = 0, dmax = 0;
+
+  // stage profiling: when set, fastsum records events before the grid fill,
+  // after it, after the spread kernel, after the convolution, after interp
+  hipEvent_t *prof_ev = nullptr;
 
   // scratch
   nfl::DBuf<float> xs;          // sorted FP32 work vector

@@ -340,6 +340,12 @@ int build_sorted_nodes(nfl_plan *P) {
   const int64_t n = P->n;
   const int d = P->d;
   int T = std::min(P->opt_tile, P->nos);
+  if (d == 3) {
+    // the matrix-core spread keeps four private copies of the padded tile in LDS
+    const int W = 2 * P->m;
+    auto lds_need = [&](int t) { const int p = t + W - 1; return (size_t)4 * p * p * p * 4 + 16384; };
+    while (T > 4 && lds_need(T) > 160 * 1024) T >>= 1;
+  }
   int tshift = 0;
   while ((1 << tshift) < T) ++tshift;
   P->tshift = tshift;
@@ -510,30 +516,81 @@ static void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w
   }
 }
 
-// Fourier transform of the window actually used,
-//   psi(t) = sinh(b s) / (s b e^{bm}),  s = sqrt(m^2 - t^2),  |t| <= m, 0 outside,
-// at frequency xi, by 64-point Gauss-Legendre quadrature on [-m, m] (psi is
-// analytic there: sinh(bs)/s is a power series in s^2).  The textbook closed
-// form pi I_0(m sqrt(b^2 - 4 pi^2 xi^2)) / (b e^{bm}) is the transform of the
-// untruncated function and differs by ~e^{-bm} relative.
-static double window_hat(double xi, int m, double b) {
-  static thread_local std::vector<double> gx, gw;
-  if (gx.empty()) gauss_legendre(64, gx, gw);
-  double acc = 0.0;
-  for (size_t k = 0; k < gx.size(); ++k) {
-    const double t = m * gx[k];
-    const double s = std::sqrt(std::max(0.0, (double)m * m - t * t));
-    const double psi = (s > 0 ? std::sinh(b * s) / s : b) / (b * std::exp(b * m));
-    acc += gw[k] * psi * std::cos(2.0 * M_PI * xi * t);
+// The Kaiser-Bessel window in grid units,
+//   psi(t) = sinh(b s) / (s b e^{bm}),  s = sqrt(m^2 - t^2),  |t| <= m,
+// with b = pi (2 - 1/sigma_os), sigma_os = 2 (the oversampling factor).
+static double kb_psi(double t, int m, double b) {
+  const double s = std::sqrt(std::max(0.0, (double)m * m - t * t));
+  return (s > 0 ? std::sinh(b * s) / s : b) / (b * std::exp(b * m));
+}
+
+// The kernels evaluate the window as 2m polynomials, one per grid offset c of
+// a node's window: psi(c - (m-1) - f) ~= sum_k coef[c][k] g^k, g = 2f - 1, for
+// the cell fraction f in [0, 1).  Degree WIN_NC-1 interpolation at Chebyshev
+// nodes in FP64, coefficients rounded to float32 (FP32 rounding level).
+static void window_poly(int m, double b, std::vector<float> &coef) {
+  const int W = 2 * m, D = WIN_NC;
+  coef.assign((size_t)WIN_MAXW * D, 0.f);
+  std::vector<double> V((size_t)D * D), y(D);
+  for (int c = 0; c < W; ++c) {
+    for (int k = 0; k < D; ++k) {
+      const double g = std::cos(M_PI * (k + 0.5) / D), f = 0.5 * (g + 1.0);
+      y[k] = kb_psi(c - (m - 1) - f, m, b);
+      double pw = 1.0;
+      for (int q = 0; q < D; ++q, pw *= g) V[(size_t)k * D + q] = pw;
+    }
+    // Gaussian elimination with partial pivoting on the D x D Vandermonde system
+    for (int col = 0; col < D; ++col) {
+      int piv = col;
+      for (int r = col + 1; r < D; ++r)
+        if (std::fabs(V[(size_t)r * D + col]) > std::fabs(V[(size_t)piv * D + col])) piv = r;
+      for (int q = 0; q < D; ++q) std::swap(V[(size_t)col * D + q], V[(size_t)piv * D + q]);
+      std::swap(y[col], y[piv]);
+      for (int r = col + 1; r < D; ++r) {
+        const double fct = V[(size_t)r * D + col] / V[(size_t)col * D + col];
+        for (int q = col; q < D; ++q) V[(size_t)r * D + q] -= fct * V[(size_t)col * D + q];
+        y[r] -= fct * y[col];
+      }
+    }
+    for (int r = D - 1; r >= 0; --r) {
+      double acc = y[r];
+      for (int q = r + 1; q < D; ++q) acc -= V[(size_t)r * D + q] * y[q];
+      y[r] = acc / V[(size_t)r * D + r];
+    }
+    for (int k = 0; k < D; ++k) coef[(size_t)c * D + k] = (float)y[k];
   }
-  return m * acc;
+}
+
+// Fourier transform, at frequency xi, of the window the kernels apply (the
+// piecewise polynomial with float32 coefficients), by 32-point Gauss-Legendre
+// quadrature on each unit interval.
+static double window_hat(double xi, int m, const std::vector<float> &coef) {
+  static thread_local std::vector<double> gx, gw;
+  if (gx.empty()) gauss_legendre(32, gx, gw);
+  double acc = 0.0;
+  for (int c = 0; c < 2 * m; ++c)
+    for (size_t k = 0; k < gx.size(); ++k) {
+      const double f = 0.5 * (gx[k] + 1.0), g = gx[k];
+      double p = 0.0;
+      for (int q = WIN_NC - 1; q >= 0; --q) p = p * g + (double)coef[(size_t)c * WIN_NC + q];
+      const double t = c - (m - 1) - f;
+      acc += 0.5 * gw[k] * p * std::cos(2.0 * M_PI * xi * t);
+    }
+  return acc;
+}
+
+int window_coefficients(int m, std::vector<float> &coef) {
+  if (m < 1 || 2 * m > WIN_MAXW) return NFL_ERR_ARG;
+  window_poly(m, M_PI * (2.0 - 0.5), coef);
+  return NFL_OK;
 }
 
 int compute_filter(int d, int N, int m, int p, double eps_B, double sigma_t,
                    std::vector<double> &out) {
-  if (d < 1 || d > 3 || N < 2 || (N & 1) || m < 1 || p < 1) return NFL_ERR_ARG;
+  if (d < 1 || d > 3 || N < 2 || (N & 1) || m < 1 || p < 1 || 2 * m > WIN_MAXW) return NFL_ERR_ARG;
   const int nos = 2 * N;
-  const double b = M_PI * (2.0 - 0.5);  // sigma_os = 2
+  std::vector<float> wcoef;
+  window_poly(m, M_PI * (2.0 - 0.5), wcoef);
   // ---- samples of K_R on I_N^d, stored at j mod N
   const double r0 = 0.5 - eps_B;
   std::vector<double> fa(p), fb(p, 0.0);
@@ -571,7 +628,7 @@ int compute_filter(int d, int N, int m, int p, double eps_B, double sigma_t,
   const double norm = std::pow((double)N, -d);
   // ---- window transform at l = -N/2..N/2
   std::vector<double> wh(N + 1);
-  for (int l = -N / 2; l <= N / 2; ++l) wh[l + N / 2] = window_hat((double)l / nos, m, b);
+  for (int l = -N / 2; l <= N / 2; ++l) wh[l + N / 2] = window_hat((double)l / nos, m, wcoef);
   // ---- half-spectrum filter: first d-1 axes l in [-N/2, N/2], last in [0, N/2]
   const int H = N / 2 + 1, F = N + 1;
   size_t cnt = (size_t)H;

@@ -24,7 +24,7 @@ def header_symbols():
 def test_library_exports_every_declared_symbol():
     L = nfl.lib()
     syms = header_symbols()
-    assert len(syms) >= 17
+    assert len(syms) >= 19
     for s in syms:
         assert hasattr(L, s), s
         assert s in nfl.SIGNATURES, "binding lacks " + s
@@ -55,6 +55,45 @@ def kb_hat_quadrature(xi, m, b=1.5 * math.pi, nq=2001):
     return h / 3 * (f[0] + f[-1] + 4 * f[1:-1:2].sum() + 2 * f[2:-1:2].sum()) / (b * math.exp(b * m))
 
 
+def kb_psi(t, m, b=1.5 * math.pi):
+    t = np.asarray(t, dtype=np.float64)
+    s = np.sqrt(np.maximum(m * m - t * t, 0.0))
+    with np.errstate(invalid="ignore", divide="ignore"):
+        return np.where(s > 0, np.sinh(b * s) / np.where(s > 0, s, 1.0), b) / (b * math.exp(b * m))
+
+
+def poly_window(coef, m, t):
+    """The piecewise polynomial window at grid offsets t in (-m, m]."""
+    t = np.asarray(t, dtype=np.float64)
+    c = np.ceil(t + m).astype(int) - 1          # t in (c - m, c - m + 1]
+    f = (c - (m - 1)) - t                       # fraction in [0, 1)
+    g = 2 * f - 1
+    out = np.zeros_like(t)
+    for q in range(coef.shape[1] - 1, -1, -1):
+        out = out * g + coef[c, q].astype(np.float64)
+    return out
+
+
+@pytest.mark.parametrize("m", [2, 3, 4, 5, 6, 7, 8])
+def test_window_polynomials_match_kaiser_bessel(m):
+    """The polynomial window equals the Kaiser-Bessel window to float32 level."""
+    coef = nfl.window_coefficients(m)
+    assert coef.shape == (2 * m, nfl.WIN_NC)
+    t = np.linspace(-m + 1e-9, m, 20001)
+    err = np.abs(poly_window(coef, m, t) - kb_psi(t, m)).max() / kb_psi(0.0, m)
+    assert err < 3e-7, err
+
+
+def poly_window_hat(coef, m, xi, nq=64):
+    """Transform of the piecewise polynomial window, Gauss-Legendre per interval."""
+    x, w = np.polynomial.legendre.leggauss(nq)
+    acc = 0.0
+    for c in range(2 * m):
+        t = (c - m) + 0.5 * (x + 1.0)             # (c - m, c - m + 1)
+        acc += 0.5 * np.sum(w * poly_window(coef, m, t) * np.cos(2 * math.pi * xi * t))
+    return acc
+
+
 @pytest.mark.parametrize("d,N,m,eps", [(1, 16, 3, 0.0), (2, 16, 4, 0.125), (3, 8, 2, 0.25)])
 def test_filter_equals_coefficients_over_window_transform(d, N, m, eps):
     sig = 0.12
@@ -62,7 +101,11 @@ def test_filter_equals_coefficients_over_window_transform(d, N, m, eps):
     F = nfl.compute_filter(d, N, m, p, eps, sig)
     b = fastsum.coefficients(sig, N, d, eps, p)           # indexed by l + N/2 on I_N^d
     nos = 2 * N
-    wh = np.array([kb_hat_quadrature(l / nos, m) for l in range(-N // 2, N // 2 + 1)])
+    coef = nfl.window_coefficients(m)
+    wh = np.array([poly_window_hat(coef, m, l / nos) for l in range(-N // 2, N // 2 + 1)])
+    # the transform of the polynomial window is the Kaiser-Bessel one to float32 level
+    wkb = np.array([kb_hat_quadrature(l / nos, m) for l in range(-N // 2, N // 2 + 1)])
+    assert np.abs(wh / wkb - 1).max() < 1e-6
     # expected on the extended set {-N/2..N/2}^(d-1) x {0..N/2}: real part of
     # the asymmetric sum = b_l split evenly between l and -l at the Nyquist indices
     ext = np.arange(-N // 2, N // 2 + 1)

@@ -70,11 +70,12 @@ def cpu_spread(u, x, m, nos):
     return g.reshape(-1)
 
 
-def make(nfl, v, sigma, N, m, eps_B=0.0, tile=None, chunk=None):
+def make(nfl, v, sigma, N, m, eps_B=0.0, tile=None, chunk=None, kernel=0):
     import torch
     v = np.asarray(v, dtype=np.float32)
     d = 1 if v.ndim == 1 else v.shape[1]
     P = nfl.Plan(d)
+    P.set_option(nfl.OPT_KERNEL, kernel)
     if tile:
         P.set_option(nfl.OPT_TILE, tile)
     if chunk:
@@ -85,18 +86,25 @@ def make(nfl, v, sigma, N, m, eps_B=0.0, tile=None, chunk=None):
 
 
 CASES = [
-    # (d, n, N, m, tile, chunk) -- several tiles, ragged n, several items per tile
-    (3, 3001, 16, 4, 4, 64),
-    (3, 2500, 32, 6, 8, 128),
-    (2, 2999, 32, 5, None, None),
-    (1, 777, 64, 3, None, None),
+    # (d, n, N, m, tile, chunk, kernel) -- several tiles, ragged n, several items
+    # per tile; kernel 0 = matrix cores, 1 = vector ALU (d = 3 only)
+    (3, 3001, 16, 4, 4, 64, 0),
+    (3, 3001, 16, 4, 4, 64, 1),
+    (3, 2500, 32, 6, 8, 128, 0),
+    (3, 2500, 32, 6, 8, 128, 1),
+    (3, 4099, 32, 5, 4, 96, 0),
+    (3, 2001, 32, 7, 16, 700, 0),
+    (3, 1777, 16, 2, 4, 64, 0),
+    (3, 1500, 32, 8, 8, 300, 0),
+    (2, 2999, 32, 5, None, None, 0),
+    (1, 777, 64, 3, None, None, 0),
 ]
 
 
-@pytest.mark.parametrize("d,n,N,m,tile,chunk", CASES)
-def test_spread_matches_cpu_gridding(nfl, d, n, N, m, tile, chunk):
+@pytest.mark.parametrize("d,n,N,m,tile,chunk,kernel", CASES)
+def test_spread_matches_cpu_gridding(nfl, d, n, N, m, tile, chunk, kernel):
     v = synth.gmm(n, d=d, k=4, seed=11 + d)
-    P = make(nfl, v, 0.08, N, m, 0.0, tile, chunk)
+    P = make(nfl, v, 0.08, N, m, 0.0, tile, chunk, kernel)
     x = synth.normal_vectors(n, seed=5)
     g = host(P.spread(tt(x)))
     u = grid_coords(v, P.info()["rho"], 0.0, 2 * N)
@@ -123,10 +131,10 @@ def test_convolve_matches_numpy_fft(nfl, d, N):
     assert err < 2e-6, err
 
 
-@pytest.mark.parametrize("d,n,N,m,tile,chunk", CASES)
-def test_interp_is_transpose_of_spread(nfl, d, n, N, m, tile, chunk):
+@pytest.mark.parametrize("d,n,N,m,tile,chunk,kernel", CASES)
+def test_interp_is_transpose_of_spread(nfl, d, n, N, m, tile, chunk, kernel):
     v = synth.gmm(n, d=d, k=4, seed=21)
-    P = make(nfl, v, 0.08, N, m, 0.0, tile, chunk)
+    P = make(nfl, v, 0.08, N, m, 0.0, tile, chunk, kernel)
     x = synth.normal_vectors(n, seed=8)
     rng = np.random.default_rng(1)
     g = rng.standard_normal((2 * N) ** d).astype(np.float32)
