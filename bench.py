@@ -47,6 +47,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-cg", action="store_true")
     ap.add_argument("--rows", type=int, default=256, help="sampled rows for the accuracy check")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="short run for hardware counters: a few products and a 256 MiB "
+                         "device copy (the reference for scaling byte counters); no JSON")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU sharding is a design "
@@ -75,6 +78,17 @@ def main():
     info = P.info()
     log("setup %.2fs  rho %.4f  sigma~ %.4f  d_E in [%.3g, %.3g]" % (
         setup_s, info["rho"], info["sigma_tilde"], info["dmin"], info["dmax"]))
+
+    if args.profile_run:
+        for _ in range(max(1, args.steps)):
+            P.apply_Ls(xd, out=yd)
+        src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("profile run done: %d products, one 256 MiB copy" % max(1, args.steps))
+        P.close()
+        return
 
     for _ in range(args.warmup):
         P.apply_Ls(xd, out=yd)

@@ -319,62 +319,89 @@ __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-constexpr int WT_STRIDE = 4 * 16;  // floats per node in the weight table
+// Weight-table row pitch (floats per node): 80 for the spread, whose reads
+// touch 4 node rows x 16 columns (rows 16 banks apart), 65 for the interp,
+// whose reads touch 16 node rows in the same column (rows 1 bank apart).
+constexpr int WT_SPREAD = 80, WT_INTERP = 65;
 
-// Fill the weight table for nodes i0 .. i0 + cnt - 1 (cnt <= 16); returns, in
-// every lane, the packed cell of node (lane % 16) (0xffffffff past cnt).
-template <int W, int IN, bool WITH_X>
-__device__ __forceinline__ uint32_t fill_weights(const float4 *__restrict__ pts, const KArgs &ka,
-                                                 int i0, int cnt, int lane,
-                                                 const float (&cf)[4][WIN_NC], float *wt) {
+// x-pitch of an LDS tile with P^3 logical cells: >= P*P and = 4 (mod 32), so
+// that 16 consecutive x-offsets land on distinct bank quadruples.
+__host__ __device__ __forceinline__ int tile_px(int P) { return P * P + ((4 - P * P) % 32 + 32) % 32; }
+
+// Fill the weight table for the 16 nodes sub*16 .. sub*16+15 of the current
+// 64-node batch held in registers (lane l holds node l of the batch: record
+// qb, input value xb); cnt = valid nodes of the sub-batch.  Returns, in every
+// lane, the packed cell of sub-batch node (lane % 16).
+template <int W, bool WITH_X, int STRIDE>
+__device__ __forceinline__ uint32_t fill_weights(const float4 &qb, float xb, int sub, int cnt,
+                                                 int lane, const float (&cf)[4][WIN_NC],
+                                                 float *wt) {
   const int node = lane & 15, part = lane >> 4;
-  float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
-  uint32_t cell = 0xffffffffu;
-  float xv = 0.f;
-  if (node < cnt) {
-    q = pts[i0 + node];
-    cell = __float_as_uint(q.w);
-    if (WITH_X && part == 0) xv = load_in<IN>(ka, i0 + node);
-  }
-  float *w = wt + node * WT_STRIDE;
+  const int src = sub * 16 + min(node, cnt - 1);
+  const float qx = __shfl(qb.x, src), qy = __shfl(qb.y, src), qz = __shfl(qb.z, src);
+  const uint32_t cell = node < cnt ? (uint32_t)__shfl((int)__float_as_uint(qb.w), src) : 0xffffffffu;
+  float *w = wt + node * STRIDE;
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int o = 4 * part + u;
-    w[0 * 16 + o] = win_poly(cf[u], q.x);
-    w[1 * 16 + o] = win_poly(cf[u], q.y);
-    w[2 * 16 + o] = win_poly(cf[u], q.z);
+    w[0 * 16 + o] = win_poly(cf[u], qx);
+    w[1 * 16 + o] = win_poly(cf[u], qy);
+    w[2 * 16 + o] = win_poly(cf[u], qz);
   }
-  if (WITH_X && part == 0) w[3 * 16] = xv;
+  if (WITH_X) {
+    const float xv = __shfl(xb, src);
+    if (part == 0) w[3 * 16] = xv;
+  }
   return cell;
+}
+
+// One 64-node batch of sorted records (and, for the spread, input values),
+// loaded one per lane; past the end: zero records.
+template <int IN, bool WITH_X>
+__device__ __forceinline__ void load_batch(const float4 *__restrict__ pts, const KArgs &ka, int i0,
+                                           int e, int lane, float4 &qb, float &xb) {
+  qb = make_float4(0.f, 0.f, 0.f, 0.f);
+  xb = 0.f;
+  if (i0 + lane < e) {
+    qb = pts[i0 + lane];
+    if (WITH_X) xb = load_in<IN>(ka, i0 + lane);
+  }
 }
 
 // Spread: for the nodes p of one grid cell
 //   G[ax][ay][az] += sum_p (x_p wx_p[ax]) (wy_p[ay] wz_p[az])
 // with v_mfma_f32_16x16x4_f32: rows = x-offsets ax (W of 16 used), K = 4
-// nodes of the cell, columns = S y-offsets times WP z-offsets (WP = W rounded
-// up to 4, 8 or 16, S = 16/WP), NB = W/S column blocks.  Lane l (node slot
+// nodes, columns = z-offsets (and, for W <= 8, S = 16/WP y-offsets packed
+// side by side), NB column blocks, one per y-offset group.  Lane l (node slot
 // l/16, column l%16) accumulates D[ax = 4 (l/16) + r][column l%16], r < 4, in
-// registers over the run of the cell, then adds it into its wave's PRIVATE
-// copy of the padded tile (plain read-add-write: every lane of a flush owns a
-// distinct cell, and LDS operations of one wave are ordered).  At the end the
-// four private tiles are summed and added into the grid.
-template <int W>
+// registers over a run of nodes, then adds it into its wave's PRIVATE copy of
+// the padded tile (plain read-add-write: every lane of a flush owns a
+// distinct cell, and the LDS operations of one wave are ordered).  At the end
+// the four private tiles are summed and added into the grid.
+//
+// ZM ("z-merge", needs T + W - 1 <= 16): the 16 columns cover the whole
+// z-extent of the padded tile, so nodes of different cells of one (x, y)
+// column of the tile share the accumulators: node p contributes to column c
+// with wz_p[c - lz_p] (lz_p = its cell's z inside the tile) and runs, hence
+// flushes, are per (x, y) column instead of per cell.
+template <int W, bool ZM>
 struct SpreadShape {
-  static constexpr int WP = W <= 4 ? 4 : (W <= 8 ? 8 : 16);
+  static constexpr int WP = ZM ? 16 : (W <= 4 ? 4 : (W <= 8 ? 8 : 16));
   static constexpr int S = 16 / WP;
   static constexpr int NB = (W + S - 1) / S;
 };
 
-template <int W, int IN>
+template <int W, int IN, bool ZM>
 __global__ __launch_bounds__(256) void k_spread3_mfma(const Item *__restrict__ items,
                                                       const float4 *__restrict__ pts, KArgs ka,
                                                       float *__restrict__ grid, int nos,
                                                       int tshift,
                                                       const float *__restrict__ wcoef) {
   constexpr int M = W / 2;
-  constexpr int WP = SpreadShape<W>::WP, S = SpreadShape<W>::S, NB = SpreadShape<W>::NB;
+  constexpr int WP = SpreadShape<W, ZM>::WP, S = SpreadShape<W, ZM>::S,
+                NB = SpreadShape<W, ZM>::NB;
   extern __shared__ float lds[];
-  const int T = 1 << tshift, P = T + W - 1, PP = P * P, P3 = PP * P;
+  const int T = 1 << tshift, P = T + W - 1, PX = tile_px(P), P3 = PX * P;
   const Item it = items[blockIdx.x];
   const int ntd = nos >> tshift;
   const int tz = it.tile % ntd, ty = (it.tile / ntd) % ntd, tx = it.tile / (ntd * ntd);
@@ -387,9 +414,11 @@ __global__ __launch_bounds__(256) void k_spread3_mfma(const Item *__restrict__ i
   const int c16 = lane & 15, p4 = lane >> 4;
   const int sub = c16 / WP, az = c16 % WP;
   float *tile = lds + wave * P3;
-  float *wt = lds + 4 * P3 + wave * (16 * WT_STRIDE);
+  float *wt = lds + 4 * P3 + wave * (16 * WT_SPREAD);
   const int len = it.end - it.start, per = (len + 3) >> 2;
   const int s = it.start + min(len, wave * per), e = it.start + min(len, (wave + 1) * per);
+  // run key: the cell, or with ZM its (x, y) column
+  const uint32_t keymask = ZM ? 0x000fffffu : 0xffffffffu;
 
   float cf[4][WIN_NC];
 #pragma unroll
@@ -403,71 +432,100 @@ __global__ __launch_bounds__(256) void k_spread3_mfma(const Item *__restrict__ i
   for (int nb = 0; nb < NB; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
   uint32_t cur = 0xffffffffu;
 
+  // add the accumulators of the run `cell` into the private tile
   auto flush = [&](uint32_t cell) {
-    const int lx = (int)(cell & 1023u) - ox, ly = (int)((cell >> 10) & 1023u) - oy,
-              lz = (int)(cell >> 20) - oz;
+    const int lx = (int)(cell & 1023u) - ox, ly = (int)((cell >> 10) & 1023u) - oy;
+    const int lz = ZM ? 0 : (int)(cell >> 20) - oz;
+    const bool zok = ZM ? (az < P) : (az < W);
     float old[NB][4];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       const int ay = S * nb + sub;
-      const float *base = tile + (lx * P + ly + ay) * P + lz + az;
+      const float *base = tile + lx * PX + (ly + ay) * P + lz + az;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int ax = 4 * p4 + r;
-        old[nb][r] = (az < W && ay < W && ax < W) ? base[ax * PP] : 0.f;
+        old[nb][r] = (zok && ay < W && ax < W) ? base[ax * PX] : 0.f;
       }
     }
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       const int ay = S * nb + sub;
-      float *base = tile + (lx * P + ly + ay) * P + lz + az;
+      float *base = tile + lx * PX + (ly + ay) * P + lz + az;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int ax = 4 * p4 + r;
-        if (az < W && ay < W && ax < W) base[ax * PP] = old[nb][r] + acc[nb][r];
+        if (zok && ay < W && ax < W) base[ax * PX] = old[nb][r] + acc[nb][r];
       }
       acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
   };
 
-  for (int i0 = s; i0 < e; i0 += 16) {
-    const int cnt = min(16, e - i0);
-    const int cellv = (int)fill_weights<W, IN, true>(pts, ka, i0, cnt, lane, cf, wt);
-    wave_sync_lds();
-    int j = 0;
-    while (j < cnt) {
-      const uint32_t cell = (uint32_t)__builtin_amdgcn_readlane(cellv, j);
-      if (cell != cur) {
-        if (cur != 0xffffffffu) flush(cur);
-        cur = cell;
+  float4 qb, qn;
+  float xb, xn;
+  load_batch<IN, true>(pts, ka, s, e, lane, qb, xb);
+  for (int b0 = s; b0 < e; b0 += 64) {
+    load_batch<IN, true>(pts, ka, b0 + 64, e, lane, qn, xn);  // prefetch the next batch
+    const int bcnt = min(64, e - b0);
+    for (int sb = 0; sb * 16 < bcnt; ++sb) {
+      const int cnt = min(16, bcnt - sb * 16);
+      const int cellv = (int)fill_weights<W, true, WT_SPREAD>(qb, xb, sb, cnt, lane, cf, wt);
+      wave_sync_lds();
+      int j = 0;
+      while (j < cnt) {
+        const uint32_t key = (uint32_t)__builtin_amdgcn_readlane(cellv, j) & keymask;
+        if (key != cur) {
+          if (cur != 0xffffffffu) flush(cur);
+          cur = key;
+        }
+        int k = 1;
+        while (k < 4 && j + k < cnt &&
+               ((uint32_t)__builtin_amdgcn_readlane(cellv, j + k) & keymask) == key)
+          ++k;
+        const int node = j + min(p4, k - 1);
+        const float *w = wt + node * WT_SPREAD;
+        const float xv = p4 < k ? w[3 * 16] : 0.f;
+        const float a = xv * w[c16 & 15];
+        float wz;
+        if (ZM) {
+          const int lzp = (int)((uint32_t)__shfl(cellv, node) >> 20) - oz;
+          const int o = az - lzp;
+          wz = (o >= 0 && o < W) ? w[2 * 16 + o] : 0.f;
+        } else {
+          wz = w[2 * 16 + (az & 15)];
+        }
+        float by[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) by[nb] = w[16 + S * nb + sub];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, by[nb] * wz, acc[nb], 0, 0, 0);
+        j += k;
       }
-      int k = 1;
-      while (k < 4 && j + k < cnt && (uint32_t)__builtin_amdgcn_readlane(cellv, j + k) == cell) ++k;
-      const float *w = wt + (j + min(p4, k - 1)) * WT_STRIDE;
-      const float xv = p4 < k ? w[3 * 16] : 0.f;
-      const float a = xv * w[c16 & 15];
-      const float wz = w[2 * 16 + (az & 15)];
-      float by[NB];
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) by[nb] = w[16 + S * nb + sub];
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, by[nb] * wz, acc[nb], 0, 0, 0);
-      j += k;
+      wave_sync_lds();
     }
-    wave_sync_lds();
+    qb = qn;
+    xb = xn;
   }
   if (cur != 0xffffffffu) flush(cur);
   __syncthreads();
 
+  // sum the private tiles and add into the grid: each wave takes rows (px, py)
+  // of the tile, 64 / ZL rows at a time with ZL >= P lanes along z
   const int mask = nos - 1;
-  for (int c = threadIdx.x; c < P3; c += 256) {
-    const float v = (lds[c] + lds[P3 + c]) + (lds[2 * P3 + c] + lds[3 * P3 + c]);
-    if (v != 0.f) {
-      const int px = c / PP, rem = c - px * PP, py = rem / P, pz = rem - py * P;
-      const int gx = (ox - (M - 1) + px) & mask, gy = (oy - (M - 1) + py) & mask,
-                gz = (oz - (M - 1) + pz) & mask;
-      unsafeAtomicAdd(&grid[((size_t)gx * nos + gy) * nos + gz], v);
+  const int ZL = P <= 16 ? 16 : (P <= 32 ? 32 : 64), RL = 64 / ZL;
+  const int pz = lane % ZL, rsub = lane / ZL;
+  for (int row0 = wave * RL; row0 < P * P; row0 += 4 * RL) {
+    const int row = row0 + rsub;
+    if (row < P * P && pz < P) {
+      const int px = row / P, py = row - px * P;
+      const int o = px * PX + py * P + pz;
+      const float v = (lds[o] + lds[P3 + o]) + (lds[2 * P3 + o] + lds[3 * P3 + o]);
+      if (v != 0.f) {
+        const int gx = (ox - (M - 1) + px) & mask, gy = (oy - (M - 1) + py) & mask,
+                  gz = (oz - (M - 1) + pz) & mask;
+        unsafeAtomicAdd(&grid[((size_t)gx * nos + gy) * nos + gz], v);
+      }
     }
   }
 }
@@ -486,24 +544,32 @@ __global__ __launch_bounds__(256) void k_interp3_mfma(const Item *__restrict__ i
                                                       const float *__restrict__ wcoef) {
   constexpr int M = W / 2, KZ = (W + 3) / 4, NQ = W * KZ;
   extern __shared__ float lds[];
-  const int T = 1 << tshift, P = T + W - 1, PP = P * P, P3 = PP * P;
+  const int T = 1 << tshift, P = T + W - 1, PP = P * P, PX = tile_px(P), P3 = PX * P;
   const Item it = items[blockIdx.x];
   const int ntd = nos >> tshift;
   const int tz = it.tile % ntd, ty = (it.tile / ntd) % ntd, tx = it.tile / (ntd * ntd);
   const int ox = tx * T, oy = ty * T, oz = tz * T;
   const int mask = nos - 1;
-  for (int c = threadIdx.x; c < P3; c += 256) {
-    const int px = c / PP, rem = c - px * PP, py = rem / P, pz = rem - py * P;
-    const int gx = (ox - (M - 1) + px) & mask, gy = (oy - (M - 1) + py) & mask,
-              gz = (oz - (M - 1) + pz) & mask;
-    lds[c] = grid[((size_t)gx * nos + gy) * nos + gz];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  {
+    // stage the padded tile: each wave takes rows (px, py), 64 / ZL at a time
+    const int ZL = P <= 16 ? 16 : (P <= 32 ? 32 : 64), RL = 64 / ZL;
+    const int pz = lane % ZL, rsub = lane / ZL;
+    for (int row0 = wave * RL; row0 < PP; row0 += 4 * RL) {
+      const int row = row0 + rsub;
+      if (row < PP && pz < P) {
+        const int px = row / P, py = row - px * P;
+        const int gx = (ox - (M - 1) + px) & mask, gy = (oy - (M - 1) + py) & mask,
+                  gz = (oz - (M - 1) + pz) & mask;
+        lds[px * PX + py * P + pz] = grid[((size_t)gx * nos + gy) * nos + gz];
+      }
+    }
   }
   __syncthreads();
 
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
   const int c16 = lane & 15, k4 = lane >> 4;
-  float *wt = lds + P3 + wave * (16 * WT_STRIDE);
+  float *wt = lds + P3 + wave * (16 * WT_INTERP);
   const int len = it.end - it.start, per = (len + 3) >> 2;
   const int s = it.start + min(len, wave * per), e = it.start + min(len, (wave + 1) * per);
 
@@ -516,52 +582,62 @@ __global__ __launch_bounds__(256) void k_interp3_mfma(const Item *__restrict__ i
   }
   float g[NQ];
   uint32_t cur = 0xffffffffu;
-  for (int i0 = s; i0 < e; i0 += 16) {
-    const int cnt = min(16, e - i0);
-    const int cellv = (int)fill_weights<W, IN, false>(pts, ka, i0, cnt, lane, cf, wt);
-    wave_sync_lds();
-    int j = 0;
-    while (j < cnt) {
-      const uint32_t cell = (uint32_t)__builtin_amdgcn_readlane(cellv, j);
-      if (cell != cur) {
-        cur = cell;
-        const int lx = (int)(cell & 1023u) - ox, ly = (int)((cell >> 10) & 1023u) - oy,
-                  lz = (int)(cell >> 20) - oz;
-        const float *base = lds + (lx + c16) * PP + ly * P + lz;
+  float4 qb, qn;
+  float xb, xn;
+  load_batch<IN, false>(pts, ka, s, e, lane, qb, xb);
+  for (int b0 = s; b0 < e; b0 += 64) {
+    load_batch<IN, false>(pts, ka, b0 + 64, e, lane, qn, xn);  // prefetch the next batch
+    const int bcnt = min(64, e - b0);
+    for (int sb = 0; sb * 16 < bcnt; ++sb) {
+      const int cnt = min(16, bcnt - sb * 16);
+      const int i0 = b0 + sb * 16;
+      const int cellv = (int)fill_weights<W, false, WT_INTERP>(qb, xb, sb, cnt, lane, cf, wt);
+      wave_sync_lds();
+      int j = 0;
+      while (j < cnt) {
+        const uint32_t cell = (uint32_t)__builtin_amdgcn_readlane(cellv, j);
+        if (cell != cur) {
+          cur = cell;
+          const int lx = (int)(cell & 1023u) - ox, ly = (int)((cell >> 10) & 1023u) - oy,
+                    lz = (int)(cell >> 20) - oz;
+          const float *base = lds + (lx + c16) * PX + ly * P + lz;
+#pragma unroll
+          for (int ay = 0; ay < W; ++ay)
+#pragma unroll
+            for (int t = 0; t < KZ; ++t) {
+              const int zz = 4 * t + k4;
+              g[ay * KZ + t] = (c16 < W && zz < W) ? base[ay * P + zz] : 0.f;
+            }
+        }
+        int k = 1;
+        while (k < 16 && j + k < cnt && (uint32_t)__builtin_amdgcn_readlane(cellv, j + k) == cell) ++k;
+        const float *w = wt + (j + min(c16, k - 1)) * WT_INTERP;
+        float wyv[W], wzv[KZ], wxv[4];
+#pragma unroll
+        for (int ay = 0; ay < W; ++ay) wyv[ay] = w[16 + ay];
+#pragma unroll
+        for (int t = 0; t < KZ; ++t) wzv[t] = w[32 + ((4 * t + k4) & 15)];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) wxv[r] = w[(4 * k4 + r) & 15];
+        f32x4 d = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int ay = 0; ay < W; ++ay)
 #pragma unroll
-          for (int t = 0; t < KZ; ++t) {
-            const int zz = 4 * t + k4;
-            g[ay * KZ + t] = (c16 < W && zz < W) ? base[ay * P + zz] : 0.f;
-          }
+          for (int t = 0; t < KZ; ++t)
+            d = __builtin_amdgcn_mfma_f32_16x16x4f32(g[ay * KZ + t], wyv[ay] * wzv[t], d, 0, 0, 0);
+        float part = 0.f;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (4 * k4 + r < W) part = fmaf(wxv[r], d[r], part);
+        part += __shfl_xor(part, 16);
+        part += __shfl_xor(part, 32);
+        if (k4 == 0 && c16 < k) store_out<OUT>(ka, i0 + j + c16, part);
+        j += k;
       }
-      int k = 1;
-      while (k < 16 && j + k < cnt && (uint32_t)__builtin_amdgcn_readlane(cellv, j + k) == cell) ++k;
-      const float *w = wt + (j + min(c16, k - 1)) * WT_STRIDE;
-      float wyv[W], wzv[KZ], wxv[4];
-#pragma unroll
-      for (int ay = 0; ay < W; ++ay) wyv[ay] = w[16 + ay];
-#pragma unroll
-      for (int t = 0; t < KZ; ++t) wzv[t] = w[32 + ((4 * t + k4) & 15)];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) wxv[r] = w[(4 * k4 + r) & 15];
-      f32x4 d = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int ay = 0; ay < W; ++ay)
-#pragma unroll
-        for (int t = 0; t < KZ; ++t)
-          d = __builtin_amdgcn_mfma_f32_16x16x4f32(g[ay * KZ + t], wyv[ay] * wzv[t], d, 0, 0, 0);
-      float part = 0.f;
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        if (4 * k4 + r < W) part = fmaf(wxv[r], d[r], part);
-      part += __shfl_xor(part, 16);
-      part += __shfl_xor(part, 32);
-      if (k4 == 0 && c16 < k) store_out<OUT>(ka, i0 + j + c16, part);
-      j += k;
+      wave_sync_lds();
     }
-    wave_sync_lds();
+    qb = qn;
+    xb = xn;
   }
 }
 
@@ -872,19 +948,30 @@ static int set_lds(K kern, size_t lds) {
   return NFL_OK;
 }
 
+template <int W, int IN, bool ZM>
+static int launch_spread3_mfma(nfl_plan *P, const KArgs &k, float *grid) {
+  const int Pd = (1 << P->tshift) + W - 1;
+  const size_t lds = (4 * (size_t)tile_px(Pd) * Pd + 4 * 16 * WT_SPREAD) * sizeof(float);
+  NFL_TRY(set_lds(k_spread3_mfma<W, IN, ZM>, lds));
+  hipLaunchKernelGGL((k_spread3_mfma<W, IN, ZM>), dim3(P->nitems), dim3(256), lds, P->stream,
+                     P->items.p, P->pts.p, k, grid, P->nos, P->tshift, P->wcoef.p);
+  NFL_HIP(hipGetLastError());
+  return NFL_OK;
+}
+
 template <int W, int IN>
 static int launch_spread3(nfl_plan *P, const KArgs &k, float *grid) {
-  const size_t lds = tile_lds_bytes(P);
   if (P->opt_kernel == 0) {
-    const size_t ldsm = 4 * lds + 4 * 16 * WT_STRIDE * sizeof(float);
-    NFL_TRY(set_lds(k_spread3_mfma<W, IN>, ldsm));
-    hipLaunchKernelGGL((k_spread3_mfma<W, IN>), dim3(P->nitems), dim3(256), ldsm, P->stream,
-                       P->items.p, P->pts.p, k, grid, P->nos, P->tshift, P->wcoef.p);
-  } else {
-    NFL_TRY(set_lds(k_spread3<W, IN>, lds));
-    hipLaunchKernelGGL((k_spread3<W, IN>), dim3(P->nitems), dim3(256), lds, P->stream, P->items.p,
-                       P->pts.p, k, grid, P->nos, P->tshift, P->wcoef.p);
+    const int T = 1 << P->tshift;
+    if constexpr (W >= 9) {
+      if (T + W - 1 <= 16) return launch_spread3_mfma<W, IN, true>(P, k, grid);
+    }
+    return launch_spread3_mfma<W, IN, false>(P, k, grid);
   }
+  const size_t lds = tile_lds_bytes(P);
+  NFL_TRY(set_lds(k_spread3<W, IN>, lds));
+  hipLaunchKernelGGL((k_spread3<W, IN>), dim3(P->nitems), dim3(256), lds, P->stream, P->items.p,
+                     P->pts.p, k, grid, P->nos, P->tshift, P->wcoef.p);
   NFL_HIP(hipGetLastError());
   return NFL_OK;
 }
@@ -892,7 +979,8 @@ static int launch_spread3(nfl_plan *P, const KArgs &k, float *grid) {
 template <int W, int IN, int OUT>
 static int launch_interp3(nfl_plan *P, const KArgs &k, const float *grid) {
   if (P->opt_kernel == 0) {
-    const size_t lds = tile_lds_bytes(P) + 4 * 16 * WT_STRIDE * sizeof(float);
+    const int Pd = (1 << P->tshift) + W - 1;
+    const size_t lds = ((size_t)tile_px(Pd) * Pd + 4 * 16 * WT_INTERP) * sizeof(float);
     NFL_TRY(set_lds(k_interp3_mfma<W, IN, OUT>, lds));
     hipLaunchKernelGGL((k_interp3_mfma<W, IN, OUT>), dim3(P->nitems), dim3(256), lds, P->stream,
                        P->items.p, P->pts.p, k, grid, P->nos, P->tshift, P->wcoef.p);

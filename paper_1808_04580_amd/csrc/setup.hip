@@ -343,7 +343,10 @@ int build_sorted_nodes(nfl_plan *P) {
   if (d == 3) {
     // the matrix-core spread keeps four private copies of the padded tile in LDS
     const int W = 2 * P->m;
-    auto lds_need = [&](int t) { const int p = t + W - 1; return (size_t)4 * p * p * p * 4 + 16384; };
+    auto lds_need = [&](int t) {
+      const int p = t + W - 1, px = p * p + ((4 - p * p) % 32 + 32) % 32;
+      return (size_t)4 * px * p * 4 + 4 * 16 * 80 * 4;
+    };
     while (T > 4 && lds_need(T) > 160 * 1024) T >>= 1;
   }
   int tshift = 0;

@@ -93,6 +93,7 @@ CASES = [
     (3, 2500, 32, 6, 8, 128, 0),
     (3, 2500, 32, 6, 8, 128, 1),
     (3, 4099, 32, 5, 4, 96, 0),
+    (3, 3333, 32, 6, 4, 200, 0),
     (3, 2001, 32, 7, 16, 700, 0),
     (3, 1777, 16, 2, 4, 64, 0),
     (3, 1500, 32, 8, 8, 300, 0),
