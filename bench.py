@@ -113,11 +113,17 @@ def main():
     flops_per_point = 2.0 * W ** 3          # one FMA per window cell
     dom = "spread" if st["spread"] >= st["interp"] else "interp"
     achieved = flops_per_point * N_POINTS / (st[dom] * 1e-3) / 1e12
+    # HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter runs recorded
+    # in profiles/; null once the kernel source has changed since they were taken
     traffic = None
     prof_json = os.path.join(ROOT, "profiles", "traffic.json")
     if os.path.exists(prof_json):
+        import hashlib
         try:
-            traffic = json.load(open(prof_json)).get(dom)
+            rec = json.load(open(prof_json))
+            src = os.path.join(ROOT, "paper_1808_04580_amd", "csrc", "nfft.hip")
+            if rec.get("nfft_hip_sha1") == hashlib.sha1(open(src, "rb").read()).hexdigest():
+                traffic = rec.get(dom)
         except Exception:
             traffic = None
     roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3),
