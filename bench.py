@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "L_s matvecs/s (n=1M, d=3, rel err≤1e-5); CG time-to-tol learned vs plain"
 N_POINTS, SIGMA, NBW, MCUT, EPS_B, TAU = 1_000_000, 0.04, 64, 6, 0.0, 10.0
-PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32 (packed issue); unpacked issue is half
+PEAK_FP32_TFLOPS = 157.3   # MI355X dense FP32 matrix-core (MFMA) peak
 PEAK_HBM_GBS = 8000.0
 
 
@@ -126,7 +126,7 @@ def main():
                 traffic = rec.get(dom)
         except Exception:
             traffic = None
-    roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3),
+    roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 3),
                 "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic}
 
