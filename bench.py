@@ -149,21 +149,50 @@ def main():
     }
     log("accuracy on %d sampled rows: %s (oracle %.1fs)" % (args.rows, acc, cpu_rows_s))
 
-    # --- CG time-to-tolerance ---------------------------------------------------
+    # --- CG time-to-tolerance: plain vs learned warm start, held-out cloud ------
     cg = None
     if not args.no_cg:
-        f = torch.as_tensor(synth.ssl_rhs(lab, 0, frac=0.02, seed=100001), device=dev)
-        P.cg_solve(f, tau=TAU, tol=1e-6, maxit=5)   # warm the path
-        torch.cuda.synchronize()
-        t0 = time.time()
-        r = P.cg_solve(f, tau=TAU, tol=1e-6, maxit=500)
-        torch.cuda.synchronize()
-        cg = {"tau": TAU, "tol": 1e-6,
-              "plain": {"iters": r["iters"], "ms": round((time.time() - t0) * 1e3, 2),
-                        "true_relres": r["relres"]},
-              "learned": None}
-        log("CG plain: %d iterations, %.1f ms, true rel. residual %.2e" % (
-            r["iters"], cg["plain"]["ms"], r["relres"]))
+        vt, labt = synth.moons_and_roll(N_POINTS, seed=100001)
+        Pt = nfl.plan(torch.as_tensor(vt, device=dev), SIGMA, N=NBW, m=MCUT, eps_B=EPS_B)
+        net = None
+        wpath = os.path.join(ROOT, "paper_1808_04580_amd", "warmstart_moons_roll.bin")
+        if os.path.exists(wpath):
+            net = nfl.WarmStart(n_classes=3, seed=0)
+            net.load(wpath)
+        fs = [torch.as_tensor(synth.ssl_rhs(labt, c, frac=0.02, seed=200000 + c), device=dev)
+              for c in range(3)]
+        Pt.cg_solve(fs[0], tau=TAU, tol=1e-6, maxit=5)   # warm the path
+        res = {"plain": [], "learned": []}
+        for c, f in enumerate(fs):
+            torch.cuda.synchronize()
+            t0 = time.time()
+            r0 = Pt.cg_solve(f, tau=TAU, tol=1e-6, maxit=500)
+            torch.cuda.synchronize()
+            res["plain"].append((r0["iters"], (time.time() - t0) * 1e3, r0["relres"]))
+            if net is not None:
+                net.attach(Pt, c)
+                torch.cuda.synchronize()
+                t0 = time.time()
+                r1 = Pt.cg_solve(f, tau=TAU, tol=1e-6, maxit=500, warm=nfl.WARM_MLP)
+                torch.cuda.synchronize()
+                res["learned"].append((r1["iters"], (time.time() - t0) * 1e3, r1["relres"]))
+                du = (r1["u"] - r0["u"]).abs().max().item() / r0["u"].abs().max().item()
+                res.setdefault("rel_diff_solution", []).append(du)
+
+        def summ(rs):
+            if not rs:
+                return None
+            return {"iters": [r[0] for r in rs], "ms": [round(r[1], 2) for r in rs],
+                    "mean_iters": float(np.mean([r[0] for r in rs])),
+                    "mean_ms": round(float(np.mean([r[1] for r in rs])), 3),
+                    "max_true_relres": float(max(r[2] for r in rs))}
+        cg = {"tau": TAU, "tol": 1e-6, "cloud_seed": 100001,
+              "rhs": "one-vs-rest, 2% labelled, classes 0..2",
+              "plain": summ(res["plain"]), "learned": summ(res["learned"]),
+              "learned_vs_plain_solution_rel_diff": res.get("rel_diff_solution")}
+        log("CG plain: %s" % cg["plain"])
+        log("CG learned: %s" % cg["learned"])
+        Pt.close()
 
     # --- CPU oracle baseline (bounded sample) ----------------------------------
     cpu = None

@@ -45,6 +45,7 @@ extern "C" {
 #define NFL_ERR_UNSUPPORTED -6  /* valid for the method, not supported by this build (e.g. N not a power of 2) */
 
 typedef struct nfl_plan *nfl_handle;
+typedef struct nfl_mlp *nfl_mlp_handle;
 
 /* Options for nfl_set_option (take effect at the next nfl_set_kernel). */
 #define NFL_OPT_P          1   /* regularisation smoothness p of K_R (Fig. tab:fastsum_param); default p = m */
@@ -126,6 +127,44 @@ int nfl_lanczos_smallest(nfl_handle h, int k, int block, double tol, int maxit,
  * nfl_mlp_*).  Synchronises. */
 int nfl_cg_solve(nfl_handle h, double tau, const double *f_dev, double *u_dev, int warm,
                  double tol, int maxit, int *iters, double *relres);
+
+/* ---- learned warm start for nfl_cg_solve ------------------------------------
+ * A pointwise network u0_i = net(features_i) predicts the solution of the
+ * kernel-SSL system (eq. ssl::system) node by node; CG then runs to tolerance
+ * from u0, so the network only changes the starting point.  Features of node
+ * i: its position in the scaled torus coordinates (times 4), its right-hand
+ * side f_i, d_E,i / mean(d_E), and a one-hot class index (one-vs-rest problems).
+ * Architecture: 16 -> 64 -> 64 -> 64 -> 1 with tanh, BF16 matrix-core
+ * operands, FP32 accumulation, FP32 master weights, Adam.  Parameter vector
+ * (9473 floats): W1[64][16], b1[64], W2[64][64], b2[64], W3[64][64], b3[64],
+ * W4[64], b4.  A network is independent of any plan; calls that take a plan
+ * read its nodes and degrees.  All calls synchronise the network's stream. */
+int nfl_mlp_create(nfl_mlp_handle *m, int n_classes, uint64_t seed, void *hip_stream);
+int nfl_mlp_destroy(nfl_mlp_handle m);
+/* One Adam step (learning rate lr) on nsample nodes of plan h drawn with seed:
+ * inputs f_dev (right-hand side) and u_dev (target solution), n doubles each,
+ * caller order; loss_host (may be NULL) receives the mean squared error
+ * before the step. */
+int nfl_mlp_train_step(nfl_mlp_handle m, nfl_handle h, const double *f_dev, const double *u_dev,
+                       int cls, int64_t nsample, uint64_t seed, double lr, double *loss_host);
+/* u_dev = net(features) for every node of h (caller order, doubles). */
+int nfl_mlp_predict(nfl_mlp_handle m, nfl_handle h, const double *f_dev, int cls, double *u_dev);
+/* Attach (m != NULL) or detach the network used by nfl_cg_solve(..., NFL_WARM_MLP),
+ * with the class index of the right-hand sides that will be solved. */
+int nfl_mlp_attach(nfl_handle h, nfl_mlp_handle m, int cls);
+/* Save / load the parameters (flat little-endian file: 8-byte magic, 4 int32
+ * header, 9473 float32).  Loading resets the optimiser state. */
+int nfl_mlp_save(nfl_mlp_handle m, const char *path);
+int nfl_mlp_load(nfl_mlp_handle m, const char *path);
+int nfl_mlp_get_params(nfl_mlp_handle m, float *params_host, int64_t count);
+int nfl_mlp_set_params(nfl_mlp_handle m, const float *params_host, int64_t count);
+/* Explicit-feature entry points (for testing): feat_dev is B x 16 float32
+ * row-major.  forward: out_dev = B network outputs.  gradient: the gradient
+ * of the mean squared error (1/B) sum (out - target)^2 with respect to the
+ * 9473 parameters (host) and the loss. */
+int nfl_mlp_forward(nfl_mlp_handle m, const float *feat_dev, int64_t B, float *out_dev);
+int nfl_mlp_gradient(nfl_mlp_handle m, const float *feat_dev, const float *target_dev, int64_t B,
+                     float *grad_host, int64_t count, double *loss_host);
 
 /* Plan information (host outputs, any may be NULL): rho, sigma_tilde = rho*sigma,
  * min and max of d_E, and eps_B / p actually used.  Synchronises. */

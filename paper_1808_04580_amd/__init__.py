@@ -59,6 +59,17 @@ SIGNATURES = {
     "nfl_compute_filter": (_i, [_i, _i, _i, _i, _d, _d, _p, _i64]),
     "nfl_profile_stages": (_i, [_p, _p, _p, _i, _p]),
     "nfl_window_coefficients": (_i, [_i, _p, _i64]),
+    "nfl_mlp_create": (_i, [ctypes.POINTER(_p), _i, ctypes.c_uint64, _p]),
+    "nfl_mlp_destroy": (_i, [_p]),
+    "nfl_mlp_train_step": (_i, [_p, _p, _p, _p, _i, _i64, ctypes.c_uint64, _d, _p]),
+    "nfl_mlp_predict": (_i, [_p, _p, _p, _i, _p]),
+    "nfl_mlp_attach": (_i, [_p, _p, _i]),
+    "nfl_mlp_save": (_i, [_p, ctypes.c_char_p]),
+    "nfl_mlp_load": (_i, [_p, ctypes.c_char_p]),
+    "nfl_mlp_get_params": (_i, [_p, _p, _i64]),
+    "nfl_mlp_set_params": (_i, [_p, _p, _i64]),
+    "nfl_mlp_forward": (_i, [_p, _p, _i64, _p]),
+    "nfl_mlp_gradient": (_i, [_p, _p, _p, _i64, _p, _i64, _p]),
     "nfl_strerror": (ctypes.c_char_p, [_i]),
     "nfl_last_error": (ctypes.c_char_p, []),
 }
@@ -290,3 +301,85 @@ def plan(points, sigma: float, N: int, m: int, eps_B: float = 0.0, stream=None, 
     P.set_points(v)
     P.set_kernel(sigma, N, m, eps_B)
     return P
+
+
+MLP_NP = 9473
+
+
+class WarmStart:
+    """The pointwise warm-start network (BF16 matrix-core MLP) for cg_solve."""
+
+    def __init__(self, n_classes: int = 3, seed: int = 0, stream=None):
+        import torch
+        self._torch = torch
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.device = self.stream.device
+        h = _p()
+        _check(lib().nfl_mlp_create(ctypes.byref(h), n_classes, seed, _p(self.stream.cuda_stream)),
+               "nfl_mlp_create")
+        self._h = h
+        self.n_classes = n_classes
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().nfl_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self) -> np.ndarray:
+        out = np.empty(MLP_NP, dtype=np.float32)
+        _check(lib().nfl_mlp_get_params(self._h, out.ctypes.data_as(_p), MLP_NP), "nfl_mlp_get_params")
+        return out
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(np.asarray(p, dtype=np.float32))
+        _check(lib().nfl_mlp_set_params(self._h, p.ctypes.data_as(_p), p.size), "nfl_mlp_set_params")
+
+    def forward(self, feat):
+        torch = self._torch
+        f = torch.as_tensor(feat, dtype=torch.float32, device=self.device).contiguous()
+        out = torch.empty(f.shape[0], dtype=torch.float32, device=self.device)
+        _check(lib().nfl_mlp_forward(self._h, _ptr(f), int(f.shape[0]), _ptr(out)), "nfl_mlp_forward")
+        return out
+
+    def gradient(self, feat, target):
+        torch = self._torch
+        f = torch.as_tensor(feat, dtype=torch.float32, device=self.device).contiguous()
+        t = torch.as_tensor(target, dtype=torch.float32, device=self.device).contiguous()
+        g = np.empty(MLP_NP, dtype=np.float32)
+        loss = ctypes.c_double()
+        _check(lib().nfl_mlp_gradient(self._h, _ptr(f), _ptr(t), int(f.shape[0]),
+                                      g.ctypes.data_as(_p), MLP_NP, ctypes.byref(loss)),
+               "nfl_mlp_gradient")
+        return loss.value, g
+
+    def train_step(self, plan: "Plan", f, u, cls: int, nsample: int, seed: int, lr: float) -> float:
+        torch = self._torch
+        f = torch.as_tensor(f, dtype=torch.float64, device=self.device).contiguous()
+        u = torch.as_tensor(u, dtype=torch.float64, device=self.device).contiguous()
+        loss = ctypes.c_double()
+        _check(lib().nfl_mlp_train_step(self._h, plan._h, _ptr(f), _ptr(u), int(cls), int(nsample),
+                                        int(seed), float(lr), ctypes.byref(loss)),
+               "nfl_mlp_train_step")
+        return loss.value
+
+    def predict(self, plan: "Plan", f, cls: int):
+        torch = self._torch
+        f = torch.as_tensor(f, dtype=torch.float64, device=self.device).contiguous()
+        u = torch.empty_like(f)
+        _check(lib().nfl_mlp_predict(self._h, plan._h, _ptr(f), int(cls), _ptr(u)), "nfl_mlp_predict")
+        return u
+
+    def attach(self, plan: "Plan", cls: int):
+        _check(lib().nfl_mlp_attach(plan._h, self._h, int(cls)), "nfl_mlp_attach")
+
+    def save(self, path: str):
+        _check(lib().nfl_mlp_save(self._h, path.encode()), "nfl_mlp_save")
+
+    def load(self, path: str):
+        _check(lib().nfl_mlp_load(self._h, path.encode()), "nfl_mlp_load")

@@ -18,10 +18,6 @@ void set_error(const std::string &msg) { g_last_error = msg; }
 int compute_filter(int d, int N, int m, int p, double eps_B, double sigma_t,
                    std::vector<double> &out);
 
-// The learned warm start is attached by nfl_mlp_*; without a trained model a
-// warm start of mode NFL_WARM_MLP is a call-order error.
-int mlp_warm_start(nfl_plan *P, const double *f_sorted, double *u_sorted);
-
 static bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
 
 static int check_vec_args(nfl_plan *P, const void *x, const void *y, int nvec, int64_t ld) {
@@ -39,13 +35,15 @@ static int degree_stats(nfl_plan *P) {
   NFL_HIP(hipMemcpyAsync(h.data(), P->deg.p, (size_t)P->n * sizeof(float), hipMemcpyDeviceToHost,
                          P->stream));
   NFL_HIP(hipStreamSynchronize(P->stream));
-  double lo = INFINITY, hi = -INFINITY;
+  double lo = INFINITY, hi = -INFINITY, sum = 0.0;
   for (float v : h) {
     lo = std::fmin(lo, (double)v);
     hi = std::fmax(hi, (double)v);
+    sum += (double)v;
   }
   P->dmin = lo;
   P->dmax = hi;
+  P->dmean = sum / (double)h.size();
   return NFL_OK;
 }
 
@@ -392,12 +390,3 @@ const char *nfl_last_error(void) { return g_last_error.c_str(); }
 
 }  // extern "C"
 
-namespace nfl {
-int mlp_warm_start(nfl_plan *P, const double *f_sorted, double *u_sorted) {
-  (void)P;
-  (void)f_sorted;
-  (void)u_sorted;
-  set_error("no warm-start network attached to this plan");
-  return NFL_ERR_ORDER;
-}
-}  // namespace nfl

@@ -478,7 +478,19 @@ __global__ __launch_bounds__(VT) void k_sub64(const double *__restrict__ f,
     r[i] = f[i] - t[i];
 }
 
-int mlp_warm_start(nfl_plan *P, const double *f_sorted, double *u_sorted);
+int gather64(nfl_plan *P, const double *src, double *dst) {
+  hipLaunchKernelGGL(k_gather64, dim3(grid_for(P->n)), dim3(VT), 0, P->stream, src, P->perm.p,
+                     P->n, dst);
+  NFL_HIP(hipGetLastError());
+  return NFL_OK;
+}
+
+int scatter64(nfl_plan *P, const double *src, double *dst) {
+  hipLaunchKernelGGL(k_scatter64, dim3(grid_for(P->n)), dim3(VT), 0, P->stream, src, P->perm.p,
+                     P->n, dst);
+  NFL_HIP(hipGetLastError());
+  return NFL_OK;
+}
 
 int cg(nfl_plan *P, double tau, const double *f_dev, double *u_dev, int warm, double tol,
        int maxit, int *iters, double *relres) {

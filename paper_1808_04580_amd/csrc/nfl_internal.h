@@ -122,7 +122,11 @@ struct nfl_plan {
   // degrees (sorted order)
   nfl::DBuf<float> deg;
   nfl::DBuf<float> dinv;        // d_E^{-1/2}
-  double dmin = 0, dmax = 0;
+  double dmin = 0, dmax = 0, dmean = 1;
+
+  // learned warm start attached with nfl_mlp_attach
+  nfl_mlp *mlp = nullptr;
+  int mlp_cls = 0;
 
   // stage profiling: when set, fastsum records events before the grid fill,
   // after it, after the spread kernel, after the convolution, after interp
@@ -187,5 +191,11 @@ int lanczos(nfl_plan *P, int k, int block, double tol, int maxit, double *evals_
             double *evecs_dev, int *iters, double *max_resid);
 int cg(nfl_plan *P, double tau, const double *f_dev, double *u_dev, int warm, double tol,
        int maxit, int *iters, double *relres);
+int gather64(nfl_plan *P, const double *src_user, double *dst_sorted);
+int scatter64(nfl_plan *P, const double *src_sorted, double *dst_user);
+
+// ---- learned warm start (mlp.hip) -------------------------------------------
+int mlp_warm_start(nfl_plan *P, const double *f_sorted, double *u_sorted);
+int mlp_forward_explicit(nfl_mlp *M, int64_t B, float *out);
 
 }  // namespace nfl

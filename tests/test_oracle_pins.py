@@ -236,3 +236,34 @@ def test_cg_matches_dense_solve():
     u, it, rel = krylov.cg(lambda p: M @ p, f, tol=1e-10, maxit=500)
     np.testing.assert_allclose(u, np.linalg.solve(M, f), atol=1e-8)
     assert rel <= 1e-10 and it < 200
+
+
+# ---- the warm-start network reference -----------------------------------------
+
+def test_mlp_gradient_matches_finite_differences():
+    """Analytic backward of the FP64 network against central differences."""
+    from oracle import mlp
+    rng = np.random.default_rng(0)
+    p = rng.normal(0, 0.3, size=mlp.NP)
+    X = rng.normal(size=(37, 16))
+    t = rng.normal(size=37)
+    L, g = mlp.loss_and_grad(p, X, t, emulate=False)
+    idx = np.concatenate([rng.choice(1024, 8), 1024 + rng.choice(64, 4), 1088 + rng.choice(4096, 8),
+                          5184 + rng.choice(64, 4), 5248 + rng.choice(4096, 8),
+                          9344 + rng.choice(64, 4), 9408 + rng.choice(64, 4), [9472]])
+    h = 1e-6
+    for i in idx:
+        e = np.zeros(mlp.NP)
+        e[i] = h
+        fd = (mlp.loss_and_grad(p + e, X, t, emulate=False)[0]
+              - mlp.loss_and_grad(p - e, X, t, emulate=False)[0]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])), (i, fd, g[i])
+
+
+def test_bf16_rounding_is_nearest_even():
+    from oracle import mlp
+    # 1 + 2^-8 is halfway between 1 and 1 + 2^-7: ties to even -> 1
+    assert mlp.bf16(1.0 + 2.0 ** -8) == 1.0
+    assert mlp.bf16(1.0 + 3 * 2.0 ** -8) == 1.0 + 2.0 ** -6
+    assert mlp.bf16(1.0 + 2.0 ** -7) == 1.0 + 2.0 ** -7
+    assert mlp.bf16(-3.0) == -3.0
