@@ -11,6 +11,13 @@ backward and the optimiser are the library's BF16 matrix-core kernels.
         --out paper_1808_04580_amd/warmstart_moons_roll.bin
 
 Training clouds use seeds 1..S; evaluation uses seeds from 100001 on.
+
+Loss "mse": mean squared error of u against u*.  Loss "energy": the energy
+norm e^T (I + tau L_s) e of the warm-start error e = u - u*, the quantity CG
+from u0 = u actually feels; its gradient with respect to the output at node i
+is 2 ((I + tau L_s) e)_i, which the mean-squared-error training step receives
+through the pseudo-target u_i - ((I + tau L_s) e)_i (one extra L_s product
+per step).
 """
 from __future__ import annotations
 
@@ -38,6 +45,9 @@ def main():
     ap.add_argument("--N", type=int, default=64)
     ap.add_argument("--m", type=int, default=6)
     ap.add_argument("--out", default=DEFAULT_OUT)
+    ap.add_argument("--loss", choices=["mse", "energy"], default="mse")
+    ap.add_argument("--init", default=None, help="start from these weights")
+    ap.add_argument("--first-seed", type=int, default=1)
     args = ap.parse_args()
 
     import numpy as np
@@ -48,10 +58,12 @@ def main():
 
     torch.cuda.set_device(0)
     net = nfl.WarmStart(n_classes=3, seed=0)
+    if args.init:
+        net.load(args.init)
     total = args.seeds * args.draws * 3
     step = 0
     t0 = time.time()
-    for s in range(1, args.seeds + 1):
+    for s in range(args.first_seed, args.first_seed + args.seeds):
         v, lab = synth.moons_and_roll(args.n, seed=s)
         P = nfl.plan(torch.as_tensor(v, device="cuda"), args.sigma, N=args.N, m=args.m)
         losses, iters = [], []
@@ -63,12 +75,19 @@ def main():
                 iters.append(r["iters"])
                 # cosine decay of the learning rate over all solves
                 lr = args.lr * 0.5 * (1 + np.cos(np.pi * step / total))
-                losses.append(net.train_step(P, fd, r["u"], c, args.nsample, step, lr))
+                target = r["u"]
+                if args.loss == "energy":
+                    u = net.predict(P, fd, c)
+                    e = (u - r["u"]).float()
+                    Me = e.double() + args.tau * P.apply_Ls(e).double()
+                    target = u - Me
+                losses.append(net.train_step(P, fd, target, c, args.nsample, step, lr))
                 step += 1
         P.close()
-        if s == 1 or s % 5 == 0 or s == args.seeds:
+        k = s - args.first_seed + 1
+        if k == 1 or k % 5 == 0 or k == args.seeds:
             print("seed %d/%d  solves %d  mean CG iters %.1f  loss %.4g  %.0fs" % (
-                s, args.seeds, step, float(np.mean(iters)), float(np.mean(losses)),
+                k, args.seeds, step, float(np.mean(iters)), float(np.mean(losses)),
                 time.time() - t0), flush=True)
     net.save(args.out)
     print("saved", args.out, flush=True)

@@ -100,3 +100,30 @@ def test_cg_with_learned_warm_start_reaches_same_solution(nfl):
     u0 = plain["u"].cpu().numpy()
     u1 = warm["u"].cpu().numpy()
     assert np.abs(u0 - u1).max() <= 2e-5 * np.abs(u0).max()
+
+
+def test_trained_network_reduces_cg_iterations(nfl):
+    """The committed network (trained by paper_1808_04580_amd.train_warmstart on
+    clouds 1..100) on a held-out cloud: fewer CG iterations to 1e-6 than u0 = 0,
+    same solution."""
+    import os
+    import torch
+    import synth
+    path = os.path.join(os.path.dirname(nfl.__file__), "warmstart_moons_roll.bin")
+    v, lab = synth.moons_and_roll(1_000_000, seed=100002)
+    P = nfl.plan(torch.as_tensor(v, device="cuda"), 0.04, N=64, m=6)
+    W = nfl.WarmStart(n_classes=3)
+    W.load(path)
+    plain, warm = [], []
+    for c in range(3):
+        f = torch.as_tensor(synth.ssl_rhs(lab, c, frac=0.02, seed=300 + c), device="cuda")
+        r0 = P.cg_solve(f, tau=10.0, tol=1e-6, maxit=300)
+        W.attach(P, c)
+        r1 = P.cg_solve(f, tau=10.0, tol=1e-6, maxit=300, warm=nfl.WARM_MLP)
+        assert r0["converged"] and r1["converged"] and r1["relres"] <= 2e-6
+        u0, u1 = r0["u"].cpu().numpy(), r1["u"].cpu().numpy()
+        assert np.abs(u0 - u1).max() <= 2e-5 * np.abs(u0).max()
+        plain.append(r0["iters"])
+        warm.append(r1["iters"])
+    print("CG iterations plain", plain, "learned", warm)
+    assert np.mean(warm) < np.mean(plain), (plain, warm)
