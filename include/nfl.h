@@ -222,6 +222,47 @@ int nfl_compute_filter(int d, int N, int m, int p, double eps_B, double sigma_ti
 #define NFL_WIN_NC 10
 int nfl_window_coefficients(int m, float *coef_host, int64_t count);
 
+/* ---- batches: many graphs, a block of vectors each, one graph launch ---- */
+
+typedef struct nfl_batch_s *nfl_batch;
+
+/* Group nplans plans into a batch that applies y = L_s x (Alg.
+ * nfft_normalized_matvec, step 5) to nvec vectors of every plan at once.
+ * Each plan must have d = 3, the matrix-core kernels (NFL_OPT_KERNEL 0) and a
+ * successful nfl_set_kernel; plans may differ in n, sigma, N, m and tile.
+ * The batch reads the plans' sorted nodes, degrees and filters (it does not
+ * copy them), so every plan must outlive the batch and must not be changed
+ * (set_points / set_kernel / set_option) while it exists: apply then fails
+ * with NFL_ERR_ORDER.  The batch owns one grid and spectrum per (plan,
+ * vector) pair (nfl_batch_info reports the bytes) and records the whole
+ * product -- grid clear, one spread launch per window width, five FFT
+ * passes, one interpolation launch per width -- as a HIP graph at creation.
+ * hip_stream: the stream the graph is launched on (may be the null stream).
+ * 1 <= nvec <= 64. */
+int nfl_batch_create(nfl_batch *b, const nfl_handle *plans, int nplans, int nvec,
+                     void *hip_stream);
+
+/* Packed vector layout of a batch: offsets_host[g] = n_0 + ... + n_{g-1}
+ * (count >= nplans + 1; offsets_host[nplans] = total n).  Plan g's block
+ * occupies x[nvec * offsets[g] .. nvec * offsets[g+1]), vector j of it
+ * starting at nvec * offsets[g] + j * n_g, each vector in plan g's caller
+ * node order. */
+int nfl_batch_offsets(nfl_batch b, int64_t *offsets_host, int64_t count);
+
+/* y = L_s x for every (plan, vector) of the batch, packed as described at
+ * nfl_batch_offsets (nvec * total n float32 each; x and y must not
+ * overlap).  One graph launch, plus a one-thread kernel when x or y differs
+ * from the previous call.  Asynchronous on the batch's stream; two applies
+ * of one batch must not run concurrently (they share the grids). */
+int nfl_batch_apply_Ls(nfl_batch b, const float *x_dev, float *y_dev);
+
+/* Batch facts (any output may be NULL): total nodes, (plan, vector) jobs,
+ * kernels in one product, device bytes of the grids and spectra. */
+int nfl_batch_info(nfl_batch b, int64_t *total_n, int *njobs, int *nkernels,
+                   int64_t *arena_bytes);
+
+int nfl_batch_destroy(nfl_batch b);
+
 const char *nfl_strerror(int code);
 const char *nfl_last_error(void);
 

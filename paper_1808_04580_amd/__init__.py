@@ -70,6 +70,11 @@ SIGNATURES = {
     "nfl_mlp_set_params": (_i, [_p, _p, _i64]),
     "nfl_mlp_forward": (_i, [_p, _p, _i64, _p]),
     "nfl_mlp_gradient": (_i, [_p, _p, _p, _i64, _p, _i64, _p]),
+    "nfl_batch_create": (_i, [ctypes.POINTER(_p), _p, _i, _i, _p]),
+    "nfl_batch_offsets": (_i, [_p, _p, _i64]),
+    "nfl_batch_apply_Ls": (_i, [_p, _p, _p]),
+    "nfl_batch_info": (_i, [_p, _p, _p, _p, _p]),
+    "nfl_batch_destroy": (_i, [_p]),
     "nfl_strerror": (ctypes.c_char_p, [_i]),
     "nfl_last_error": (ctypes.c_char_p, []),
 }
@@ -301,6 +306,70 @@ def plan(points, sigma: float, N: int, m: int, eps_B: float = 0.0, stream=None, 
     P.set_points(v)
     P.set_kernel(sigma, N, m, eps_B)
     return P
+
+
+class Batch:
+    """Several d = 3 plans, nvec vectors each, applied together by one HIP
+    graph launch (nfl_batch_*).  The plans must stay alive and unchanged
+    while the batch exists; x and y use the packed layout of
+    nfl_batch_offsets: plan g's block is x[nvec*off[g] : nvec*off[g+1]],
+    vector j of it x[nvec*off[g] + j*n_g : ... + n_g]."""
+
+    def __init__(self, plans, nvec: int, stream=None):
+        import torch
+        self._torch = torch
+        self.plans = list(plans)
+        self.nvec = int(nvec)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        hs = (_p * len(self.plans))(*[P._h for P in self.plans])
+        h = _p()
+        _check(lib().nfl_batch_create(ctypes.byref(h), hs, len(self.plans), self.nvec,
+                                      _p(self.stream.cuda_stream)), "nfl_batch_create")
+        self._h = h
+        off = np.zeros(len(self.plans) + 1, dtype=np.int64)
+        _check(lib().nfl_batch_offsets(self._h, off.ctypes.data_as(_p), off.size), "nfl_batch_offsets")
+        self.offsets = off
+        self.total_n = int(off[-1])
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().nfl_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        tn, nb = ctypes.c_int64(), ctypes.c_int64()
+        nj, nk = ctypes.c_int(), ctypes.c_int()
+        _check(lib().nfl_batch_info(self._h, ctypes.byref(tn), ctypes.byref(nj), ctypes.byref(nk),
+                                    ctypes.byref(nb)), "nfl_batch_info")
+        return {"total_n": tn.value, "jobs": nj.value, "kernels": nk.value,
+                "arena_bytes": nb.value}
+
+    def pack(self, blocks):
+        """Packed float32 device vector from per-plan (nvec, n_g) blocks."""
+        t = self._torch
+        parts = [t.as_tensor(b, dtype=t.float32, device=self.stream.device).reshape(-1)
+                 for b in blocks]
+        return t.cat(parts).contiguous()
+
+    def unpack(self, y):
+        """Per-plan (nvec, n_g) views of a packed vector."""
+        return [y[self.nvec * int(a):self.nvec * int(b)].view(self.nvec, int(b - a))
+                for a, b in zip(self.offsets[:-1], self.offsets[1:])]
+
+    def apply_Ls(self, x, out=None):
+        t = self._torch
+        x = x.contiguous()
+        if x.dtype != t.float32 or x.numel() != self.nvec * self.total_n:
+            raise ValueError("x must be float32 with nvec * total_n elements")
+        y = out if out is not None else t.empty_like(x)
+        _check(lib().nfl_batch_apply_Ls(self._h, _ptr(x), _ptr(y)), "nfl_batch_apply_Ls")
+        return y
 
 
 MLP_NP = 9473

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnfl.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
-SOURCES = ["api.hip", "setup.hip", "nfft.hip", "krylov.hip", "mlp.hip"]
+SOURCES = ["api.hip", "setup.hip", "nfft.hip", "krylov.hip", "mlp.hip", "batch.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

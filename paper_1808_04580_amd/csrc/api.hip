@@ -95,6 +95,7 @@ int nfl_destroy(nfl_handle P) {
 
 int nfl_set_option(nfl_handle P, int opt, double value) {
   if (!P) { set_error("null handle"); return NFL_ERR_ARG; }
+  ++P->gen;
   switch (opt) {
     case NFL_OPT_P:
       if (value < 0 || value > 16 || value != std::floor(value)) { set_error("p must be 0 (= m) or 1..16"); return NFL_ERR_ARG; }
@@ -126,6 +127,7 @@ int nfl_set_points(nfl_handle P, int64_t n, const float *v_dev) {
   if (n < 2) { set_error("need n >= 2 points"); return NFL_ERR_ARG; }
   if (n > (int64_t)1 << 30) { set_error("n above 2^30 is not supported"); return NFL_ERR_UNSUPPORTED; }
   if (!v_dev) { set_error("null point pointer"); return NFL_ERR_ARG; }
+  ++P->gen;
   P->have_points = false;
   P->have_kernel = false;
   P->n = n;
@@ -150,6 +152,7 @@ int nfl_set_kernel(nfl_handle P, double sigma, int N, int m, double eps_B) {
   if (!is_pow2(N) || N < 8 || N > 256) { set_error("this build needs N a power of 2 in [8, 256]"); return NFL_ERR_UNSUPPORTED; }
   if (m < 2 || m > 8) { set_error("this build supports 2 <= m <= 8"); return NFL_ERR_UNSUPPORTED; }
   if (2 * m > N) { set_error("window wider than half the grid (need m <= N/2)"); return NFL_ERR_UNSUPPORTED; }
+  ++P->gen;
   P->have_kernel = false;
   P->sigma = sigma;
   P->N = N;

@@ -1,0 +1,594 @@
+// Device code shared by the single-graph and the batched NFFT kernels:
+// window polynomials, input/output operations, the matrix-core spread and
+// interpolation bodies (d = 3) and the LDS FFT line transforms.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "nfl_internal.h"
+
+namespace nfl {
+
+// ---------------------------------------------------------------------------
+// Window.  The Kaiser-Bessel window psi(t) = sinh(b s)/(s b e^{bm}),
+// s = sqrt(m^2 - t^2), t in (-m, m] (grid units), is applied as 2m
+// polynomials, one per grid offset c of a node's window:
+//   psi(c - (m-1) - f) = sum_k coef[c][k] g^k,  g = 2f - 1,
+// where f in [0, 1) is the node's fraction inside its cell.  The host fits the
+// coefficients (FP64, rounded to float32) and deconvolves with the exact
+// transform of this piecewise polynomial.
+// ---------------------------------------------------------------------------
+template <int NC>
+__device__ __forceinline__ float win_poly(const float (&cf)[NC], float f) {
+  const float g = fmaf(2.f, f, -1.f);
+  float p = cf[NC - 1];
+#pragma unroll
+  for (int k = NC - 2; k >= 0; --k) p = fmaf(p, g, cf[k]);
+  return p;
+}
+
+__device__ __forceinline__ void load_coef(const float *__restrict__ wcoef, int c, float (&cf)[WIN_NC]) {
+#pragma unroll
+  for (int k = 0; k < WIN_NC; ++k) cf[k] = wcoef[c * WIN_NC + k];
+}
+
+struct KArgs {
+  const float *x32;
+  float *y32;
+  const double *x64;
+  double *y64;
+  double tau;
+  const int *perm;
+  const float *dinv;
+  float *deg_out;
+  float *dinv_out;
+};
+
+template <int IN>
+__device__ __forceinline__ float load_in(const KArgs &a, int i) {
+  if constexpr (IN == IN_USER_F32) return a.x32[a.perm[i]];
+  else if constexpr (IN == IN_USER_F32_DINV) return a.dinv[i] * a.x32[a.perm[i]];
+  else if constexpr (IN == IN_ONES) return 1.0f;
+  else if constexpr (IN == IN_SORTED_F32) return a.x32[i];
+  else return (float)((double)a.dinv[i] * a.x64[i]);
+}
+
+template <int OUT>
+__device__ __forceinline__ void store_out(const KArgs &a, int i, float f) {
+  if constexpr (OUT == OUT_USER_RAW) {
+    a.y32[a.perm[i]] = f;
+  } else if constexpr (OUT == OUT_USER_W) {
+    const int j = a.perm[i];
+    a.y32[j] = f - a.x32[j];
+  } else if constexpr (OUT == OUT_USER_LS) {
+    const int j = a.perm[i];
+    const float xu = a.x32[j], di = a.dinv[i];
+    const float xt = di * xu;
+    a.y32[j] = xu - di * (f - xt);
+  } else if constexpr (OUT == OUT_USER_A) {
+    const int j = a.perm[i];
+    const float di = a.dinv[i];
+    const float xt = di * a.x32[j];
+    a.y32[j] = di * (f - xt);
+  } else if constexpr (OUT == OUT_DEGREE) {
+    const float dg = f - 1.0f;
+    a.deg_out[i] = dg;
+    a.dinv_out[i] = dg > 0.f ? 1.0f / __builtin_sqrtf(dg) : 0.f;
+  } else if constexpr (OUT == OUT_SORTED_F64_A) {
+    const double di = (double)a.dinv[i];
+    const float xt = (float)(di * a.x64[i]);
+    a.y64[i] = di * ((double)f - (double)xt);
+  } else {
+    const double di = (double)a.dinv[i];
+    const double xv = a.x64[i];
+    const float xt = (float)(di * xv);
+    const double av = di * ((double)f - (double)xt);
+    a.y64[i] = xv + a.tau * (xv - av);
+  }
+}
+
+__device__ __forceinline__ float readlane_f(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+
+// ---------------------------------------------------------------------------
+// d = 3 spread and interpolation on the matrix cores.
+//
+// Nodes are processed in sub-batches of 16.  Per sub-batch each lane l
+// evaluates, for node l%16, the window polynomials of the offsets
+// 4 (l/16) .. 4 (l/16) + 3 on all three axes (12 Horner evaluations) and writes
+// them to a per-wave weight table wt[node][axis][offset] in LDS (the x value
+// of the node rides along in wt[node][3][0]).  The matrix-core loop then reads
+// its operands from the table with independent broadcast loads.
+// ---------------------------------------------------------------------------
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Weight-table row pitch (floats per node): 80 for the spread, whose reads
+// touch 4 node rows x 16 columns (rows 16 banks apart), 65 for the interp,
+// whose reads touch 16 node rows in the same column (rows 1 bank apart).
+constexpr int WT_SPREAD = 80, WT_INTERP = 65;
+
+// x-pitch of an LDS tile with P^3 logical cells: >= P*P and = 4 (mod 32), so
+// that 16 consecutive x-offsets land on distinct bank quadruples.
+__host__ __device__ __forceinline__ int tile_px(int P) { return P * P + ((4 - P * P) % 32 + 32) % 32; }
+
+// Fill the weight table for the 16 nodes sub*16 .. sub*16+15 of the current
+// 64-node batch held in registers (lane l holds node l of the batch: record
+// qb, input value xb); cnt = valid nodes of the sub-batch.  Returns, in every
+// lane, the packed cell of sub-batch node (lane % 16).
+template <int W, bool WITH_X, int STRIDE>
+__device__ __forceinline__ uint32_t fill_weights(const float4 &qb, float xb, int sub, int cnt,
+                                                 int lane, const float (&cf)[4][WIN_NC],
+                                                 float *wt) {
+  const int node = lane & 15, part = lane >> 4;
+  const int src = sub * 16 + min(node, cnt - 1);
+  const float qx = __shfl(qb.x, src), qy = __shfl(qb.y, src), qz = __shfl(qb.z, src);
+  const uint32_t cell = node < cnt ? (uint32_t)__shfl((int)__float_as_uint(qb.w), src) : 0xffffffffu;
+  float *w = wt + node * STRIDE;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int o = 4 * part + u;
+    w[0 * 16 + o] = win_poly(cf[u], qx);
+    w[1 * 16 + o] = win_poly(cf[u], qy);
+    w[2 * 16 + o] = win_poly(cf[u], qz);
+  }
+  if (WITH_X) {
+    const float xv = __shfl(xb, src);
+    if (part == 0) w[3 * 16] = xv;
+  }
+  return cell;
+}
+
+// One 64-node batch of sorted records (and, for the spread, input values),
+// loaded one per lane; past the end: zero records.
+template <int IN, bool WITH_X>
+__device__ __forceinline__ void load_batch(const float4 *__restrict__ pts, const KArgs &ka, int i0,
+                                           int e, int lane, float4 &qb, float &xb) {
+  qb = make_float4(0.f, 0.f, 0.f, 0.f);
+  xb = 0.f;
+  if (i0 + lane < e) {
+    qb = pts[i0 + lane];
+    if (WITH_X) xb = load_in<IN>(ka, i0 + lane);
+  }
+}
+
+// Spread: for the nodes p of one grid cell
+//   G[ax][ay][az] += sum_p (x_p wx_p[ax]) (wy_p[ay] wz_p[az])
+// with v_mfma_f32_16x16x4_f32: rows = x-offsets ax (W of 16 used), K = 4
+// nodes, columns = z-offsets (and, for W <= 8, S = 16/WP y-offsets packed
+// side by side), NB column blocks, one per y-offset group.  Lane l (node slot
+// l/16, column l%16) accumulates D[ax = 4 (l/16) + r][column l%16], r < 4, in
+// registers over a run of nodes, then adds it into its wave's PRIVATE copy of
+// the padded tile (plain read-add-write: every lane of a flush owns a
+// distinct cell, and the LDS operations of one wave are ordered).  At the end
+// the four private tiles are summed and added into the grid.
+//
+// ZM ("z-merge", needs T + W - 1 <= 16): the 16 columns cover the whole
+// z-extent of the padded tile, so nodes of different cells of one (x, y)
+// column of the tile share the accumulators: node p contributes to column c
+// with wz_p[c - lz_p] (lz_p = its cell's z inside the tile) and runs, hence
+// flushes, are per (x, y) column instead of per cell.
+template <int W, bool ZM>
+struct SpreadShape {
+  static constexpr int WP = ZM ? 16 : (W <= 4 ? 4 : (W <= 8 ? 8 : 16));
+  static constexpr int S = 16 / WP;
+  static constexpr int NB = (W + S - 1) / S;
+};
+
+template <int W, int IN, bool ZM>
+__device__ __forceinline__ void spread3_mfma_body(const Item it, const float4 *__restrict__ pts,
+                                                  const KArgs ka, float *__restrict__ grid,
+                                                  int nos, int tshift,
+                                                  const float *__restrict__ wcoef) {
+  constexpr int M = W / 2;
+  constexpr int WP = SpreadShape<W, ZM>::WP, S = SpreadShape<W, ZM>::S,
+                NB = SpreadShape<W, ZM>::NB;
+  extern __shared__ float lds[];
+  const int T = 1 << tshift, P = T + W - 1, PX = tile_px(P), P3 = PX * P;
+  const int ntd = nos >> tshift;
+  const int tz = it.tile % ntd, ty = (it.tile / ntd) % ntd, tx = it.tile / (ntd * ntd);
+  const int ox = tx * T, oy = ty * T, oz = tz * T;
+  for (int c = threadIdx.x; c < 4 * P3; c += 256) lds[c] = 0.f;
+  __syncthreads();
+
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int c16 = lane & 15, p4 = lane >> 4;
+  const int sub = c16 / WP, az = c16 % WP;
+  float *tile = lds + wave * P3;
+  float *wt = lds + 4 * P3 + wave * (16 * WT_SPREAD);
+  const int len = it.end - it.start, per = (len + 3) >> 2;
+  const int s = it.start + min(len, wave * per), e = it.start + min(len, (wave + 1) * per);
+  // run key: the cell, or with ZM its (x, y) column
+  const uint32_t keymask = ZM ? 0x000fffffu : 0xffffffffu;
+
+  float cf[4][WIN_NC];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int o = 4 * p4 + u;
+#pragma unroll
+    for (int k = 0; k < WIN_NC; ++k) cf[u][k] = o < W ? wcoef[o * WIN_NC + k] : 0.f;
+  }
+  f32x4 acc[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  uint32_t cur = 0xffffffffu;
+
+  // add the accumulators of the run `cell` into the private tile
+  auto flush = [&](uint32_t cell) {
+    const int lx = (int)(cell & 1023u) - ox, ly = (int)((cell >> 10) & 1023u) - oy;
+    const int lz = ZM ? 0 : (int)(cell >> 20) - oz;
+    const bool zok = ZM ? (az < P) : (az < W);
+    float old[NB][4];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int ay = S * nb + sub;
+      const float *base = tile + lx * PX + (ly + ay) * P + lz + az;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ax = 4 * p4 + r;
+        old[nb][r] = (zok && ay < W && ax < W) ? base[ax * PX] : 0.f;
+      }
+    }
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int ay = S * nb + sub;
+      float *base = tile + lx * PX + (ly + ay) * P + lz + az;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ax = 4 * p4 + r;
+        if (zok && ay < W && ax < W) base[ax * PX] = old[nb][r] + acc[nb][r];
+      }
+      acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+  };
+
+  float4 qb, qn;
+  float xb, xn;
+  load_batch<IN, true>(pts, ka, s, e, lane, qb, xb);
+  for (int b0 = s; b0 < e; b0 += 64) {
+    load_batch<IN, true>(pts, ka, b0 + 64, e, lane, qn, xn);  // prefetch the next batch
+    const int bcnt = min(64, e - b0);
+    for (int sb = 0; sb * 16 < bcnt; ++sb) {
+      const int cnt = min(16, bcnt - sb * 16);
+      const int cellv = (int)fill_weights<W, true, WT_SPREAD>(qb, xb, sb, cnt, lane, cf, wt);
+      wave_sync_lds();
+      int j = 0;
+      while (j < cnt) {
+        const uint32_t key = (uint32_t)__builtin_amdgcn_readlane(cellv, j) & keymask;
+        if (key != cur) {
+          if (cur != 0xffffffffu) flush(cur);
+          cur = key;
+        }
+        int k = 1;
+        while (k < 4 && j + k < cnt &&
+               ((uint32_t)__builtin_amdgcn_readlane(cellv, j + k) & keymask) == key)
+          ++k;
+        const int node = j + min(p4, k - 1);
+        const float *w = wt + node * WT_SPREAD;
+        const float xv = p4 < k ? w[3 * 16] : 0.f;
+        const float a = xv * w[c16 & 15];
+        float wz;
+        if (ZM) {
+          const int lzp = (int)((uint32_t)__shfl(cellv, node) >> 20) - oz;
+          const int o = az - lzp;
+          wz = (o >= 0 && o < W) ? w[2 * 16 + o] : 0.f;
+        } else {
+          wz = w[2 * 16 + (az & 15)];
+        }
+        float by[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) by[nb] = w[16 + S * nb + sub];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, by[nb] * wz, acc[nb], 0, 0, 0);
+        j += k;
+      }
+      wave_sync_lds();
+    }
+    qb = qn;
+    xb = xn;
+  }
+  if (cur != 0xffffffffu) flush(cur);
+  __syncthreads();
+
+  // sum the private tiles and add into the grid: each wave takes rows (px, py)
+  // of the tile, 64 / ZL rows at a time with ZL >= P lanes along z
+  const int mask = nos - 1;
+  const int ZL = P <= 16 ? 16 : (P <= 32 ? 32 : 64), RL = 64 / ZL;
+  const int pz = lane % ZL, rsub = lane / ZL;
+  for (int row0 = wave * RL; row0 < P * P; row0 += 4 * RL) {
+    const int row = row0 + rsub;
+    if (row < P * P && pz < P) {
+      const int px = row / P, py = row - px * P;
+      const int o = px * PX + py * P + pz;
+      const float v = (lds[o] + lds[P3 + o]) + (lds[2 * P3 + o] + lds[3 * P3 + o]);
+      if (v != 0.f) {
+        const int gx = (ox - (M - 1) + px) & mask, gy = (oy - (M - 1) + py) & mask,
+                  gz = (oz - (M - 1) + pz) & mask;
+        unsafeAtomicAdd(&grid[((size_t)gx * nos + gy) * nos + gz], v);
+      }
+    }
+  }
+}
+
+// Interpolation, the transpose of the spread: for up to 16 nodes p of one cell
+//   D[ax][p] = sum_ay wy_p[ay] sum_az G[ax][ay][az] wz_p[az],  f_p = sum_ax wx_p[ax] D[ax][p],
+// rows = x-offsets, columns = nodes, K over (ay, 4 consecutive az) in W * KZ
+// steps (KZ = ceil(W/4)).  The cell's window G, read from the workgroup's
+// shared LDS copy of the padded tile, is the register-resident A operand:
+// lane l holds G[ax = l%16][ay][4 t + l/16].
+template <int W, int IN, int OUT>
+__device__ __forceinline__ void interp3_mfma_body(const Item *__restrict__ items, int item,
+                                                  const float4 *__restrict__ pts,
+                                                  const KArgs ka,
+                                                  const float *__restrict__ grid, int nos,
+                                                  int tshift,
+                                                  const float *__restrict__ wcoef) {
+  constexpr int M = W / 2, KZ = (W + 3) / 4, NQ = W * KZ;
+  extern __shared__ float lds[];
+  const int T = 1 << tshift, P = T + W - 1, PP = P * P, PX = tile_px(P), P3 = PX * P;
+  const Item it = items[item];
+  const int ntd = nos >> tshift;
+  const int tz = it.tile % ntd, ty = (it.tile / ntd) % ntd, tx = it.tile / (ntd * ntd);
+  const int ox = tx * T, oy = ty * T, oz = tz * T;
+  const int mask = nos - 1;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  {
+    // stage the padded tile: each wave takes rows (px, py), 64 / ZL at a time
+    const int ZL = P <= 16 ? 16 : (P <= 32 ? 32 : 64), RL = 64 / ZL;
+    const int pz = lane % ZL, rsub = lane / ZL;
+    for (int row0 = wave * RL; row0 < PP; row0 += 4 * RL) {
+      const int row = row0 + rsub;
+      if (row < PP && pz < P) {
+        const int px = row / P, py = row - px * P;
+        const int gx = (ox - (M - 1) + px) & mask, gy = (oy - (M - 1) + py) & mask,
+                  gz = (oz - (M - 1) + pz) & mask;
+        lds[px * PX + py * P + pz] = grid[((size_t)gx * nos + gy) * nos + gz];
+      }
+    }
+  }
+  __syncthreads();
+
+  const int c16 = lane & 15, k4 = lane >> 4;
+  float *wt = lds + P3 + wave * (16 * WT_INTERP);
+  const int len = it.end - it.start, per = (len + 3) >> 2;
+  const int s = it.start + min(len, wave * per), e = it.start + min(len, (wave + 1) * per);
+
+  float cf[4][WIN_NC];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int o = 4 * k4 + u;
+#pragma unroll
+    for (int k = 0; k < WIN_NC; ++k) cf[u][k] = o < W ? wcoef[o * WIN_NC + k] : 0.f;
+  }
+  float g[NQ];
+  uint32_t cur = 0xffffffffu;
+  float4 qb, qn;
+  float xb, xn;
+  load_batch<IN, false>(pts, ka, s, e, lane, qb, xb);
+  for (int b0 = s; b0 < e; b0 += 64) {
+    load_batch<IN, false>(pts, ka, b0 + 64, e, lane, qn, xn);  // prefetch the next batch
+    const int bcnt = min(64, e - b0);
+    for (int sb = 0; sb * 16 < bcnt; ++sb) {
+      const int cnt = min(16, bcnt - sb * 16);
+      const int i0 = b0 + sb * 16;
+      const int cellv = (int)fill_weights<W, false, WT_INTERP>(qb, xb, sb, cnt, lane, cf, wt);
+      wave_sync_lds();
+      int j = 0;
+      while (j < cnt) {
+        const uint32_t cell = (uint32_t)__builtin_amdgcn_readlane(cellv, j);
+        if (cell != cur) {
+          cur = cell;
+          const int lx = (int)(cell & 1023u) - ox, ly = (int)((cell >> 10) & 1023u) - oy,
+                    lz = (int)(cell >> 20) - oz;
+          const float *base = lds + (lx + c16) * PX + ly * P + lz;
+#pragma unroll
+          for (int ay = 0; ay < W; ++ay)
+#pragma unroll
+            for (int t = 0; t < KZ; ++t) {
+              const int zz = 4 * t + k4;
+              g[ay * KZ + t] = (c16 < W && zz < W) ? base[ay * P + zz] : 0.f;
+            }
+        }
+        int k = 1;
+        while (k < 16 && j + k < cnt && (uint32_t)__builtin_amdgcn_readlane(cellv, j + k) == cell) ++k;
+        const float *w = wt + (j + min(c16, k - 1)) * WT_INTERP;
+        float wyv[W], wzv[KZ], wxv[4];
+#pragma unroll
+        for (int ay = 0; ay < W; ++ay) wyv[ay] = w[16 + ay];
+#pragma unroll
+        for (int t = 0; t < KZ; ++t) wzv[t] = w[32 + ((4 * t + k4) & 15)];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) wxv[r] = w[(4 * k4 + r) & 15];
+        f32x4 d = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ay = 0; ay < W; ++ay)
+#pragma unroll
+          for (int t = 0; t < KZ; ++t)
+            d = __builtin_amdgcn_mfma_f32_16x16x4f32(g[ay * KZ + t], wyv[ay] * wzv[t], d, 0, 0, 0);
+        float part = 0.f;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (4 * k4 + r < W) part = fmaf(wxv[r], d[r], part);
+        part += __shfl_xor(part, 16);
+        part += __shfl_xor(part, 32);
+        if (k4 == 0 && c16 < k) store_out<OUT>(ka, i0 + j + c16, part);
+        j += k;
+      }
+      wave_sync_lds();
+    }
+    qb = qn;
+    xb = xn;
+  }
+}
+
+
+// ---------------------------------------------------------------------------
+// FFT: radix-2 Stockham in LDS on `nl` lines of length L = nos.  The twiddle
+// table holds e^{-2 pi i k/L}, k < L/2; SIGN = +1 gives the inverse
+// (unnormalised) transform.  Result returned in `a` (buffers are swapped).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+template <int SIGN>
+__device__ void lds_fft(float2 *&a, float2 *&b, int L, int logL, int nl,
+                        const float2 *__restrict__ tw) {
+  const int half_n = L >> 1;
+  for (int s = 0; s < logL; ++s) {
+    const int half = 1 << s;
+    for (int idx = threadIdx.x; idx < nl * half_n; idx += blockDim.x) {
+      const int line = idx >> (logL - 1), j = idx & (half_n - 1);
+      const int k = j & (half - 1), g = j >> s;
+      float2 w = tw[k << (logL - 1 - s)];
+      if (SIGN > 0) w.y = -w.y;
+      const float2 x0 = a[line * L + j], x1 = a[line * L + j + half_n];
+      const float2 t = cmul(w, x1);
+      const int o = line * L + (g << (s + 1)) + k;
+      b[o] = make_float2(x0.x + t.x, x0.y + t.y);
+      b[o + half] = make_float2(x0.x - t.x, x0.y - t.y);
+    }
+    __syncthreads();
+    float2 *tmp = a;
+    a = b;
+    b = tmp;
+  }
+}
+
+constexpr int FFT_THREADS = 256, FFT_ELEMS = 2048;
+
+// Real lines along the last (contiguous) axis -> half spectrum lz in [0, Hz).
+__device__ __forceinline__ void r2c_lines_body(int blk, const float *__restrict__ grid,
+                                               float2 *__restrict__ H, int nlines, int L,
+                                               int logL, int lpb, int Hz,
+                                               const float2 *__restrict__ tw) {
+  extern __shared__ float2 sm[];
+  float2 *a = sm, *b = sm + lpb * L;
+  const int l0 = blk * lpb;
+  const int nl = min(lpb, nlines - l0);
+  for (int idx = threadIdx.x; idx < lpb * L; idx += FFT_THREADS) {
+    const int li = idx / L;
+    a[idx] = make_float2(li < nl ? grid[(size_t)l0 * L + idx] : 0.f, 0.f);
+  }
+  __syncthreads();
+  lds_fft<-1>(a, b, L, logL, lpb, tw);
+  for (int idx = threadIdx.x; idx < nl * Hz; idx += FFT_THREADS) {
+    const int li = idx / Hz, lz = idx - li * Hz;
+    H[(size_t)(l0 + li) * Hz + lz] = a[li * L + lz];
+  }
+}
+
+// Half spectrum (lz in [0, Hz), Hermitian in lz) -> real lines.
+__device__ __forceinline__ void c2r_lines_body(int blk, const float2 *__restrict__ H,
+                                               float *__restrict__ grid, int nlines, int L,
+                                               int logL, int lpb, int Hz,
+                                               const float2 *__restrict__ tw) {
+  extern __shared__ float2 sm[];
+  float2 *a = sm, *b = sm + lpb * L;
+  const int l0 = blk * lpb;
+  const int nl = min(lpb, nlines - l0);
+  for (int idx = threadIdx.x; idx < lpb * L; idx += FFT_THREADS) a[idx] = make_float2(0.f, 0.f);
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < nl * Hz; idx += FFT_THREADS) {
+    const int li = idx / Hz, lz = idx - li * Hz;
+    const float2 h = H[(size_t)(l0 + li) * Hz + lz];
+    a[li * L + lz] = h;
+    if (lz > 0) a[li * L + L - lz] = make_float2(h.x, -h.y);
+  }
+  __syncthreads();
+  lds_fft<+1>(a, b, L, logL, lpb, tw);
+  for (int idx = threadIdx.x; idx < nl * L; idx += FFT_THREADS)
+    grid[(size_t)l0 * L + idx] = a[idx].x;
+}
+
+// d = 3 middle axis (y), forward: H1[(x*L + y)*Hz + lz] -> H2[(x*F + y')*Hz + lz],
+// keeping ly = y' - N/2 in [-N/2, N/2].
+__device__ __forceinline__ void y_fwd_body(int blk, const float2 *__restrict__ H1,
+                                           float2 *__restrict__ H2, int L, int logL, int lpb,
+                                           int Hz, int N, const float2 *__restrict__ tw) {
+  extern __shared__ float2 sm[];
+  float2 *a = sm, *b = sm + lpb * L;
+  const int ngroups = (Hz + lpb - 1) / lpb;
+  const int x = blk / ngroups, lz0 = (blk % ngroups) * lpb;
+  const int nl = min(lpb, Hz - lz0);
+  const int F = N + 1;
+  for (int idx = threadIdx.x; idx < lpb * L; idx += FFT_THREADS) {
+    const int y = idx / lpb, li = idx - y * lpb;
+    a[li * L + y] = li < nl ? H1[((size_t)x * L + y) * Hz + lz0 + li] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  lds_fft<-1>(a, b, L, logL, lpb, tw);
+  for (int idx = threadIdx.x; idx < F * nl; idx += FFT_THREADS) {
+    const int yp = idx / nl, li = idx - yp * nl;
+    const int ly = (yp - N / 2 + L) & (L - 1);
+    H2[((size_t)x * F + yp) * Hz + lz0 + li] = a[li * L + ly];
+  }
+}
+
+__device__ __forceinline__ void y_inv_body(int blk, const float2 *__restrict__ H2,
+                                           float2 *__restrict__ H1, int L, int logL, int lpb,
+                                           int Hz, int N, const float2 *__restrict__ tw) {
+  extern __shared__ float2 sm[];
+  float2 *a = sm, *b = sm + lpb * L;
+  const int ngroups = (Hz + lpb - 1) / lpb;
+  const int x = blk / ngroups, lz0 = (blk % ngroups) * lpb;
+  const int nl = min(lpb, Hz - lz0);
+  const int F = N + 1;
+  for (int idx = threadIdx.x; idx < lpb * L; idx += FFT_THREADS) a[idx] = make_float2(0.f, 0.f);
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < F * nl; idx += FFT_THREADS) {
+    const int yp = idx / nl, li = idx - yp * nl;
+    const int ly = (yp - N / 2 + L) & (L - 1);
+    a[li * L + ly] = H2[((size_t)x * F + yp) * Hz + lz0 + li];
+  }
+  __syncthreads();
+  lds_fft<+1>(a, b, L, logL, lpb, tw);
+  for (int idx = threadIdx.x; idx < lpb * L; idx += FFT_THREADS) {
+    const int y = idx / lpb, li = idx - y * lpb;
+    if (li < nl) H1[((size_t)x * L + y) * Hz + lz0 + li] = a[li * L + y];
+  }
+}
+
+// First axis (x): forward FFT, multiply by the filter on lx in [-N/2, N/2]
+// (zero elsewhere), inverse FFT.  Hx[x*C + c], filter[(lx + N/2)*C + c].
+__device__ __forceinline__ void x_filter_body(int blk, float2 *__restrict__ Hx,
+                                              const float *__restrict__ filt, int C, int L,
+                                              int logL, int lpb, int N,
+                                              const float2 *__restrict__ tw) {
+  extern __shared__ float2 sm[];
+  float2 *a = sm, *b = sm + lpb * L;
+  const int c0 = blk * lpb;
+  const int nl = min(lpb, C - c0);
+  for (int idx = threadIdx.x; idx < lpb * L; idx += FFT_THREADS) {
+    const int x = idx / lpb, li = idx - x * lpb;
+    a[li * L + x] = li < nl ? Hx[(size_t)x * C + c0 + li] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  lds_fft<-1>(a, b, L, logL, lpb, tw);
+  for (int idx = threadIdx.x; idx < lpb * L; idx += FFT_THREADS) {
+    const int li = idx / L, x = idx - li * L;
+    const int lx = x < L / 2 ? x : x - L;
+    float f = 0.f;
+    if (li < nl && lx >= -N / 2 && lx <= N / 2) f = filt[(size_t)(lx + N / 2) * C + c0 + li];
+    a[idx].x *= f;
+    a[idx].y *= f;
+  }
+  __syncthreads();
+  lds_fft<+1>(a, b, L, logL, lpb, tw);
+  for (int idx = threadIdx.x; idx < lpb * L; idx += FFT_THREADS) {
+    const int x = idx / lpb, li = idx - x * lpb;
+    if (li < nl) Hx[(size_t)x * C + c0 + li] = a[li * L + x];
+  }
+}
+
+}  // namespace nfl

@@ -83,6 +83,7 @@ struct nfl_plan {
   int d = 0;
   hipStream_t stream = nullptr;
   int device = 0;
+  uint64_t gen = 0;             // bumped by every call that changes the plan
 
   // points
   int64_t n = 0;
