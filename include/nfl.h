@@ -222,6 +222,37 @@ int nfl_compute_filter(int d, int N, int m, int p, double eps_B, double sigma_ti
 #define NFL_WIN_NC 10
 int nfl_window_coefficients(int m, float *coef_host, int64_t count);
 
+/* ---- accuracy probe and parameter search ---------------------------------- */
+
+/* Exact sums on sampled rows by a direct FP64 GPU kernel over all n points
+ * (the definitions of Section 2, zero diagonal): for each r < nrows with
+ * j = rows_host[r] (caller order, 0 <= j < n),
+ *   wx_host[r]  = sum_{i != j} exp(-||v_j - v_i||^2 / sigma^2) x_i,
+ *   deg_host[r] = sum_{i != j} exp(-||v_j - v_i||^2 / sigma^2).
+ * wx_host or deg_host may be NULL (x_dev may be NULL when wx_host is).
+ * Needs nfl_set_points only; 1 <= nrows <= 65535.  O(nrows * n) work.
+ * Synchronises. */
+int nfl_direct_rows(nfl_handle h, double sigma, const float *x_dev, const int64_t *rows_host,
+                    int nrows, double *wx_host, double *deg_host);
+
+/* Choose N, m, eps_B and the tile for this plan's points and sigma so that
+ * max(rel_inf(d), rel_inf(W x)) on nrows seeded sampled rows (x uniform in
+ * [-1, 1)) against nfl_direct_rows stays <= target, at the smallest product
+ * time: smallest N (eps_B in {0, 1/16, 1/8}, widest window), then smallest m,
+ * then the fastest tile in {4, 8, 16} (the paper's defaults of Section 3.2
+ * are the starting point of this search, not its result).  The plan is left
+ * set to the chosen configuration (as after nfl_set_kernel).  cache_path
+ * (may be NULL): a text file of results keyed by (d, floor(log4 n),
+ * floor(2 log2 sigma~), target); a cached configuration is verified on this
+ * plan with the same probe and re-tuned if it misses.  Outputs (any may be
+ * NULL): N, m, eps_B, tile, the probe error, ms per L_s product, cached =
+ * 1 if the configuration came from the cache.  Returns NFL_NOT_CONVERGED
+ * (plan set to the most accurate configuration tried) when no configuration
+ * reaches the target.  Synchronises; runs many products. */
+int nfl_autotune(nfl_handle h, double sigma, double target, int nrows, uint64_t seed,
+                 const char *cache_path, int *N, int *m, double *eps_B, int *tile,
+                 double *err, double *ms, int *cached);
+
 /* ---- batches: many graphs, a block of vectors each, one graph launch ---- */
 
 typedef struct nfl_batch_s *nfl_batch;

@@ -70,6 +70,9 @@ SIGNATURES = {
     "nfl_mlp_set_params": (_i, [_p, _p, _i64]),
     "nfl_mlp_forward": (_i, [_p, _p, _i64, _p]),
     "nfl_mlp_gradient": (_i, [_p, _p, _p, _i64, _p, _i64, _p]),
+    "nfl_direct_rows": (_i, [_p, _d, _p, _p, _i, _p, _p]),
+    "nfl_autotune": (_i, [_p, _d, _d, _i, ctypes.c_uint64, ctypes.c_char_p, _p, _p, _p, _p, _p,
+                          _p, _p]),
     "nfl_batch_create": (_i, [ctypes.POINTER(_p), _p, _i, _i, _p]),
     "nfl_batch_offsets": (_i, [_p, _p, _i64]),
     "nfl_batch_apply_Ls": (_i, [_p, _p, _p]),
@@ -285,6 +288,33 @@ class Plan:
         f = torch.empty(self.n, dtype=torch.float32, device=self.device)
         _check(lib().nfl_interp(self._h, _ptr(g.contiguous()), _ptr(f)), "nfl_interp")
         return f
+
+    def direct_rows(self, sigma: float, rows, x=None):
+        """Exact (W x)_j and d_j on the given caller-order rows (GPU, FP64):
+        returns (wx or None, deg) as float64 numpy arrays."""
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        deg = np.empty(rows.size, dtype=np.float64)
+        wx = np.empty(rows.size, dtype=np.float64) if x is not None else None
+        xp = _ptr(x.contiguous()) if x is not None else None
+        _check(lib().nfl_direct_rows(self._h, float(sigma), xp, rows.ctypes.data_as(_p), rows.size,
+                                     wx.ctypes.data_as(_p) if wx is not None else None,
+                                     deg.ctypes.data_as(_p)), "nfl_direct_rows")
+        return wx, deg
+
+    def autotune(self, sigma: float, target: float = 1e-5, rows: int = 256, seed: int = 1,
+                 cache: str | None = None) -> dict:
+        """Search (N, m, eps_B, tile) for this plan (nfl_autotune); the plan is
+        left set to the result."""
+        N, m, tile, cached = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        eps, err, ms = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        code = _check(lib().nfl_autotune(self._h, float(sigma), float(target), int(rows), int(seed),
+                                         cache.encode() if cache else None, ctypes.byref(N),
+                                         ctypes.byref(m), ctypes.byref(eps), ctypes.byref(tile),
+                                         ctypes.byref(err), ctypes.byref(ms), ctypes.byref(cached)),
+                      "nfl_autotune", allow_soft=True)
+        return {"N": N.value, "m": m.value, "eps_B": eps.value, "tile": tile.value,
+                "err": err.value, "ms": ms.value, "cached": bool(cached.value),
+                "reached": code == NFL_OK}
 
     def filter(self) -> np.ndarray:
         N = self._N
