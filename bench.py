@@ -12,9 +12,13 @@ resident in HBM.  Also reported:
   * CG time-to-tolerance for (I + 10 L_s) u = f at relative residual 1e-6,
     plain (u0 = 0) and, when a trained warm-start network is available,
     learned;
-  * the oracle timed on the host cores on a bounded sample (cpu_baseline).
+  * the oracle timed on the host cores on a bounded sample (cpu_baseline);
+  * the batched workload: 64 Gaussian-mixture graphs of uneven size, each
+    autotuned to rel err 1e-5, L_s on 8 vectors per graph in one graph
+    launch, against the same products issued plan by plan.
 
-Usage: python bench.py [--gpus 1] [--steps 200] [--warmup 10] [--no-cpu]
+Usage: python bench.py [--gpus 1] [--steps 200] [--warmup 10] [--no-cpu] [--no-cg]
+                       [--no-batched]
 """
 from __future__ import annotations
 
@@ -39,6 +43,105 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def kernel_src_sha1():
+    """SHA-1 of the sources of the spread / FFT / interpolation kernels."""
+    import hashlib
+    h = hashlib.sha1()
+    for f in ("nfft.hip", "nfft_device.h"):
+        h.update(open(os.path.join(ROOT, "paper_1808_04580_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
+def batched_leg(nfl, synth, torch, dev, graphs=64, nvec=8, reps=20):
+    """64 Gaussian-mixture graphs (n log-uniform in [1e3, 2e5], sigma U[0.03,
+    0.15]), each autotuned to rel err 1e-5 (cached configurations verified per
+    graph), L_s applied to 8 vectors per graph by one graph launch."""
+    from oracle import graph
+    cache = os.path.join(ROOT, "paper_1808_04580_amd", "autotune_cache.txt")
+    clouds = synth.batched_clouds(graphs, seed=0)
+    plans, cfg = [], []
+    t0 = time.time()
+    for g, (v, sigma) in enumerate(clouds):
+        P = nfl.Plan(3)
+        P.set_points(torch.as_tensor(v, device=dev))
+        r = P.autotune(sigma, target=1e-5, rows=256, seed=g + 1,
+                       cache=cache if os.path.exists(cache) else None)
+        if not r["reached"]:
+            raise RuntimeError("graph %d: no configuration reaches 1e-5 (%s)" % (g, r))
+        plans.append(P)
+        cfg.append(r)
+    tune_s = time.time() - t0
+    B = nfl.Batch(plans, nvec)
+    xs = [synth.normal_vectors(len(v), nvec=nvec, seed=1000 + g) for g, (v, _) in enumerate(clouds)]
+    X = B.pack(xs)
+    Y = torch.empty_like(X)
+    for _ in range(3):
+        B.apply_Ls(X, out=Y)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(B.stream)
+    for _ in range(reps):
+        B.apply_Ls(X, out=Y)
+    e1.record(B.stream)
+    torch.cuda.synchronize()
+    ms_batch = e0.elapsed_time(e1) / reps
+    # the same products issued plan by plan (8 vectors per call)
+    Xs = [torch.as_tensor(x, device=dev) for x in xs]
+    Ys = [torch.empty_like(x) for x in Xs]
+    for P, x, y in zip(plans, Xs, Ys):
+        P.apply_Ls(x, out=y)
+    torch.cuda.synchronize()
+    e0.record(plans[0].stream)
+    for _ in range(3):
+        for P, x, y in zip(plans, Xs, Ys):
+            P.apply_Ls(x, out=y)
+    e1.record(plans[0].stream)
+    torch.cuda.synchronize()
+    ms_seq = e0.elapsed_time(e1) / 3
+    Yb = B.unpack(Y)
+    diff = max(float((Yb[g] - Ys[g]).abs().max() / Ys[g].abs().max()) for g in range(graphs))
+    # the tuned operators against the FP64 direct oracle on sampled rows of
+    # W x and d, for the smallest, median and largest graph
+    rng = np.random.default_rng(11)
+    sizes = np.array([len(v) for v, _ in clouds])
+    acc = []
+    for g in sorted({int(sizes.argmin()), int(np.argsort(sizes)[graphs // 2]), int(sizes.argmax())}):
+        v, sigma = clouds[g]
+        rows = np.sort(rng.choice(len(v), size=min(64, len(v)), replace=False))
+        x = xs[g][0].astype(np.float64)
+        yW = plans[g].apply_W(Xs[g][0]).cpu().numpy().astype(np.float64)[rows]
+        dg = plans[g].degree().cpu().numpy().astype(np.float64)[rows]
+        rW = graph.w_rows(v, sigma, x, rows)
+        rd = graph.degree(v, sigma, rows)
+        acc.append({"graph": g, "n": len(v), "rows": int(rows.size),
+                    "rel_inf_deg": float(np.abs(dg - rd).max() / np.abs(rd).max()),
+                    "rel_inf_Wx": float(np.abs(yW - rW).max() / np.abs(rW).max())})
+    info = B.info()
+    hist = {}
+    for r in cfg:
+        key = "N%d_m%d_T%d" % (r["N"], r["m"], r["tile"])
+        hist[key] = hist.get(key, 0) + 1
+    out = {
+        "workload": "64 GMM graphs, d=3, n log-uniform [1e3, 2e5] (total %d), sigma U[0.03, 0.15], "
+                    "8 FP32 vectors each, L_s by one HIP graph launch" % info["total_n"],
+        "ms_per_batch": round(ms_batch, 4),
+        "vector_matvecs_per_s": round(graphs * nvec / (ms_batch * 1e-3), 1),
+        "node_vector_products_per_s": round(info["total_n"] * nvec / (ms_batch * 1e-3), 1),
+        "ms_plan_by_plan": round(ms_seq, 4),
+        "speedup_vs_plan_by_plan": round(ms_seq / ms_batch, 2),
+        "kernels_per_batch": info["kernels"], "arena_bytes": info["arena_bytes"],
+        "tune_s": round(tune_s, 2), "cache_hits": int(sum(r["cached"] for r in cfg)),
+        "configs": hist, "max_probe_err": max(r["err"] for r in cfg),
+        "batch_vs_single_rel_diff": diff, "oracle_rows": acc,
+    }
+    log("batched: %s" % {k: out[k] for k in ("ms_per_batch", "ms_plan_by_plan", "tune_s",
+                                             "cache_hits", "configs")})
+    B.close()
+    for P in plans:
+        P.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -47,6 +150,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-cg", action="store_true")
     ap.add_argument("--rows", type=int, default=256, help="sampled rows for the accuracy check")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-graph batched leg")
     ap.add_argument("--profile-run", action="store_true",
                     help="short run for hardware counters: a few products and a 256 MiB "
                          "device copy (the reference for scaling byte counters); no JSON")
@@ -121,8 +225,7 @@ def main():
         import hashlib
         try:
             rec = json.load(open(prof_json))
-            src = os.path.join(ROOT, "paper_1808_04580_amd", "csrc", "nfft.hip")
-            if rec.get("nfft_hip_sha1") == hashlib.sha1(open(src, "rb").read()).hexdigest():
+            if rec.get("kernel_src_sha1") == kernel_src_sha1():
                 traffic = rec.get(dom)
         except Exception:
             traffic = None
@@ -194,6 +297,11 @@ def main():
         log("CG learned: %s" % cg["learned"])
         Pt.close()
 
+    # --- many graphs, 8 vectors each, one graph launch ----------------------------
+    batched = None
+    if not args.no_batched:
+        batched = batched_leg(nfl, synth, torch, dev)
+
     # --- CPU oracle baseline (bounded sample) ----------------------------------
     cpu = None
     if not args.no_cpu:
@@ -227,6 +335,7 @@ def main():
         "cg": cg,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batched": batched,
     }
     print(json.dumps(out), flush=True)
     P.close()

@@ -36,7 +36,8 @@ struct BJob {
   float2 *spec1;
   float2 *spec2;
   int64_t xoff;   // offset of this job's vector in the packed x / y
-  int nos, N, tshift, logL, lpb, pad;
+  int nos, N, tshift, logL;
+  int lpz, lpy, lpx, pad;   // FFT lines per workgroup: z, y and x passes
 };
 
 struct BItem {
@@ -97,16 +98,17 @@ __device__ __forceinline__ int find_job(const int *__restrict__ first, int njobs
 
 enum { FFT_R2C = 0, FFT_YF = 1, FFT_XF = 2, FFT_YI = 3, FFT_C2R = 4, FFT_STAGES = 5 };
 
-// Workgroups one job needs in each FFT pass (same split as the single-plan
-// convolution: lpb lines of length L per workgroup).
-static int fft_blocks(int stage, int L, int N, int lpb) {
+// Workgroups one job needs in each FFT pass.  As the single-plan convolution,
+// except for the x pass: with many jobs in flight, its workgroups take full
+// FFT_ELEMS / L columns instead of splitting one grid finely.
+static int fft_blocks(int stage, int L, int N) {
   const int Hz = N / 2 + 1, F = N + 1;
   switch (stage) {
     case FFT_R2C:
-    case FFT_C2R: return (L * L + lpb - 1) / lpb;
+    case FFT_C2R: return (L * L + fft_lpb_z(L) - 1) / fft_lpb_z(L);
     case FFT_YF:
-    case FFT_YI: return L * ((Hz + lpb - 1) / lpb);
-    default: return (F * Hz + lpb - 1) / lpb;
+    case FFT_YI: return L * ((Hz + fft_lpb_y(L) - 1) / fft_lpb_y(L));
+    default: return (F * Hz + fft_lpb_z(L) - 1) / fft_lpb_z(L);
   }
 }
 
@@ -119,15 +121,15 @@ __global__ __launch_bounds__(FFT_THREADS) void kb_fft(const int *__restrict__ fi
   const int lb = blk - __builtin_amdgcn_readfirstlane(first[j]);
   const int L = J.nos, N = J.N, Hz = N / 2 + 1;
   if constexpr (STAGE == FFT_R2C)
-    r2c_lines_body(lb, J.grid, J.spec1, L * L, L, J.logL, J.lpb, Hz, J.tw);
+    r2c_lines_body(lb, J.grid, J.spec1, L * L, L, J.logL, J.lpz, Hz, J.tw);
   else if constexpr (STAGE == FFT_YF)
-    y_fwd_body(lb, J.spec1, J.spec2, L, J.logL, J.lpb, Hz, N, J.tw);
+    y_fwd_body(lb, J.spec1, J.spec2, L, J.logL, J.lpy, Hz, N, J.tw);
   else if constexpr (STAGE == FFT_XF)
-    x_filter_body(lb, J.spec2, J.filt, (N + 1) * Hz, L, J.logL, J.lpb, N, J.tw);
+    x_filter_body(lb, J.spec2, J.filt, (N + 1) * Hz, L, J.logL, J.lpx, N, J.tw);
   else if constexpr (STAGE == FFT_YI)
-    y_inv_body(lb, J.spec2, J.spec1, L, J.logL, J.lpb, Hz, N, J.tw);
+    y_inv_body(lb, J.spec2, J.spec1, L, J.logL, J.lpy, Hz, N, J.tw);
   else
-    c2r_lines_body(lb, J.spec1, J.grid, L * L, L, J.logL, J.lpb, Hz, J.tw);
+    c2r_lines_body(lb, J.spec1, J.grid, L * L, L, J.logL, J.lpz, Hz, J.tw);
 }
 
 // One launch of the spread or interpolation kernels: all jobs of one window
@@ -190,7 +192,7 @@ static int launch_group(const BGroup &g, const BItem *list, const BJob *jobs, co
 
 template <int STAGE>
 static int launch_fft(const int *first, int njobs, int nblocks, const BJob *jobs, hipStream_t s) {
-  constexpr size_t lds = (size_t)2 * FFT_ELEMS * sizeof(float2);
+  constexpr size_t lds = ((size_t)2 * FFT_ELEMS + FFT_MAXL) * sizeof(float2);
   hipLaunchKernelGGL((kb_fft<STAGE>), dim3(nblocks), dim3(FFT_THREADS), lds, s, first, njobs,
                      jobs);
   NFL_HIP(hipGetLastError());
@@ -311,7 +313,9 @@ static int batch_build(nfl_batch_s *B) {
       J.N = P->N;
       J.tshift = P->tshift;
       J.logL = logL;
-      J.lpb = std::max(1, FFT_ELEMS / P->nos);
+      J.lpz = fft_lpb_z(P->nos);
+      J.lpy = fft_lpb_y(P->nos);
+      J.lpx = fft_lpb_z(P->nos);
     }
   }
 
@@ -369,7 +373,7 @@ static int batch_build(nfl_batch_s *B) {
     int64_t acc = 0;
     for (int q = 0; q < B->njobs; ++q) {
       hf[(size_t)st * (B->njobs + 1) + q] = (int)acc;
-      acc += fft_blocks(st, hj[q].nos, hj[q].N, hj[q].lpb);
+      acc += fft_blocks(st, hj[q].nos, hj[q].N);
     }
     if (acc > 0x7fffffff) { set_error("batch: FFT grid too large"); return NFL_ERR_UNSUPPORTED; }
     hf[(size_t)st * (B->njobs + 1) + B->njobs] = (int)acc;
@@ -428,7 +432,7 @@ int nfl_batch_create(nfl_batch *b, const nfl_handle *plans, int nplans, int nvec
     if (P->d != 3) { set_error("batch: plans must have d = 3"); return NFL_ERR_UNSUPPORTED; }
     if (P->opt_kernel != 0) { set_error("batch: plans must use the matrix-core kernels"); return NFL_ERR_UNSUPPORTED; }
     if (P->device != dev) { set_error("batch: plans on another device"); return NFL_ERR_ARG; }
-    if (P->nos > FFT_ELEMS) { set_error("batch: grid too large"); return NFL_ERR_UNSUPPORTED; }
+    if (P->nos > FFT_MAXL) { set_error("batch: grid too large"); return NFL_ERR_UNSUPPORTED; }
   }
   nfl_batch_s *B = new (std::nothrow) nfl_batch_s();
   if (!B) { set_error("host allocation failed"); return NFL_ERR_OOM; }

@@ -546,41 +546,41 @@ int convolve(nfl_plan *P, const float *gin, float *gout) {
   const int L = P->nos, N = P->N, Hz = N / 2 + 1, F = N + 1;
   int logL = 0;
   while ((1 << logL) < L) ++logL;
-  const int lpb = std::max(1, FFT_ELEMS / L);
-  const size_t lds = (size_t)2 * lpb * L * sizeof(float2);
+  const int lpz = fft_lpb_z(L);
+  const size_t ldz = fft_lds_bytes(lpz, L);
   const float2 *tw = P->tw.p;
   if (P->d == 1) {
-    hipLaunchKernelGGL(k_r2c_lines, dim3(1), dim3(FFT_THREADS), lds, P->stream, gin, P->spec1.p,
-                       1, L, logL, lpb, Hz, tw);
+    hipLaunchKernelGGL(k_r2c_lines, dim3(1), dim3(FFT_THREADS), ldz, P->stream, gin, P->spec1.p,
+                       1, L, logL, lpz, Hz, tw);
     hipLaunchKernelGGL(k_filter1, dim3(1), dim3(256), 0, P->stream, P->spec1.p, P->filt.p, Hz);
-    hipLaunchKernelGGL(k_c2r_lines, dim3(1), dim3(FFT_THREADS), lds, P->stream, P->spec1.p, gout,
-                       1, L, logL, lpb, Hz, tw);
+    hipLaunchKernelGGL(k_c2r_lines, dim3(1), dim3(FFT_THREADS), ldz, P->stream, P->spec1.p, gout,
+                       1, L, logL, lpz, Hz, tw);
   } else if (P->d == 2) {
     const int nlines = L;
-    const int nb = (nlines + lpb - 1) / lpb;
-    hipLaunchKernelGGL(k_r2c_lines, dim3(nb), dim3(FFT_THREADS), lds, P->stream, gin, P->spec1.p,
-                       nlines, L, logL, lpb, Hz, tw);
-    const int nbx = (Hz + lpb - 1) / lpb;
-    hipLaunchKernelGGL(k_x_filter, dim3(nbx), dim3(FFT_THREADS), lds, P->stream, P->spec1.p,
-                       P->filt.p, Hz, L, logL, lpb, N, tw);
-    hipLaunchKernelGGL(k_c2r_lines, dim3(nb), dim3(FFT_THREADS), lds, P->stream, P->spec1.p, gout,
-                       nlines, L, logL, lpb, Hz, tw);
+    const int nb = (nlines + lpz - 1) / lpz;
+    hipLaunchKernelGGL(k_r2c_lines, dim3(nb), dim3(FFT_THREADS), ldz, P->stream, gin, P->spec1.p,
+                       nlines, L, logL, lpz, Hz, tw);
+    hipLaunchKernelGGL(k_x_filter, dim3(Hz), dim3(FFT_THREADS), fft_lds_bytes(1, L), P->stream,
+                       P->spec1.p, P->filt.p, Hz, L, logL, 1, N, tw);
+    hipLaunchKernelGGL(k_c2r_lines, dim3(nb), dim3(FFT_THREADS), ldz, P->stream, P->spec1.p, gout,
+                       nlines, L, logL, lpz, Hz, tw);
   } else {
     const int nlines = L * L;
-    const int nb = (nlines + lpb - 1) / lpb;
-    hipLaunchKernelGGL(k_r2c_lines, dim3(nb), dim3(FFT_THREADS), lds, P->stream, gin, P->spec1.p,
-                       nlines, L, logL, lpb, Hz, tw);
-    const int ngroups = (Hz + lpb - 1) / lpb;
-    hipLaunchKernelGGL(k_y_fwd, dim3(L * ngroups), dim3(FFT_THREADS), lds, P->stream, P->spec1.p,
-                       P->spec2.p, L, logL, lpb, Hz, N, tw);
-    const int C = F * Hz;
-    const int nbx = (C + lpb - 1) / lpb;
-    hipLaunchKernelGGL(k_x_filter, dim3(nbx), dim3(FFT_THREADS), lds, P->stream, P->spec2.p,
-                       P->filt.p, C, L, logL, lpb, N, tw);
-    hipLaunchKernelGGL(k_y_inv, dim3(L * ngroups), dim3(FFT_THREADS), lds, P->stream, P->spec2.p,
-                       P->spec1.p, L, logL, lpb, Hz, N, tw);
-    hipLaunchKernelGGL(k_c2r_lines, dim3(nb), dim3(FFT_THREADS), lds, P->stream, P->spec1.p, gout,
-                       nlines, L, logL, lpb, Hz, tw);
+    const int nb = (nlines + lpz - 1) / lpz;
+    hipLaunchKernelGGL(k_r2c_lines, dim3(nb), dim3(FFT_THREADS), ldz, P->stream, gin, P->spec1.p,
+                       nlines, L, logL, lpz, Hz, tw);
+    const int lpy = fft_lpb_y(L), ngroups = (Hz + lpy - 1) / lpy;
+    const size_t ldy = fft_lds_bytes(lpy, L);
+    hipLaunchKernelGGL(k_y_fwd, dim3(L * ngroups), dim3(FFT_THREADS), ldy, P->stream, P->spec1.p,
+                       P->spec2.p, L, logL, lpy, Hz, N, tw);
+    const int C = F * Hz, lpx = fft_lpb_x(L);
+    hipLaunchKernelGGL(k_x_filter, dim3((C + lpx - 1) / lpx), dim3(FFT_THREADS),
+                       fft_lds_bytes(lpx, L), P->stream, P->spec2.p, P->filt.p, C, L, logL, lpx,
+                       N, tw);
+    hipLaunchKernelGGL(k_y_inv, dim3(L * ngroups), dim3(FFT_THREADS), ldy, P->stream, P->spec2.p,
+                       P->spec1.p, L, logL, lpy, Hz, N, tw);
+    hipLaunchKernelGGL(k_c2r_lines, dim3(nb), dim3(FFT_THREADS), ldz, P->stream, P->spec1.p, gout,
+                       nlines, L, logL, lpz, Hz, tw);
   }
   NFL_HIP(hipGetLastError());
   return NFL_OK;

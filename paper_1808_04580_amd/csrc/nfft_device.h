@@ -433,30 +433,81 @@ __device__ __forceinline__ void interp3_mfma_body(const Item *__restrict__ items
 
 
 // ---------------------------------------------------------------------------
-// FFT: radix-2 Stockham in LDS on `nl` lines of length L = nos.  The twiddle
-// table holds e^{-2 pi i k/L}, k < L/2; SIGN = +1 gives the inverse
-// (unnormalised) transform.  Result returned in `a` (buffers are swapped).
+// FFT: Stockham autosort in LDS on `nl` lines of length L = nos (a power of
+// 2), radix-4 passes and one radix-2 pass when log2 L is odd.  A pass that
+// merges r sub-transforms of length m reads x_t = a[j + t L/r] (t < r),
+// multiplies by w^{t k} (w = e^{-2 pi i/(r m)}, k = j mod m), takes the
+// r-point DFT over t and writes output u to b[(j/m) r m + u m + k].  The
+// twiddles come from an LDS table twl[k] = e^{-2 pi i k/L}, k < L, which each
+// kernel fills from the global half table (e^{-2 pi i k/L}, k < L/2) before
+// its first barrier.  SIGN = +1 gives the inverse (unnormalised) transform.
+// The result is returned in `a` (buffers are swapped).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
+constexpr int FFT_THREADS = 256, FFT_ELEMS = 2048, FFT_MAXL = 512;
+
+__device__ __forceinline__ void load_twiddles(float2 *twl, const float2 *__restrict__ tw, int L) {
+  for (int k = threadIdx.x; k < L / 2; k += FFT_THREADS) {
+    const float2 w = tw[k];
+    twl[k] = w;
+    twl[k + L / 2] = make_float2(-w.x, -w.y);
+  }
+}
+
 template <int SIGN>
 __device__ void lds_fft(float2 *&a, float2 *&b, int L, int logL, int nl,
-                        const float2 *__restrict__ tw) {
-  const int half_n = L >> 1;
-  for (int s = 0; s < logL; ++s) {
-    const int half = 1 << s;
-    for (int idx = threadIdx.x; idx < nl * half_n; idx += blockDim.x) {
-      const int line = idx >> (logL - 1), j = idx & (half_n - 1);
-      const int k = j & (half - 1), g = j >> s;
-      float2 w = tw[k << (logL - 1 - s)];
-      if (SIGN > 0) w.y = -w.y;
-      const float2 x0 = a[line * L + j], x1 = a[line * L + j + half_n];
-      const float2 t = cmul(w, x1);
-      const int o = line * L + (g << (s + 1)) + k;
-      b[o] = make_float2(x0.x + t.x, x0.y + t.y);
-      b[o + half] = make_float2(x0.x - t.x, x0.y - t.y);
+                        const float2 *__restrict__ twl) {
+  int logm = 0;
+  while (logm < logL) {
+    const int m = 1 << logm;
+    if (logL - logm >= 2) {
+      const int Lr = L >> 2, sh = logL - 2 - logm;
+      for (int idx = threadIdx.x; idx < nl * Lr; idx += FFT_THREADS) {
+        const int line = idx >> (logL - 2), j = idx & (Lr - 1);
+        const int k = j & (m - 1), g = j >> logm;
+        const float2 *src = a + line * L + j;
+        const float2 x0 = src[0];
+        float2 x1 = src[Lr], x2 = src[2 * Lr], x3 = src[3 * Lr];
+        const int st = k << sh;
+        float2 w1 = twl[st], w2 = twl[2 * st], w3 = twl[3 * st];
+        if (SIGN > 0) {
+          w1.y = -w1.y;
+          w2.y = -w2.y;
+          w3.y = -w3.y;
+        }
+        x1 = cmul(x1, w1);
+        x2 = cmul(x2, w2);
+        x3 = cmul(x3, w3);
+        const float2 s02 = make_float2(x0.x + x2.x, x0.y + x2.y);
+        const float2 d02 = make_float2(x0.x - x2.x, x0.y - x2.y);
+        const float2 s13 = make_float2(x1.x + x3.x, x1.y + x3.y);
+        const float2 d13 = make_float2(x1.x - x3.x, x1.y - x3.y);
+        // -i d13 (forward) or +i d13 (inverse)
+        const float2 rd = SIGN < 0 ? make_float2(d13.y, -d13.x) : make_float2(-d13.y, d13.x);
+        float2 *dst = b + line * L + (g << (logm + 2)) + k;
+        dst[0] = make_float2(s02.x + s13.x, s02.y + s13.y);
+        dst[m] = make_float2(d02.x + rd.x, d02.y + rd.y);
+        dst[2 * m] = make_float2(s02.x - s13.x, s02.y - s13.y);
+        dst[3 * m] = make_float2(d02.x - rd.x, d02.y - rd.y);
+      }
+      logm += 2;
+    } else {
+      const int half_n = L >> 1;
+      for (int idx = threadIdx.x; idx < nl * half_n; idx += FFT_THREADS) {
+        const int line = idx >> (logL - 1), j = idx & (half_n - 1);
+        const int k = j & (m - 1), g = j >> logm;
+        float2 w = twl[k << (logL - 1 - logm)];
+        if (SIGN > 0) w.y = -w.y;
+        const float2 x0 = a[line * L + j], x1 = a[line * L + j + half_n];
+        const float2 t = cmul(w, x1);
+        const int o = line * L + (g << (logm + 1)) + k;
+        b[o] = make_float2(x0.x + t.x, x0.y + t.y);
+        b[o + m] = make_float2(x0.x - t.x, x0.y - t.y);
+      }
+      logm += 1;
     }
     __syncthreads();
     float2 *tmp = a;
@@ -465,7 +516,29 @@ __device__ void lds_fft(float2 *&a, float2 *&b, int L, int logL, int nl,
   }
 }
 
-constexpr int FFT_THREADS = 256, FFT_ELEMS = 2048;
+// LDS of one FFT workgroup: two buffers of lpb lines and the twiddle table.
+__host__ __device__ __forceinline__ size_t fft_lds_bytes(int lpb, int L) {
+  return ((size_t)2 * lpb * L + L) * 8;
+}
+
+// Lines per workgroup of each pass for lines of length L, N = L/2:
+//   z passes (r2c / c2r): FFT_ELEMS / L lines;
+//   y passes: the Hz = N/2 + 1 columns split into equal groups of at most
+//     FFT_ELEMS / L;
+//   x pass: enough workgroups (>= 512) for the (N+1)(N/2+1) columns.
+__host__ __device__ __forceinline__ int fft_lpb_z(int L) { return L >= FFT_ELEMS ? 1 : FFT_ELEMS / L; }
+__host__ __device__ __forceinline__ int fft_lpb_y(int L) {
+  const int Hz = L / 4 + 1, mx = fft_lpb_z(L);
+  const int groups = (Hz + mx - 1) / mx;
+  return (Hz + groups - 1) / groups;
+}
+__host__ __device__ __forceinline__ int fft_lpb_x(int L) {
+  const int C = (L / 2 + 1) * (L / 4 + 1);
+  int l = C / 512;
+  if (l < 1) l = 1;
+  const int mx = fft_lpb_z(L);
+  return l > mx ? mx : l;
+}
 
 // Real lines along the last (contiguous) axis -> half spectrum lz in [0, Hz).
 __device__ __forceinline__ void r2c_lines_body(int blk, const float *__restrict__ grid,
@@ -473,7 +546,8 @@ __device__ __forceinline__ void r2c_lines_body(int blk, const float *__restrict_
                                                int logL, int lpb, int Hz,
                                                const float2 *__restrict__ tw) {
   extern __shared__ float2 sm[];
-  float2 *a = sm, *b = sm + lpb * L;
+  float2 *a = sm, *b = sm + lpb * L, *twl = sm + 2 * lpb * L;
+  load_twiddles(twl, tw, L);
   const int l0 = blk * lpb;
   const int nl = min(lpb, nlines - l0);
   for (int idx = threadIdx.x; idx < lpb * L; idx += FFT_THREADS) {
@@ -481,7 +555,7 @@ __device__ __forceinline__ void r2c_lines_body(int blk, const float *__restrict_
     a[idx] = make_float2(li < nl ? grid[(size_t)l0 * L + idx] : 0.f, 0.f);
   }
   __syncthreads();
-  lds_fft<-1>(a, b, L, logL, lpb, tw);
+  lds_fft<-1>(a, b, L, logL, nl, twl);
   for (int idx = threadIdx.x; idx < nl * Hz; idx += FFT_THREADS) {
     const int li = idx / Hz, lz = idx - li * Hz;
     H[(size_t)(l0 + li) * Hz + lz] = a[li * L + lz];
@@ -494,10 +568,11 @@ __device__ __forceinline__ void c2r_lines_body(int blk, const float2 *__restrict
                                                int logL, int lpb, int Hz,
                                                const float2 *__restrict__ tw) {
   extern __shared__ float2 sm[];
-  float2 *a = sm, *b = sm + lpb * L;
+  float2 *a = sm, *b = sm + lpb * L, *twl = sm + 2 * lpb * L;
+  load_twiddles(twl, tw, L);
   const int l0 = blk * lpb;
   const int nl = min(lpb, nlines - l0);
-  for (int idx = threadIdx.x; idx < lpb * L; idx += FFT_THREADS) a[idx] = make_float2(0.f, 0.f);
+  for (int idx = threadIdx.x; idx < nl * L; idx += FFT_THREADS) a[idx] = make_float2(0.f, 0.f);
   __syncthreads();
   for (int idx = threadIdx.x; idx < nl * Hz; idx += FFT_THREADS) {
     const int li = idx / Hz, lz = idx - li * Hz;
@@ -506,28 +581,29 @@ __device__ __forceinline__ void c2r_lines_body(int blk, const float2 *__restrict
     if (lz > 0) a[li * L + L - lz] = make_float2(h.x, -h.y);
   }
   __syncthreads();
-  lds_fft<+1>(a, b, L, logL, lpb, tw);
+  lds_fft<+1>(a, b, L, logL, nl, twl);
   for (int idx = threadIdx.x; idx < nl * L; idx += FFT_THREADS)
     grid[(size_t)l0 * L + idx] = a[idx].x;
 }
 
 // d = 3 middle axis (y), forward: H1[(x*L + y)*Hz + lz] -> H2[(x*F + y')*Hz + lz],
-// keeping ly = y' - N/2 in [-N/2, N/2].
+// keeping ly = y' - N/2 in [-N/2, N/2]; lpb columns lz per workgroup.
 __device__ __forceinline__ void y_fwd_body(int blk, const float2 *__restrict__ H1,
                                            float2 *__restrict__ H2, int L, int logL, int lpb,
                                            int Hz, int N, const float2 *__restrict__ tw) {
   extern __shared__ float2 sm[];
-  float2 *a = sm, *b = sm + lpb * L;
+  float2 *a = sm, *b = sm + lpb * L, *twl = sm + 2 * lpb * L;
+  load_twiddles(twl, tw, L);
   const int ngroups = (Hz + lpb - 1) / lpb;
   const int x = blk / ngroups, lz0 = (blk % ngroups) * lpb;
   const int nl = min(lpb, Hz - lz0);
   const int F = N + 1;
-  for (int idx = threadIdx.x; idx < lpb * L; idx += FFT_THREADS) {
-    const int y = idx / lpb, li = idx - y * lpb;
-    a[li * L + y] = li < nl ? H1[((size_t)x * L + y) * Hz + lz0 + li] : make_float2(0.f, 0.f);
+  for (int idx = threadIdx.x; idx < nl * L; idx += FFT_THREADS) {
+    const int y = idx / nl, li = idx - y * nl;
+    a[li * L + y] = H1[((size_t)x * L + y) * Hz + lz0 + li];
   }
   __syncthreads();
-  lds_fft<-1>(a, b, L, logL, lpb, tw);
+  lds_fft<-1>(a, b, L, logL, nl, twl);
   for (int idx = threadIdx.x; idx < F * nl; idx += FFT_THREADS) {
     const int yp = idx / nl, li = idx - yp * nl;
     const int ly = (yp - N / 2 + L) & (L - 1);
@@ -539,12 +615,13 @@ __device__ __forceinline__ void y_inv_body(int blk, const float2 *__restrict__ H
                                            float2 *__restrict__ H1, int L, int logL, int lpb,
                                            int Hz, int N, const float2 *__restrict__ tw) {
   extern __shared__ float2 sm[];
-  float2 *a = sm, *b = sm + lpb * L;
+  float2 *a = sm, *b = sm + lpb * L, *twl = sm + 2 * lpb * L;
+  load_twiddles(twl, tw, L);
   const int ngroups = (Hz + lpb - 1) / lpb;
   const int x = blk / ngroups, lz0 = (blk % ngroups) * lpb;
   const int nl = min(lpb, Hz - lz0);
   const int F = N + 1;
-  for (int idx = threadIdx.x; idx < lpb * L; idx += FFT_THREADS) a[idx] = make_float2(0.f, 0.f);
+  for (int idx = threadIdx.x; idx < nl * L; idx += FFT_THREADS) a[idx] = make_float2(0.f, 0.f);
   __syncthreads();
   for (int idx = threadIdx.x; idx < F * nl; idx += FFT_THREADS) {
     const int yp = idx / nl, li = idx - yp * nl;
@@ -552,10 +629,10 @@ __device__ __forceinline__ void y_inv_body(int blk, const float2 *__restrict__ H
     a[li * L + ly] = H2[((size_t)x * F + yp) * Hz + lz0 + li];
   }
   __syncthreads();
-  lds_fft<+1>(a, b, L, logL, lpb, tw);
-  for (int idx = threadIdx.x; idx < lpb * L; idx += FFT_THREADS) {
-    const int y = idx / lpb, li = idx - y * lpb;
-    if (li < nl) H1[((size_t)x * L + y) * Hz + lz0 + li] = a[li * L + y];
+  lds_fft<+1>(a, b, L, logL, nl, twl);
+  for (int idx = threadIdx.x; idx < nl * L; idx += FFT_THREADS) {
+    const int y = idx / nl, li = idx - y * nl;
+    H1[((size_t)x * L + y) * Hz + lz0 + li] = a[li * L + y];
   }
 }
 
@@ -566,28 +643,29 @@ __device__ __forceinline__ void x_filter_body(int blk, float2 *__restrict__ Hx,
                                               int logL, int lpb, int N,
                                               const float2 *__restrict__ tw) {
   extern __shared__ float2 sm[];
-  float2 *a = sm, *b = sm + lpb * L;
+  float2 *a = sm, *b = sm + lpb * L, *twl = sm + 2 * lpb * L;
+  load_twiddles(twl, tw, L);
   const int c0 = blk * lpb;
   const int nl = min(lpb, C - c0);
-  for (int idx = threadIdx.x; idx < lpb * L; idx += FFT_THREADS) {
-    const int x = idx / lpb, li = idx - x * lpb;
-    a[li * L + x] = li < nl ? Hx[(size_t)x * C + c0 + li] : make_float2(0.f, 0.f);
+  for (int idx = threadIdx.x; idx < nl * L; idx += FFT_THREADS) {
+    const int x = idx / nl, li = idx - x * nl;
+    a[li * L + x] = Hx[(size_t)x * C + c0 + li];
   }
   __syncthreads();
-  lds_fft<-1>(a, b, L, logL, lpb, tw);
-  for (int idx = threadIdx.x; idx < lpb * L; idx += FFT_THREADS) {
+  lds_fft<-1>(a, b, L, logL, nl, twl);
+  for (int idx = threadIdx.x; idx < nl * L; idx += FFT_THREADS) {
     const int li = idx / L, x = idx - li * L;
     const int lx = x < L / 2 ? x : x - L;
     float f = 0.f;
-    if (li < nl && lx >= -N / 2 && lx <= N / 2) f = filt[(size_t)(lx + N / 2) * C + c0 + li];
+    if (lx >= -N / 2 && lx <= N / 2) f = filt[(size_t)(lx + N / 2) * C + c0 + li];
     a[idx].x *= f;
     a[idx].y *= f;
   }
   __syncthreads();
-  lds_fft<+1>(a, b, L, logL, lpb, tw);
-  for (int idx = threadIdx.x; idx < lpb * L; idx += FFT_THREADS) {
-    const int x = idx / lpb, li = idx - x * lpb;
-    if (li < nl) Hx[(size_t)x * C + c0 + li] = a[li * L + x];
+  lds_fft<+1>(a, b, L, logL, nl, twl);
+  for (int idx = threadIdx.x; idx < nl * L; idx += FFT_THREADS) {
+    const int x = idx / nl, li = idx - x * nl;
+    Hx[(size_t)x * C + c0 + li] = a[li * L + x];
   }
 }
 

@@ -114,7 +114,7 @@ def test_spread_matches_cpu_gridding(nfl, d, n, N, m, tile, chunk, kernel):
     assert err < 2e-6, err
 
 
-@pytest.mark.parametrize("d,N", [(1, 64), (2, 32), (3, 16), (3, 32)])
+@pytest.mark.parametrize("d,N", [(1, 64), (1, 256), (2, 32), (2, 128), (3, 16), (3, 32), (3, 64)])
 def test_convolve_matches_numpy_fft(nfl, d, N):
     v = synth.gmm(500, d=d, k=3, seed=2)
     P = make(nfl, v, 0.1, N, 3 if N <= 16 else 4)
