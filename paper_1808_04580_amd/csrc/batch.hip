@@ -55,22 +55,28 @@ __global__ void k_batch_set_io(BIO *io, const float *x, float *y) {
   io->y = y;
 }
 
-template <int W, bool ZM>
-__global__ __launch_bounds__(256) void kb_spread(const BItem *__restrict__ list,
-                                                 const BJob *__restrict__ jobs,
-                                                 const BIO *__restrict__ io) {
+// Items of at most SHORT_ITEM nodes run on one-wave workgroups (NW = 1):
+// a quarter of the LDS of the four-wave form, so several times more of these
+// short items are in flight per compute unit, and one private tile to clear
+// and flush instead of four.
+constexpr int SHORT_ITEM = 128;
+
+template <int W, bool ZM, int NW>
+__global__ __launch_bounds__(64 * NW) void kb_spread(const BItem *__restrict__ list,
+                                                     const BJob *__restrict__ jobs,
+                                                     const BIO *__restrict__ io) {
   const BItem b = list[blockIdx.x];
   const BJob &J = jobs[b.job];
   KArgs ka{};
   ka.x32 = io->x + J.xoff;
   ka.perm = J.perm;
   ka.dinv = J.dinv;
-  spread3_mfma_body<W, IN_USER_F32_DINV, ZM>(J.items[b.item], J.pts, ka, J.grid, J.nos, J.tshift,
-                                             J.wcoef);
+  spread3_mfma_body<W, IN_USER_F32_DINV, ZM, NW>(J.items[b.item], J.pts, ka, J.grid, J.nos,
+                                                 J.tshift, J.wcoef);
 }
 
-template <int W>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W <= 8 ? 5 : 1)))
+template <int W, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(W <= 8 ? 5 : 1)))
 void kb_interp(const BItem *__restrict__ list, const BJob *__restrict__ jobs,
                const BIO *__restrict__ io) {
   const BItem b = list[blockIdx.x];
@@ -80,8 +86,8 @@ void kb_interp(const BItem *__restrict__ list, const BJob *__restrict__ jobs,
   ka.y32 = io->y + J.xoff;
   ka.perm = J.perm;
   ka.dinv = J.dinv;
-  interp3_mfma_body<W, IN_USER_F32_DINV, OUT_USER_LS>(J.items, b.item, J.pts, ka, J.grid, J.nos,
-                                                      J.tshift, J.wcoef);
+  interp3_mfma_body<W, IN_USER_F32_DINV, OUT_USER_LS, NW>(J.items, b.item, J.pts, ka, J.grid,
+                                                          J.nos, J.tshift, J.wcoef);
 }
 
 // Job of workgroup `blk`: the largest j with first[j] <= blk (first[0] = 0).
@@ -132,13 +138,14 @@ __global__ __launch_bounds__(FFT_THREADS) void kb_fft(const int *__restrict__ fi
     c2r_lines_body(lb, J.spec1, J.grid, L * L, L, J.logL, J.lpz, Hz, J.tw);
 }
 
-// One launch of the spread or interpolation kernels: all jobs of one window
-// width W (and z-merge mode for the spread).
+// The spread or interpolation launches of all jobs of one window width W (and
+// z-merge mode for the spread): [0] four-wave workgroups, [1] one-wave
+// workgroups for short items.
 struct BGroup {
   int W = 0;
   bool zm = false;
-  int begin = 0, count = 0;   // range in the item list
-  size_t lds_spread = 0, lds_interp = 0;
+  int begin[2] = {0, 0}, count[2] = {0, 0};   // ranges in the item list
+  size_t lds_spread[2] = {0, 0}, lds_interp[2] = {0, 0};
 };
 
 static bool use_zmerge(int W, int T) { return W >= 9 && T + W - 1 <= 16; }
@@ -151,29 +158,38 @@ static int set_max_lds(K kern, size_t lds) {
   return NFL_OK;
 }
 
-template <int W>
-static int launch_group_w(const BGroup &g, const BItem *list, const BJob *jobs, const BIO *io,
-                          hipStream_t s, bool spread_pass, bool prepare) {
+template <int W, int NW>
+static int launch_group_wn(const BGroup &g, int v, const BItem *list, const BJob *jobs,
+                           const BIO *io, hipStream_t s, bool spread_pass, bool prepare) {
+  if (!prepare && g.count[v] == 0) return NFL_OK;
   if (spread_pass) {
     if constexpr (W >= 9) {
       if (g.zm) {
-        if (prepare) return set_max_lds(kb_spread<W, true>, g.lds_spread);
-        hipLaunchKernelGGL((kb_spread<W, true>), dim3(g.count), dim3(256), g.lds_spread, s,
-                           list + g.begin, jobs, io);
+        if (prepare) return set_max_lds(kb_spread<W, true, NW>, g.lds_spread[v]);
+        hipLaunchKernelGGL((kb_spread<W, true, NW>), dim3(g.count[v]), dim3(64 * NW),
+                           g.lds_spread[v], s, list + g.begin[v], jobs, io);
         NFL_HIP(hipGetLastError());
         return NFL_OK;
       }
     }
-    if (prepare) return set_max_lds(kb_spread<W, false>, g.lds_spread);
-    hipLaunchKernelGGL((kb_spread<W, false>), dim3(g.count), dim3(256), g.lds_spread, s,
-                       list + g.begin, jobs, io);
+    if (prepare) return set_max_lds(kb_spread<W, false, NW>, g.lds_spread[v]);
+    hipLaunchKernelGGL((kb_spread<W, false, NW>), dim3(g.count[v]), dim3(64 * NW),
+                       g.lds_spread[v], s, list + g.begin[v], jobs, io);
   } else {
-    if (prepare) return set_max_lds(kb_interp<W>, g.lds_interp);
-    hipLaunchKernelGGL((kb_interp<W>), dim3(g.count), dim3(256), g.lds_interp, s,
-                       list + g.begin, jobs, io);
+    if (prepare) return set_max_lds(kb_interp<W, NW>, g.lds_interp[v]);
+    hipLaunchKernelGGL((kb_interp<W, NW>), dim3(g.count[v]), dim3(64 * NW), g.lds_interp[v], s,
+                       list + g.begin[v], jobs, io);
   }
   NFL_HIP(hipGetLastError());
   return NFL_OK;
+}
+
+template <int W>
+static int launch_group_w(const BGroup &g, const BItem *list, const BJob *jobs, const BIO *io,
+                          hipStream_t s, bool spread_pass, bool prepare) {
+  const int rc = launch_group_wn<W, 4>(g, 0, list, jobs, io, s, spread_pass, prepare);
+  if (rc < 0) return rc;
+  return launch_group_wn<W, 1>(g, 1, list, jobs, io, s, spread_pass, prepare);
 }
 
 static int launch_group(const BGroup &g, const BItem *list, const BJob *jobs, const BIO *io,
@@ -345,10 +361,14 @@ static int batch_build(nfl_batch_s *B) {
       B->groups.back().zm = zm;
     }
     const int Pd = (1 << P->tshift) + W - 1;
-    const size_t ls = (4 * (size_t)tile_px(Pd) * Pd + 4 * 16 * WT_SPREAD) * sizeof(float);
-    const size_t li = ((size_t)tile_px(Pd) * Pd + 4 * 16 * WT_INTERP) * sizeof(float);
-    B->groups[k].lds_spread = std::max(B->groups[k].lds_spread, ls);
-    B->groups[k].lds_interp = std::max(B->groups[k].lds_interp, li);
+    const size_t p3 = (size_t)tile_px(Pd) * Pd;
+    for (int v = 0; v < 2; ++v) {
+      const size_t nw = v == 0 ? 4 : 1;
+      const size_t ls = (nw * p3 + nw * 16 * WT_SPREAD) * sizeof(float);
+      const size_t li = (p3 + nw * 16 * WT_INTERP) * sizeof(float);
+      B->groups[k].lds_spread[v] = std::max(B->groups[k].lds_spread[v], ls);
+      B->groups[k].lds_interp[v] = std::max(B->groups[k].lds_interp[v], li);
+    }
     for (int j = 0; j < nv; ++j)
       for (int t = 0; t < P->nitems; ++t) {
         glists[k].push_back({g * nv + j, t});
@@ -361,8 +381,13 @@ static int batch_build(nfl_batch_s *B) {
     for (size_t i = 0; i < ord.size(); ++i) ord[i] = (int)i;
     std::stable_sort(ord.begin(), ord.end(),
                      [&](int a, int b) { return glens[k][a] > glens[k][b]; });
-    B->groups[k].begin = (int)all.size();
-    B->groups[k].count = (int)ord.size();
+    // longest first; the short tail goes to the one-wave launch
+    size_t nlong = 0;
+    while (nlong < ord.size() && glens[k][ord[nlong]] > SHORT_ITEM) ++nlong;
+    B->groups[k].begin[0] = (int)all.size();
+    B->groups[k].count[0] = (int)nlong;
+    B->groups[k].begin[1] = (int)(all.size() + nlong);
+    B->groups[k].count[1] = (int)(ord.size() - nlong);
     for (int i : ord) all.push_back(glists[k][i]);
   }
   if (all.size() > (size_t)0x7fffffff) { set_error("batch: too many work items"); return NFL_ERR_UNSUPPORTED; }
@@ -395,7 +420,8 @@ static int batch_build(nfl_batch_s *B) {
     NFL_TRY(launch_group(g, nullptr, nullptr, nullptr, nullptr, true, true));
     NFL_TRY(launch_group(g, nullptr, nullptr, nullptr, nullptr, false, true));
   }
-  B->nkernels = 1 + 2 * (int)B->groups.size() + FFT_STAGES;
+  B->nkernels = 1 + FFT_STAGES;
+  for (const BGroup &g : B->groups) B->nkernels += 2 * ((g.count[0] > 0) + (g.count[1] > 0));
 
   // record the sequence once
   NFL_HIP(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));

@@ -314,12 +314,270 @@ static int apply_SSL64(nfl_plan *P, double tau, const double *q, double *w) {
   return fastsum(P, IN_SORTED_F64_DINV, OUT_SORTED_F64_SSL, a);
 }
 
-int lanczos(nfl_plan *P, int k, int block, double tol, int maxit, double *evals_host,
-            double *evecs_dev, int *iters, double *max_resid) {
-  if (block != 1) {
-    set_error("lanczos: only block = 1 is implemented");
+// ---------------------------------------------------------------------------
+// Symmetric eigensolver for the block projection: cyclic Jacobi with the
+// round-robin (circle) pairing of the indices, one workgroup.  In each round
+// the m/2 disjoint rotations are computed from the current matrix and then
+// applied at once, first to the rows, then to the columns and to V.  The
+// matrix is A = (H + H^T)/2 of the leading m x m part of H (column-major,
+// leading dimension ldH); the sweeps stop when the off-diagonal Frobenius norm
+// is below 1e-15 of the whole norm.  eval[m] unsorted, V[col*m + row];
+// status[0] = 1 if 40 sweeps did not converge.
+// ---------------------------------------------------------------------------
+constexpr int JAC_THREADS = 1024, JAC_MAXM = 1024;
+
+__device__ double jac_block_sum(double v, double *sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int k = 0; k < JAC_THREADS / 64; ++k) t += sh[k];
+  __syncthreads();
+  return t;  // valid in every thread
+}
+
+__global__ __launch_bounds__(JAC_THREADS) void k_sym_jacobi(const double *__restrict__ H,
+                                                            int64_t ldH, int m,
+                                                            double *__restrict__ A,
+                                                            double *__restrict__ V,
+                                                            double *__restrict__ eval,
+                                                            int *__restrict__ status) {
+  __shared__ double sh[JAC_THREADS / 64];
+  __shared__ double rc[JAC_MAXM / 2], rs[JAC_MAXM / 2];
+  __shared__ int rp[JAC_MAXM / 2], rq[JAC_MAXM / 2];
+  const int tid = threadIdx.x;
+  for (int64_t idx = tid; idx < (int64_t)m * m; idx += JAC_THREADS) {
+    const int i = (int)(idx % m), j = (int)(idx / m);
+    A[idx] = 0.5 * (H[(int64_t)j * ldH + i] + H[(int64_t)i * ldH + j]);
+    V[idx] = i == j ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  double nn = 0.0;
+  for (int64_t idx = tid; idx < (int64_t)m * m; idx += JAC_THREADS) nn += A[idx] * A[idx];
+  const double nrm = sqrt(jac_block_sum(nn, sh));
+  const int M = m + (m & 1), npair = M / 2;
+  int st = 1;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    double off = 0.0;
+    for (int64_t idx = tid; idx < (int64_t)m * m; idx += JAC_THREADS)
+      if (idx % m != idx / m) off += A[idx] * A[idx];
+    off = sqrt(jac_block_sum(off, sh));
+    if (off <= 1e-15 * nrm) {
+      st = 0;
+      break;
+    }
+    for (int r = 0; r < M - 1; ++r) {
+      for (int i = tid; i < npair; i += JAC_THREADS) {
+        const int a = i == 0 ? 0 : ((i - 1 + r) % (M - 1)) + 1;
+        const int bb = M - 1 - i == 0 ? 0 : ((M - 2 - i + r) % (M - 1)) + 1;
+        const int p = min(a, bb), q = max(a, bb);
+        double c = 1.0, s = 0.0;
+        if (q < m) {
+          const double apq = A[(int64_t)q * m + p];
+          if (fabs(apq) > 1e-300) {
+            const double tau = (A[(int64_t)q * m + q] - A[(int64_t)p * m + p]) / (2.0 * apq);
+            const double t = fabs(tau) > 1e150
+                                 ? 0.5 / tau
+                                 : (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + t * t);
+            s = t * c;
+          }
+        }
+        rp[i] = p;
+        rq[i] = q < m ? q : -1;
+        rc[i] = c;
+        rs[i] = s;
+      }
+      __syncthreads();
+      // rows p, q of A
+      for (int64_t idx = tid; idx < (int64_t)npair * m; idx += JAC_THREADS) {
+        const int i = (int)(idx / m), k = (int)(idx % m);
+        const int q = rq[i];
+        if (q < 0) continue;
+        const int p = rp[i];
+        const double c = rc[i], s = rs[i];
+        const double ap = A[(int64_t)k * m + p], aq = A[(int64_t)k * m + q];
+        A[(int64_t)k * m + p] = c * ap - s * aq;
+        A[(int64_t)k * m + q] = s * ap + c * aq;
+      }
+      __syncthreads();
+      // columns p, q of A and of V
+      for (int64_t idx = tid; idx < (int64_t)npair * m; idx += JAC_THREADS) {
+        const int i = (int)(idx / m), k = (int)(idx % m);
+        const int q = rq[i];
+        if (q < 0) continue;
+        const int p = rp[i];
+        const double c = rc[i], s = rs[i];
+        const double ap = A[(int64_t)p * m + k], aq = A[(int64_t)q * m + k];
+        A[(int64_t)p * m + k] = c * ap - s * aq;
+        A[(int64_t)q * m + k] = s * ap + c * aq;
+        const double vp = V[(int64_t)p * m + k], vq = V[(int64_t)q * m + k];
+        V[(int64_t)p * m + k] = c * vp - s * vq;
+        V[(int64_t)q * m + k] = s * vp + c * vq;
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = tid; i < m; i += JAC_THREADS) eval[i] = A[(int64_t)i * m + i];
+  if (tid == 0) status[0] = st;
+}
+
+// h[i] += c[i], i < J (one column of the projection)
+__global__ __launch_bounds__(VT) void k_add_col(double *__restrict__ h,
+                                                const double *__restrict__ c, int J) {
+  for (int i = blockIdx.x * VT + threadIdx.x; i < J; i += gridDim.x * VT) h[i] += c[i];
+}
+
+// Block Lanczos with full reorthogonalisation for the k largest eigenvalues of
+// A_E (Section 4 with blocks of b vectors).  Column J0 + c of the basis is
+// multiplied by A_E; the product is orthogonalised twice against every
+// column built so far (which also forms the QR factor of the new block) and
+// normalised into the next column.  H holds the coefficients: column J0 + c
+// gets the projections in rows < J0 + b + c and the norm in row J0 + b + c,
+// so the leading J x J part of H is the projection Q^T A_E Q and the b x b
+// block below it the R factor of the next block.  Ritz residual of (theta, s):
+// || R s_last || with s_last the last b components of s.
+static int block_lanczos(nfl_plan *P, int k, int b, double tol, int maxit, double *evals_host,
+                         double *evecs_dev, int *iters, double *max_resid) {
+  const int64_t n = P->n;
+  maxit = (int)std::min<int64_t>(maxit, n - b);
+  const int maxblk = maxit / b;
+  if (maxblk < 1 || k > maxblk * b) {
+    set_error("block lanczos: need k <= maxit and room for one block");
+    return NFL_ERR_ARG;
+  }
+  const int mcols = maxblk * b;          // columns whose products are formed
+  if (mcols > JAC_MAXM) {
+    set_error("block lanczos: maxit above 1024 is not supported");
     return NFL_ERR_UNSUPPORTED;
   }
+  const int64_t ld = n, ldH = mcols + b;
+  DBuf<double> Q, W, H, cvec, part, Aw, Vw, ev;
+  DBuf<int> st, sel;
+  NFL_TRY(Q.ensure((size_t)ld * (mcols + b)));
+  NFL_TRY(W.ensure((size_t)n * b));
+  NFL_TRY(H.ensure((size_t)ldH * ldH));
+  NFL_TRY(cvec.ensure(mcols + b));
+  Reducer R;
+  NFL_TRY(R.init(n));
+  NFL_TRY(part.ensure((size_t)R.nb * (mcols + b)));
+  NFL_TRY(Aw.ensure((size_t)mcols * mcols));
+  NFL_TRY(Vw.ensure((size_t)mcols * mcols));
+  NFL_TRY(ev.ensure(mcols));
+  NFL_TRY(st.ensure(1));
+  NFL_TRY(sel.ensure(k));
+  const int gb = grid_for(n);
+  hipStream_t s = P->stream;
+  hipLaunchKernelGGL(k_fill64, dim3(256), dim3(VT), 0, s, H.p, (int64_t)(ldH * ldH), 0.0);
+
+  // orthogonalise w twice against the first ncol columns, adding the
+  // coefficients to hcol (may be null); then normalise into column ncol,
+  // its norm written to *nrm_dev
+  auto orth_next = [&](double *w, int ncol, double *hcol, double *nrm_dev) -> int {
+    for (int pass = 0; pass < 2 && ncol > 0; ++pass) {
+      hipLaunchKernelGGL(k_gemv_t_partial, dim3(R.nb), dim3(VT), 0, s, Q.p, ld, ncol, w, n,
+                         part.p);
+      hipLaunchKernelGGL(k_gemv_t_final, dim3(1), dim3(VT), 0, s, part.p, R.nb, ncol, cvec.p);
+      if (hcol)
+        hipLaunchKernelGGL(k_add_col, dim3((ncol + VT - 1) / VT), dim3(VT), 0, s, hcol, cvec.p,
+                           ncol);
+      hipLaunchKernelGGL(k_gemv_n_sub, dim3(gb), dim3(VT), 0, s, Q.p, ld, ncol, cvec.p, w, n);
+    }
+    NFL_TRY(dot(P, R, w, w, nrm_dev, 1));
+    hipLaunchKernelGGL(k_scale_inv, dim3(gb), dim3(VT), 0, s, w, nrm_dev, n,
+                       Q.p + (int64_t)ncol * ld);
+    NFL_HIP(hipGetLastError());
+    return NFL_OK;
+  };
+
+  // start block: b seeded vectors, orthonormalised
+  for (int c = 0; c < b; ++c) {
+    hipLaunchKernelGGL(k_start_vector, dim3(gb), dim3(VT), 0, s, W.p, P->perm.p, n,
+                       (uint64_t)(c + 1));
+    NFL_TRY(orth_next(W.p, c, nullptr, cvec.p + mcols + b - 1));
+  }
+
+  std::vector<double> h_eval, h_V, h_R((size_t)b * b);
+  std::vector<int> h_sel(k);
+  int Jc = 0, nblk = 0;
+  bool converged = false;
+  double worst = INFINITY;
+  while (nblk < maxblk) {
+    const int J0 = nblk * b;
+    for (int c = 0; c < b; ++c) NFL_TRY(apply_A64(P, Q.p + (int64_t)(J0 + c) * ld, W.p + (int64_t)c * n));
+    for (int c = 0; c < b; ++c) {
+      const int ncol = J0 + b + c;
+      double *hcol = H.p + (int64_t)(J0 + c) * ldH;
+      NFL_TRY(orth_next(W.p + (int64_t)c * n, ncol, hcol, hcol + ncol));
+    }
+    ++nblk;
+    Jc = nblk * b;
+    const bool last = nblk == maxblk;
+    const int every = Jc <= 100 ? std::max(1, 8 / b) : std::max(1, 16 / b);
+    if (Jc >= k && (nblk % every == 0 || last)) {
+      hipLaunchKernelGGL(k_sym_jacobi, dim3(1), dim3(JAC_THREADS), 0, s, H.p, ldH, Jc, Aw.p, Vw.p,
+                         ev.p, st.p);
+      NFL_HIP(hipGetLastError());
+      h_eval.resize(Jc);
+      h_V.resize((size_t)Jc * Jc);
+      int h_st = 0;
+      NFL_HIP(hipMemcpyAsync(h_eval.data(), ev.p, Jc * sizeof(double), hipMemcpyDeviceToHost, s));
+      NFL_HIP(hipMemcpyAsync(h_V.data(), Vw.p, (size_t)Jc * Jc * sizeof(double),
+                             hipMemcpyDeviceToHost, s));
+      for (int c = 0; c < b; ++c)   // R: rows Jc..Jc+b-1 of columns Jc-b+c
+        NFL_HIP(hipMemcpyAsync(h_R.data() + (size_t)c * b, H.p + (int64_t)(Jc - b + c) * ldH + Jc,
+                               b * sizeof(double), hipMemcpyDeviceToHost, s));
+      NFL_HIP(hipMemcpyAsync(&h_st, st.p, sizeof(int), hipMemcpyDeviceToHost, s));
+      NFL_HIP(hipStreamSynchronize(s));
+      if (h_st != 0) {
+        set_error("block lanczos: Jacobi eigensolver did not converge");
+        return NFL_ERR_HIP;
+      }
+      std::vector<int> order(Jc);
+      std::iota(order.begin(), order.end(), 0);
+      std::sort(order.begin(), order.end(), [&](int a, int bb) { return h_eval[a] > h_eval[bb]; });
+      worst = 0.0;
+      for (int c = 0; c < k; ++c) {
+        h_sel[c] = order[c];
+        const double *sv = h_V.data() + (size_t)order[c] * Jc;
+        double r2 = 0.0;
+        for (int r = 0; r < b; ++r) {
+          double t = 0.0;
+          for (int q = 0; q < b; ++q) t += h_R[(size_t)q * b + r] * sv[Jc - b + q];
+          r2 += t * t;
+        }
+        worst = std::max(worst, std::sqrt(r2));
+      }
+      if (worst <= tol) {
+        converged = true;
+        break;
+      }
+    }
+  }
+  for (int c = 0; c < k; ++c) evals_host[c] = 1.0 - h_eval[h_sel[c]];
+  if (evecs_dev) {
+    DBuf<double> Vout;
+    NFL_TRY(Vout.ensure((size_t)n * k));
+    NFL_HIP(hipMemcpyAsync(sel.p, h_sel.data(), k * sizeof(int), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_ritz, dim3(gb), dim3(VT), 0, s, Q.p, ld, Jc, Vw.p, sel.p, k, n, Vout.p);
+    for (int c = 0; c < k; ++c)
+      hipLaunchKernelGGL(k_scatter64, dim3(gb), dim3(VT), 0, s, Vout.p + (int64_t)c * n,
+                         P->perm.p, n, evecs_dev + (int64_t)c * n);
+    NFL_HIP(hipGetLastError());
+    NFL_HIP(hipStreamSynchronize(s));
+  }
+  if (iters) *iters = Jc;
+  if (max_resid) *max_resid = worst;
+  return converged ? NFL_OK : NFL_NOT_CONVERGED;
+}
+
+int lanczos(nfl_plan *P, int k, int block, double tol, int maxit, double *evals_host,
+            double *evecs_dev, int *iters, double *max_resid) {
+  if (block > 1)
+    return block_lanczos(P, k, block, tol, maxit, evals_host, evecs_dev, iters, max_resid);
   const int64_t n = P->n;
   maxit = (int)std::min<int64_t>(maxit, n);
   if (k < 1 || k > maxit) {

@@ -168,7 +168,8 @@ __device__ __forceinline__ void load_batch(const float4 *__restrict__ pts, const
 // registers over a run of nodes, then adds it into its wave's PRIVATE copy of
 // the padded tile (plain read-add-write: every lane of a flush owns a
 // distinct cell, and the LDS operations of one wave are ordered).  At the end
-// the four private tiles are summed and added into the grid.
+// the NW private tiles (one per wave: NW = 4, or 1 for the one-wave variant
+// used on short items) are summed and added into the grid.
 //
 // ZM ("z-merge", needs T + W - 1 <= 16): the 16 columns cover the whole
 // z-extent of the padded tile, so nodes of different cells of one (x, y)
@@ -182,7 +183,7 @@ struct SpreadShape {
   static constexpr int NB = (W + S - 1) / S;
 };
 
-template <int W, int IN, bool ZM>
+template <int W, int IN, bool ZM, int NW = 4>
 __device__ __forceinline__ void spread3_mfma_body(const Item it, const float4 *__restrict__ pts,
                                                   const KArgs ka, float *__restrict__ grid,
                                                   int nos, int tshift,
@@ -195,7 +196,7 @@ __device__ __forceinline__ void spread3_mfma_body(const Item it, const float4 *_
   const int ntd = nos >> tshift;
   const int tz = it.tile % ntd, ty = (it.tile / ntd) % ntd, tx = it.tile / (ntd * ntd);
   const int ox = tx * T, oy = ty * T, oz = tz * T;
-  for (int c = threadIdx.x; c < 4 * P3; c += 256) lds[c] = 0.f;
+  for (int c = threadIdx.x; c < NW * P3; c += 64 * NW) lds[c] = 0.f;
   __syncthreads();
 
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -203,8 +204,8 @@ __device__ __forceinline__ void spread3_mfma_body(const Item it, const float4 *_
   const int c16 = lane & 15, p4 = lane >> 4;
   const int sub = c16 / WP, az = c16 % WP;
   float *tile = lds + wave * P3;
-  float *wt = lds + 4 * P3 + wave * (16 * WT_SPREAD);
-  const int len = it.end - it.start, per = (len + 3) >> 2;
+  float *wt = lds + NW * P3 + wave * (16 * WT_SPREAD);
+  const int len = it.end - it.start, per = (len + NW - 1) / NW;
   const int s = it.start + min(len, wave * per), e = it.start + min(len, (wave + 1) * per);
   // run key: the cell, or with ZM its (x, y) column
   const uint32_t keymask = ZM ? 0x000fffffu : 0xffffffffu;
@@ -304,12 +305,15 @@ __device__ __forceinline__ void spread3_mfma_body(const Item it, const float4 *_
   const int mask = nos - 1;
   const int ZL = P <= 16 ? 16 : (P <= 32 ? 32 : 64), RL = 64 / ZL;
   const int pz = lane % ZL, rsub = lane / ZL;
-  for (int row0 = wave * RL; row0 < P * P; row0 += 4 * RL) {
+  for (int row0 = wave * RL; row0 < P * P; row0 += NW * RL) {
     const int row = row0 + rsub;
     if (row < P * P && pz < P) {
       const int px = row / P, py = row - px * P;
       const int o = px * PX + py * P + pz;
-      const float v = (lds[o] + lds[P3 + o]) + (lds[2 * P3 + o] + lds[3 * P3 + o]);
+      float v;
+      if constexpr (NW == 4) v = (lds[o] + lds[P3 + o]) + (lds[2 * P3 + o] + lds[3 * P3 + o]);
+      else if constexpr (NW == 2) v = lds[o] + lds[P3 + o];
+      else v = lds[o];
       if (v != 0.f) {
         const int gx = (ox - (M - 1) + px) & mask, gy = (oy - (M - 1) + py) & mask,
                   gz = (oz - (M - 1) + pz) & mask;
@@ -325,7 +329,7 @@ __device__ __forceinline__ void spread3_mfma_body(const Item it, const float4 *_
 // steps (KZ = ceil(W/4)).  The cell's window G, read from the workgroup's
 // shared LDS copy of the padded tile, is the register-resident A operand:
 // lane l holds G[ax = l%16][ay][4 t + l/16].
-template <int W, int IN, int OUT>
+template <int W, int IN, int OUT, int NW = 4>
 __device__ __forceinline__ void interp3_mfma_body(const Item *__restrict__ items, int item,
                                                   const float4 *__restrict__ pts,
                                                   const KArgs ka,
@@ -346,7 +350,7 @@ __device__ __forceinline__ void interp3_mfma_body(const Item *__restrict__ items
     // stage the padded tile: each wave takes rows (px, py), 64 / ZL at a time
     const int ZL = P <= 16 ? 16 : (P <= 32 ? 32 : 64), RL = 64 / ZL;
     const int pz = lane % ZL, rsub = lane / ZL;
-    for (int row0 = wave * RL; row0 < PP; row0 += 4 * RL) {
+    for (int row0 = wave * RL; row0 < PP; row0 += NW * RL) {
       const int row = row0 + rsub;
       if (row < PP && pz < P) {
         const int px = row / P, py = row - px * P;
@@ -360,7 +364,7 @@ __device__ __forceinline__ void interp3_mfma_body(const Item *__restrict__ items
 
   const int c16 = lane & 15, k4 = lane >> 4;
   float *wt = lds + P3 + wave * (16 * WT_INTERP);
-  const int len = it.end - it.start, per = (len + 3) >> 2;
+  const int len = it.end - it.start, per = (len + NW - 1) / NW;
   const int s = it.start + min(len, wave * per), e = it.start + min(len, (wave + 1) * per);
 
   float cf[4][WIN_NC];

@@ -214,13 +214,15 @@ def test_invariants_of_the_approximate_operator(nfl):
     assert np.abs(Y[1] - Lb).max() <= 1e-6 * np.abs(Lb).max()
 
 
-def test_lanczos_matches_dense_eigh(nfl):
-    """10 smallest eigenpairs of L_s on the n = 5000 blob workload (N = 64):
-    eigenvalues within 1e-6 of LAPACK on the dense FP64 matrix; residuals of
-    the returned vectors against the dense matrix small."""
+@pytest.mark.parametrize("block", [1, 3, 4])
+def test_lanczos_matches_dense_eigh(nfl, block):
+    """10 smallest eigenpairs of L_s on the n = 5000 blob workload (N = 64),
+    single-vector and block Lanczos: eigenvalues within 1e-6 of LAPACK on the
+    dense FP64 matrix; residuals of the returned vectors against the dense
+    matrix small."""
     v = synth.blobs2d(5000, seed=0)
     P = make(nfl, v, 0.05, 64, 4, 1.0 / 16)
-    r = P.lanczos_smallest(10, tol=1e-8, maxit=300)
+    r = P.lanczos_smallest(10, tol=1e-8, maxit=300, block=block)
     lam_ref, U = graph.smallest_eigs_dense(v, 0.05, 10)
     assert r["converged"]
     assert np.abs(r["evals"] - lam_ref).max() <= 1e-6, (r["evals"], lam_ref)
@@ -230,6 +232,21 @@ def test_lanczos_matches_dense_eigh(nfl):
     for i in range(10):
         res = np.linalg.norm(Ls @ V[:, i] - r["evals"][i] * V[:, i])
         assert res <= 1e-4, (i, res)
+
+
+@pytest.mark.parametrize("block", [1, 4])
+def test_image_subsample_lanczos_matches_dense_eigh(nfl, block):
+    """Image-segmentation graph (316 x 316 RGB, 6 regions, noise 0.02) on a
+    seeded 5000-pixel subsample, sigma = 0.1, N = 64, m = 5: the 10 smallest
+    eigenvalues of L_s within 1e-6 of LAPACK on the dense FP64 matrix."""
+    img = synth.image_rgb(316, seed=0)
+    idx = np.sort(np.random.default_rng(5).choice(img.shape[0], size=5000, replace=False))
+    v = np.ascontiguousarray(img[idx])
+    P = make(nfl, v, 0.1, 64, 5)
+    r = P.lanczos_smallest(10, tol=1e-8, maxit=300, block=block, vectors=False)
+    lam_ref, _ = graph.smallest_eigs_dense(v, 0.1, 10)
+    assert r["converged"], r
+    assert np.abs(r["evals"] - lam_ref).max() <= 1e-6, (r["evals"], lam_ref)
 
 
 def test_cg_matches_dense_solve(nfl):
