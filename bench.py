@@ -151,6 +151,8 @@ def main():
     ap.add_argument("--no-cg", action="store_true")
     ap.add_argument("--rows", type=int, default=256, help="sampled rows for the accuracy check")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-graph batched leg")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="run only the 64-graph batched leg and print its JSON record")
     ap.add_argument("--profile-run", action="store_true",
                     help="short run for hardware counters: a few products and a 256 MiB "
                          "device copy (the reference for scaling byte counters); no JSON")
@@ -168,6 +170,9 @@ def main():
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
+    if args.batched_only:
+        print(json.dumps(batched_leg(nfl, synth, torch, dev)), flush=True)
+        return
     t0 = time.time()
     v, lab = synth.moons_and_roll(N_POINTS, seed=1)
     x = synth.normal_vectors(N_POINTS, seed=12345)

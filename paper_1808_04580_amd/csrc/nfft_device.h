@@ -96,8 +96,8 @@ __device__ __forceinline__ float readlane_f(float v, int lane) {
 // d = 3 spread and interpolation on the matrix cores.
 //
 // Nodes are processed in sub-batches of 16.  Per sub-batch each lane l
-// evaluates, for node l%16, the window polynomials of the offsets
-// 4 (l/16) .. 4 (l/16) + 3 on all three axes (12 Horner evaluations) and writes
+// evaluates, for node l/4, the window polynomials of the offsets
+// 4 (l%4) .. 4 (l%4) + 3 on all three axes (12 Horner evaluations) and writes
 // them to a per-wave weight table wt[node][axis][offset] in LDS (the x value
 // of the node rides along in wt[node][3][0]).  The matrix-core loop then reads
 // its operands from the table with independent broadcast loads.
@@ -127,23 +127,37 @@ template <int W, bool WITH_X, int STRIDE>
 __device__ __forceinline__ uint32_t fill_weights(const float4 &qb, float xb, int sub, int cnt,
                                                  int lane, const float (&cf)[4][WIN_NC],
                                                  float *wt) {
-  const int node = lane & 15, part = lane >> 4;
+  // weights: lane l evaluates node l/4 at offsets 4 (l%4) .. 4 (l%4) + 3.  With
+  // a row pitch that is a multiple of 4 the four values go out as one 16-byte
+  // store; eight consecutive lanes then cover eight distinct 4-bank groups.
+  const int node = lane >> 2, part = lane & 3;
   const int src = sub * 16 + min(node, cnt - 1);
   const float qx = __shfl(qb.x, src), qy = __shfl(qb.y, src), qz = __shfl(qb.z, src);
-  const uint32_t cell = node < cnt ? (uint32_t)__shfl((int)__float_as_uint(qb.w), src) : 0xffffffffu;
-  float *w = wt + node * STRIDE;
+  float *w = wt + node * STRIDE + 4 * part;
+  if constexpr (STRIDE % 4 == 0) {
+    *reinterpret_cast<float4 *>(w) = make_float4(win_poly(cf[0], qx), win_poly(cf[1], qx),
+                                                 win_poly(cf[2], qx), win_poly(cf[3], qx));
+    *reinterpret_cast<float4 *>(w + 16) = make_float4(win_poly(cf[0], qy), win_poly(cf[1], qy),
+                                                      win_poly(cf[2], qy), win_poly(cf[3], qy));
+    *reinterpret_cast<float4 *>(w + 32) = make_float4(win_poly(cf[0], qz), win_poly(cf[1], qz),
+                                                      win_poly(cf[2], qz), win_poly(cf[3], qz));
+  } else {
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int o = 4 * part + u;
-    w[0 * 16 + o] = win_poly(cf[u], qx);
-    w[1 * 16 + o] = win_poly(cf[u], qy);
-    w[2 * 16 + o] = win_poly(cf[u], qz);
+    for (int u = 0; u < 4; ++u) {
+      w[0 * 16 + u] = win_poly(cf[u], qx);
+      w[1 * 16 + u] = win_poly(cf[u], qy);
+      w[2 * 16 + u] = win_poly(cf[u], qz);
+    }
   }
   if (WITH_X) {
     const float xv = __shfl(xb, src);
-    if (part == 0) w[3 * 16] = xv;
+    if (part == 0) wt[node * STRIDE + 3 * 16] = xv;
   }
-  return cell;
+  // cells: lane l returns the packed cell of sub-batch node l % 16
+  const int cn = lane & 15;
+  const int csrc = sub * 16 + min(cn, cnt - 1);
+  const uint32_t cell = (uint32_t)__shfl((int)__float_as_uint(qb.w), csrc);
+  return cn < cnt ? cell : 0xffffffffu;
 }
 
 // One 64-node batch of sorted records (and, for the spread, input values),
@@ -213,7 +227,7 @@ __device__ __forceinline__ void spread3_mfma_body(const Item it, const float4 *_
   float cf[4][WIN_NC];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    const int o = 4 * p4 + u;
+    const int o = 4 * (lane & 3) + u;   // the offsets this lane evaluates in fill_weights
 #pragma unroll
     for (int k = 0; k < WIN_NC; ++k) cf[u][k] = o < W ? wcoef[o * WIN_NC + k] : 0.f;
   }
@@ -370,7 +384,7 @@ __device__ __forceinline__ void interp3_mfma_body(const Item *__restrict__ items
   float cf[4][WIN_NC];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    const int o = 4 * k4 + u;
+    const int o = 4 * (lane & 3) + u;   // the offsets this lane evaluates in fill_weights
 #pragma unroll
     for (int k = 0; k < WIN_NC; ++k) cf[u][k] = o < W ? wcoef[o * WIN_NC + k] : 0.f;
   }

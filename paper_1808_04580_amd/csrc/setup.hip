@@ -329,11 +329,14 @@ __global__ __launch_bounds__(256) void k_gather_nodes(const float4 *__restrict__
   perm[i] = (int)j;
 }
 
-__global__ __launch_bounds__(256) void k_tile_count(const uint32_t *__restrict__ keys, int64_t n,
-                                                    int shift, uint32_t *__restrict__ cnt) {
+// Sorted keys: the nodes of a tile are contiguous.  end[tile] = one past its
+// last node (tiles without nodes keep 0).
+__global__ __launch_bounds__(256) void k_tile_ends(const uint32_t *__restrict__ keys, int64_t n,
+                                                   int shift, uint32_t *__restrict__ end) {
   const int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x;
   if (i >= n) return;
-  atomicAdd(&cnt[keys[i] >> shift], 1u);
+  const uint32_t t = keys[i] >> shift;
+  if (i + 1 == n || (keys[i + 1] >> shift) != t) end[t] = (uint32_t)(i + 1);
 }
 
 int build_sorted_nodes(nfl_plan *P) {
@@ -379,7 +382,7 @@ int build_sorted_nodes(nfl_plan *P) {
                      P->perm.p);
   hipError_t e = hipMemsetAsync(cnt, 0, (size_t)ntiles * 4, P->stream);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_tile_count, dim3(nb), dim3(256), 0, P->stream, keys, n, d * tshift, cnt);
+    hipLaunchKernelGGL(k_tile_ends, dim3(nb), dim3(256), 0, P->stream, keys, n, d * tshift, cnt);
     e = hipGetLastError();
   }
   std::vector<uint32_t> hc((size_t)ntiles);
@@ -390,6 +393,16 @@ int build_sorted_nodes(nfl_plan *P) {
   if (e != hipSuccess) {
     set_error(std::string("build_sorted_nodes: ") + hipGetErrorString(e));
     return NFL_ERR_HIP;
+  }
+  // tile sizes from the run ends (tiles are in sorted order)
+  {
+    uint32_t prev = 0;
+    for (int64_t t = 0; t < ntiles; ++t) {
+      if (hc[(size_t)t] == 0) continue;
+      const uint32_t e_t = hc[(size_t)t];
+      hc[(size_t)t] = e_t - prev;
+      prev = e_t;
+    }
   }
   // Work items: each occupied tile split into near-equal chunks of at most
   // opt_chunk nodes.
