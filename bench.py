@@ -311,11 +311,14 @@ def main():
     cpu = None
     if not args.no_cpu:
         import oracle
-        S = 2048
-        srows = np.sort(rng.choice(N_POINTS, size=S, replace=False))
+        # the direct FP64 sum on chunks of seeded rows until ~12 s of host work
+        perm = rng.permutation(N_POINTS)
         x64 = x.astype(np.float64)
+        S, chunk = 0, 4096
         t0 = time.time()
-        graph.w_rows(v, SIGMA, x64, srows)
+        while time.time() - t0 < 12.0 and S + chunk <= N_POINTS:
+            graph.w_rows(v, SIGMA, x64, np.sort(perm[S:S + chunk]))
+            S += chunk
         dt = time.time() - t0
         per_matvec = dt * N_POINTS / S
         cpu = {"value": 1.0 / per_matvec, "unit": "matvecs/s", "cores": oracle.num_threads(),

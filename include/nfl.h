@@ -52,7 +52,9 @@ typedef struct nfl_mlp *nfl_mlp_handle;
 #define NFL_OPT_TILE       2   /* grid tile edge T for spread/interp (power of 2, 4..32); default 4 */
 #define NFL_OPT_CHUNK      3   /* max nodes per spread/interp work item; default 512 */
 #define NFL_OPT_EPS_B_DEFAULT 4 /* if value != 0, nfl_set_kernel with eps_B < 0 uses eps_B = p/N (the paper's default) */
-#define NFL_OPT_KERNEL     5   /* d = 3 spread/interp: 0 = matrix-core (MFMA) kernels (default), 1 = vector-ALU kernels; takes effect immediately */
+#define NFL_OPT_KERNEL     5   /* d = 3 spread/interp: 0 = matrix-core (MFMA) kernels (default; tile-stationary
+                                   where tile + 2m - 1 <= 16, else per-cell runs), 1 = vector-ALU kernels,
+                                   2 = matrix-core kernels with per-cell runs only; takes effect immediately */
 
 /* Create a plan for nodes in R^d, d in {1, 2, 3}.  `hip_stream` is a
  * hipStream_t (NULL = the default stream).  Allocates nothing on the device
@@ -264,10 +266,10 @@ typedef struct nfl_batch_s *nfl_batch;
  * The batch reads the plans' sorted nodes, degrees and filters (it does not
  * copy them), so every plan must outlive the batch and must not be changed
  * (set_points / set_kernel / set_option) while it exists: apply then fails
- * with NFL_ERR_ORDER.  The batch owns one grid and spectrum per (plan,
+ * with NFL_ERR_ORDER.  The batch owns two grids and the spectra per (plan,
  * vector) pair (nfl_batch_info reports the bytes) and records the whole
- * product -- grid clear, one spread launch per window width, five FFT
- * passes, one interpolation launch per width -- as a HIP graph at creation.
+ * product -- spread launches per window width and kernel form, five FFT
+ * passes, interpolation launches -- as a HIP graph at creation.
  * hip_stream: the stream the graph is launched on (may be the null stream).
  * 1 <= nvec <= 64. */
 int nfl_batch_create(nfl_batch *b, const nfl_handle *plans, int nplans, int nvec,

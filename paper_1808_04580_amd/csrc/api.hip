@@ -81,6 +81,7 @@ int nfl_destroy(nfl_handle P) {
   P->wcoef.release();
   P->tw.release();
   P->grid.release();
+  P->grid2.release();
   P->spec1.release();
   P->spec2.release();
   P->deg.release();
@@ -113,7 +114,7 @@ int nfl_set_option(nfl_handle P, int opt, double value) {
       P->opt_eps_default = value != 0;
       return NFL_OK;
     case NFL_OPT_KERNEL:
-      if (value != 0 && value != 1) { set_error("kernel must be 0 (matrix cores) or 1 (vector ALU)"); return NFL_ERR_ARG; }
+      if (value != 0 && value != 1 && value != 2) { set_error("kernel must be 0 (matrix cores), 1 (vector ALU) or 2 (matrix cores, per-cell runs)"); return NFL_ERR_ARG; }
       P->opt_kernel = (int)value;
       return NFL_OK;
     default:
@@ -193,6 +194,8 @@ int nfl_set_kernel(nfl_handle P, double sigma, int N, int m, double eps_B) {
   int64_t gsz = 1;
   for (int t = 0; t < P->d; ++t) gsz *= P->nos;
   NFL_TRY(P->grid.ensure(gsz));
+  NFL_TRY(P->grid2.ensure(gsz));
+  P->grid_clean = false;
   const int Hz = N / 2 + 1, F = N + 1;
   size_t s1 = Hz, s2 = 0;
   if (P->d == 2) s1 = (size_t)P->nos * Hz;

@@ -8,8 +8,10 @@
 // list of (job, item) pairs -- one launch per window width, since the width
 // is a compile-time shape of the matrix-core loops -- and the FFT passes map
 // each workgroup to a job by a search over per-job workgroup offsets.  The
-// sequence (grid clear, spreads, five FFT passes, interpolations) is
-// captured once into a HIP graph; an apply is one graph launch.  The input
+// sequence (spreads, five FFT passes, interpolations) is captured once into a
+// HIP graph; an apply is one graph launch.  Each job has two grids: the spread
+// grid, which the r2c pass leaves zero for the next replay, and the grid the
+// c2r pass writes and the interpolation reads.  The input
 // and output base pointers live in a small device record that a one-thread
 // kernel rewrites when they change, so the captured graph never changes.
 #include <hip/hip_runtime.h>
@@ -32,12 +34,13 @@ struct BJob {
   const float *wcoef;
   const float *filt;
   const float2 *tw;
-  float *grid;
+  float *grid;    // spread output, left zero by the r2c pass
+  float *grid2;   // c2r output, interpolation input
   float2 *spec1;
   float2 *spec2;
   int64_t xoff;   // offset of this job's vector in the packed x / y
   int nos, N, tshift, logL;
-  int lpz, lpy, lpx, pad;   // FFT lines per workgroup: z, y and x passes
+  int lpz, lpy, lpx, pad;   // FFT lines per workgroup: z (real lines), y and x passes
 };
 
 struct BItem {
@@ -86,8 +89,37 @@ void kb_interp(const BItem *__restrict__ list, const BJob *__restrict__ jobs,
   ka.y32 = io->y + J.xoff;
   ka.perm = J.perm;
   ka.dinv = J.dinv;
-  interp3_mfma_body<W, IN_USER_F32_DINV, OUT_USER_LS, NW>(J.items, b.item, J.pts, ka, J.grid,
+  interp3_mfma_body<W, IN_USER_F32_DINV, OUT_USER_LS, NW>(J.items, b.item, J.pts, ka, J.grid2,
                                                           J.nos, J.tshift, J.wcoef);
+}
+
+template <int W, int T, int NW>
+__global__ __launch_bounds__(64 * NW) void kb_spread_tile(const BItem *__restrict__ list,
+                                                          const BJob *__restrict__ jobs,
+                                                          const BIO *__restrict__ io) {
+  const BItem b = list[blockIdx.x];
+  const BJob &J = jobs[b.job];
+  KArgs ka{};
+  ka.x32 = io->x + J.xoff;
+  ka.perm = J.perm;
+  ka.dinv = J.dinv;
+  spread3_tile_body<W, T, IN_USER_F32_DINV, NW>(J.items[b.item], J.pts, ka, J.grid, J.nos,
+                                                J.wcoef);
+}
+
+template <int W, int T, int NW>
+__global__ __launch_bounds__(64 * NW) void kb_interp_tile(const BItem *__restrict__ list,
+                                                          const BJob *__restrict__ jobs,
+                                                          const BIO *__restrict__ io) {
+  const BItem b = list[blockIdx.x];
+  const BJob &J = jobs[b.job];
+  KArgs ka{};
+  ka.x32 = io->x + J.xoff;
+  ka.y32 = io->y + J.xoff;
+  ka.perm = J.perm;
+  ka.dinv = J.dinv;
+  interp3_tile_body<W, T, IN_USER_F32_DINV, OUT_USER_LS, NW>(J.items, b.item, J.pts, ka, J.grid2,
+                                                             J.nos, J.wcoef);
 }
 
 // Job of workgroup `blk`: the largest j with first[j] <= blk (first[0] = 0).
@@ -111,7 +143,7 @@ static int fft_blocks(int stage, int L, int N) {
   const int Hz = N / 2 + 1, F = N + 1;
   switch (stage) {
     case FFT_R2C:
-    case FFT_C2R: return (L * L + fft_lpb_z(L) - 1) / fft_lpb_z(L);
+    case FFT_C2R: return (L * L + fft_lpb_zr(L) - 1) / fft_lpb_zr(L);
     case FFT_YF:
     case FFT_YI: return L * ((Hz + fft_lpb_y(L) - 1) / fft_lpb_y(L));
     default: return (F * Hz + fft_lpb_z(L) - 1) / fft_lpb_z(L);
@@ -127,7 +159,7 @@ __global__ __launch_bounds__(FFT_THREADS) void kb_fft(const int *__restrict__ fi
   const int lb = blk - __builtin_amdgcn_readfirstlane(first[j]);
   const int L = J.nos, N = J.N, Hz = N / 2 + 1;
   if constexpr (STAGE == FFT_R2C)
-    r2c_lines_body(lb, J.grid, J.spec1, L * L, L, J.logL, J.lpz, Hz, J.tw);
+    r2c_lines_body<true>(lb, J.grid, J.spec1, L * L, L, J.logL, J.lpz, Hz, J.tw);
   else if constexpr (STAGE == FFT_YF)
     y_fwd_body(lb, J.spec1, J.spec2, L, J.logL, J.lpy, Hz, N, J.tw);
   else if constexpr (STAGE == FFT_XF)
@@ -135,20 +167,24 @@ __global__ __launch_bounds__(FFT_THREADS) void kb_fft(const int *__restrict__ fi
   else if constexpr (STAGE == FFT_YI)
     y_inv_body(lb, J.spec2, J.spec1, L, J.logL, J.lpy, Hz, N, J.tw);
   else
-    c2r_lines_body(lb, J.spec1, J.grid, L * L, L, J.logL, J.lpz, Hz, J.tw);
+    c2r_lines_body(lb, J.spec1, J.grid2, L * L, L, J.logL, J.lpz, Hz, J.tw);
 }
 
-// The spread or interpolation launches of all jobs of one window width W (and
-// z-merge mode for the spread): [0] four-wave workgroups, [1] one-wave
-// workgroups for short items.
+// The spread or interpolation launches of all jobs of one window width W and
+// kernel form (per-cell runs, z-merged per-cell runs, or tile-stationary with
+// tile T): [0] four-wave workgroups, [1] one-wave workgroups for short items.
+enum { FORM_RUNS = 0, FORM_ZMERGE = 1, FORM_TILE4 = 4, FORM_TILE8 = 8 };
 struct BGroup {
   int W = 0;
-  bool zm = false;
+  int form = FORM_RUNS;
   int begin[2] = {0, 0}, count[2] = {0, 0};   // ranges in the item list
   size_t lds_spread[2] = {0, 0}, lds_interp[2] = {0, 0};
 };
 
-static bool use_zmerge(int W, int T) { return W >= 9 && T + W - 1 <= 16; }
+static int kernel_form(int W, int T) {
+  if (T + W - 1 <= 16 && (T == 4 || T == 8)) return T == 4 ? FORM_TILE4 : FORM_TILE8;
+  return (W >= 9 && T + W - 1 <= 16) ? FORM_ZMERGE : FORM_RUNS;
+}
 
 template <class K>
 static int set_max_lds(K kern, size_t lds) {
@@ -162,9 +198,39 @@ template <int W, int NW>
 static int launch_group_wn(const BGroup &g, int v, const BItem *list, const BJob *jobs,
                            const BIO *io, hipStream_t s, bool spread_pass, bool prepare) {
   if (!prepare && g.count[v] == 0) return NFL_OK;
+  if constexpr (W + 3 <= 16) {
+    if (g.form == FORM_TILE4) {
+      if (spread_pass) {
+        if (prepare) return set_max_lds(kb_spread_tile<W, 4, NW>, g.lds_spread[v]);
+        hipLaunchKernelGGL((kb_spread_tile<W, 4, NW>), dim3(g.count[v]), dim3(64 * NW),
+                           g.lds_spread[v], s, list + g.begin[v], jobs, io);
+      } else {
+        if (prepare) return set_max_lds(kb_interp_tile<W, 4, NW>, g.lds_interp[v]);
+        hipLaunchKernelGGL((kb_interp_tile<W, 4, NW>), dim3(g.count[v]), dim3(64 * NW),
+                           g.lds_interp[v], s, list + g.begin[v], jobs, io);
+      }
+      NFL_HIP(hipGetLastError());
+      return NFL_OK;
+    }
+  }
+  if constexpr (W + 7 <= 16) {
+    if (g.form == FORM_TILE8) {
+      if (spread_pass) {
+        if (prepare) return set_max_lds(kb_spread_tile<W, 8, NW>, g.lds_spread[v]);
+        hipLaunchKernelGGL((kb_spread_tile<W, 8, NW>), dim3(g.count[v]), dim3(64 * NW),
+                           g.lds_spread[v], s, list + g.begin[v], jobs, io);
+      } else {
+        if (prepare) return set_max_lds(kb_interp_tile<W, 8, NW>, g.lds_interp[v]);
+        hipLaunchKernelGGL((kb_interp_tile<W, 8, NW>), dim3(g.count[v]), dim3(64 * NW),
+                           g.lds_interp[v], s, list + g.begin[v], jobs, io);
+      }
+      NFL_HIP(hipGetLastError());
+      return NFL_OK;
+    }
+  }
   if (spread_pass) {
     if constexpr (W >= 9) {
-      if (g.zm) {
+      if (g.form == FORM_ZMERGE) {
         if (prepare) return set_max_lds(kb_spread<W, true, NW>, g.lds_spread[v]);
         hipLaunchKernelGGL((kb_spread<W, true, NW>), dim3(g.count[v]), dim3(64 * NW),
                            g.lds_spread[v], s, list + g.begin[v], jobs, io);
@@ -249,7 +315,6 @@ namespace nfl {
 
 // The launch sequence of one batched product, enqueued on stream s.
 static int batch_sequence(nfl_batch_s *B, hipStream_t s) {
-  NFL_TRY(fill_f32(B->grids.p, B->grid_elems, 0.f, s));
   for (const BGroup &g : B->groups)
     NFL_TRY(launch_group(g, B->list.p, B->jobs.p, B->io.p, s, true));
   const int nj = B->njobs;
@@ -300,11 +365,14 @@ static int batch_build(nfl_batch_s *B) {
       s2sum += (int64_t)L * F * Hz;
     }
   }
-  NFL_TRY(B->grids.ensure((size_t)gsum));
+  NFL_TRY(B->grids.ensure((size_t)2 * gsum));
   NFL_TRY(B->spec1.ensure((size_t)s1sum));
   NFL_TRY(B->spec2.ensure((size_t)s2sum));
   B->grid_elems = gsum;
-  B->arena_bytes = gsum * 4 + (s1sum + s2sum) * 8;
+  B->arena_bytes = 2 * gsum * 4 + (s1sum + s2sum) * 8;
+  // the spread grids start clear; every replay leaves them clear again
+  NFL_TRY(fill_f32(B->grids.p, gsum, 0.f, B->stream));
+  NFL_HIP(hipStreamSynchronize(B->stream));
 
   for (int g = 0; g < np; ++g) {
     const nfl_plan *P = B->plans[g];
@@ -322,6 +390,7 @@ static int batch_build(nfl_batch_s *B) {
       J.filt = P->filt.p;
       J.tw = P->tw.p;
       J.grid = B->grids.p + goff[q];
+      J.grid2 = B->grids.p + gsum + goff[q];
       J.spec1 = B->spec1.p + s1off[q];
       J.spec2 = B->spec2.p + s2off[q];
       J.xoff = (int64_t)nv * B->off[g] + (int64_t)j * P->n;
@@ -329,7 +398,7 @@ static int batch_build(nfl_batch_s *B) {
       J.N = P->N;
       J.tshift = P->tshift;
       J.logL = logL;
-      J.lpz = fft_lpb_z(P->nos);
+      J.lpz = fft_lpb_zr(P->nos);
       J.lpy = fft_lpb_y(P->nos);
       J.lpx = fft_lpb_z(P->nos);
     }
@@ -339,7 +408,7 @@ static int batch_build(nfl_batch_s *B) {
   // mode; inside a group the items run longest first
   struct Key {
     int W;
-    bool zm;
+    int form;
   };
   std::vector<Key> keys;
   std::vector<std::vector<BItem>> glists;
@@ -349,23 +418,28 @@ static int batch_build(nfl_batch_s *B) {
     std::vector<Item> its((size_t)P->nitems);
     NFL_HIP(hipMemcpy(its.data(), P->items.p, its.size() * sizeof(Item), hipMemcpyDeviceToHost));
     const int W = 2 * P->m;
-    const bool zm = use_zmerge(W, 1 << P->tshift);
+    const int form = kernel_form(W, 1 << P->tshift);
     size_t k = 0;
-    while (k < keys.size() && !(keys[k].W == W && keys[k].zm == zm)) ++k;
+    while (k < keys.size() && !(keys[k].W == W && keys[k].form == form)) ++k;
     if (k == keys.size()) {
-      keys.push_back({W, zm});
+      keys.push_back({W, form});
       glists.emplace_back();
       glens.emplace_back();
       B->groups.emplace_back();
       B->groups.back().W = W;
-      B->groups.back().zm = zm;
+      B->groups.back().form = form;
     }
     const int Pd = (1 << P->tshift) + W - 1;
     const size_t p3 = (size_t)tile_px(Pd) * Pd;
     for (int v = 0; v < 2; ++v) {
       const size_t nw = v == 0 ? 4 : 1;
-      const size_t ls = (nw * p3 + nw * 16 * WT_SPREAD) * sizeof(float);
-      const size_t li = (p3 + nw * 16 * WT_INTERP) * sizeof(float);
+      size_t ls = (nw * p3 + nw * 16 * WT_SPREAD) * sizeof(float);
+      size_t li = (p3 + nw * 16 * WT_INTERP) * sizeof(float);
+      if (form == FORM_TILE4 || form == FORM_TILE8) {
+        const size_t tile = (size_t)Pd * ts_xs(Pd);
+        ls = std::max(tile + nw * 16 * TS_PITCH, nw >= 2 ? 2 * tile : tile) * sizeof(float);
+        li = (tile + nw * 16 * TS_PITCH_I) * sizeof(float);
+      }
       B->groups[k].lds_spread[v] = std::max(B->groups[k].lds_spread[v], ls);
       B->groups[k].lds_interp[v] = std::max(B->groups[k].lds_interp[v], li);
     }
@@ -420,7 +494,7 @@ static int batch_build(nfl_batch_s *B) {
     NFL_TRY(launch_group(g, nullptr, nullptr, nullptr, nullptr, true, true));
     NFL_TRY(launch_group(g, nullptr, nullptr, nullptr, nullptr, false, true));
   }
-  B->nkernels = 1 + FFT_STAGES;
+  B->nkernels = FFT_STAGES;
   for (const BGroup &g : B->groups) B->nkernels += 2 * ((g.count[0] > 0) + (g.count[1] > 0));
 
   // record the sequence once

@@ -6,6 +6,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
+#include <unordered_map>
 
 #include "nfft_device.h"
 #include "nfl_internal.h"
@@ -240,6 +242,23 @@ void k_interp3_mfma(const Item *__restrict__ items,
   interp3_mfma_body<W, IN, OUT>(items, blockIdx.x, pts, ka, grid, nos, tshift, wcoef);
 }
 
+// Tile-stationary forms (T + W - 1 <= 16), one workgroup per item.
+template <int W, int T, int IN>
+__global__ __launch_bounds__(256) void k_spread3_tile(const Item *__restrict__ items,
+                                                      const float4 *__restrict__ pts, KArgs ka,
+                                                      float *__restrict__ grid, int nos,
+                                                      const float *__restrict__ wcoef) {
+  spread3_tile_body<W, T, IN>(items[blockIdx.x], pts, ka, grid, nos, wcoef);
+}
+
+template <int W, int T, int IN, int OUT>
+__global__ __launch_bounds__(256) void k_interp3_tile(const Item *__restrict__ items,
+                                                      const float4 *__restrict__ pts, KArgs ka,
+                                                      const float *__restrict__ grid, int nos,
+                                                      const float *__restrict__ wcoef) {
+  interp3_tile_body<W, T, IN, OUT>(items, blockIdx.x, pts, ka, grid, nos, wcoef);
+}
+
 // ---------------------------------------------------------------------------
 // d = 1, 2: one thread per node, direct global accumulation / gathering.
 // ---------------------------------------------------------------------------
@@ -324,11 +343,12 @@ __global__ __launch_bounds__(256) void k_interp12(const float4 *__restrict__ pts
 
 
 // FFT passes of one plan (line layouts in the bodies' comments).
-__global__ __launch_bounds__(FFT_THREADS) void k_r2c_lines(const float *__restrict__ grid,
+template <bool ZERO>
+__global__ __launch_bounds__(FFT_THREADS) void k_r2c_lines(float *__restrict__ grid,
                                                            float2 *__restrict__ H, int nlines,
                                                            int L, int logL, int lpb, int Hz,
                                                            const float2 *__restrict__ tw) {
-  r2c_lines_body(blockIdx.x, grid, H, nlines, L, logL, lpb, Hz, tw);
+  r2c_lines_body<ZERO>(blockIdx.x, grid, H, nlines, L, logL, lpb, Hz, tw);
 }
 
 __global__ __launch_bounds__(FFT_THREADS) void k_c2r_lines(const float2 *__restrict__ H,
@@ -415,11 +435,19 @@ static size_t tile_lds_bytes(const nfl_plan *P) {
   return (size_t)Pd * Pd * Pd * sizeof(float);
 }
 
+// Raise a kernel's dynamic LDS limit once per process (per size): launches
+// recorded into a HIP graph then make no attribute calls.
 template <class K>
 static int set_lds(K kern, size_t lds) {
-  if (lds > 65536)
-    NFL_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)lds));
+  if (lds <= 65536) return NFL_OK;
+  static std::mutex mu;
+  static std::unordered_map<const void *, size_t> done;
+  std::lock_guard<std::mutex> lock(mu);
+  size_t &cur = done[(const void *)kern];
+  if (cur >= lds) return NFL_OK;
+  NFL_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds));
+  cur = lds;
   return NFL_OK;
 }
 
@@ -434,9 +462,46 @@ static int launch_spread3_mfma(nfl_plan *P, const KArgs &k, float *grid) {
   return NFL_OK;
 }
 
+static size_t tile_form_lds(int W, int T, bool spread) {
+  const int Pd = T + W - 1;
+  // spread: two tile copies must fit once the weight tables are free
+  const size_t tables = (size_t)4 * 16 * (spread ? TS_PITCH : TS_PITCH_I);
+  const size_t need = (size_t)Pd * ts_xs(Pd) + tables;
+  return std::max(need, spread ? (size_t)2 * Pd * ts_xs(Pd) : need) * sizeof(float);
+}
+
+template <int W, int T, int IN>
+static int launch_spread3_tile(nfl_plan *P, const KArgs &k, float *grid) {
+  const size_t lds = tile_form_lds(W, T, true);
+  NFL_TRY(set_lds(k_spread3_tile<W, T, IN>, lds));
+  hipLaunchKernelGGL((k_spread3_tile<W, T, IN>), dim3(P->nitems), dim3(256), lds, P->stream,
+                     P->items.p, P->pts.p, k, grid, P->nos, P->wcoef.p);
+  NFL_HIP(hipGetLastError());
+  return NFL_OK;
+}
+
+template <int W, int T, int IN, int OUT>
+static int launch_interp3_tile(nfl_plan *P, const KArgs &k, const float *grid) {
+  const size_t lds = tile_form_lds(W, T, false);
+  NFL_TRY(set_lds(k_interp3_tile<W, T, IN, OUT>, lds));
+  hipLaunchKernelGGL((k_interp3_tile<W, T, IN, OUT>), dim3(P->nitems), dim3(256), lds, P->stream,
+                     P->items.p, P->pts.p, k, grid, P->nos, P->wcoef.p);
+  NFL_HIP(hipGetLastError());
+  return NFL_OK;
+}
+
 template <int W, int IN>
 static int launch_spread3(nfl_plan *P, const KArgs &k, float *grid) {
   if (P->opt_kernel == 0) {
+    const int T = 1 << P->tshift;
+    if constexpr (W + 3 <= 16) {
+      if (T == 4) return launch_spread3_tile<W, 4, IN>(P, k, grid);
+    }
+    if constexpr (W + 7 <= 16) {
+      if (T == 8) return launch_spread3_tile<W, 8, IN>(P, k, grid);
+    }
+  }
+  if (P->opt_kernel != 1) {
     const int T = 1 << P->tshift;
     if constexpr (W >= 9) {
       if (T + W - 1 <= 16) return launch_spread3_mfma<W, IN, true>(P, k, grid);
@@ -454,6 +519,15 @@ static int launch_spread3(nfl_plan *P, const KArgs &k, float *grid) {
 template <int W, int IN, int OUT>
 static int launch_interp3(nfl_plan *P, const KArgs &k, const float *grid) {
   if (P->opt_kernel == 0) {
+    const int T = 1 << P->tshift;
+    if constexpr (W + 3 <= 16) {
+      if (T == 4) return launch_interp3_tile<W, 4, IN, OUT>(P, k, grid);
+    }
+    if constexpr (W + 7 <= 16) {
+      if (T == 8) return launch_interp3_tile<W, 8, IN, OUT>(P, k, grid);
+    }
+  }
+  if (P->opt_kernel != 1) {
     const int Pd = (1 << P->tshift) + W - 1;
     const size_t lds = ((size_t)tile_px(Pd) * Pd + 4 * 16 * WT_INTERP) * sizeof(float);
     NFL_TRY(set_lds(k_interp3_mfma<W, IN, OUT>, lds));
@@ -490,10 +564,10 @@ static int spread_in(nfl_plan *P, const KArgs &k, float *grid) {
   return NFL_OK;
 }
 
-int spread(nfl_plan *P, int in_mode, const VecArgs &a, float *grid) {
+int spread(nfl_plan *P, int in_mode, const VecArgs &a, float *grid, bool clear) {
   int64_t gsz = 1;
   for (int t = 0; t < P->d; ++t) gsz *= P->nos;
-  NFL_TRY(fill_f32(grid, gsz, 0.f, P->stream));
+  if (clear) NFL_TRY(fill_f32(grid, gsz, 0.f, P->stream));
   if (P->prof_ev) NFL_HIP(hipEventRecord(P->prof_ev[1], P->stream));
   const KArgs k = make_kargs(P, a);
   switch (in_mode) {
@@ -542,15 +616,18 @@ int interp(nfl_plan *P, const float *grid, int in_mode, int out_mode, const VecA
   return NFL_ERR_ARG;
 }
 
-int convolve(nfl_plan *P, const float *gin, float *gout) {
+int convolve(nfl_plan *P, const float *gin_c, float *gout, bool zero_in) {
+  // the input is written only when zero_in (then it is the plan's own grid)
+  float *gin = const_cast<float *>(gin_c);
+  auto r2c = zero_in ? k_r2c_lines<true> : k_r2c_lines<false>;
   const int L = P->nos, N = P->N, Hz = N / 2 + 1, F = N + 1;
   int logL = 0;
   while ((1 << logL) < L) ++logL;
-  const int lpz = fft_lpb_z(L);
-  const size_t ldz = fft_lds_bytes(lpz, L);
+  const int lpz = fft_lpb_zr(L);                 // real lines per workgroup, two per FFT
+  const size_t ldz = fft_lds_bytes(lpz / 2, L);
   const float2 *tw = P->tw.p;
   if (P->d == 1) {
-    hipLaunchKernelGGL(k_r2c_lines, dim3(1), dim3(FFT_THREADS), ldz, P->stream, gin, P->spec1.p,
+    hipLaunchKernelGGL(r2c, dim3(1), dim3(FFT_THREADS), ldz, P->stream, gin, P->spec1.p,
                        1, L, logL, lpz, Hz, tw);
     hipLaunchKernelGGL(k_filter1, dim3(1), dim3(256), 0, P->stream, P->spec1.p, P->filt.p, Hz);
     hipLaunchKernelGGL(k_c2r_lines, dim3(1), dim3(FFT_THREADS), ldz, P->stream, P->spec1.p, gout,
@@ -558,7 +635,7 @@ int convolve(nfl_plan *P, const float *gin, float *gout) {
   } else if (P->d == 2) {
     const int nlines = L;
     const int nb = (nlines + lpz - 1) / lpz;
-    hipLaunchKernelGGL(k_r2c_lines, dim3(nb), dim3(FFT_THREADS), ldz, P->stream, gin, P->spec1.p,
+    hipLaunchKernelGGL(r2c, dim3(nb), dim3(FFT_THREADS), ldz, P->stream, gin, P->spec1.p,
                        nlines, L, logL, lpz, Hz, tw);
     hipLaunchKernelGGL(k_x_filter, dim3(Hz), dim3(FFT_THREADS), fft_lds_bytes(1, L), P->stream,
                        P->spec1.p, P->filt.p, Hz, L, logL, 1, N, tw);
@@ -567,7 +644,7 @@ int convolve(nfl_plan *P, const float *gin, float *gout) {
   } else {
     const int nlines = L * L;
     const int nb = (nlines + lpz - 1) / lpz;
-    hipLaunchKernelGGL(k_r2c_lines, dim3(nb), dim3(FFT_THREADS), ldz, P->stream, gin, P->spec1.p,
+    hipLaunchKernelGGL(r2c, dim3(nb), dim3(FFT_THREADS), ldz, P->stream, gin, P->spec1.p,
                        nlines, L, logL, lpz, Hz, tw);
     const int lpy = fft_lpb_y(L), ngroups = (Hz + lpy - 1) / lpy;
     const size_t ldy = fft_lds_bytes(lpy, L);
@@ -586,13 +663,19 @@ int convolve(nfl_plan *P, const float *gin, float *gout) {
   return NFL_OK;
 }
 
+// Two grids: the spread accumulates into `grid`, which the r2c pass reads and
+// leaves zero for the next product (so no separate clear once it is clean);
+// the c2r pass writes `grid2`, which the interpolation reads.
 int fastsum(nfl_plan *P, int in_mode, int out_mode, const VecArgs &a) {
   if (P->prof_ev) NFL_HIP(hipEventRecord(P->prof_ev[0], P->stream));
-  NFL_TRY(spread(P, in_mode, a, P->grid.p));
+  const bool clear = !P->grid_clean;
+  P->grid_clean = false;
+  NFL_TRY(spread(P, in_mode, a, P->grid.p, clear));
   if (P->prof_ev) NFL_HIP(hipEventRecord(P->prof_ev[2], P->stream));
-  NFL_TRY(convolve(P, P->grid.p, P->grid.p));
+  NFL_TRY(convolve(P, P->grid.p, P->grid2.p, true));
+  P->grid_clean = true;
   if (P->prof_ev) NFL_HIP(hipEventRecord(P->prof_ev[3], P->stream));
-  NFL_TRY(interp(P, P->grid.p, in_mode, out_mode, a));
+  NFL_TRY(interp(P, P->grid2.p, in_mode, out_mode, a));
   if (P->prof_ev) NFL_HIP(hipEventRecord(P->prof_ev[4], P->stream));
   return NFL_OK;
 }

@@ -229,7 +229,7 @@ __device__ __forceinline__ void spread3_mfma_body(const Item it, const float4 *_
   for (int u = 0; u < 4; ++u) {
     const int o = 4 * (lane & 3) + u;   // the offsets this lane evaluates in fill_weights
 #pragma unroll
-    for (int k = 0; k < WIN_NC; ++k) cf[u][k] = o < W ? wcoef[o * WIN_NC + k] : 0.f;
+    for (int k = 0; k < WIN_NC; ++k) cf[u][k] = wcoef[o * WIN_NC + k];   // rows 2m..15 of the table are 0
   }
   f32x4 acc[NB];
 #pragma unroll
@@ -386,7 +386,7 @@ __device__ __forceinline__ void interp3_mfma_body(const Item *__restrict__ items
   for (int u = 0; u < 4; ++u) {
     const int o = 4 * (lane & 3) + u;   // the offsets this lane evaluates in fill_weights
 #pragma unroll
-    for (int k = 0; k < WIN_NC; ++k) cf[u][k] = o < W ? wcoef[o * WIN_NC + k] : 0.f;
+    for (int k = 0; k < WIN_NC; ++k) cf[u][k] = wcoef[o * WIN_NC + k];   // rows 2m..15 of the table are 0
   }
   float g[NQ];
   uint32_t cur = 0xffffffffu;
@@ -449,6 +449,275 @@ __device__ __forceinline__ void interp3_mfma_body(const Item *__restrict__ items
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Tile-stationary spread and interpolation (T + W - 1 <= 16).
+//
+// All nodes of a work item lie in one T^3 tile, so all their windows lie in
+// the padded tile of P = T + W - 1 <= 16 cells per axis, and the 16 x 16 block
+// of v_mfma_f32_16x16x4_f32 covers a whole x-by-z slice of it.  With the
+// window rows of every node shifted to its cell's place in the padded tile,
+// the contraction runs over arbitrary groups of 4 nodes, whatever their cells:
+//   spread:  G[ax][ay][az] += sum_p (x_p wx_p[ax]) (wy_p[ay] wz_p[az]),
+//            rows ax, K = 4 nodes, columns az, one accumulator per ay (P of
+//            them): the wave's whole padded tile stays in registers, so there
+//            are no per-cell runs and no per-run flushes; at the end the
+//            waves add their tiles into one LDS copy (ds_add_f32), which is
+//            added into the grid with global atomics;
+//   interp:  D[ax][p] = sum_{ay,az} G[ax][ay][az] wy_p[ay] wz_p[az] with the
+//            item's padded tile as the register-resident A operand (loaded
+//            once per item), 16 nodes as the columns, K = (ay, az) in 4P
+//            steps; f_p = sum_ax wx_p[ax] D[ax][p].
+// Weight table per wave: 16 node rows of TS_PITCH words, the shifted x, y and
+// z rows at word 0, 32 and 64 (row entries outside the node's window are 0).
+// The LDS tile is laid out [ax][ay * 16 + az] with row stride TS_XS(P).
+// ---------------------------------------------------------------------------
+// Row pitches: the spread reads two node rows per half-wave (pitch = 16 mod
+// 32 puts them 16 banks apart); the interpolation reads 16 node rows per
+// half-wave, including 16-byte reads (pitch/4 odd: eight consecutive rows in
+// distinct 4-bank groups).
+constexpr int TS_PITCH = 112, TS_PITCH_I = 100;
+
+__host__ __device__ constexpr int ts_xs(int P) { return P * 16 + 4; }   // 4 rows apart = 16 banks
+
+// Fill the shifted weight rows of sub-batch nodes sub*16 .. sub*16+15: lane l
+// evaluates node l/4 at offsets 4 (l%4) .. +3 and writes them at offset + its
+// cell's position in the tile.  SPREAD: the x row carries x_p wx_p (x_p = 0
+// for nodes past cnt).
+template <int T, bool SPREAD, int PITCH>
+__device__ __forceinline__ void fill_shifted(const float4 &qb, float xb, int sub, int cnt,
+                                             int lane, const float (&cf)[4][WIN_NC], float *wt,
+                                             int ox, int oy, int oz) {
+  const int node = lane >> 2, part = lane & 3;
+  const int src = sub * 16 + min(node, cnt - 1);
+  const float qx = __shfl(qb.x, src), qy = __shfl(qb.y, src), qz = __shfl(qb.z, src);
+  const uint32_t cell = (uint32_t)__shfl((int)__float_as_uint(qb.w), src);
+  float xv = 1.f;
+  if constexpr (SPREAD) {
+    xv = __shfl(xb, src);
+    if (node >= cnt) xv = 0.f;
+  }
+  const int lx = (int)(cell & 1023u) - ox, ly = (int)((cell >> 10) & 1023u) - oy,
+            lz = (int)(cell >> 20) - oz;
+  float *row = wt + node * PITCH;
+  if (part == 0) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int z = 0; z < T; z += 4)
+        *reinterpret_cast<float4 *>(row + 32 * a + z) = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int o = 4 * part + u;
+    row[lx + o] = xv * win_poly(cf[u], qx);
+    row[32 + ly + o] = win_poly(cf[u], qy);
+    row[64 + lz + o] = win_poly(cf[u], qz);
+  }
+}
+
+template <int W, int T, int IN, int NW = 4>
+__device__ __forceinline__ void spread3_tile_body(const Item it, const float4 *__restrict__ pts,
+                                                  const KArgs ka, float *__restrict__ grid,
+                                                  int nos, const float *__restrict__ wcoef) {
+  constexpr int M = W / 2, P = T + W - 1, XS = ts_xs(P);
+  static_assert(P <= 16, "tile-stationary form needs T + W - 1 <= 16");
+  extern __shared__ float lds[];
+  const int ntd = nos / T;
+  const int tz = it.tile % ntd, ty = (it.tile / ntd) % ntd, tx = it.tile / (ntd * ntd);
+  const int ox = tx * T, oy = ty * T, oz = tz * T;
+
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int c16 = lane & 15, p4 = lane >> 4;
+  float *wt = lds + P * XS + wave * (16 * TS_PITCH);
+  const int len = it.end - it.start, per = (len + NW - 1) / NW;
+  const int s = it.start + min(len, wave * per), e = it.start + min(len, (wave + 1) * per);
+
+  float cf[4][WIN_NC];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int o = 4 * (lane & 3) + u;
+#pragma unroll
+    for (int k = 0; k < WIN_NC; ++k) cf[u][k] = wcoef[o * WIN_NC + k];   // rows 2m..15 of the table are 0
+  }
+  f32x4 acc[P];
+#pragma unroll
+  for (int y = 0; y < P; ++y) acc[y] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  float4 qb, qn;
+  float xb, xn;
+  load_batch<IN, true>(pts, ka, s, e, lane, qb, xb);
+  for (int b0 = s; b0 < e; b0 += 64) {
+    load_batch<IN, true>(pts, ka, b0 + 64, e, lane, qn, xn);  // prefetch the next batch
+    const int bcnt = min(64, e - b0);
+    for (int sb = 0; sb * 16 < bcnt; ++sb) {
+      const int cnt = min(16, bcnt - sb * 16);
+      fill_shifted<T, true, TS_PITCH>(qb, xb, sb, cnt, lane, cf, wt, ox, oy, oz);
+      wave_sync_lds();
+      for (int st = 0; st * 4 < cnt; ++st) {
+        const float *w = wt + (4 * st + p4) * TS_PITCH;
+        const float a = w[c16];
+        const float wz = w[64 + c16];
+        float wy[16];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float4 v = *reinterpret_cast<const float4 *>(w + 32 + 4 * q);
+          wy[4 * q] = v.x;
+          wy[4 * q + 1] = v.y;
+          wy[4 * q + 2] = v.z;
+          wy[4 * q + 3] = v.w;
+        }
+#pragma unroll
+        for (int y = 0; y < P; ++y)
+          acc[y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, wy[y] * wz, acc[y], 0, 0, 0);
+      }
+      wave_sync_lds();
+    }
+    qb = qn;
+    xb = xn;
+  }
+  // Sum the waves' tiles without LDS atomics (measured far slower than plain
+  // LDS traffic): once every wave is done with its weight table, waves 0 and 1
+  // store their tiles into copies C0 and C1 (the LDS of the tables), then
+  // waves 2 and 3 add theirs into C0 and C1; the flush adds C0 + C1.
+  constexpr int NC = NW >= 2 ? 2 : 1;
+  static_assert(NW == 1 || NW == 2 || NW == 4, "one, two or four waves");
+  __syncthreads();
+  {
+    float *cp = lds + (wave % NC) * (P * XS);
+    auto put = [&](bool add) {
+      if (c16 < P) {
+#pragma unroll
+        for (int y = 0; y < P; ++y)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int ax = 4 * p4 + r;
+            if (ax < P) {
+              float *q = cp + ax * XS + y * 16 + c16;
+              *q = add ? *q + acc[y][r] : acc[y][r];
+            }
+          }
+      }
+    };
+    if (wave < NC) put(false);
+    __syncthreads();
+    if (NW == 4 && wave >= NC) put(true);
+    __syncthreads();
+  }
+  // into the grid: each wave takes rows (px, py), four at a time, z along lanes
+  const int mask = nos - 1;
+  const int pz = lane & 15, rsub = lane >> 4;
+  for (int row0 = wave * 4; row0 < P * P; row0 += NW * 4) {
+    const int row = row0 + rsub;
+    if (row < P * P && pz < P) {
+      const int px = row / P, py = row - px * P;
+      const int o = px * XS + py * 16 + pz;
+      const float v = NC == 2 ? lds[o] + lds[P * XS + o] : lds[o];
+      if (v != 0.f) {
+        const int gx = (ox - (M - 1) + px) & mask, gy = (oy - (M - 1) + py) & mask,
+                  gz = (oz - (M - 1) + pz) & mask;
+        unsafeAtomicAdd(&grid[((size_t)gx * nos + gy) * nos + gz], v);
+      }
+    }
+  }
+}
+
+template <int W, int T, int IN, int OUT, int NW = 4>
+__device__ __forceinline__ void interp3_tile_body(const Item *__restrict__ items, int item,
+                                                  const float4 *__restrict__ pts,
+                                                  const KArgs ka,
+                                                  const float *__restrict__ grid, int nos,
+                                                  const float *__restrict__ wcoef) {
+  constexpr int M = W / 2, P = T + W - 1, XS = ts_xs(P), NS = 4 * P;
+  static_assert(P <= 16, "tile-stationary form needs T + W - 1 <= 16");
+  extern __shared__ float lds[];
+  float *tile = lds;
+  const Item it = items[item];
+  const int ntd = nos / T;
+  const int tz = it.tile % ntd, ty = (it.tile / ntd) % ntd, tx = it.tile / (ntd * ntd);
+  const int ox = tx * T, oy = ty * T, oz = tz * T;
+  const int mask = nos - 1;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int c16 = lane & 15, p4 = lane >> 4;
+  {
+    // stage the padded tile, z padded to 16 with zeros
+    for (int row0 = wave * 4; row0 < P * P; row0 += NW * 4) {
+      const int row = row0 + p4;
+      if (row < P * P) {
+        const int px = row / P, py = row - px * P;
+        float v = 0.f;
+        if (c16 < P) {
+          const int gx = (ox - (M - 1) + px) & mask, gy = (oy - (M - 1) + py) & mask,
+                    gz = (oz - (M - 1) + c16) & mask;
+          v = grid[((size_t)gx * nos + gy) * nos + gz];
+        }
+        tile[px * XS + py * 16 + c16] = v;
+      }
+    }
+  }
+  __syncthreads();
+  // A operand: lane (row c16, k = p4) holds G[c16][4 s + p4], s < 4P
+  float g[NS];
+#pragma unroll
+  for (int st = 0; st < NS; ++st) g[st] = c16 < P ? tile[c16 * XS + 4 * st + p4] : 0.f;
+
+  float *wt = lds + P * XS + wave * (16 * TS_PITCH_I);
+  const int len = it.end - it.start, per = (len + NW - 1) / NW;
+  const int s = it.start + min(len, wave * per), e = it.start + min(len, (wave + 1) * per);
+  float cf[4][WIN_NC];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int o = 4 * (lane & 3) + u;
+#pragma unroll
+    for (int k = 0; k < WIN_NC; ++k) cf[u][k] = wcoef[o * WIN_NC + k];   // rows 2m..15 of the table are 0
+  }
+  float4 qb, qn;
+  float xb, xn;
+  load_batch<IN, false>(pts, ka, s, e, lane, qb, xb);
+  for (int b0 = s; b0 < e; b0 += 64) {
+    load_batch<IN, false>(pts, ka, b0 + 64, e, lane, qn, xn);  // prefetch the next batch
+    const int bcnt = min(64, e - b0);
+    for (int sb = 0; sb * 16 < bcnt; ++sb) {
+      const int cnt = min(16, bcnt - sb * 16);
+      const int i0 = b0 + sb * 16;
+      fill_shifted<T, false, TS_PITCH_I>(qb, xb, sb, cnt, lane, cf, wt, ox, oy, oz);
+      wave_sync_lds();
+      const float *w = wt + c16 * TS_PITCH_I;    // column c16 = node c16
+      float wz4[4], wy[16];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) wz4[q] = w[64 + 4 * q + p4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float4 v = *reinterpret_cast<const float4 *>(w + 32 + 4 * q);
+        wy[4 * q] = v.x;
+        wy[4 * q + 1] = v.y;
+        wy[4 * q + 2] = v.z;
+        wy[4 * q + 3] = v.w;
+      }
+      f32x4 d[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) d[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int st = 0; st < NS; ++st)
+        d[st & 3] = __builtin_amdgcn_mfma_f32_16x16x4f32(g[st], wy[st >> 2] * wz4[st & 3],
+                                                         d[st & 3], 0, 0, 0);
+      float part = 0.f;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float dr = (d[0][r] + d[1][r]) + (d[2][r] + d[3][r]);
+        part = fmaf(w[4 * p4 + r], dr, part);
+      }
+      part += __shfl_xor(part, 16);
+      part += __shfl_xor(part, 32);
+      if (p4 == 0 && c16 < cnt) store_out<OUT>(ka, i0 + c16, part);
+      wave_sync_lds();
+    }
+    qb = qn;
+    xb = xn;
+  }
+}
 
 // ---------------------------------------------------------------------------
 // FFT: Stockham autosort in LDS on `nl` lines of length L = nos (a power of
@@ -545,6 +814,8 @@ __host__ __device__ __forceinline__ size_t fft_lds_bytes(int lpb, int L) {
 //     FFT_ELEMS / L;
 //   x pass: enough workgroups (>= 512) for the (N+1)(N/2+1) columns.
 __host__ __device__ __forceinline__ int fft_lpb_z(int L) { return L >= FFT_ELEMS ? 1 : FFT_ELEMS / L; }
+// real lines per workgroup of the r2c / c2r passes (two per complex line)
+__host__ __device__ __forceinline__ int fft_lpb_zr(int L) { return 2 * fft_lpb_z(L); }
 __host__ __device__ __forceinline__ int fft_lpb_y(int L) {
   const int Hz = L / 4 + 1, mx = fft_lpb_z(L);
   const int groups = (Hz + mx - 1) / mx;
@@ -559,49 +830,72 @@ __host__ __device__ __forceinline__ int fft_lpb_x(int L) {
 }
 
 // Real lines along the last (contiguous) axis -> half spectrum lz in [0, Hz).
-__device__ __forceinline__ void r2c_lines_body(int blk, const float *__restrict__ grid,
+// Two real lines a, b go through one complex transform of z = a + i b; with
+// Z = FFT(z): A[k] = (Z[k] + conj Z[-k]) / 2, B[k] = (Z[k] - conj Z[-k]) / (2i).
+// lpb real lines (an even number) per workgroup.  ZERO: each input element is
+// set to 0 after it is read (every element is read once, by one thread), which
+// leaves the spread grid clear for the next product.
+template <bool ZERO = false>
+__device__ __forceinline__ void r2c_lines_body(int blk, float *__restrict__ grid,
                                                float2 *__restrict__ H, int nlines, int L,
                                                int logL, int lpb, int Hz,
                                                const float2 *__restrict__ tw) {
   extern __shared__ float2 sm[];
-  float2 *a = sm, *b = sm + lpb * L, *twl = sm + 2 * lpb * L;
+  const int np = lpb >> 1;
+  float2 *a = sm, *b = sm + np * L, *twl = sm + 2 * np * L;
   load_twiddles(twl, tw, L);
   const int l0 = blk * lpb;
-  const int nl = min(lpb, nlines - l0);
-  for (int idx = threadIdx.x; idx < lpb * L; idx += FFT_THREADS) {
-    const int li = idx / L;
-    a[idx] = make_float2(li < nl ? grid[(size_t)l0 * L + idx] : 0.f, 0.f);
+  const int nl = min(lpb, nlines - l0), npp = (nl + 1) >> 1;
+  for (int idx = threadIdx.x; idx < npp * L; idx += FFT_THREADS) {
+    const int pl = idx / L, j = idx - pl * L;
+    float *pa = grid + (size_t)(l0 + 2 * pl) * L + j;
+    const float re = *pa;
+    const float im = 2 * pl + 1 < nl ? pa[L] : 0.f;
+    a[idx] = make_float2(re, im);
+    if (ZERO) {
+      *pa = 0.f;
+      if (2 * pl + 1 < nl) pa[L] = 0.f;
+    }
   }
   __syncthreads();
-  lds_fft<-1>(a, b, L, logL, nl, twl);
+  lds_fft<-1>(a, b, L, logL, npp, twl);
   for (int idx = threadIdx.x; idx < nl * Hz; idx += FFT_THREADS) {
-    const int li = idx / Hz, lz = idx - li * Hz;
-    H[(size_t)(l0 + li) * Hz + lz] = a[li * L + lz];
+    const int li = idx / Hz, k = idx - li * Hz, pl = li >> 1;
+    const float2 zk = a[pl * L + k], zm = a[pl * L + ((L - k) & (L - 1))];
+    H[(size_t)(l0 + li) * Hz + k] = (li & 1) == 0
+                                        ? make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y))
+                                        : make_float2(0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x));
   }
 }
 
-// Half spectrum (lz in [0, Hz), Hermitian in lz) -> real lines.
+// Half spectra (lz in [0, Hz), Hermitian in lz, zero beyond) -> real lines,
+// two per complex transform: IFFT(A + i B) = a + i b for real a, b.
 __device__ __forceinline__ void c2r_lines_body(int blk, const float2 *__restrict__ H,
                                                float *__restrict__ grid, int nlines, int L,
                                                int logL, int lpb, int Hz,
                                                const float2 *__restrict__ tw) {
   extern __shared__ float2 sm[];
-  float2 *a = sm, *b = sm + lpb * L, *twl = sm + 2 * lpb * L;
+  const int np = lpb >> 1;
+  float2 *a = sm, *b = sm + np * L, *twl = sm + 2 * np * L;
   load_twiddles(twl, tw, L);
   const int l0 = blk * lpb;
-  const int nl = min(lpb, nlines - l0);
-  for (int idx = threadIdx.x; idx < nl * L; idx += FFT_THREADS) a[idx] = make_float2(0.f, 0.f);
+  const int nl = min(lpb, nlines - l0), npp = (nl + 1) >> 1;
+  for (int idx = threadIdx.x; idx < npp * L; idx += FFT_THREADS) a[idx] = make_float2(0.f, 0.f);
   __syncthreads();
-  for (int idx = threadIdx.x; idx < nl * Hz; idx += FFT_THREADS) {
-    const int li = idx / Hz, lz = idx - li * Hz;
-    const float2 h = H[(size_t)(l0 + li) * Hz + lz];
-    a[li * L + lz] = h;
-    if (lz > 0) a[li * L + L - lz] = make_float2(h.x, -h.y);
+  for (int idx = threadIdx.x; idx < npp * Hz; idx += FFT_THREADS) {
+    const int pl = idx / Hz, k = idx - pl * Hz;
+    const float2 A = H[(size_t)(l0 + 2 * pl) * Hz + k];
+    const float2 B = 2 * pl + 1 < nl ? H[(size_t)(l0 + 2 * pl + 1) * Hz + k] : make_float2(0.f, 0.f);
+    a[pl * L + k] = make_float2(A.x - B.y, A.y + B.x);                  // A + i B
+    if (k > 0) a[pl * L + L - k] = make_float2(A.x + B.y, B.x - A.y);   // conj A + i conj B
   }
   __syncthreads();
-  lds_fft<+1>(a, b, L, logL, nl, twl);
-  for (int idx = threadIdx.x; idx < nl * L; idx += FFT_THREADS)
-    grid[(size_t)l0 * L + idx] = a[idx].x;
+  lds_fft<+1>(a, b, L, logL, npp, twl);
+  for (int idx = threadIdx.x; idx < nl * L; idx += FFT_THREADS) {
+    const int li = idx / L, j = idx - li * L;
+    const float2 v = a[(li >> 1) * L + j];
+    grid[(size_t)l0 * L + idx] = (li & 1) ? v.y : v.x;
+  }
 }
 
 // d = 3 middle axis (y), forward: H1[(x*L + y)*Hz + lz] -> H2[(x*F + y')*Hz + lz],

@@ -113,11 +113,13 @@ struct nfl_plan {
 
   // FFT / filter
   nfl::DBuf<float> wcoef;       // window polynomials, WIN_MAXW x WIN_NC
-  int opt_kernel = 0;           // 0: MFMA spread/interp (d = 3), 1: VALU
+  int opt_kernel = 0;           // 0: MFMA (tile-stationary where possible), 1: VALU, 2: MFMA per-cell runs
   nfl::DBuf<float> filt;        // half spectrum, FP32
   std::vector<double> filt_host;
   nfl::DBuf<float2> tw;         // e^{-2 pi i k / nos}, k < nos/2
-  nfl::DBuf<float> grid;        // nos^d real
+  nfl::DBuf<float> grid;        // nos^d real: spread output, left zero by the r2c pass
+  nfl::DBuf<float> grid2;       // nos^d real: c2r output, interpolation input
+  bool grid_clean = false;      // `grid` is known to be zero
   nfl::DBuf<float2> spec1, spec2;
 
   // degrees (sorted order)
@@ -179,8 +181,9 @@ struct VecArgs {
   double tau = 0;
 };
 
-int spread(nfl_plan *P, int in_mode, const VecArgs &a, float *grid);
-int convolve(nfl_plan *P, const float *gin, float *gout);
+int spread(nfl_plan *P, int in_mode, const VecArgs &a, float *grid, bool clear = true);
+// zero_in: the r2c pass sets the input grid to 0 as it reads it
+int convolve(nfl_plan *P, const float *gin, float *gout, bool zero_in = false);
 int interp(nfl_plan *P, const float *grid, int in_mode, int out_mode, const VecArgs &a);
 // whole fast summation with the given input/output modes (grid = plan grid)
 int fastsum(nfl_plan *P, int in_mode, int out_mode, const VecArgs &a);

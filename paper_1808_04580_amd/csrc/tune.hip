@@ -11,7 +11,8 @@
 //      power-of-2 N whose error at the widest window (m = min(8, N/2)) is
 //      below 0.3 x target; the smallest such N wins;
 //   2. window: the smallest m at that N and eps_B with error <= 0.7 x target;
-//   3. tile: the fastest of T = 4, 8, 16 (d = 3), timed with HIP events.
+//   3. tile: the fastest of T = 4, 8, 16 (d = 3), timed as a captured HIP
+//      graph of products (GPU time, without host launch overhead).
 // Results are kept in a text cache keyed by (d, size class of n, band of
 // sigma~, target).  A cached configuration is verified on the graph at hand
 // with the same probe and tuned afresh if it misses the target.
@@ -208,29 +209,50 @@ static int probe_error(nfl_plan *P, Probe &pr, double *err) {
   return NFL_OK;
 }
 
-// Average milliseconds of one L_s product (HIP events on the plan's stream).
+// Average milliseconds of one L_s product on the GPU: `reps` products are
+// captured into a HIP graph (on a private stream, with the plan's stream
+// swapped out during the capture) and the graph launch is timed with HIP
+// events on the plan's stream, so small graphs are timed without the host's
+// launch overhead.  The product path records no memset nodes.
 static int probe_time(nfl_plan *P, Probe &pr, int reps, double *ms) {
   VecArgs a;
   a.x32 = pr.x.p;
   a.y32 = pr.y.p;
-  for (int r = 0; r < 2; ++r) NFL_TRY(fastsum(P, IN_USER_F32_DINV, OUT_USER_LS, a));
-  hipEvent_t e0, e1;
-  NFL_HIP(hipEventCreate(&e0));
-  NFL_HIP(hipEventCreate(&e1));
+  NFL_TRY(fastsum(P, IN_USER_F32_DINV, OUT_USER_LS, a));   // kernel attributes set outside capture
+  hipStream_t cap = nullptr, user = P->stream;
+  NFL_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ge = nullptr;
   int rc = NFL_OK;
-  if (hipEventRecord(e0, P->stream) != hipSuccess) rc = NFL_ERR_HIP;
+  P->stream = cap;
+  if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) rc = NFL_ERR_HIP;
   for (int r = 0; r < reps && rc == NFL_OK; ++r) rc = fastsum(P, IN_USER_F32_DINV, OUT_USER_LS, a);
+  const hipError_t ec = hipStreamEndCapture(cap, &g);
+  P->stream = user;
+  if (rc == NFL_OK && ec != hipSuccess) rc = NFL_ERR_HIP;
+  if (rc == NFL_OK && hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) rc = NFL_ERR_HIP;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
   float t = 0.f;
-  if (rc == NFL_OK && (hipEventRecord(e1, P->stream) != hipSuccess ||
-                       hipEventSynchronize(e1) != hipSuccess ||
-                       hipEventElapsedTime(&t, e0, e1) != hipSuccess)) {
-    set_error("autotune: event timing failed");
+  if (rc == NFL_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
     rc = NFL_ERR_HIP;
+  if (rc == NFL_OK && (hipGraphLaunch(ge, user) != hipSuccess ||      // warm
+                       hipEventRecord(e0, user) != hipSuccess ||
+                       hipGraphLaunch(ge, user) != hipSuccess ||
+                       hipEventRecord(e1, user) != hipSuccess ||
+                       hipEventSynchronize(e1) != hipSuccess ||
+                       hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+    rc = NFL_ERR_HIP;
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (ge) (void)hipGraphExecDestroy(ge);
+  if (g) (void)hipGraphDestroy(g);
+  (void)hipStreamDestroy(cap);
+  if (rc != NFL_OK) {
+    set_error("autotune: graph timing failed");
+    return rc;
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   *ms = t / reps;
-  return rc;
+  return NFL_OK;
 }
 
 // ---- cache ------------------------------------------------------------------

@@ -43,6 +43,19 @@ def test_error_codes_without_gpu():
     out = np.empty(10)
     assert L.nfl_compute_filter(3, 15, 4, 4, 0.0, 0.1, out.ctypes.data_as(ctypes.c_void_p), 10) \
         == nfl.NFL_ERR_ARG
+    # batches, the accuracy probe and the tuner reject null handles / bad
+    # arguments before touching a device
+    b = ctypes.c_void_p()
+    assert L.nfl_batch_create(None, None, 1, 1, None) == nfl.NFL_ERR_ARG
+    assert L.nfl_batch_create(ctypes.byref(b), None, 0, 8, None) == nfl.NFL_ERR_ARG
+    assert L.nfl_batch_apply_Ls(None, None, None) == nfl.NFL_ERR_ARG
+    assert L.nfl_batch_offsets(None, None, 0) == nfl.NFL_ERR_ARG
+    assert L.nfl_batch_info(None, None, None, None, None) == nfl.NFL_ERR_ARG
+    assert L.nfl_batch_destroy(None) == nfl.NFL_OK
+    assert L.nfl_direct_rows(None, 0.1, None, None, 1, None, None) == nfl.NFL_ERR_ARG
+    assert L.nfl_autotune(None, 0.1, 1e-5, 64, 1, None, None, None, None, None, None, None,
+                          None) == nfl.NFL_ERR_ARG
+    assert L.nfl_set_option(None, nfl.OPT_KERNEL, 2) == nfl.NFL_ERR_ARG
 
 
 def kb_hat_quadrature(xi, m, b=1.5 * math.pi, nq=2001):

@@ -87,7 +87,14 @@ def make(nfl, v, sigma, N, m, eps_B=0.0, tile=None, chunk=None, kernel=0):
 
 CASES = [
     # (d, n, N, m, tile, chunk, kernel) -- several tiles, ragged n, several items
-    # per tile; kernel 0 = matrix cores, 1 = vector ALU (d = 3 only)
+    # per tile; kernel 0 = matrix cores (tile-stationary where tile + 2m - 1 <= 16,
+    # else per-cell runs), 1 = vector ALU, 2 = matrix cores with per-cell runs
+    # (d = 3 only)
+    (3, 2777, 32, 4, 8, 256, 0),
+    (3, 2222, 32, 3, 8, 100, 0),
+    (3, 3333, 32, 6, 4, 200, 2),
+    (3, 4099, 32, 5, 4, 96, 2),
+    (3, 3001, 16, 4, 4, 64, 2),
     (3, 3001, 16, 4, 4, 64, 0),
     (3, 3001, 16, 4, 4, 64, 1),
     (3, 2500, 32, 6, 8, 128, 0),
