@@ -437,7 +437,8 @@ static int batch_build(nfl_batch_s *B) {
       size_t li = (p3 + nw * 16 * WT_INTERP) * sizeof(float);
       if (form == FORM_TILE4 || form == FORM_TILE8) {
         const size_t tile = (size_t)Pd * ts_xs(Pd);
-        ls = std::max(tile + nw * 16 * TS_PITCH, nw >= 2 ? 2 * tile : tile) * sizeof(float);
+        const size_t copies = (nw >= 2 ? 2 : 1) * (size_t)16 * ts_xs(Pd);
+        ls = std::max(tile + nw * 16 * TS_PITCH, copies) * sizeof(float);
         li = (tile + nw * 16 * TS_PITCH_I) * sizeof(float);
       }
       B->groups[k].lds_spread[v] = std::max(B->groups[k].lds_spread[v], ls);

@@ -467,7 +467,7 @@ static size_t tile_form_lds(int W, int T, bool spread) {
   // spread: two tile copies must fit once the weight tables are free
   const size_t tables = (size_t)4 * 16 * (spread ? TS_PITCH : TS_PITCH_I);
   const size_t need = (size_t)Pd * ts_xs(Pd) + tables;
-  return std::max(need, spread ? (size_t)2 * Pd * ts_xs(Pd) : need) * sizeof(float);
+  return std::max(need, spread ? (size_t)2 * 16 * ts_xs(Pd) : need) * sizeof(float);
 }
 
 template <int W, int T, int IN>

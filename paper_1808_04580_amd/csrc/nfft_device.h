@@ -469,7 +469,10 @@ __device__ __forceinline__ void interp3_mfma_body(const Item *__restrict__ items
 //            once per item), 16 nodes as the columns, K = (ay, az) in 4P
 //            steps; f_p = sum_ax wx_p[ax] D[ax][p].
 // Weight table per wave: 16 node rows of TS_PITCH words, the shifted x, y and
-// z rows at word 0, 32 and 64 (row entries outside the node's window are 0).
+// z rows at word 0, 32 and 64 (row entries outside the node's window are 0),
+// the node's cell y inside the tile at word 96.  In the spread, matrix
+// instructions whose y-slice lies outside the windows of all four of their
+// nodes (exact zeros) are skipped with a wave-uniform branch.
 // The LDS tile is laid out [ax][ay * 16 + az] with row stride TS_XS(P).
 // ---------------------------------------------------------------------------
 // Row pitches: the spread reads two node rows per half-wave (pitch = 16 mod
@@ -506,6 +509,7 @@ __device__ __forceinline__ void fill_shifted(const float4 &qb, float xb, int sub
 #pragma unroll
       for (int z = 0; z < T; z += 4)
         *reinterpret_cast<float4 *>(row + 32 * a + z) = make_float4(0.f, 0.f, 0.f, 0.f);
+    row[96] = __int_as_float(ly);   // the node's y-window is padded y in [ly, ly + W)
   }
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
@@ -555,22 +559,43 @@ __device__ __forceinline__ void spread3_tile_body(const Item it, const float4 *_
       const int cnt = min(16, bcnt - sb * 16);
       fill_shifted<T, true, TS_PITCH>(qb, xb, sb, cnt, lane, cf, wt, ox, oy, oz);
       wave_sync_lds();
-      for (int st = 0; st * 4 < cnt; ++st) {
+      // steps of 4 nodes; the operands of step st + 1 are loaded while the
+      // matrix instructions of step st issue
+      const int nst = (cnt + 3) >> 2;
+      float a, wz, wy[16];
+      int ly;
+      auto load_step = [&](int st, float &a_, float &wz_, float (&wy_)[16], int &ly_) {
         const float *w = wt + (4 * st + p4) * TS_PITCH;
-        const float a = w[c16];
-        const float wz = w[64 + c16];
-        float wy[16];
+        a_ = w[c16];
+        wz_ = w[64 + c16];
+        ly_ = __float_as_int(w[96]);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const float4 v = *reinterpret_cast<const float4 *>(w + 32 + 4 * q);
-          wy[4 * q] = v.x;
-          wy[4 * q + 1] = v.y;
-          wy[4 * q + 2] = v.z;
-          wy[4 * q + 3] = v.w;
+          wy_[4 * q] = v.x;
+          wy_[4 * q + 1] = v.y;
+          wy_[4 * q + 2] = v.z;
+          wy_[4 * q + 3] = v.w;
         }
+      };
+      load_step(0, a, wz, wy, ly);
+      for (int st = 0; st < nst; ++st) {
+        float an = 0.f, wzn = 0.f, wyn[16];
+        int lyn = 0;
+        if (st + 1 < nst) load_step(st + 1, an, wzn, wyn, lyn);
+        // y-slices touched by the step's 4 nodes (lanes 0, 16, 32, 48 hold them)
+        const int l0 = __builtin_amdgcn_readlane(ly, 0), l1 = __builtin_amdgcn_readlane(ly, 16),
+                  l2 = __builtin_amdgcn_readlane(ly, 32), l3 = __builtin_amdgcn_readlane(ly, 48);
+        const int ylo = min(min(l0, l1), min(l2, l3)), yhi = max(max(l0, l1), max(l2, l3)) + W;
 #pragma unroll
         for (int y = 0; y < P; ++y)
-          acc[y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, wy[y] * wz, acc[y], 0, 0, 0);
+          if (y >= ylo && y < yhi)
+            acc[y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, wy[y] * wz, acc[y], 0, 0, 0);
+        a = an;
+        wz = wzn;
+        ly = lyn;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) wy[q] = wyn[q];
       }
       wave_sync_lds();
     }
@@ -579,30 +604,37 @@ __device__ __forceinline__ void spread3_tile_body(const Item it, const float4 *_
   }
   // Sum the waves' tiles without LDS atomics (measured far slower than plain
   // LDS traffic): once every wave is done with its weight table, waves 0 and 1
-  // store their tiles into copies C0 and C1 (the LDS of the tables), then
-  // waves 2 and 3 add theirs into C0 and C1; the flush adds C0 + C1.
+  // store their tiles into copies C0 and C1 (in the LDS of the tables), then
+  // waves 2 and 3 add theirs into C0 and C1; the flush adds C0 + C1.  The
+  // workgroup's LDS must hold 2 x 16 x ts_xs(P) floats.
   constexpr int NC = NW >= 2 ? 2 : 1;
   static_assert(NW == 1 || NW == 2 || NW == 4, "one, two or four waves");
   __syncthreads();
   {
-    float *cp = lds + (wave % NC) * (P * XS);
-    auto put = [&](bool add) {
-      if (c16 < P) {
+    // copies of 16 x-rows (row 15 and z-columns >= P are written, never read)
+    float *cp = lds + (wave % NC) * (16 * XS) + (4 * p4) * XS + c16;
+    if (wave < NC) {
 #pragma unroll
-        for (int y = 0; y < P; ++y)
+      for (int y = 0; y < P; ++y)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int ax = 4 * p4 + r;
-            if (ax < P) {
-              float *q = cp + ax * XS + y * 16 + c16;
-              *q = add ? *q + acc[y][r] : acc[y][r];
-            }
-          }
-      }
-    };
-    if (wave < NC) put(false);
+        for (int r = 0; r < 4; ++r) cp[r * XS + y * 16] = acc[y][r];
+    }
     __syncthreads();
-    if (NW == 4 && wave >= NC) put(true);
+    if (NW == 4 && wave >= NC) {
+      // read-add-write in groups of 4 y-slices: 16 loads in flight at a time
+#pragma unroll
+      for (int y0 = 0; y0 < P; y0 += 4) {
+        float old[4][4];
+#pragma unroll
+        for (int y = y0; y < y0 + 4 && y < P; ++y)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) old[y - y0][r] = cp[r * XS + y * 16];
+#pragma unroll
+        for (int y = y0; y < y0 + 4 && y < P; ++y)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) cp[r * XS + y * 16] = old[y - y0][r] + acc[y][r];
+      }
+    }
     __syncthreads();
   }
   // into the grid: each wave takes rows (px, py), four at a time, z along lanes
@@ -613,7 +645,7 @@ __device__ __forceinline__ void spread3_tile_body(const Item it, const float4 *_
     if (row < P * P && pz < P) {
       const int px = row / P, py = row - px * P;
       const int o = px * XS + py * 16 + pz;
-      const float v = NC == 2 ? lds[o] + lds[P * XS + o] : lds[o];
+      const float v = NC == 2 ? lds[o] + lds[16 * XS + o] : lds[o];
       if (v != 0.f) {
         const int gx = (ox - (M - 1) + px) & mask, gy = (oy - (M - 1) + py) & mask,
                   gz = (oz - (M - 1) + pz) & mask;
