@@ -766,7 +766,7 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-constexpr int FFT_THREADS = 256, FFT_ELEMS = 2048, FFT_MAXL = 512;
+constexpr int FFT_THREADS = 128, FFT_ELEMS = 512, FFT_MAXL = 512;
 
 __device__ __forceinline__ void load_twiddles(float2 *twl, const float2 *__restrict__ tw, int L) {
   for (int k = threadIdx.x; k < L / 2; k += FFT_THREADS) {
@@ -844,7 +844,7 @@ __host__ __device__ __forceinline__ size_t fft_lds_bytes(int lpb, int L) {
 //   z passes (r2c / c2r): FFT_ELEMS / L lines;
 //   y passes: the Hz = N/2 + 1 columns split into equal groups of at most
 //     FFT_ELEMS / L;
-//   x pass: enough workgroups (>= 512) for the (N+1)(N/2+1) columns.
+//   x pass: enough workgroups (>= 1024) for the (N+1)(N/2+1) columns.
 __host__ __device__ __forceinline__ int fft_lpb_z(int L) { return L >= FFT_ELEMS ? 1 : FFT_ELEMS / L; }
 // real lines per workgroup of the r2c / c2r passes (two per complex line)
 __host__ __device__ __forceinline__ int fft_lpb_zr(int L) { return 2 * fft_lpb_z(L); }
@@ -855,7 +855,7 @@ __host__ __device__ __forceinline__ int fft_lpb_y(int L) {
 }
 __host__ __device__ __forceinline__ int fft_lpb_x(int L) {
   const int C = (L / 2 + 1) * (L / 4 + 1);
-  int l = C / 512;
+  int l = C / 1024;
   if (l < 1) l = 1;
   const int mx = fft_lpb_z(L);
   return l > mx ? mx : l;
