@@ -418,12 +418,18 @@ int build_sorted_nodes(nfl_plan *P) {
       it.tile = (int)t;
       it.start = (int)(start + c * k / nch);
       it.end = (int)(start + c * (k + 1) / nch);
-      it.pad = 0;
+      it.pad = (int)k;
       maxlen = std::max(maxlen, it.end - it.start);
       items.push_back(it);
     }
     start += c;
   }
+  // First chunks of all tiles, then second chunks, ...: chunks of one tile
+  // then run apart in time, so their tile flushes (atomic adds to the same
+  // grid cells) do not queue on the same addresses.
+  std::stable_sort(items.begin(), items.end(),
+                   [](const Item &a, const Item &b) { return a.pad < b.pad; });
+  for (Item &it : items) it.pad = 0;
   P->nitems = (int)items.size();
   P->max_item_len = maxlen;
   NFL_TRY(P->items.ensure(items.size()));
