@@ -21,6 +21,8 @@ Modules
 ``krylov``   Lanczos with full reorthogonalisation (Section 4) and CG for the
              kernel-SSL system (eq. ssl::system).
 ``mlp``      FP64 reference of the pointwise warm-start network.
+``nystrom``  the Nystrom-Gaussian-NFFT eigenvalue approximation (Alg.
+             nystrom_hybrid, Section 5.2), steps 3-8 on a given operator.
 
 Parity pins
 -----------

@@ -98,6 +98,30 @@ def moons_and_roll(n: int = 1_000_000, seed: int = 1, noise: float = 0.01):
     return _to_ball(v), lab
 
 
+def spirals(n: int, classes: int = 5, seed: int = 0, height: float = 10.0,
+            radius: float = 2.0, turns: float = 1.5, noise: float = 0.15):
+    """Interleaved 3-D spiral arms, one class per arm, n / classes points each
+    (the first n % classes arms get one more).  Arm c at parameter t ~ U[0, 1]:
+    angle 2 pi (turns t + c / classes), distance from the axis
+    radius (0.25 + t), height `height` t, plus N(0, noise^2) per coordinate.
+    Returns (points f32 in the ball, labels, scale) with `scale` the factor
+    from the generator's units to the returned coordinates (a width quoted in
+    generator units times `scale` is the width for the returned points)."""
+    rng = np.random.default_rng(seed)
+    sizes = [n // classes + (1 if c < n % classes else 0) for c in range(classes)]
+    parts = []
+    for c, m in enumerate(sizes):
+        t = rng.uniform(0.0, 1.0, size=m)
+        ang = 2.0 * np.pi * (turns * t + c / classes)
+        rad = radius * (0.25 + t)
+        parts.append(np.stack([rad * np.cos(ang), rad * np.sin(ang), height * t], axis=1))
+    v = np.concatenate(parts, axis=0) + rng.normal(0.0, noise, size=(n, 3))
+    c0 = 0.5 * (v.min(axis=0) + v.max(axis=0))
+    r = np.sqrt(((v - c0) ** 2).sum(axis=1)).max()
+    lab = np.repeat(np.arange(classes), sizes)
+    return _to_ball(v), lab, RADIUS / r
+
+
 def batched_clouds(count: int = 64, seed: int = 0, n_lo: int = 1000, n_hi: int = 200_000,
                    d: int = 3):
     """`count` independent Gaussian-mixture clouds: n log-uniform in

@@ -9,7 +9,7 @@ import math
 import numpy as np
 import pytest
 
-from oracle import fastsum, graph, krylov
+from oracle import fastsum, graph, krylov, nystrom
 import synth
 
 
@@ -236,6 +236,95 @@ def test_cg_matches_dense_solve():
     u, it, rel = krylov.cg(lambda p: M @ p, f, tol=1e-10, maxit=500)
     np.testing.assert_allclose(u, np.linalg.solve(M, f), atol=1e-8)
     assert rel <= 1e-10 and it < 200
+
+
+# ---- Nystrom-Gaussian-NFFT (Alg. nystrom_hybrid) --------------------------------
+
+def _lowrank(n, lam, seed):
+    """A = U diag(lam) U^T with a random orthonormal U (n x len(lam))."""
+    U, _ = np.linalg.qr(np.random.default_rng(seed).standard_normal((n, len(lam))))
+    return (U * np.asarray(lam)[None, :]) @ U.T, U
+
+
+def test_nystrom_exact_for_low_rank_psd():
+    """For A positive semidefinite of rank r <= M <= L, range(A G) = range(A),
+    so the rank-M Nystrom matrix is A itself: the k largest eigenpairs come out
+    exactly, and M shrinks to r (the other eigenvalues of Q^T A Q are zero)."""
+    lam = np.array([1.0, 0.8, 0.55, 0.4, 0.25, 0.1])
+    A, U = _lowrank(60, lam, seed=5)
+    G = np.random.default_rng(6).standard_normal((60, 12))
+    th, V, m_used = nystrom.nystrom_gaussian(lambda X: A @ X, G, k=4, M=8)
+    assert m_used == 6
+    np.testing.assert_allclose(th, lam[:4], atol=1e-12)
+    np.testing.assert_allclose(np.abs(np.sum(V * U[:, :4], axis=0)), 1.0, atol=1e-10)
+
+
+def test_nystrom_keeps_only_the_positive_part():
+    """With negative eigenvalues in the range (A indefinite, as the graph's A
+    is), step 5 drops them: the result is the positive part of A."""
+    A_pos, U = _lowrank(50, [0.9, 0.7, 0.5], seed=7)
+    w = np.random.default_rng(8).standard_normal(50)
+    w -= U @ (U.T @ w)
+    w /= np.linalg.norm(w)
+    A = A_pos - 0.8 * np.outer(w, w)
+    G = np.random.default_rng(9).standard_normal((50, 8))
+    th, V, m_used = nystrom.nystrom_gaussian(lambda X: A @ X, G, k=3, M=8)
+    assert m_used == 3
+    np.testing.assert_allclose(th, [0.9, 0.7, 0.5], atol=1e-12)
+    assert np.abs(V.T @ w).max() < 1e-10
+
+
+def test_nystrom_full_sample_is_the_truncated_eigendecomposition():
+    """L = n: Q is square orthogonal, Q^T A Q is similar to A, and the rank-M
+    matrix is A's truncation to its M largest (positive) eigenvalues; on a
+    graph A of Section 2 these match LAPACK's eigh."""
+    v, _, sc = synth.spirals(60, seed=1)
+    A = graph.dense_A(v, 3.5 * sc)
+    G = np.random.default_rng(2).standard_normal((60, 60))
+    th, V, m_used = nystrom.nystrom_gaussian(lambda X: A @ X, G, k=8, M=8)
+    ev, EV = np.linalg.eigh(A)
+    np.testing.assert_allclose(th, ev[::-1][:8], atol=1e-11)
+    assert abs(th[0] - 1.0) < 1e-12          # top eigenvalue of A is 1 (Section 2)
+    for i in range(8):
+        assert np.linalg.norm(A @ V[:, i] - th[i] * V[:, i]) < 1e-9
+
+
+def test_nystrom_steps_6_7_match_the_dense_nystrom_matrix():
+    """Steps 6-7 (QR of B1 U_M, eigendecomposition of Rh Sigma^{-1} Rh^T) are
+    the eigendecomposition of (A Q)(Q^T A Q)_M^{-1}(A Q)^T; formed densely
+    with Q from an SVD instead, LAPACK's eigh gives the same pairs."""
+    v, _, sc = synth.spirals(400, seed=3)
+    A = graph.dense_A(v, 3.5 * sc)
+    G = np.random.default_rng(4).standard_normal((400, 20))
+    th, V, m_used = nystrom.nystrom_gaussian(lambda X: A @ X, G, k=10, M=10)
+    assert m_used == 10
+    N = nystrom.nystrom_matrix(lambda X: A @ X, G, 10)
+    ev = np.linalg.eigvalsh(N)[::-1][:10]
+    np.testing.assert_allclose(th, ev, atol=1e-11)
+    np.testing.assert_allclose((V * th[None, :]) @ V.T, N, atol=1e-11)
+    np.testing.assert_allclose(V.T @ V, np.eye(10), atol=1e-12)
+
+
+def test_nystrom_depends_on_the_range_of_G_only():
+    """Q = orth(A G) is unchanged (up to rotation) by G -> G S, S invertible,
+    and every later step is invariant under that rotation."""
+    v, _, sc = synth.spirals(300, seed=5)
+    A = graph.dense_A(v, 3.5 * sc)
+    rng = np.random.default_rng(6)
+    G = rng.standard_normal((300, 16))
+    S = rng.standard_normal((16, 16)) + 4.0 * np.eye(16)
+    t1, V1, _ = nystrom.nystrom_gaussian(lambda X: A @ X, G, k=6, M=10)
+    t2, V2, _ = nystrom.nystrom_gaussian(lambda X: A @ X, G @ S, k=6, M=10)
+    np.testing.assert_allclose(t1, t2, atol=1e-10)
+    np.testing.assert_allclose(np.abs(np.sum(V1 * V2, axis=0)), 1.0, atol=1e-8)
+
+
+def test_nystrom_rejects_bad_sizes():
+    A = np.eye(10)
+    with pytest.raises(ValueError):
+        nystrom.nystrom_gaussian(lambda X: A @ X, np.ones((10, 4)), k=5, M=4)
+    with pytest.raises(ValueError):
+        nystrom.nystrom_gaussian(lambda X: -(A @ X), np.eye(10)[:, :4], k=1, M=2)
 
 
 # ---- the warm-start network reference -----------------------------------------
