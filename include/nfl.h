@@ -114,6 +114,27 @@ int nfl_apply_A(nfl_handle h, const float *x_dev, float *y_dev, int nvec, int64_
 int nfl_lanczos_smallest(nfl_handle h, int k, int block, double tol, int maxit,
                          double *evals_host, double *evecs_dev, int *iters, double *max_resid);
 
+/* The k largest eigenpairs of A_E = D_E^{-1/2} W_E D_E^{-1/2} by the
+ * Nystrom-Gaussian-NFFT method (Alg. nystrom_hybrid, Section 5.2):
+ * Y = A_E G, Q = orth(Y); B1 = A_E Q, B2 = Q^T B1; Sigma_M, U_M = the M
+ * largest positive eigenpairs of B2; Qh Rh = B1 U_M;
+ * Uh Lambda Uh^T = Rh Sigma_M^{-1} Rh^T; V = Qh Uh; the k largest of Lambda.
+ * 2L NFFT products (FP32) and FP64 tall-skinny algebra; QR factorisations by
+ * shifted CholeskyQR3.
+ * G_dev: n x L FP64 column-major in caller order with leading dimension
+ * ldg >= n, the Gaussian matrix (drawn by the caller; only its range
+ * matters).  1 <= k <= M <= L <= n, L <= 64 in this build
+ * (NFL_ERR_UNSUPPORTED above).  "Positive" in step 5 means above 1e-10 times
+ * the largest absolute eigenvalue of B2; if fewer than M qualify, M shrinks to
+ * their number (*m_used, host, may be NULL), and fewer than k is NFL_ERR_ARG,
+ * as is a numerically rank-deficient A_E G or B1 U_M.
+ * evals_host: k doubles, descending eigenvalues of the rank-M approximation
+ * (1 - these approximate the smallest eigenvalues of L_s).  evecs_dev: n x k
+ * FP64 column-major in caller order, orthonormal (NULL to skip).
+ * Device work memory: 3 n L doubles.  Synchronises. */
+int nfl_nystrom(nfl_handle h, const double *G_dev, int64_t ldg, int L, int M, int k,
+                double *evals_host, double *evecs_dev, int *m_used);
+
 /* Warm-start modes of nfl_cg_solve. */
 #define NFL_WARM_ZERO 0
 #define NFL_WARM_USER 1

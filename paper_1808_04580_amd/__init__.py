@@ -50,6 +50,7 @@ SIGNATURES = {
     "nfl_apply_A": (_i, [_p, _p, _p, _i, _i64]),
     "nfl_lanczos_smallest": (_i, [_p, _i, _i, _d, _i, _p, _p, _p, _p]),
     "nfl_cg_solve": (_i, [_p, _d, _p, _p, _i, _d, _i, _p, _p]),
+    "nfl_nystrom": (_i, [_p, _p, _i64, _i, _i, _i, _p, _p, _p]),
     "nfl_get_info": (_i, [_p, _p, _p, _p, _p, _p, _p]),
     "nfl_grid_size": (_i64, [_p]),
     "nfl_spread": (_i, [_p, _p, _p]),
@@ -240,6 +241,32 @@ class Plan:
                       "nfl_lanczos_smallest", allow_soft=True)
         return dict(evals=ev, evecs=(V.T if V is not None else None), iters=it.value,
                     max_resid=res.value, converged=(code == NFL_OK))
+
+    def nystrom(self, k: int, L: int = 20, M: int = None, G=None, seed: int = 0,
+                vectors: bool = True):
+        """Nystrom-Gaussian-NFFT (Alg. nystrom_hybrid): the k largest eigenpairs
+        of A_E from the n x L Gaussian matrix G (drawn here from `seed` when not
+        given; (n, L) array in caller order)."""
+        torch = self._torch
+        M = k if M is None else M
+        if G is None:
+            gen = torch.Generator(device=self.device)
+            gen.manual_seed(int(seed))
+            Gt = torch.randn((L, self.n), dtype=torch.float64, device=self.device, generator=gen)
+        else:
+            Gt = torch.as_tensor(G, dtype=torch.float64, device=self.device)
+            if Gt.dim() != 2 or Gt.shape[0] != self.n:
+                raise ValueError("G must be (n, L)")
+            L = Gt.shape[1]
+            Gt = Gt.T.contiguous()
+        ev = np.empty(k, dtype=np.float64)
+        V = torch.empty((k, self.n), dtype=torch.float64, device=self.device) if vectors else None
+        mu = ctypes.c_int()
+        _check(lib().nfl_nystrom(self._h, _ptr(Gt), self.n, int(L), int(M), int(k),
+                                 ev.ctypes.data_as(_p), _p(_ptr(V)) if V is not None else None,
+                                 ctypes.byref(mu)), "nfl_nystrom")
+        return dict(evals=ev, evals_Ls=1.0 - ev, evecs=(V.T if V is not None else None),
+                    m_used=mu.value)
 
     def cg_solve(self, f, tau: float, tol: float = 1e-6, maxit: int = 1000,
                  warm: int = WARM_ZERO, u0=None):

@@ -262,6 +262,16 @@ int nfl_lanczos_smallest(nfl_handle P, int k, int block, double tol, int maxit, 
   return lanczos(P, k, block, tol, maxit, evals_host, evecs_dev, iters, max_resid);
 }
 
+int nfl_nystrom(nfl_handle P, const double *G_dev, int64_t ldg, int L, int M, int k,
+                double *evals_host, double *evecs_dev, int *m_used) {
+  if (!P) { set_error("null handle"); return NFL_ERR_ARG; }
+  if (!P->have_kernel) { set_error("nystrom before a successful nfl_set_kernel"); return NFL_ERR_ORDER; }
+  if (!G_dev || !evals_host) { set_error("null G or eigenvalue output"); return NFL_ERR_ARG; }
+  if (k < 1 || M < k || L < M || L > P->n) { set_error("need 1 <= k <= M <= L <= n"); return NFL_ERR_ARG; }
+  if (ldg < P->n) { set_error("ldg < n"); return NFL_ERR_ARG; }
+  return nystrom(P, G_dev, ldg, L, M, k, evals_host, evecs_dev, m_used);
+}
+
 int nfl_cg_solve(nfl_handle P, double tau, const double *f_dev, double *u_dev, int warm, double tol,
                  int maxit, int *iters, double *relres) {
   if (!P) { set_error("null handle"); return NFL_ERR_ARG; }

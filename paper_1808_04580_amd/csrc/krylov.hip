@@ -279,7 +279,7 @@ __global__ __launch_bounds__(64) void k_tridiag_apply(const double *__restrict__
 // Host helpers
 // ---------------------------------------------------------------------------
 struct Reducer {
-  DBuf<double> part;
+  LBuf<double> part;
   int nb = 0;
   int init(int64_t n) {
     nb = (int)std::max<int64_t>(1, std::min<int64_t>(VBLOCKS, (n + VT - 1) / VT));
@@ -425,6 +425,18 @@ __global__ __launch_bounds__(JAC_THREADS) void k_sym_jacobi(const double *__rest
   if (tid == 0) status[0] = st;
 }
 
+int sym_eig(hipStream_t s, const double *H, int64_t ldH, int m, double *A_work, double *V,
+            double *eval, int *status) {
+  if (m < 1 || m > JAC_MAXM) {
+    set_error("symmetric eigensolver: order outside 1..1024");
+    return NFL_ERR_UNSUPPORTED;
+  }
+  hipLaunchKernelGGL(k_sym_jacobi, dim3(1), dim3(JAC_THREADS), 0, s, H, ldH, m, A_work, V, eval,
+                     status);
+  NFL_HIP(hipGetLastError());
+  return NFL_OK;
+}
+
 // h[i] += c[i], i < J (one column of the projection)
 __global__ __launch_bounds__(VT) void k_add_col(double *__restrict__ h,
                                                 const double *__restrict__ c, int J) {
@@ -455,8 +467,8 @@ static int block_lanczos(nfl_plan *P, int k, int b, double tol, int maxit, doubl
     return NFL_ERR_UNSUPPORTED;
   }
   const int64_t ld = n, ldH = mcols + b;
-  DBuf<double> Q, W, H, cvec, part, Aw, Vw, ev;
-  DBuf<int> st, sel;
+  LBuf<double> Q, W, H, cvec, part, Aw, Vw, ev;
+  LBuf<int> st, sel;
   NFL_TRY(Q.ensure((size_t)ld * (mcols + b)));
   NFL_TRY(W.ensure((size_t)n * b));
   NFL_TRY(H.ensure((size_t)ldH * ldH));
@@ -559,7 +571,7 @@ static int block_lanczos(nfl_plan *P, int k, int b, double tol, int maxit, doubl
   }
   for (int c = 0; c < k; ++c) evals_host[c] = 1.0 - h_eval[h_sel[c]];
   if (evecs_dev) {
-    DBuf<double> Vout;
+    LBuf<double> Vout;
     NFL_TRY(Vout.ensure((size_t)n * k));
     NFL_HIP(hipMemcpyAsync(sel.p, h_sel.data(), k * sizeof(int), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_ritz, dim3(gb), dim3(VT), 0, s, Q.p, ld, Jc, Vw.p, sel.p, k, n, Vout.p);
@@ -585,9 +597,9 @@ int lanczos(nfl_plan *P, int k, int block, double tol, int maxit, double *evals_
     return NFL_ERR_ARG;
   }
   const int64_t ld = n;
-  DBuf<double> Q, w, sc, cvec, part, rot, ev, Z;
-  DBuf<int64_t> nrot;
-  DBuf<int> st, sel;
+  LBuf<double> Q, w, sc, cvec, part, rot, ev, Z;
+  LBuf<int64_t> nrot;
+  LBuf<int> st, sel;
   NFL_TRY(Q.ensure((size_t)ld * (maxit + 1)));
   NFL_TRY(w.ensure(n));
   NFL_TRY(sc.ensure(2 * (size_t)maxit + 8));  // alpha[0..maxit), beta[0..maxit]
@@ -680,7 +692,7 @@ int lanczos(nfl_plan *P, int k, int block, double tol, int maxit, double *evals_
   }
   for (int c = 0; c < k; ++c) evals_host[c] = 1.0 - h_eval[h_sel[c]];  // ascending lambda
   if (evecs_dev) {
-    DBuf<double> V;
+    LBuf<double> V;
     NFL_TRY(V.ensure((size_t)n * k));
     NFL_HIP(hipMemcpyAsync(sel.p, h_sel.data(), k * sizeof(int), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_ritz, dim3(gb), dim3(VT), 0, s, Q.p, ld, J, Z.p, sel.p, k, n, V.p);
@@ -754,7 +766,7 @@ int cg(nfl_plan *P, double tau, const double *f_dev, double *u_dev, int warm, do
        int maxit, int *iters, double *relres) {
   const int64_t n = P->n;
   hipStream_t s = P->stream;
-  DBuf<double> f, u, r, p, q, sc;
+  LBuf<double> f, u, r, p, q, sc;
   NFL_TRY(f.ensure(n));
   NFL_TRY(u.ensure(n));
   NFL_TRY(r.ensure(n));

@@ -460,7 +460,7 @@ static float plan_dinvmean(nfl_plan *P, DBuf<double> &tmp) {
 }
 
 int mlp_predict_sorted(nfl_mlp *M, nfl_plan *P, int cls, const double *f_sorted, double *u0) {
-  DBuf<double> tmp;
+  LBuf<double> tmp;
   const int64_t nb16 = (P->n + 15) / 16;
   const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(2048, (nb16 + 3) / 4));
   hipLaunchKernelGGL(k_mlp_infer, dim3(blocks), dim3(256), 0, P->stream, M->wbf.p, M->prm.p,
@@ -603,7 +603,7 @@ int nfl_mlp_train_step(nfl_mlp_handle M, nfl_handle P, const double *f_dev, cons
   NFL_TRY(M->target.ensure((size_t)ns));
   if (M->stream != P->stream) NFL_HIP(hipStreamSynchronize(P->stream));
   NFL_HIP(hipMemcpyAsync(M->idx.p, idx.data(), ns * 4, hipMemcpyHostToDevice, M->stream));
-  DBuf<double> tmp;
+  LBuf<double> tmp;
   hipLaunchKernelGGL(k_mlp_features, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, M->stream,
                      P->pts.p, P->perm.p, P->deg.p, plan_dinvmean(P, tmp), f_dev, u_dev, cls, P->nos,
                      P->d, M->idx.p, ns, M->feat.p, M->target.p);
@@ -618,7 +618,7 @@ int nfl_mlp_predict(nfl_mlp_handle M, nfl_handle P, const double *f_dev, int cls
   if (!M || !P || !f_dev || !u_dev) { set_error("bad arguments"); return NFL_ERR_ARG; }
   if (!P->have_kernel) { set_error("plan has no kernel"); return NFL_ERR_ORDER; }
   if (cls < 0 || cls >= M->ncls) { set_error("class out of range"); return NFL_ERR_ARG; }
-  DBuf<double> fs, us;
+  LBuf<double> fs, us;
   NFL_TRY(fs.ensure(P->n));
   NFL_TRY(us.ensure(P->n));
   NFL_TRY(gather64(P, f_dev, fs.p));

@@ -56,6 +56,16 @@ struct DBuf {
   }
 };
 
+// A function-local device buffer, freed when it goes out of scope (hipFree
+// waits for the device work still using it).  Not copyable.
+template <class T>
+struct LBuf : DBuf<T> {
+  LBuf() = default;
+  LBuf(const LBuf &) = delete;
+  LBuf &operator=(const LBuf &) = delete;
+  ~LBuf() { this->release(); }
+};
+
 // One unit of spread/interp work: a contiguous range of sorted nodes inside
 // one grid tile.
 struct Item {
@@ -197,6 +207,16 @@ int cg(nfl_plan *P, double tau, const double *f_dev, double *u_dev, int warm, do
        int maxit, int *iters, double *relres);
 int gather64(nfl_plan *P, const double *src_user, double *dst_sorted);
 int scatter64(nfl_plan *P, const double *src_sorted, double *dst_user);
+// Eigendecomposition of the symmetric part of the leading m x m block of H
+// (column-major, leading dimension ldH), m <= 1024, one workgroup of cyclic
+// Jacobi: eval[m] unsorted, V[col * m + row]; A_work holds m * m doubles;
+// status[0] = 1 if the sweeps did not converge.  Asynchronous on s.
+int sym_eig(hipStream_t s, const double *H, int64_t ldH, int m, double *A_work, double *V,
+            double *eval, int *status);
+
+// ---- Nystrom-Gaussian-NFFT (nystrom.hip) ------------------------------------
+int nystrom(nfl_plan *P, const double *G_user, int64_t ldg, int L, int M, int k,
+            double *evals_host, double *evecs_dev, int *m_used);
 
 // ---- learned warm start (mlp.hip) -------------------------------------------
 int mlp_warm_start(nfl_plan *P, const double *f_sorted, double *u_sorted);

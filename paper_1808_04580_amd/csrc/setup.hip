@@ -361,7 +361,7 @@ int build_sorted_nodes(nfl_plan *P) {
   const int64_t ntiles = 1LL << (d * (lognos - tshift));
 
   // temporaries: keys, idx, records, tile counts
-  DBuf<unsigned char> work;
+  LBuf<unsigned char> work;
   const size_t need = (size_t)n * 4 * 2 + (size_t)n * 16 + (size_t)ntiles * 4 + 64;
   NFL_TRY(work.ensure(need));
   uint32_t *keys = (uint32_t *)work.p;

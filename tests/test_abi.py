@@ -56,6 +56,7 @@ def test_error_codes_without_gpu():
     assert L.nfl_autotune(None, 0.1, 1e-5, 64, 1, None, None, None, None, None, None, None,
                           None) == nfl.NFL_ERR_ARG
     assert L.nfl_set_option(None, nfl.OPT_KERNEL, 2) == nfl.NFL_ERR_ARG
+    assert L.nfl_nystrom(None, None, 0, 1, 1, 1, None, None, None) == nfl.NFL_ERR_ARG
 
 
 def kb_hat_quadrature(xi, m, b=1.5 * math.pi, nq=2001):
