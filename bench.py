@@ -16,9 +16,12 @@ resident in HBM.  Also reported:
   * the batched workload: 64 Gaussian-mixture graphs of uneven size, each
     autotuned to rel err 1e-5, L_s on 8 vectors per graph in one graph
     launch, against the same products issued plan by plan.
+  * the Nystrom-Gaussian-NFFT eigenvalue approximation (Alg. nystrom_hybrid)
+    on the paper's spiral workload (n = 1e5, L = 50, M = k = 10), against
+    Lanczos on the same plan, and at n = 1M on the benchmark plan.
 
 Usage: python bench.py [--gpus 1] [--steps 200] [--warmup 10] [--no-cpu] [--no-cg]
-                       [--no-batched]
+                       [--no-batched] [--no-nystrom]
 """
 from __future__ import annotations
 
@@ -142,6 +145,48 @@ def batched_leg(nfl, synth, torch, dev, graphs=64, nvec=8, reps=20):
     return out
 
 
+def nystrom_leg(nfl, synth, torch, dev, P_main=None, reps=3):
+    """Alg. nystrom_hybrid on the paper's eigenvalue workload: 3-D spirals of
+    five classes, n = 100,000, sigma = 3.5 in generator units, NFFT setup #2
+    (N = 32, m = 4, eps_B = 0), L = 50 Gaussian columns, M = 10, k = 10; timed
+    against Lanczos (k = 10, tol 1e-6) on the same plan, with the largest
+    eigenvalue gap between the two.  With P_main, also the n = 1M plan of the
+    L_s benchmark (L = 50, M = k = 10)."""
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = fn()
+        torch.cuda.synchronize()
+        return r, (time.perf_counter() - t0) * 1000.0 / reps
+
+    n, L, M, k = 100_000, 50, 10, 10
+    v, _, sc = synth.spirals(n, seed=0)
+    P = nfl.plan(torch.as_tensor(v, device=dev), 3.5 * sc, N=32, m=4, eps_B=0.0)
+    xa = torch.as_tensor(synth.normal_vectors(n, seed=3), device=dev)
+    ya = torch.empty_like(xa)
+    _, ms_a = timed(lambda: P.apply_A(xa, out=ya))
+    r, ms = timed(lambda: P.nystrom(k, L=L, M=M, seed=1))
+    lz, ms_l = timed(lambda: P.lanczos_smallest(k, tol=1e-6, maxit=300))
+    P.close()
+    out = {"workload": "3-D spirals, 5 classes, n=100,000, sigma=3.5 (generator units), "
+                       "N=32, m=4, eps_B=0 (setup #2); L=50, M=10, k=10",
+           "ms": round(ms, 3), "products": 2 * L, "ms_one_A_product": round(ms_a, 4),
+           "m_used": r["m_used"], "evals": [round(float(e), 6) for e in r["evals"]],
+           "lanczos_ms": round(ms_l, 3), "lanczos_iters": lz["iters"],
+           "max_abs_eval_diff_vs_lanczos": float(np.abs(r["evals_Ls"] - lz["evals"]).max())}
+    log("nystrom n=1e5: %.2f ms (%d products, %.3f ms each), lanczos %.2f ms (%d it), "
+        "max |lambda diff| %.2e" % (ms, 2 * L, ms_a, ms_l, lz["iters"],
+                                    out["max_abs_eval_diff_vs_lanczos"]))
+    if P_main is not None:
+        r2, ms2 = timed(lambda: P_main.nystrom(k, L=L, M=M, seed=1))
+        out["n1M"] = {"ms": round(ms2, 3), "m_used": r2["m_used"],
+                      "evals": [round(float(e), 6) for e in r2["evals"]]}
+        log("nystrom n=1e6: %.2f ms" % ms2)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +198,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-graph batched leg")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the 64-graph batched leg and print its JSON record")
+    ap.add_argument("--no-nystrom", action="store_true", help="skip the Nystrom eigenvalue leg")
+    ap.add_argument("--nystrom-only", action="store_true",
+                    help="run only the Nystrom leg (n = 1e5 spirals) and print its JSON record")
     ap.add_argument("--profile-run", action="store_true",
                     help="short run for hardware counters: a few products and a 256 MiB "
                          "device copy (the reference for scaling byte counters); no JSON")
@@ -172,6 +220,9 @@ def main():
     dev = torch.device("cuda", 0)
     if args.batched_only:
         print(json.dumps(batched_leg(nfl, synth, torch, dev)), flush=True)
+        return
+    if args.nystrom_only:
+        print(json.dumps(nystrom_leg(nfl, synth, torch, dev, reps=1)), flush=True)
         return
     t0 = time.time()
     v, lab = synth.moons_and_roll(N_POINTS, seed=1)
@@ -307,6 +358,11 @@ def main():
     if not args.no_batched:
         batched = batched_leg(nfl, synth, torch, dev)
 
+    # --- Nystrom-Gaussian-NFFT eigenvalue leg ------------------------------------
+    nys = None
+    if not args.no_nystrom:
+        nys = nystrom_leg(nfl, synth, torch, dev, P_main=P)
+
     # --- CPU oracle baseline (bounded sample) ----------------------------------
     cpu = None
     if not args.no_cpu:
@@ -344,6 +400,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "batched": batched,
+        "nystrom": nys,
     }
     print(json.dumps(out), flush=True)
     P.close()

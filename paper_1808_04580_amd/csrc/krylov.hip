@@ -123,12 +123,28 @@ __global__ __launch_bounds__(VT) void k_gemv_t_partial(const double *__restrict_
   }
 }
 
-__global__ __launch_bounds__(VT) void k_gemv_t_final(const double *__restrict__ part, int nb,
-                                                     int J, double *__restrict__ c) {
-  for (int j = blockIdx.x * VT + threadIdx.x; j < J; j += gridDim.x * VT) {
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += part[(int64_t)b * J + j];
-    c[j] = s;
+// out[e] = sum over w < nb of part[w * width + e], e < width (the column sums
+// of an nb x width row-major array of partial results).  A workgroup takes 16
+// consecutive columns; its 16 thread rows sum interleaved slices of w, which
+// are then added in slice order (fixed order -> deterministic).
+constexpr int CS_E = 16, CS_S = VT / CS_E;
+
+__global__ __launch_bounds__(VT) void k_colsum(const double *__restrict__ part, int nb, int width,
+                                               double *__restrict__ out) {
+  __shared__ double sh[CS_S][CS_E + 1];
+  const int el = threadIdx.x % CS_E, sl = threadIdx.x / CS_E;
+  const int e = blockIdx.x * CS_E + el;
+  double s = 0.0;
+  if (e < width) {
+#pragma unroll 8
+    for (int w = sl; w < nb; w += CS_S) s += part[(int64_t)w * width + e];
+  }
+  sh[sl][el] = s;
+  __syncthreads();
+  if (sl == 0 && e < width) {
+    double t = 0.0;
+    for (int k = 0; k < CS_S; ++k) t += sh[k][el];
+    out[e] = t;
   }
 }
 
@@ -339,12 +355,21 @@ __device__ double jac_block_sum(double v, double *sh) {
   return t;  // valid in every thread
 }
 
+// IN_LDS (m <= JAC_LDS_MAXM): A and V live in dynamic LDS (2 m^2 doubles)
+// during the sweeps and V is copied to Vg at the end; otherwise both are the
+// global work arrays.
+constexpr int JAC_LDS_MAXM = 64;
+
+template <bool IN_LDS>
 __global__ __launch_bounds__(JAC_THREADS) void k_sym_jacobi(const double *__restrict__ H,
                                                             int64_t ldH, int m,
-                                                            double *__restrict__ A,
-                                                            double *__restrict__ V,
+                                                            double *__restrict__ Ag,
+                                                            double *__restrict__ Vg,
                                                             double *__restrict__ eval,
                                                             int *__restrict__ status) {
+  extern __shared__ double jac_dyn[];
+  double *A = IN_LDS ? jac_dyn : Ag;
+  double *V = IN_LDS ? jac_dyn + (size_t)m * m : Vg;
   __shared__ double sh[JAC_THREADS / 64];
   __shared__ double rc[JAC_MAXM / 2], rs[JAC_MAXM / 2];
   __shared__ int rp[JAC_MAXM / 2], rq[JAC_MAXM / 2];
@@ -422,7 +447,16 @@ __global__ __launch_bounds__(JAC_THREADS) void k_sym_jacobi(const double *__rest
     }
   }
   for (int i = tid; i < m; i += JAC_THREADS) eval[i] = A[(int64_t)i * m + i];
+  if (IN_LDS)
+    for (int64_t idx = tid; idx < (int64_t)m * m; idx += JAC_THREADS) Vg[idx] = V[idx];
   if (tid == 0) status[0] = st;
+}
+
+int colsum(hipStream_t s, const double *part, int nb, int width, double *out) {
+  hipLaunchKernelGGL(k_colsum, dim3((width + CS_E - 1) / CS_E), dim3(VT), 0, s, part, nb, width,
+                     out);
+  NFL_HIP(hipGetLastError());
+  return NFL_OK;
 }
 
 int sym_eig(hipStream_t s, const double *H, int64_t ldH, int m, double *A_work, double *V,
@@ -431,8 +465,17 @@ int sym_eig(hipStream_t s, const double *H, int64_t ldH, int m, double *A_work, 
     set_error("symmetric eigensolver: order outside 1..1024");
     return NFL_ERR_UNSUPPORTED;
   }
-  hipLaunchKernelGGL(k_sym_jacobi, dim3(1), dim3(JAC_THREADS), 0, s, H, ldH, m, A_work, V, eval,
-                     status);
+  if (m <= JAC_LDS_MAXM) {
+    static const hipError_t attr = hipFuncSetAttribute(
+        (const void *)k_sym_jacobi<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        2 * JAC_LDS_MAXM * JAC_LDS_MAXM * (int)sizeof(double));
+    NFL_HIP(attr);
+    hipLaunchKernelGGL(k_sym_jacobi<true>, dim3(1), dim3(JAC_THREADS),
+                       (size_t)2 * m * m * sizeof(double), s, H, ldH, m, A_work, V, eval, status);
+  } else {
+    hipLaunchKernelGGL(k_sym_jacobi<false>, dim3(1), dim3(JAC_THREADS), 0, s, H, ldH, m, A_work,
+                       V, eval, status);
+  }
   NFL_HIP(hipGetLastError());
   return NFL_OK;
 }
@@ -492,7 +535,8 @@ static int block_lanczos(nfl_plan *P, int k, int b, double tol, int maxit, doubl
     for (int pass = 0; pass < 2 && ncol > 0; ++pass) {
       hipLaunchKernelGGL(k_gemv_t_partial, dim3(R.nb), dim3(VT), 0, s, Q.p, ld, ncol, w, n,
                          part.p);
-      hipLaunchKernelGGL(k_gemv_t_final, dim3(1), dim3(VT), 0, s, part.p, R.nb, ncol, cvec.p);
+      hipLaunchKernelGGL(k_colsum, dim3((ncol + CS_E - 1) / CS_E), dim3(VT), 0, s, part.p, R.nb,
+                         ncol, cvec.p);
       if (hcol)
         hipLaunchKernelGGL(k_add_col, dim3((ncol + VT - 1) / VT), dim3(VT), 0, s, hcol, cvec.p,
                            ncol);
@@ -530,9 +574,7 @@ static int block_lanczos(nfl_plan *P, int k, int b, double tol, int maxit, doubl
     const bool last = nblk == maxblk;
     const int every = Jc <= 100 ? std::max(1, 8 / b) : std::max(1, 16 / b);
     if (Jc >= k && (nblk % every == 0 || last)) {
-      hipLaunchKernelGGL(k_sym_jacobi, dim3(1), dim3(JAC_THREADS), 0, s, H.p, ldH, Jc, Aw.p, Vw.p,
-                         ev.p, st.p);
-      NFL_HIP(hipGetLastError());
+      NFL_TRY(sym_eig(s, H.p, ldH, Jc, Aw.p, Vw.p, ev.p, st.p));
       h_eval.resize(Jc);
       h_V.resize((size_t)Jc * Jc);
       int h_st = 0;
@@ -643,7 +685,8 @@ int lanczos(nfl_plan *P, int k, int block, double tol, int maxit, double *evals_
     for (int pass = 0; pass < 2; ++pass) {
       hipLaunchKernelGGL(k_gemv_t_partial, dim3(R.nb), dim3(VT), 0, s, Q.p, ld, j + 1, w.p, n,
                          part.p);
-      hipLaunchKernelGGL(k_gemv_t_final, dim3(1), dim3(VT), 0, s, part.p, R.nb, j + 1, cvec.p);
+      hipLaunchKernelGGL(k_colsum, dim3((j + 1 + CS_E - 1) / CS_E), dim3(VT), 0, s, part.p, R.nb,
+                         j + 1, cvec.p);
       hipLaunchKernelGGL(k_gemv_n_sub, dim3(gb), dim3(VT), 0, s, Q.p, ld, j + 1, cvec.p, w.p, n);
     }
     NFL_TRY(dot(P, R, w.p, w.p, beta + j + 1, 1));

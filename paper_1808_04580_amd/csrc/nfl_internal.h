@@ -207,6 +207,8 @@ int cg(nfl_plan *P, double tau, const double *f_dev, double *u_dev, int warm, do
        int maxit, int *iters, double *relres);
 int gather64(nfl_plan *P, const double *src_user, double *dst_sorted);
 int scatter64(nfl_plan *P, const double *src_sorted, double *dst_user);
+// out[e] = sum_{w < nb} part[w * width + e] for e < width, in a fixed order.
+int colsum(hipStream_t s, const double *part, int nb, int width, double *out);
 // Eigendecomposition of the symmetric part of the leading m x m block of H
 // (column-major, leading dimension ldH), m <= 1024, one workgroup of cyclic
 // Jacobi: eval[m] unsorted, V[col * m + row]; A_work holds m * m doubles;

@@ -42,8 +42,8 @@ constexpr double POS_REL = 1e-10;
 
 // ---- Gram matrix C = X^T Y (X: n x a, Y: n x b, a, b <= 64) ------------------
 // Each workgroup stages GR_ROWS rows of X and Y in LDS and accumulates a 4 x 4
-// block of C per thread over its share of the row chunks; partial sums per
-// workgroup are added in a fixed order by k_gram_final (deterministic).
+// block of C per thread over its share of the row chunks; the partial sums
+// of the workgroups are added in a fixed order by colsum (deterministic).
 constexpr int GR_ROWS = 32;
 constexpr int GR_PITCH = NYS_MAXL + 1;   // odd pitch: conflict-free column stores
 constexpr int GR_MAXB = 1024;
@@ -95,16 +95,6 @@ __global__ __launch_bounds__(NT) void k_gram_partial(const double *__restrict__ 
 #pragma unroll
     for (int q = 0; q < 4; ++q)
       if (i0 + p < a && j0 + q < b) out[(int64_t)(j0 + q) * a + i0 + p] = acc[p][q];
-}
-
-// C[e] = sum over workgroups of part[wg * ab + e], e < ab, in workgroup order.
-__global__ __launch_bounds__(NT) void k_gram_final(const double *__restrict__ part, int nb,
-                                                   int ab, double *__restrict__ C) {
-  const int e = blockIdx.x * NT + threadIdx.x;
-  if (e >= ab) return;
-  double s = 0.0;
-  for (int w = 0; w < nb; ++w) s += part[(int64_t)w * ab + e];
-  C[e] = s;
 }
 
 // ---- out = X C (X: n x a, C: a x b row-major with row length ldc >= the
@@ -200,21 +190,24 @@ __global__ __launch_bounds__(NT) void k_chol(const double *__restrict__ Gm, int 
     const int r = e % a, c = e / a;
     Rcm[e] = r <= c ? S[r * SM_PITCH + c] : 0.0;
   }
-  // column c of R^{-1} by back substitution, bottom row first
-  for (int c = t; c < ldc; c += NT) {
-    for (int r = a - 1; r >= 0; --r) {
-      double v = 0.0;
-      if (c < a && r <= c) {
-        if (r == c) {
-          v = 1.0 / S[c * SM_PITCH + c];
-        } else {
-          double sum = 0.0;
-          for (int k = r + 1; k <= c; ++k) sum += S[r * SM_PITCH + k] * Rinv[(int64_t)k * ldc + c];
-          v = -sum / S[r * SM_PITCH + r];
-        }
-      }
-      Rinv[(int64_t)r * ldc + c] = v;
+  // column c of R^{-1} by back substitution, bottom row first, kept in LDS:
+  // X[r][c] (r < c) at S[c][r] (the lower triangle, unused by R), X[c][c] in xd
+  __shared__ double xd[NYS_MAXL];
+  for (int c = t; c < a; c += NT) {
+    const double xc = 1.0 / S[c * SM_PITCH + c];
+    xd[c] = xc;
+    for (int r = c - 1; r >= 0; --r) {
+      double sum = S[r * SM_PITCH + c] * xc;
+      for (int k = r + 1; k < c; ++k) sum += S[r * SM_PITCH + k] * S[c * SM_PITCH + k];
+      S[c * SM_PITCH + r] = -sum / S[r * SM_PITCH + r];
     }
+  }
+  __syncthreads();
+  for (int e = t; e < a * ldc; e += NT) {
+    const int r = e / ldc, c = e % ldc;
+    double v = 0.0;
+    if (c < a) v = r < c ? S[c * SM_PITCH + r] : (r == c ? xd[c] : 0.0);
+    Rinv[e] = v;
   }
   if (t == 0) status[0] = 0;
 }
@@ -287,10 +280,8 @@ int gram(nfl_plan *P, NysWork &W, const double *X, int a, const double *Y, int b
   const int nb = (int)std::min<int64_t>(GR_MAXB, (n + GR_ROWS - 1) / GR_ROWS);
   hipLaunchKernelGGL(k_gram_partial, dim3(nb), dim3(NT), 0, P->stream, X, n, a, Y, n, b, n,
                      W.part.p);
-  hipLaunchKernelGGL(k_gram_final, dim3((a * b + NT - 1) / NT), dim3(NT), 0, P->stream, W.part.p,
-                     nb, a * b, C);
   NFL_HIP(hipGetLastError());
-  return NFL_OK;
+  return colsum(P->stream, W.part.p, nb, a * b, C);
 }
 
 int rowmul(nfl_plan *P, const double *X, int a, const double *C, int ldc, int b, double *out) {
