@@ -384,11 +384,16 @@ __global__ __launch_bounds__(JAC_THREADS) void k_sym_jacobi(const double *__rest
   for (int64_t idx = tid; idx < (int64_t)m * m; idx += JAC_THREADS) nn += A[idx] * A[idx];
   const double nrm = sqrt(jac_block_sum(nn, sh));
   const int M = m + (m & 1), npair = M / 2;
+  // (pair or row, column) index spaces use the stride KS; for small orders it
+  // is the constant 64, so that splitting an index needs no division
+  const int KS = IN_LDS ? JAC_LDS_MAXM : m;
   int st = 1;
   for (int sweep = 0; sweep < 40; ++sweep) {
     double off = 0.0;
-    for (int64_t idx = tid; idx < (int64_t)m * m; idx += JAC_THREADS)
-      if (idx % m != idx / m) off += A[idx] * A[idx];
+    for (int64_t idx = tid; idx < (int64_t)KS * KS; idx += JAC_THREADS) {
+      const int r = (int)(idx / KS), c = (int)(idx % KS);
+      if (r < m && c < m && r != c) off += A[(int64_t)c * m + r] * A[(int64_t)c * m + r];
+    }
     off = sqrt(jac_block_sum(off, sh));
     if (off <= 1e-15 * nrm) {
       st = 0;
@@ -418,10 +423,10 @@ __global__ __launch_bounds__(JAC_THREADS) void k_sym_jacobi(const double *__rest
       }
       __syncthreads();
       // rows p, q of A
-      for (int64_t idx = tid; idx < (int64_t)npair * m; idx += JAC_THREADS) {
-        const int i = (int)(idx / m), k = (int)(idx % m);
+      for (int64_t idx = tid; idx < (int64_t)npair * KS; idx += JAC_THREADS) {
+        const int i = (int)(idx / KS), k = (int)(idx % KS);
         const int q = rq[i];
-        if (q < 0) continue;
+        if (q < 0 || k >= m) continue;
         const int p = rp[i];
         const double c = rc[i], s = rs[i];
         const double ap = A[(int64_t)k * m + p], aq = A[(int64_t)k * m + q];
@@ -430,10 +435,10 @@ __global__ __launch_bounds__(JAC_THREADS) void k_sym_jacobi(const double *__rest
       }
       __syncthreads();
       // columns p, q of A and of V
-      for (int64_t idx = tid; idx < (int64_t)npair * m; idx += JAC_THREADS) {
-        const int i = (int)(idx / m), k = (int)(idx % m);
+      for (int64_t idx = tid; idx < (int64_t)npair * KS; idx += JAC_THREADS) {
+        const int i = (int)(idx / KS), k = (int)(idx % KS);
         const int q = rq[i];
-        if (q < 0) continue;
+        if (q < 0 || k >= m) continue;
         const int p = rp[i];
         const double c = rc[i], s = rs[i];
         const double ap = A[(int64_t)p * m + k], aq = A[(int64_t)q * m + k];

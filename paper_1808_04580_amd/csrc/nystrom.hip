@@ -139,16 +139,16 @@ __global__ __launch_bounds__(NT) void k_chol(const double *__restrict__ Gm, int 
                                              double *__restrict__ Rinv, int ldc,
                                              int *__restrict__ status) {
   __shared__ double S[NYS_MAXL * SM_PITCH];   // S[r * SM_PITCH + c]
-  __shared__ int fail;
+  __shared__ double rd[NYS_MAXL];             // diagonal of R
   __shared__ double shift;
   const int t = threadIdx.x;
+  const int col = t & 63, rgrp = t >> 6;      // column and row group of this thread
   for (int e = t; e < a * a; e += NT) {
     const int r = e % a, c = e / a;
     S[r * SM_PITCH + c] = Gm[e];
   }
   __syncthreads();
   if (t == 0) {
-    fail = 0;
     double sh = 0.0;
     if (shift_rows > 0) {
       double tr = 0.0;
@@ -160,23 +160,24 @@ __global__ __launch_bounds__(NT) void k_chol(const double *__restrict__ Gm, int 
   __syncthreads();
   for (int i = t; i < a; i += NT) S[i * SM_PITCH + i] += shift;
   __syncthreads();
+  // Step j reads the pivot d = S[j][j] (the same value in every thread, so a
+  // failure is seen by all), updates the trailing block with the unscaled row
+  // j (S[r][c] -= S[j][r] S[j][c] / d, j < r <= c) and, in the same phase,
+  // scales the previous row into row j-1 of R; one barrier per step.
+  int fail = 0;
   for (int j = 0; j < a; ++j) {
-    if (t == 0) {
-      const double d = S[j * SM_PITCH + j];
-      if (!(d > 0.0) || !isfinite(d))
-        fail = j + 1;
-      else
-        S[j * SM_PITCH + j] = sqrt(d);
+    const double d = S[j * SM_PITCH + j];
+    if (!(d > 0.0) || !isfinite(d)) {
+      fail = j + 1;
+      break;
     }
-    __syncthreads();
-    if (fail) break;
-    const double rjj = S[j * SM_PITCH + j];
-    for (int c = j + 1 + t; c < a; c += NT) S[j * SM_PITCH + c] /= rjj;
-    __syncthreads();
-    const int w = a - j - 1;
-    for (int e = t; e < w * w; e += NT) {
-      const int r = j + 1 + e % w, c = j + 1 + e / w;
-      if (r <= c) S[r * SM_PITCH + c] -= S[j * SM_PITCH + r] * S[j * SM_PITCH + c];
+    if (t == 0) rd[j] = sqrt(d);
+    if (j > 0 && rgrp == 0 && col > j - 1 && col < a)
+      S[(j - 1) * SM_PITCH + col] /= sqrt(S[(j - 1) * SM_PITCH + (j - 1)]);
+    if (col > j && col < a) {
+      const double sjc = S[j * SM_PITCH + col] / d;
+      for (int r = j + 1 + rgrp; r <= col; r += NT / 64)
+        S[r * SM_PITCH + col] -= S[j * SM_PITCH + r] * sjc;
     }
     __syncthreads();
   }
@@ -186,20 +187,21 @@ __global__ __launch_bounds__(NT) void k_chol(const double *__restrict__ Gm, int 
     if (t == 0) status[0] = fail;
     return;
   }
+  // R[r][c] = S[r][c] (r < c), rd[r] (r == c)
   for (int e = t; e < a * a; e += NT) {
     const int r = e % a, c = e / a;
-    Rcm[e] = r <= c ? S[r * SM_PITCH + c] : 0.0;
+    Rcm[e] = r < c ? S[r * SM_PITCH + c] : (r == c ? rd[r] : 0.0);
   }
   // column c of R^{-1} by back substitution, bottom row first, kept in LDS:
   // X[r][c] (r < c) at S[c][r] (the lower triangle, unused by R), X[c][c] in xd
   __shared__ double xd[NYS_MAXL];
   for (int c = t; c < a; c += NT) {
-    const double xc = 1.0 / S[c * SM_PITCH + c];
+    const double xc = 1.0 / rd[c];
     xd[c] = xc;
     for (int r = c - 1; r >= 0; --r) {
       double sum = S[r * SM_PITCH + c] * xc;
       for (int k = r + 1; k < c; ++k) sum += S[r * SM_PITCH + k] * S[c * SM_PITCH + k];
-      S[c * SM_PITCH + r] = -sum / S[r * SM_PITCH + r];
+      S[c * SM_PITCH + r] = -sum / rd[r];
     }
   }
   __syncthreads();
