@@ -27,6 +27,14 @@ Readings of the paper taken here (listed with the rest in the design notes):
 * Nodes are shifted to their bounding-box midpoint and always scaled so that
   the largest norm is exactly 1/4 - eps_B/2 (Alg. nfft_normalized_matvec,
   steps 1-2); sigma becomes rho * sigma.  W itself does not change.
+* Other radial kernels of eq. W_general (multiquadric (r^2 + c^2)^{1/2},
+  inverse multiquadric (r^2 + c^2)^{-1/2}): c is a length like sigma, so in
+  the scaled coordinates it becomes rho * c and, both kernels being
+  homogeneous in (r, c), the sums come out multiplied by rho (multiquadric)
+  or 1/rho (inverse multiquadric); they are divided by that factor
+  afterwards.  (Alg. nfft_normalized_matvec prints c/rho and the reverse
+  factors, which contradicts this homogeneity; the direct sums in the
+  original coordinates decide, see the pins.)
 """
 from __future__ import annotations
 
@@ -91,15 +99,77 @@ def two_point_taylor(a: float, b: float, A, B):
     return np.linalg.solve(M, rhs)
 
 
-class RegKernel:
-    """K_R of the regularisation ansatz for the Gaussian, as a radial function."""
+# ---- other radial kernels of eq. W_general -----------------------------------
 
-    def __init__(self, sigma: float, eps_B: float, p: int):
+KINDS = ("gaussian", "multiquadric", "inverse_multiquadric")
+_ALPHA = {"multiquadric": 0.5, "inverse_multiquadric": -0.5}
+
+
+def radial_kernel(kind: str, param: float):
+    """K as a function of r = ||y||: exp(-r^2/s^2) (param = s), or
+    (r^2 + c^2)^alpha with alpha = 1/2 (multiquadric) or -1/2 (inverse
+    multiquadric), param = c."""
+    if kind == "gaussian":
+        return lambda r: gaussian(r, param)
+    a = _ALPHA[kind]
+    return lambda r: (np.asarray(r, dtype=np.float64) ** 2 + param * param) ** a
+
+
+def power_radial_derivs(r0: float, c: float, alpha: float, p: int):
+    """[K(r0), ..., K^{(p-1)}(r0)] for K(r) = (r^2 + c^2)^alpha.
+
+    With u0 = r0^2 + c^2 and t(h) = (2 r0 h + h^2)/u0,
+    K(r0 + h) = u0^alpha (1 + t)^alpha = u0^alpha sum_j binom(alpha, j) t^j,
+    and t^j = h^j (2 r0 + h)^j / u0^j contributes binom(j, k - j) (2 r0)^(2j-k)
+    / u0^j to the coefficient of h^k (k/2 <= j <= k); K^{(k)}(r0) is k! times
+    that coefficient."""
+    u0 = r0 * r0 + c * c
+
+    def gbinom(a, j):
+        out = 1.0
+        for i in range(j):
+            out *= (a - i) / (i + 1)
+        return out
+
+    out = []
+    for k in range(p):
+        acc = 0.0
+        for j in range((k + 1) // 2, k + 1):
+            acc += gbinom(alpha, j) * math.comb(j, k - j) * (2.0 * r0) ** (2 * j - k) / u0 ** j
+        out.append(math.factorial(k) * u0 ** alpha * acc)
+    return out
+
+
+def radial_derivs(kind: str, r0: float, param: float, p: int):
+    if kind == "gaussian":
+        return gaussian_radial_derivs(r0, param, p)
+    return power_radial_derivs(r0, param, _ALPHA[kind], p)
+
+
+def scaled_param(kind: str, param: float, rho: float) -> float:
+    """The kernel parameter in the scaled coordinates (a length: times rho)."""
+    return param * rho
+
+
+def output_scale(kind: str, rho: float) -> float:
+    """K(y; param) = output_scale * K(rho y; rho param) (homogeneity)."""
+    return {"gaussian": 1.0, "multiquadric": 1.0 / rho, "inverse_multiquadric": rho}[kind]
+
+
+class RegKernel:
+    """K_R of the regularisation ansatz, as a radial function (Gaussian by
+    default; `kind` selects another kernel of eq. W_general, `sigma` is then
+    its parameter c)."""
+
+    def __init__(self, sigma: float, eps_B: float, p: int, kind: str = "gaussian"):
         self.sigma, self.eps_B, self.p = float(sigma), float(eps_B), int(p)
+        self.kind = kind
+        self.K = radial_kernel(kind, self.sigma)
         self.r0 = 0.5 - self.eps_B
+        self.k_half = float(self.K(0.5))
         if self.eps_B > 0:
-            A = gaussian_radial_derivs(self.r0, self.sigma, self.p)
-            B = [math.exp(-(0.5 / self.sigma) ** 2)] + [0.0] * (self.p - 1)
+            A = radial_derivs(kind, self.r0, self.sigma, self.p)
+            B = [self.k_half] + [0.0] * (self.p - 1)
             self.coef = two_point_taylor(self.r0, 0.5, A, B)
         else:
             self.coef = None
@@ -110,10 +180,10 @@ class RegKernel:
 
     def __call__(self, r):
         r = np.asarray(r, dtype=np.float64)
-        out = gaussian(r, self.sigma)
+        out = self.K(r)
         if self.coef is None:
             # eps_B = 0: no transition region; constant K(1/2) beyond radius 1/2
-            return np.where(r <= 0.5, out, math.exp(-(0.5 / self.sigma) ** 2))
+            return np.where(r <= 0.5, out, self.k_half)
         mid = (r > self.r0) & (r <= 0.5)
         out = np.where(mid, self.T_B(r), out)
         out = np.where(r > 0.5, self.T_B(0.5), out)
@@ -127,12 +197,13 @@ def index_set(N: int):
     return np.arange(-N // 2, N // 2)
 
 
-def coefficients(sigma: float, N: int, d: int, eps_B: float, p: int) -> np.ndarray:
+def coefficients(sigma: float, N: int, d: int, eps_B: float, p: int,
+                 kind: str = "gaussian") -> np.ndarray:
     """b_l for l in I_N^d, array of shape (N,)*d indexed by l + N/2.
 
     b_l = N^{-d} sum_{j in I_N^d} K_R(j/N) exp(-2 pi i j.l/N), computed as a DFT
     (numpy's FFT as the library primitive) of the samples placed at j mod N."""
-    K = RegKernel(sigma, eps_B, p)
+    K = RegKernel(sigma, eps_B, p, kind)
     j = index_set(N)
     grids = np.meshgrid(*([j / N] * d), indexing="ij")
     r = np.sqrt(sum(g * g for g in grids))
@@ -230,26 +301,30 @@ def trig_matrix(vt, bhat: np.ndarray, N: int):
 
 class TrigGraph:
     """Steps 1-5 of Alg. nfft_normalized_matvec with Alg. nfft_fastsum replaced
-    by its exact trigonometric operator (K(0) = 1 for the Gaussian)."""
+    by its exact trigonometric operator.  apply_Wt approximates W~ = W + K(0) I
+    in the original coordinates (for the Gaussian K(0) = 1)."""
 
-    def __init__(self, v, sigma: float, N: int, eps_B: float, p: int):
+    def __init__(self, v, sigma: float, N: int, eps_B: float, p: int, kind: str = "gaussian"):
         self.c, self.rho, self.vt = scaling(v, eps_B)
-        self.sigma_t = sigma * self.rho
+        self.kind = kind
+        self.sigma_t = scaled_param(kind, sigma, self.rho)
+        self.scale = output_scale(kind, self.rho)
+        self.K0 = float(radial_kernel(kind, sigma)(0.0))
         self.N = N
-        self.bhat = coefficients(self.sigma_t, N, self.vt.shape[1], eps_B, p)
+        self.bhat = coefficients(self.sigma_t, N, self.vt.shape[1], eps_B, p, kind)
         ones = np.ones(self.vt.shape[0])
-        self.d = trig_operator(self.vt, ones, self.bhat, N) - 1.0      # step 4
+        self.d = self.apply_Wt(ones) - self.K0                       # step 4
         self.dinv = 1.0 / np.sqrt(self.d)
 
     def apply_Wt(self, x):
-        return trig_operator(self.vt, x, self.bhat, self.N)
+        return self.scale * trig_operator(self.vt, x, self.bhat, self.N)
 
     def apply_W(self, x):
-        return self.apply_Wt(x) - np.asarray(x, dtype=np.float64)
+        return self.apply_Wt(x) - self.K0 * np.asarray(x, dtype=np.float64)
 
     def apply_A(self, x):                                             # step 5
         xs = self.dinv * np.asarray(x, dtype=np.float64)
-        return self.dinv * (self.apply_Wt(xs) - xs)
+        return self.dinv * (self.apply_Wt(xs) - self.K0 * xs)
 
     def apply_Ls(self, x):
         return np.asarray(x, dtype=np.float64) - self.apply_A(x)
@@ -257,15 +332,16 @@ class TrigGraph:
 
 # ---- Section 3.1: error quantities ------------------------------------------
 
-def kerr_sampled(bhat, N, sigma, eps_B, d, samples=20000, seed=0):
+def kerr_sampled(bhat, N, sigma, eps_B, d, samples=20000, seed=0, kind="gaussian"):
     """max |K(y) - Re K_RF(y)| over random y with ||y|| <= 1/2 - eps_B
-    (eq. KERR_estimate, maximum discretised by sampling)."""
+    (eq. KERR_estimate, maximum discretised by sampling); K of the given kind
+    with parameter sigma (in the scaled coordinates)."""
     rng = np.random.default_rng(seed)
     g = rng.normal(size=(samples, d))
     g /= np.linalg.norm(g, axis=1, keepdims=True)
     r = (0.5 - eps_B) * rng.uniform(0.0, 1.0, size=samples) ** (1.0 / d)
     y = g * r[:, None]
-    return float(np.abs(gaussian(r, sigma) - K_RF(y, bhat, N).real).max())
+    return float(np.abs(radial_kernel(kind, sigma)(r) - K_RF(y, bhat, N).real).max())
 
 
 def lemma_bound(eps: float, eta: float) -> float:

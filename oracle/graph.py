@@ -5,7 +5,8 @@ float32 dataset is promoted exactly, sigma is used in the same coordinates.
 
 Definitions followed (Section 2):
 * weights: W_ji = exp(-||v_j - v_i||^2 / sigma^2) for j != i, W_jj = 0
-  (eq. W_gaussian);
+  (eq. W_gaussian); the dense forms also take the other radial kernels of
+  eq. W_general (multiquadric, inverse multiquadric);
 * degree: d_j = sum_i W_ji, D = diag(d);
 * combinatorial Laplacian L = D - W;
 * symmetric normalised Laplacian L_s = I - D^{-1/2} W D^{-1/2} (eq. nomlap);
@@ -90,28 +91,43 @@ def Ls_rows(v, sigma, x, rows, d):
 
 # ---- dense forms for small n (a second, independent code path) -------------
 
-def dense_W(v, sigma: float) -> np.ndarray:
-    """The n x n weight matrix formed explicitly (small n only)."""
+def kernel_matrix(v, param: float, kind: str = "gaussian") -> np.ndarray:
+    """K(v_i - v_j) for all i, j including the diagonal K(0) (eq. W_general):
+    exp(-r^2/param^2) for the Gaussian, sqrt(r^2 + param^2) for the
+    multiquadric, 1/sqrt(r^2 + param^2) for the inverse multiquadric kernel
+    (small n only)."""
     V = _v64(v)
     diff = V[:, None, :] - V[None, :, :]
-    W = np.exp(-(diff * diff).sum(axis=2) / (sigma * sigma))
+    r2 = (diff * diff).sum(axis=2)
+    if kind == "gaussian":
+        return np.exp(-r2 / (param * param))
+    if kind == "multiquadric":
+        return np.sqrt(r2 + param * param)
+    if kind == "inverse_multiquadric":
+        return 1.0 / np.sqrt(r2 + param * param)
+    raise ValueError(kind)
+
+
+def dense_W(v, sigma: float, kind: str = "gaussian") -> np.ndarray:
+    """The n x n weight matrix formed explicitly (small n only), zero diagonal."""
+    W = kernel_matrix(v, sigma, kind)
     np.fill_diagonal(W, 0.0)
     return W
 
 
-def dense_L(v, sigma):
-    W = dense_W(v, sigma)
+def dense_L(v, sigma, kind: str = "gaussian"):
+    W = dense_W(v, sigma, kind)
     return np.diag(W.sum(axis=1)) - W
 
 
-def dense_Ls(v, sigma):
-    W = dense_W(v, sigma)
+def dense_Ls(v, sigma, kind: str = "gaussian"):
+    W = dense_W(v, sigma, kind)
     s = 1.0 / np.sqrt(W.sum(axis=1))
     return np.eye(W.shape[0]) - s[:, None] * W * s[None, :]
 
 
-def dense_A(v, sigma):
-    W = dense_W(v, sigma)
+def dense_A(v, sigma, kind: str = "gaussian"):
+    W = dense_W(v, sigma, kind)
     s = 1.0 / np.sqrt(W.sum(axis=1))
     return s[:, None] * W * s[None, :]
 

@@ -137,6 +137,84 @@ def test_coefficients_closed_form_small_sigma():
     np.testing.assert_allclose(b, ref, atol=1e-15)
 
 
+@pytest.mark.parametrize("kind", ["multiquadric", "inverse_multiquadric"])
+def test_power_kernel_derivatives(kind):
+    """Radial derivatives of (r^2 + c^2)^alpha: the first two against the
+    textbook closed forms, all against central differences of the next-lower
+    one (step 1e-5, truncation ~ (h/c)^2)."""
+    c, r0, p = 0.3, 0.37, 7
+    D = fastsum.radial_derivs(kind, r0, c, p)
+    u = r0 * r0 + c * c
+    if kind == "multiquadric":
+        closed = [math.sqrt(u), r0 / math.sqrt(u), c * c / u ** 1.5]
+    else:
+        closed = [u ** -0.5, -r0 * u ** -1.5, (2 * r0 * r0 - c * c) * u ** -2.5]
+    for k in range(3):
+        assert abs(D[k] - closed[k]) <= 1e-14 * max(1.0, abs(closed[k])), k
+    h = 1e-5
+    for k in range(1, p):
+        lo = fastsum.radial_derivs(kind, r0 - h, c, k)[k - 1]
+        hi = fastsum.radial_derivs(kind, r0 + h, c, k)[k - 1]
+        fd = (hi - lo) / (2 * h)
+        assert abs(D[k] - fd) <= 1e-6 * max(abs(D[k]), abs(D[k - 1]) / c), k
+
+
+@pytest.mark.parametrize("kind,p", [("multiquadric", 4), ("inverse_multiquadric", 6)])
+def test_two_point_taylor_conditions_other_kernels(kind, p):
+    """The regularisation of the other kernels meets the same Hermite
+    conditions: K and p-1 derivatives at 1/2 - eps_B, K(1/2) and flat at 1/2."""
+    c, eps = 0.15, 1.0 / 8
+    K = fastsum.RegKernel(c, eps, p, kind)
+    poly = np.polynomial.Polynomial(K.coef)
+    h = 0.5 - K.r0
+    A = fastsum.radial_derivs(kind, K.r0, c, p)
+    want_half = float(fastsum.radial_kernel(kind, c)(0.5))
+    for k in range(p):
+        dk = poly.deriv(k) if k else poly
+        scale = sum(abs(cf) * q**k for q, cf in enumerate(K.coef)) / h**k
+        assert abs(dk(0.0) / h**k - A[k]) <= 1e-12 * scale + 1e-14
+        assert abs(dk(1.0) / h**k - (want_half if k == 0 else 0.0)) <= 1e-12 * scale + 1e-14
+
+
+@pytest.mark.parametrize("kind", ["multiquadric", "inverse_multiquadric"])
+def test_coefficients_interpolate_samples_other_kernels(kind):
+    """K_RF(j/N) = K_R(j/N) on I_N^d for the other kernels too."""
+    d, N, eps, c = 2, 16, 1.0 / 8, 0.1
+    b = fastsum.coefficients(c, N, d, eps, 4, kind)
+    j = fastsum.index_set(N)
+    nodes = np.stack(np.meshgrid(*([j / N] * d), indexing="ij"), axis=-1).reshape(-1, d)
+    K = fastsum.RegKernel(c, eps, 4, kind)
+    got = fastsum.K_RF(nodes, b, N)
+    np.testing.assert_allclose(got.real, K(np.linalg.norm(nodes, axis=1)), atol=1e-12)
+
+
+@pytest.mark.parametrize("kind,c", [("multiquadric", 0.2), ("inverse_multiquadric", 0.2)])
+def test_other_kernels_scaled_operator_matches_direct_sums(kind, c):
+    """In the scaled coordinates the parameter is rho c and the sums carry the
+    homogeneity factor (rho for the multiquadric, 1/rho for the inverse
+    multiquadric), which the operator divides out: W x and the degrees then
+    match the direct sums in the original coordinates within
+    ||x||_1 ||K_ERR||_inf times that factor.  (The other reading, c / rho with
+    the reverse factors, misses by orders of magnitude.)"""
+    v = synth.gmm(300, d=3, k=3, seed=11)
+    N, eps, p = 64, 1.0 / 8, 6
+    T = fastsum.TrigGraph(v, c, N, eps, p, kind)
+    W = graph.dense_W(v, c, kind)
+    x = np.random.default_rng(2).standard_normal(300)
+    kerr = fastsum.kerr_sampled(T.bhat, N, T.sigma_t, eps, 3, samples=20000, kind=kind)
+    bound = 2.0 * T.scale * kerr * np.abs(x).sum()
+    err = np.abs(T.apply_W(x) - W @ x).max()
+    assert err <= bound
+    assert np.abs(T.d - W.sum(axis=1)).max() <= 2.0 * T.scale * kerr * 300
+    # and the bound is meaningful: well below the size of W x
+    assert bound < 1e-2 * np.abs(W @ x).max()
+    # the inverted reading of the parameter scaling is far off
+    c2, rho, vt = fastsum.scaling(v, eps)
+    b_wrong = fastsum.coefficients(c / rho, N, 3, eps, p, kind)
+    wrong = (1.0 / fastsum.output_scale(kind, rho)) * fastsum.trig_operator(vt, x, b_wrong, N)
+    assert np.abs(wrong - T.K0 * x - W @ x).max() > 100 * bound
+
+
 # ---- Oracle B: the exact trigonometric operator -----------------------------
 
 def test_trig_operator_on_grid_nodes_is_the_direct_sum():
