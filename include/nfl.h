@@ -83,6 +83,25 @@ int nfl_set_points(nfl_handle h, int64_t n, const float *v_dev);
  * NFL_ERR_DEGREE if some d_E,i <= 0 (then apply calls fail with ORDER). */
 int nfl_set_kernel(nfl_handle h, double sigma, int N, int m, double eps_B);
 
+/* Radial kernels of eq. W_general for nfl_set_kernel_ex. */
+#define NFL_KERNEL_GAUSSIAN               0  /* exp(-r^2 / param^2), K(0) = 1 */
+#define NFL_KERNEL_MULTIQUADRIC           1  /* (r^2 + param^2)^{1/2}, K(0) = param */
+#define NFL_KERNEL_INVERSE_MULTIQUADRIC   2  /* (r^2 + param^2)^{-1/2}, K(0) = 1/param */
+
+/* nfl_set_kernel for any kernel of eq. W_general above (Alg.
+ * nfft_normalized_matvec, steps 1-4): W_ij = K(v_i - v_j) for i != j, W_ii = 0,
+ * param > 0 in the coordinates of the points.  The parameter is a length: in
+ * the scaled coordinates it becomes rho * param, and the multiquadric sums
+ * come out times rho, the inverse multiquadric ones times 1/rho (homogeneity);
+ * both are undone.  The NFFT works with the kernel divided by K(0), so that
+ * L_s and A products run exactly as for the Gaussian; nfl_apply_W and
+ * nfl_degree multiply their outputs by K(0), and nfl_get_info reports the
+ * degree range in the original units.  The kernel-approximation error of
+ * these slowly decaying kernels is much larger than the Gaussian's at the same
+ * N (choose N = 64 or more and eps_B around 1/8); nfl_autotune and
+ * nfl_direct_rows are for the Gaussian only. */
+int nfl_set_kernel_ex(nfl_handle h, int kind, double param, int N, int m, double eps_B);
+
 int nfl_set_option(nfl_handle h, int opt, double value);
 
 /* d_E (step 4 of Alg. nfft_normalized_matvec): n float32 in caller order. */
@@ -234,6 +253,11 @@ int nfl_profile_stages(nfl_handle h, const float *x_dev, float *y_dev, int nrep,
  * must be >= (N+1)^(d-1) (N/2+1).  N a power of 2. */
 int nfl_compute_filter(int d, int N, int m, int p, double eps_B, double sigma_tilde,
                        double *filter_host, int64_t count);
+
+/* nfl_compute_filter for a kernel kind (NFL_KERNEL_*): the filter of the
+ * kernel divided by K(0), sigma_tilde = the scaled parameter. */
+int nfl_compute_filter_ex(int kind, int d, int N, int m, int p, double eps_B, double sigma_tilde,
+                          double *filter_host, int64_t count);
 
 /* The window the kernels apply (host, no GPU): for each of the 2m grid
  * offsets c of a node's window, NFL_WIN_NC float32 coefficients of the

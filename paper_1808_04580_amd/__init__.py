@@ -29,6 +29,7 @@ OPT_TILE = 2
 OPT_CHUNK = 3
 OPT_EPS_B_DEFAULT = 4
 OPT_KERNEL = 5
+KERNELS = {"gaussian": 0, "multiquadric": 1, "inverse_multiquadric": 2}
 
 WARM_ZERO = 0
 WARM_USER = 1
@@ -43,6 +44,7 @@ SIGNATURES = {
     "nfl_destroy": (_i, [_p]),
     "nfl_set_points": (_i, [_p, _i64, _p]),
     "nfl_set_kernel": (_i, [_p, _d, _i, _i, _d]),
+    "nfl_set_kernel_ex": (_i, [_p, _i, _d, _i, _i, _d]),
     "nfl_set_option": (_i, [_p, _i, _d]),
     "nfl_degree": (_i, [_p, _p]),
     "nfl_apply_W": (_i, [_p, _p, _p, _i, _i64]),
@@ -58,6 +60,7 @@ SIGNATURES = {
     "nfl_interp": (_i, [_p, _p, _p]),
     "nfl_get_filter": (_i, [_p, _p, _i64]),
     "nfl_compute_filter": (_i, [_i, _i, _i, _i, _d, _d, _p, _i64]),
+    "nfl_compute_filter_ex": (_i, [_i, _i, _i, _i, _i, _d, _d, _p, _i64]),
     "nfl_profile_stages": (_i, [_p, _p, _p, _i, _p]),
     "nfl_window_coefficients": (_i, [_i, _p, _i64]),
     "nfl_mlp_create": (_i, [ctypes.POINTER(_p), _i, ctypes.c_uint64, _p]),
@@ -116,12 +119,15 @@ def strerror(code: int) -> str:
     return lib().nfl_strerror(code).decode()
 
 
-def compute_filter(d: int, N: int, m: int, p: int, eps_B: float, sigma_tilde: float) -> np.ndarray:
-    """The half-spectrum filter (host FP64, no GPU needed)."""
+def compute_filter(d: int, N: int, m: int, p: int, eps_B: float, sigma_tilde: float,
+                   kind: str = "gaussian") -> np.ndarray:
+    """The half-spectrum filter (host FP64, no GPU needed); for kernels other
+    than the Gaussian, of the kernel divided by K(0)."""
     count = (N + 1) ** (d - 1) * (N // 2 + 1)
     out = np.empty(count, dtype=np.float64)
-    _check(lib().nfl_compute_filter(d, N, m, p, float(eps_B), float(sigma_tilde),
-                                    out.ctypes.data_as(_p), count), "nfl_compute_filter")
+    _check(lib().nfl_compute_filter_ex(KERNELS[kind], d, N, m, p, float(eps_B),
+                                       float(sigma_tilde), out.ctypes.data_as(_p), count),
+           "nfl_compute_filter_ex")
     shape = tuple([N + 1] * (d - 1) + [N // 2 + 1])
     return out.reshape(shape)
 
@@ -187,9 +193,12 @@ class Plan:
         self.n = int(v.shape[0])
         _check(lib().nfl_set_points(self._h, self.n, _ptr(v)), "nfl_set_points")
 
-    def set_kernel(self, sigma: float, N: int, m: int, eps_B: float = 0.0):
-        _check(lib().nfl_set_kernel(self._h, float(sigma), int(N), int(m), float(eps_B)),
-               "nfl_set_kernel")
+    def set_kernel(self, sigma: float, N: int, m: int, eps_B: float = 0.0,
+                   kind: str = "gaussian"):
+        """sigma: the kernel parameter (Gaussian width, or c of the
+        (inverse) multiquadric kernel)."""
+        _check(lib().nfl_set_kernel_ex(self._h, KERNELS[kind], float(sigma), int(N), int(m),
+                                       float(eps_B)), "nfl_set_kernel_ex")
         self._N = int(N)
 
     def info(self) -> dict:
@@ -351,7 +360,8 @@ class Plan:
         return out
 
 
-def plan(points, sigma: float, N: int, m: int, eps_B: float = 0.0, stream=None, **options):
+def plan(points, sigma: float, N: int, m: int, eps_B: float = 0.0, stream=None,
+         kind: str = "gaussian", **options):
     """Create, fill and return a Plan for float32 points (n, d) on the GPU."""
     import torch
     v = torch.as_tensor(points)
@@ -361,7 +371,7 @@ def plan(points, sigma: float, N: int, m: int, eps_B: float = 0.0, stream=None, 
         P.set_option({"p": OPT_P, "tile": OPT_TILE, "chunk": OPT_CHUNK, "kernel": OPT_KERNEL}[k],
                      val)
     P.set_points(v)
-    P.set_kernel(sigma, N, m, eps_B)
+    P.set_kernel(sigma, N, m, eps_B, kind=kind)
     return P
 
 

@@ -16,7 +16,23 @@ static thread_local std::string g_last_error;
 void set_error(const std::string &msg) { g_last_error = msg; }
 
 int compute_filter(int d, int N, int m, int p, double eps_B, double sigma_t,
-                   std::vector<double> &out);
+                   std::vector<double> &out, int kind);
+
+// y[i] *= s, i < n (W and degree outputs of non-Gaussian kernels: the NFFT
+// works with K / K(0))
+__global__ void k_scale_f32(float *__restrict__ y, int64_t n, float s) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] *= s;
+}
+
+static int scale_out(nfl_plan *P, float *y) {
+  if (P->wscale == 1.0) return NFL_OK;
+  const int blocks = (int)std::min<int64_t>(4096, (P->n + 255) / 256);
+  hipLaunchKernelGGL(k_scale_f32, dim3(blocks), dim3(256), 0, P->stream, y, P->n, (float)P->wscale);
+  NFL_HIP(hipGetLastError());
+  return NFL_OK;
+}
 
 static bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
 
@@ -142,9 +158,14 @@ int nfl_set_points(nfl_handle P, int64_t n, const float *v_dev) {
 }
 
 int nfl_set_kernel(nfl_handle P, double sigma, int N, int m, double eps_B) {
+  return nfl_set_kernel_ex(P, NFL_KERNEL_GAUSSIAN, sigma, N, m, eps_B);
+}
+
+int nfl_set_kernel_ex(nfl_handle P, int kind, double sigma, int N, int m, double eps_B) {
   if (!P) { set_error("null handle"); return NFL_ERR_ARG; }
   if (!P->have_points) { set_error("set_kernel before set_points"); return NFL_ERR_ORDER; }
-  if (!(sigma > 0) || !std::isfinite(sigma)) { set_error("sigma must be > 0"); return NFL_ERR_ARG; }
+  if (kind < NFL_KERNEL_GAUSSIAN || kind > NFL_KERNEL_INVERSE_MULTIQUADRIC) { set_error("unknown kernel kind"); return NFL_ERR_ARG; }
+  if (!(sigma > 0) || !std::isfinite(sigma)) { set_error("kernel parameter must be > 0"); return NFL_ERR_ARG; }
   if (N < 2 || (N & 1)) { set_error("N must be even and >= 2"); return NFL_ERR_ARG; }
   if (m < 1) { set_error("m must be >= 1"); return NFL_ERR_ARG; }
   const int p = P->opt_p > 0 ? P->opt_p : m;
@@ -155,7 +176,9 @@ int nfl_set_kernel(nfl_handle P, double sigma, int N, int m, double eps_B) {
   if (2 * m > N) { set_error("window wider than half the grid (need m <= N/2)"); return NFL_ERR_UNSUPPORTED; }
   ++P->gen;
   P->have_kernel = false;
+  P->kind = kind;
   P->sigma = sigma;
+  P->wscale = kind == NFL_KERNEL_GAUSSIAN ? 1.0 : (kind == NFL_KERNEL_MULTIQUADRIC ? sigma : 1.0 / sigma);
   P->N = N;
   P->m = m;
   P->p = p;
@@ -225,7 +248,8 @@ int nfl_degree(nfl_handle P, float *d_dev) {
   if (!P) { set_error("null handle"); return NFL_ERR_ARG; }
   if (!P->have_kernel) { set_error("degree before a successful nfl_set_kernel"); return NFL_ERR_ORDER; }
   if (!d_dev) { set_error("null output"); return NFL_ERR_ARG; }
-  return scatter_f32(P, P->deg.p, d_dev);
+  NFL_TRY(scatter_f32(P, P->deg.p, d_dev));
+  return scale_out(P, d_dev);
 }
 
 static int apply_common(nfl_handle P, const float *x, float *y, int nvec, int64_t ld, int in_mode,
@@ -241,7 +265,9 @@ static int apply_common(nfl_handle P, const float *x, float *y, int nvec, int64_
 }
 
 int nfl_apply_W(nfl_handle P, const float *x, float *y, int nvec, int64_t ld) {
-  return apply_common(P, x, y, nvec, ld, IN_USER_F32, OUT_USER_W);
+  NFL_TRY(apply_common(P, x, y, nvec, ld, IN_USER_F32, OUT_USER_W));
+  for (int k = 0; k < nvec && P->wscale != 1.0; ++k) NFL_TRY(scale_out(P, y + (int64_t)k * ld));
+  return NFL_OK;
 }
 
 int nfl_apply_Ls(nfl_handle P, const float *x, float *y, int nvec, int64_t ld) {
@@ -288,8 +314,8 @@ int nfl_get_info(nfl_handle P, double *rho, double *sigma_tilde, double *dmin, d
   if (!P->have_kernel) { set_error("info before a successful nfl_set_kernel"); return NFL_ERR_ORDER; }
   if (rho) *rho = P->rho;
   if (sigma_tilde) *sigma_tilde = P->sigma_t;
-  if (dmin) *dmin = P->dmin;
-  if (dmax) *dmax = P->dmax;
+  if (dmin) *dmin = P->dmin * P->wscale;
+  if (dmax) *dmax = P->dmax * P->wscale;
   if (eps_B) *eps_B = P->eps_B;
   if (p) *p = P->p;
   return NFL_OK;
@@ -331,14 +357,21 @@ int nfl_get_filter(nfl_handle P, double *filter_host, int64_t count) {
 
 int nfl_compute_filter(int d, int N, int m, int p, double eps_B, double sigma_tilde,
                        double *filter_host, int64_t count) {
+  return nfl_compute_filter_ex(NFL_KERNEL_GAUSSIAN, d, N, m, p, eps_B, sigma_tilde, filter_host,
+                               count);
+}
+
+int nfl_compute_filter_ex(int kind, int d, int N, int m, int p, double eps_B, double sigma_tilde,
+                          double *filter_host, int64_t count) {
   if (!filter_host) { set_error("null output"); return NFL_ERR_ARG; }
+  if (kind < NFL_KERNEL_GAUSSIAN || kind > NFL_KERNEL_INVERSE_MULTIQUADRIC) { set_error("unknown kernel kind"); return NFL_ERR_ARG; }
   if (d < 1 || d > 3 || N < 2 || (N & 1) || !is_pow2(N) || m < 1 || p < 1 ||
       !(eps_B >= 0 && eps_B < 0.5) || !(sigma_tilde > 0)) {
     set_error("bad filter arguments");
     return NFL_ERR_ARG;
   }
   std::vector<double> f;
-  NFL_TRY(compute_filter(d, N, m, p, eps_B, sigma_tilde, f));
+  NFL_TRY(compute_filter(d, N, m, p, eps_B, sigma_tilde, f, kind));
   if (count < (int64_t)f.size()) { set_error("filter buffer too small"); return NFL_ERR_ARG; }
   std::memcpy(filter_host, f.data(), f.size() * sizeof(double));
   return NFL_OK;

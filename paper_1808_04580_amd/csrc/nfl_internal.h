@@ -108,7 +108,12 @@ struct nfl_plan {
   int opt_chunk = 512;
   bool opt_eps_default = false;
 
-  // kernel / NFFT parameters
+  // kernel / NFFT parameters; sigma is the kernel parameter (Gaussian width or
+  // multiquadric c), sigma_t = rho * sigma its value in the scaled
+  // coordinates; the NFFT works with the kernel divided by K(0), so W and the
+  // degrees come out divided by wscale = K(0) (L_s and A do not change)
+  int kind = NFL_KERNEL_GAUSSIAN;
+  double wscale = 1.0;
   double sigma = 0, eps_B = 0, rho = 1, sigma_t = 0;
   int N = 0, m = 0, p = 0, nos = 0, tshift = 3;
   bool have_kernel = false;

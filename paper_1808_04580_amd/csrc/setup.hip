@@ -465,6 +465,29 @@ static void gauss_derivs(double r, double s, int p, double *out) {
   }
 }
 
+// Radial derivatives K^{(k)}(r0), k < p, of (1 + r^2/c^2)^alpha: the
+// multiquadric (alpha = 1/2) or inverse multiquadric (alpha = -1/2) kernel of
+// eq. W_general divided by its value at 0.  With u(h) = 1 + (r0 + h)^2/c^2
+// (a quadratic in h), the Taylor coefficients w_k of u^alpha follow from
+// u w' = alpha u' w (J. C. P. Miller's recurrence for powers of a power
+// series): w_k = (1 / (k u_0)) sum_{j=1}^{min(k, 2)} ((alpha + 1) j - k) u_j w_{k-j};
+// K^{(k)}(r0) = k! w_k.
+static void power_derivs(double r0, double c, double alpha, int p, double *out) {
+  const double u[3] = {1.0 + r0 * r0 / (c * c), 2.0 * r0 / (c * c), 1.0 / (c * c)};
+  std::vector<double> w((size_t)p);
+  w[0] = std::pow(u[0], alpha);
+  for (int k = 1; k < p; ++k) {
+    double acc = 0.0;
+    for (int j = 1; j <= std::min(k, 2); ++j) acc += ((alpha + 1.0) * j - k) * u[j] * w[k - j];
+    w[k] = acc / (k * u[0]);
+  }
+  double f = 1.0;
+  for (int k = 0; k < p; ++k) {
+    if (k > 0) f *= k;
+    out[k] = f * w[k];
+  }
+}
+
 static double binom(int a, int b) {
   double r = 1.0;
   for (int i = 1; i <= b; ++i) r = r * (a - b + i) / i;
@@ -608,19 +631,30 @@ int window_coefficients(int m, std::vector<float> &coef) {
 }
 
 int compute_filter(int d, int N, int m, int p, double eps_B, double sigma_t,
-                   std::vector<double> &out) {
+                   std::vector<double> &out, int kind) {
   if (d < 1 || d > 3 || N < 2 || (N & 1) || m < 1 || p < 1 || 2 * m > WIN_MAXW) return NFL_ERR_ARG;
+  if (kind < NFL_KERNEL_GAUSSIAN || kind > NFL_KERNEL_INVERSE_MULTIQUADRIC) return NFL_ERR_ARG;
   const int nos = 2 * N;
   std::vector<float> wcoef;
   window_poly(m, M_PI * (2.0 - 0.5), wcoef);
   // ---- samples of K_R on I_N^d, stored at j mod N
   const double r0 = 0.5 - eps_B;
+  // the kernel in the scaled coordinates, divided by its value at 0 (sigma_t
+  // is the scaled width or the scaled multiquadric parameter c)
+  const double alpha = kind == NFL_KERNEL_MULTIQUADRIC ? 0.5 : -0.5;
+  auto Kn = [&](double r) -> double {
+    if (kind == NFL_KERNEL_GAUSSIAN) return std::exp(-(r * r) / (sigma_t * sigma_t));
+    return std::pow(1.0 + (r * r) / (sigma_t * sigma_t), alpha);
+  };
   std::vector<double> fa(p), fb(p, 0.0);
-  gauss_derivs(r0, sigma_t, p, fa.data());
-  fb[0] = std::exp(-(0.25) / (sigma_t * sigma_t));
+  if (kind == NFL_KERNEL_GAUSSIAN)
+    gauss_derivs(r0, sigma_t, p, fa.data());
+  else
+    power_derivs(r0, sigma_t, alpha, p, fa.data());
+  fb[0] = Kn(0.5);
   const double k_half = fb[0];
   auto KR = [&](double r) -> double {
-    if (r <= r0) return std::exp(-(r * r) / (sigma_t * sigma_t));
+    if (r <= r0) return Kn(r);
     if (eps_B <= 0.0) return k_half;  // no transition region
     if (r <= 0.5) return two_point_taylor(r, r0, 0.5, fa.data(), fb.data(), p);
     return two_point_taylor(0.5, r0, 0.5, fa.data(), fb.data(), p);
@@ -683,7 +717,7 @@ int compute_filter(int d, int N, int m, int p, double eps_B, double sigma_t,
 }
 
 int build_filter_host(nfl_plan *P) {
-  return compute_filter(P->d, P->N, P->m, P->p, P->eps_B, P->sigma_t, P->filt_host);
+  return compute_filter(P->d, P->N, P->m, P->p, P->eps_B, P->sigma_t, P->filt_host, P->kind);
 }
 
 }  // namespace nfl

@@ -57,6 +57,7 @@ def test_error_codes_without_gpu():
                           None) == nfl.NFL_ERR_ARG
     assert L.nfl_set_option(None, nfl.OPT_KERNEL, 2) == nfl.NFL_ERR_ARG
     assert L.nfl_nystrom(None, None, 0, 1, 1, 1, None, None, None) == nfl.NFL_ERR_ARG
+    assert L.nfl_set_kernel_ex(None, 1, 0.1, 32, 4, 0.0) == nfl.NFL_ERR_ARG
 
 
 def kb_hat_quadrature(xi, m, b=1.5 * math.pi, nq=2001):
@@ -137,3 +138,32 @@ def test_filter_equals_coefficients_over_window_transform(d, N, m, eps):
         den = np.prod([wh[li + N // 2] ** 2 for li in l])
         exp[q] = val / den
     np.testing.assert_allclose(F.reshape(-1), exp, rtol=1e-10, atol=1e-12 * np.abs(exp).max())
+
+
+@pytest.mark.parametrize("kind,d,N,m,eps", [("multiquadric", 2, 16, 4, 0.125),
+                                            ("inverse_multiquadric", 3, 8, 3, 0.25)])
+def test_filter_other_kernels_equals_coefficients_over_window_transform(kind, d, N, m, eps):
+    """The library's host filter for the other kernels (derivatives by a
+    power-series recurrence) against the oracle's coefficients (derivatives
+    by the binomial series), divided by K(0) and the squared window
+    transform, at the interior frequencies."""
+    c = 0.12
+    p = m
+    F = nfl.compute_filter(d, N, m, p, eps, c, kind=kind)
+    K0 = float(fastsum.radial_kernel(kind, c)(0.0))
+    b = fastsum.coefficients(c, N, d, eps, p, kind) / K0
+    nos = 2 * N
+    coef = nfl.window_coefficients(m)
+    wh = np.array([poly_window_hat(coef, m, l / nos) for l in range(-N // 2, N // 2 + 1)])
+    ext = np.arange(-N // 2, N // 2 + 1)
+    grids = np.meshgrid(*([ext] * (d - 1) + [np.arange(0, N // 2 + 1)]), indexing="ij")
+    L = np.stack(grids, axis=-1).reshape(-1, d)
+    exp = np.empty(L.shape[0])
+    for q, l in enumerate(L):
+        val = 0.0
+        if np.all(l <= N // 2 - 1):
+            val += 0.5 * b[tuple(l + N // 2)]
+        if np.all(-l <= N // 2 - 1):
+            val += 0.5 * b[tuple(-l + N // 2)]
+        exp[q] = val / np.prod([wh[li + N // 2] ** 2 for li in l])
+    np.testing.assert_allclose(F.reshape(-1), exp, rtol=1e-9, atol=1e-11 * np.abs(exp).max())
