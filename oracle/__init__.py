@@ -21,6 +21,8 @@ Modules
 ``krylov``   Lanczos with full reorthogonalisation (Section 4) and CG for the
              kernel-SSL system (eq. ssl::system).
 ``mlp``      FP64 reference of the pointwise warm-start network.
+``krr``      kernel ridge regression (Section 6.3): (K + beta I) alpha = f by
+             a dense solve, and the prediction sum.
 ``nystrom``  the Nystrom-Gaussian-NFFT eigenvalue approximation (Alg.
              nystrom_hybrid, Section 5.2), steps 3-8 on a given operator.
 

@@ -9,7 +9,7 @@ import math
 import numpy as np
 import pytest
 
-from oracle import fastsum, graph, krylov, nystrom
+from oracle import fastsum, graph, krr, krylov, nystrom
 import synth
 
 
@@ -403,6 +403,43 @@ def test_nystrom_rejects_bad_sizes():
         nystrom.nystrom_gaussian(lambda X: A @ X, np.ones((10, 4)), k=5, M=4)
     with pytest.raises(ValueError):
         nystrom.nystrom_gaussian(lambda X: -(A @ X), np.eye(10)[:, :4], k=1, M=2)
+
+
+# ---- kernel ridge regression (Section 6.3) -----------------------------------
+
+@pytest.mark.parametrize("kind,param", [("gaussian", 0.3), ("inverse_multiquadric", 0.2)])
+def test_krr_closed_forms(kind, param):
+    """One point: alpha = f / (K(0) + beta).  Two points at distance r:
+    [[K0 + b, k], [k, K0 + b]]^{-1} f by the 2 x 2 inverse.  Large beta:
+    alpha -> f / beta."""
+    K0 = 1.0 if kind == "gaussian" else 1.0 / param
+    one = np.array([[0.1, 0.2]])
+    a1 = krr.solve(one, param, 0.5, [3.0], kind)
+    assert abs(a1[0] - 3.0 / (K0 + 0.5)) < 1e-15
+    two = np.array([[0.0, 0.0], [0.3, 0.4]])
+    r2 = 0.25
+    k = math.exp(-r2 / param ** 2) if kind == "gaussian" else 1.0 / math.sqrt(r2 + param ** 2)
+    b, f = 0.7, np.array([1.0, -2.0])
+    det = (K0 + b) ** 2 - k * k
+    ref = np.array([(K0 + b) * f[0] - k * f[1], -k * f[0] + (K0 + b) * f[1]]) / det
+    np.testing.assert_allclose(krr.solve(two, param, b, f, kind), ref, rtol=1e-14)
+    v = synth.blobs2d(50, seed=1)
+    f = np.random.default_rng(0).standard_normal(50)
+    big = 1e9
+    np.testing.assert_allclose(krr.solve(v, param, big, f, kind) * big, f, rtol=1e-6)
+
+
+def test_krr_matches_cg_and_predicts_training_values():
+    """The dense solve agrees with CG on the same SPD system, and the
+    prediction at the training points is K alpha = f - beta alpha."""
+    v = synth.blobs2d(300, seed=4)
+    f = np.sign(v[:, 0]).astype(np.float64)
+    s, b = 0.05, 0.1
+    K = krr.gram(v, s)
+    a = krr.solve(v, s, b, f)
+    u, it, rel = krylov.cg(lambda p: K @ p + b * p, f, tol=1e-12, maxit=2000)
+    np.testing.assert_allclose(a, u, atol=1e-8 * np.abs(a).max())
+    np.testing.assert_allclose(krr.predict(v, a, v, s), f - b * a, atol=1e-9)
 
 
 # ---- the warm-start network reference -----------------------------------------
