@@ -18,10 +18,12 @@ resident in HBM.  Also reported:
     launch, against the same products issued plan by plan.
   * the Nystrom-Gaussian-NFFT eigenvalue approximation (Alg. nystrom_hybrid)
     on the paper's spiral workload (n = 1e5, L = 50, M = k = 10), against
-    Lanczos on the same plan, and at n = 1M on the benchmark plan.
+    Lanczos on the same plan, and at n = 1M on the benchmark plan;
+  * L_s products with the inverse multiquadric and multiquadric kernels on the
+    same cloud, with their accuracy on sampled rows.
 
 Usage: python bench.py [--gpus 1] [--steps 200] [--warmup 10] [--no-cpu] [--no-cg]
-                       [--no-batched] [--no-nystrom]
+                       [--no-batched] [--no-nystrom] [--no-kernels]
 """
 from __future__ import annotations
 
@@ -187,6 +189,43 @@ def nystrom_leg(nfl, synth, torch, dev, P_main=None, reps=3):
     return out
 
 
+def kernels_leg(nfl, synth, torch, dev, v, x, reps=50, rows=64):
+    """L_s products with the inverse multiquadric and multiquadric kernels
+    (eq. W_general) on the n = 1M benchmark cloud, c = 0.05, N = 64, m = 6,
+    eps_B = 1/8, and the relative error of W x on sampled rows against direct
+    FP64 sums (numpy, in the original coordinates)."""
+    out = {}
+    n = v.shape[0]
+    sel = np.sort(np.random.default_rng(7).choice(n, size=rows, replace=False))
+    v64, x64 = v.astype(np.float64), x.astype(np.float64)
+    xd = torch.as_tensor(x, device=dev)
+    yd = torch.empty_like(xd)
+    for kind in ("inverse_multiquadric", "multiquadric"):
+        c = 0.05
+        P = nfl.plan(torch.as_tensor(v, device=dev), c, N=64, m=6, eps_B=0.125, kind=kind)
+        for _ in range(3):
+            P.apply_Ls(xd, out=yd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            P.apply_Ls(xd, out=yd)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000.0 / reps
+        Wx = P.apply_W(xd).cpu().numpy().astype(np.float64)[sel]
+        P.close()
+        ref = np.empty(rows)
+        for i, r in enumerate(sel):
+            d2 = ((v64 - v64[r]) ** 2).sum(axis=1)
+            k = np.sqrt(d2 + c * c) if kind == "multiquadric" else 1.0 / np.sqrt(d2 + c * c)
+            k[r] = 0.0
+            ref[i] = k @ x64
+        out[kind] = {"ms_per_Ls": round(ms, 4), "rel_err_Wx_rows": float(np.abs(Wx - ref).max() / np.abs(ref).max())}
+        log("kernel %s: %.4f ms per L_s product, rel err of W x on %d rows %.2e" % (
+            kind, ms, rows, out[kind]["rel_err_Wx_rows"]))
+    out["config"] = "n=1,000,000 (benchmark cloud), c=0.05, N=64, m=6, eps_B=1/8"
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -199,6 +238,8 @@ def main():
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the 64-graph batched leg and print its JSON record")
     ap.add_argument("--no-nystrom", action="store_true", help="skip the Nystrom eigenvalue leg")
+    ap.add_argument("--no-kernels", action="store_true",
+                    help="skip the (inverse) multiquadric kernel leg")
     ap.add_argument("--nystrom-only", action="store_true",
                     help="run only the Nystrom leg (n = 1e5 spirals) and print its JSON record")
     ap.add_argument("--profile-run", action="store_true",
@@ -363,6 +404,11 @@ def main():
     if not args.no_nystrom:
         nys = nystrom_leg(nfl, synth, torch, dev, P_main=P)
 
+    # --- other kernels of eq. W_general ------------------------------------------
+    kern = None
+    if not args.no_kernels:
+        kern = kernels_leg(nfl, synth, torch, dev, v, x)
+
     # --- CPU oracle baseline (bounded sample) ----------------------------------
     cpu = None
     if not args.no_cpu:
@@ -401,6 +447,7 @@ def main():
         "cpu_baseline": cpu,
         "batched": batched,
         "nystrom": nys,
+        "kernels": kern,
     }
     print(json.dumps(out), flush=True)
     P.close()

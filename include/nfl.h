@@ -170,6 +170,21 @@ int nfl_nystrom(nfl_handle h, const double *G_dev, int64_t ldg, int L, int M, in
 int nfl_cg_solve(nfl_handle h, double tau, const double *f_dev, double *u_dev, int warm,
                  double tol, int maxit, int *iters, double *relres);
 
+/* Kernel ridge regression (Section 6.3): CG for (K + beta I) alpha = f with
+ * the Gram matrix K_ij = K(v_i - v_j) of the plan's kernel, diagonal K(0)
+ * included (K = W + K(0) I; Gaussian or inverse multiquadric: positive
+ * definite; the multiquadric Gram matrix is not, and CG may fail on it).
+ * beta >= 0.  The paper's preconditioner is unspecified; the diagonal one is
+ * the scalar K(0) + beta here, so plain CG is run.  FP64 vectors in caller
+ * order, FP32 NFFT products.  Stops when the recurrence residual
+ * ||r|| / ||f|| <= tol or after maxit iterations; relres (host, may be NULL)
+ * is the true residual recomputed with the same operator.  f_dev, alpha_dev:
+ * n doubles; warm: NFL_WARM_ZERO (alpha0 = 0) or NFL_WARM_USER (alpha0 read
+ * from alpha_dev).  The prediction at the training points is
+ * K alpha = nfl_apply_W(alpha) + K(0) alpha.  Synchronises. */
+int nfl_krr_solve(nfl_handle h, double beta, const double *f_dev, double *alpha_dev, int warm,
+                  double tol, int maxit, int *iters, double *relres);
+
 /* ---- learned warm start for nfl_cg_solve ------------------------------------
  * A pointwise network u0_i = net(features_i) predicts the solution of the
  * kernel-SSL system (eq. ssl::system) node by node; CG then runs to tolerance

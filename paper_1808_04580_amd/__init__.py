@@ -53,6 +53,7 @@ SIGNATURES = {
     "nfl_lanczos_smallest": (_i, [_p, _i, _i, _d, _i, _p, _p, _p, _p]),
     "nfl_cg_solve": (_i, [_p, _d, _p, _p, _i, _d, _i, _p, _p]),
     "nfl_nystrom": (_i, [_p, _p, _i64, _i, _i, _i, _p, _p, _p]),
+    "nfl_krr_solve": (_i, [_p, _d, _p, _p, _i, _d, _i, _p, _p]),
     "nfl_get_info": (_i, [_p, _p, _p, _p, _p, _p, _p]),
     "nfl_grid_size": (_i64, [_p]),
     "nfl_spread": (_i, [_p, _p, _p]),
@@ -292,6 +293,24 @@ class Plan:
                                          float(tol), int(maxit), ctypes.byref(it),
                                          ctypes.byref(rel)), "nfl_cg_solve", allow_soft=True)
         return dict(u=u, iters=it.value, relres=rel.value, converged=(code == NFL_OK))
+
+    def krr_solve(self, f, beta: float, tol: float = 1e-6, maxit: int = 1000, alpha0=None):
+        """Kernel ridge regression (Section 6.3): alpha = (K + beta I)^{-1} f by
+        CG, K the Gram matrix of the plan's kernel (diagonal included)."""
+        torch = self._torch
+        f = torch.as_tensor(f, dtype=torch.float64, device=self.device).contiguous()
+        if alpha0 is not None:
+            a = torch.as_tensor(alpha0, dtype=torch.float64, device=self.device).clone().contiguous()
+            warm = WARM_USER
+        else:
+            a = torch.empty_like(f)
+            warm = WARM_ZERO
+        it = ctypes.c_int()
+        rel = ctypes.c_double()
+        code = _check(lib().nfl_krr_solve(self._h, float(beta), _ptr(f), _ptr(a), int(warm),
+                                          float(tol), int(maxit), ctypes.byref(it),
+                                          ctypes.byref(rel)), "nfl_krr_solve", allow_soft=True)
+        return dict(alpha=a, iters=it.value, relres=rel.value, converged=(code == NFL_OK))
 
     def profile_stages(self, x, nrep: int = 20) -> dict:
         """Average ms per L_s product of: grid clear, spread, convolution, interp, total."""

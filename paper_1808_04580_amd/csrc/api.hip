@@ -308,6 +308,16 @@ int nfl_cg_solve(nfl_handle P, double tau, const double *f_dev, double *u_dev, i
   return cg(P, tau, f_dev, u_dev, warm, tol, maxit, iters, relres);
 }
 
+int nfl_krr_solve(nfl_handle P, double beta, const double *f_dev, double *alpha_dev, int warm,
+                  double tol, int maxit, int *iters, double *relres) {
+  if (!P) { set_error("null handle"); return NFL_ERR_ARG; }
+  if (!P->have_kernel) { set_error("krr before a successful nfl_set_kernel"); return NFL_ERR_ORDER; }
+  if (!f_dev || !alpha_dev) { set_error("null vector pointer"); return NFL_ERR_ARG; }
+  if (!(beta >= 0) || !std::isfinite(beta) || !(tol > 0) || maxit < 0) { set_error("need beta >= 0, tol > 0, maxit >= 0"); return NFL_ERR_ARG; }
+  if (warm != NFL_WARM_ZERO && warm != NFL_WARM_USER) { set_error("krr warm start: NFL_WARM_ZERO or NFL_WARM_USER"); return NFL_ERR_ARG; }
+  return krr_solve(P, beta, f_dev, alpha_dev, warm, tol, maxit, iters, relres);
+}
+
 int nfl_get_info(nfl_handle P, double *rho, double *sigma_tilde, double *dmin, double *dmax,
                  double *eps_B, int *p) {
   if (!P) { set_error("null handle"); return NFL_ERR_ARG; }

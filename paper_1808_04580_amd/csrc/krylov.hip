@@ -810,13 +810,59 @@ int scatter64(nfl_plan *P, const double *src, double *dst) {
   return NFL_OK;
 }
 
-int cg(nfl_plan *P, double tau, const double *f_dev, double *u_dev, int warm, double tol,
-       int maxit, int *iters, double *relres) {
+// ---------------------------------------------------------------------------
+// Kernel ridge regression (Section 6.3): CG on (K + beta I) alpha = f with the
+// Gram matrix K = W + K(0) I of the plan's kernel.  The vectors stay in the
+// caller's order: the product converts p to FP32, runs the fast summation
+// with raw sums out (the kernel over K(0), diagonal included) and forms
+// q = K(0) * sums + beta p in FP64.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(VT) void k_to_f32(const double *__restrict__ x, int64_t n,
+                                               float *__restrict__ y) {
+  for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT)
+    y[i] = (float)x[i];
+}
+
+__global__ __launch_bounds__(VT) void k_krr_combine(const float *__restrict__ t,
+                                                    const double *__restrict__ x, double s,
+                                                    double beta, int64_t n,
+                                                    double *__restrict__ q) {
+  for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT)
+    q[i] = s * (double)t[i] + beta * x[i];
+}
+
+struct KrrOp {
+  nfl_plan *P;
+  double beta;
+  float *x32, *t32;
+  int operator()(const double *x, double *q) const {
+    const int gb = grid_for(P->n);
+    hipLaunchKernelGGL(k_to_f32, dim3(gb), dim3(VT), 0, P->stream, x, P->n, x32);
+    VecArgs a;
+    a.x32 = x32;
+    a.y32 = t32;
+    NFL_TRY(fastsum(P, IN_USER_F32, OUT_USER_RAW, a));
+    hipLaunchKernelGGL(k_krr_combine, dim3(gb), dim3(VT), 0, P->stream, t32, x, P->wscale, beta,
+                       P->n, q);
+    NFL_HIP(hipGetLastError());
+    return NFL_OK;
+  }
+};
+
+struct SslOp {
+  nfl_plan *P;
+  double tau;
+  int operator()(const double *x, double *q) const { return apply_SSL64(P, tau, x, q); }
+};
+
+// CG iterations for M u = f on vectors f, u (u holds the start) of the plan's
+// length, any fixed node order; M applied by op.
+template <class Op>
+static int cg_core(nfl_plan *P, const Op &op, const double *f, double *u, double tol, int maxit,
+                   int *iters, double *relres) {
   const int64_t n = P->n;
   hipStream_t s = P->stream;
-  LBuf<double> f, u, r, p, q, sc;
-  NFL_TRY(f.ensure(n));
-  NFL_TRY(u.ensure(n));
+  LBuf<double> r, p, q, sc;
   NFL_TRY(r.ensure(n));
   NFL_TRY(p.ensure(n));
   NFL_TRY(q.ensure(n));
@@ -824,18 +870,10 @@ int cg(nfl_plan *P, double tau, const double *f_dev, double *u_dev, int warm, do
   Reducer R;
   NFL_TRY(R.init(n));
   const int gb = grid_for(n);
-  hipLaunchKernelGGL(k_gather64, dim3(gb), dim3(VT), 0, s, f_dev, P->perm.p, n, f.p);
-  if (warm == NFL_WARM_USER) {
-    hipLaunchKernelGGL(k_gather64, dim3(gb), dim3(VT), 0, s, u_dev, P->perm.p, n, u.p);
-  } else if (warm == NFL_WARM_MLP) {
-    NFL_TRY(mlp_warm_start(P, f.p, u.p));
-  } else {
-    hipLaunchKernelGGL(k_fill64, dim3(gb), dim3(VT), 0, s, u.p, n, 0.0);
-  }
   // sc: [0] rr, [1] p.q, [2] rr_new, [3] ||f||
-  NFL_TRY(dot(P, R, f.p, f.p, sc.p + 3, 1));
-  NFL_TRY(apply_SSL64(P, tau, u.p, q.p));
-  hipLaunchKernelGGL(k_sub64, dim3(gb), dim3(VT), 0, s, f.p, q.p, n, r.p);
+  NFL_TRY(dot(P, R, f, f, sc.p + 3, 1));
+  NFL_TRY(op(u, q.p));
+  hipLaunchKernelGGL(k_sub64, dim3(gb), dim3(VT), 0, s, f, q.p, n, r.p);
   NFL_HIP(hipMemcpyAsync(p.p, r.p, n * sizeof(double), hipMemcpyDeviceToDevice, s));
   NFL_TRY(dot(P, R, r.p, r.p, sc.p + 0));
   double h[4];
@@ -845,9 +883,9 @@ int cg(nfl_plan *P, double tau, const double *f_dev, double *u_dev, int warm, do
   int it = 0;
   double rel = nf > 0 ? std::sqrt(h[0]) / nf : 0.0;
   while (nf > 0 && rel > tol && it < maxit) {
-    NFL_TRY(apply_SSL64(P, tau, p.p, q.p));
+    NFL_TRY(op(p.p, q.p));
     NFL_TRY(dot(P, R, p.p, q.p, sc.p + 1));
-    hipLaunchKernelGGL(k_cg_step, dim3(R.nb), dim3(VT), 0, s, u.p, r.p, p.p, q.p, sc.p, n,
+    hipLaunchKernelGGL(k_cg_step, dim3(R.nb), dim3(VT), 0, s, u, r.p, p.p, q.p, sc.p, n,
                        R.part.p);
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(VT), 0, s, R.part.p, R.nb, sc.p + 2, 0);
     hipLaunchKernelGGL(k_cg_dir, dim3(gb), dim3(VT), 0, s, p.p, r.p, sc.p, n);
@@ -862,19 +900,55 @@ int cg(nfl_plan *P, double tau, const double *f_dev, double *u_dev, int warm, do
   // true residual with the same operator
   double trueres = 0.0;
   if (nf > 0) {
-    NFL_TRY(apply_SSL64(P, tau, u.p, q.p));
-    hipLaunchKernelGGL(k_sub64, dim3(gb), dim3(VT), 0, s, f.p, q.p, n, r.p);
+    NFL_TRY(op(u, q.p));
+    hipLaunchKernelGGL(k_sub64, dim3(gb), dim3(VT), 0, s, f, q.p, n, r.p);
     NFL_TRY(dot(P, R, r.p, r.p, sc.p + 4, 1));
     NFL_HIP(hipMemcpyAsync(h, sc.p + 4, sizeof(double), hipMemcpyDeviceToHost, s));
     NFL_HIP(hipStreamSynchronize(s));
     trueres = h[0] / nf;
   }
-  hipLaunchKernelGGL(k_scatter64, dim3(gb), dim3(VT), 0, s, u.p, P->perm.p, n, u_dev);
-  NFL_HIP(hipGetLastError());
-  NFL_HIP(hipStreamSynchronize(s));
   if (iters) *iters = it;
   if (relres) *relres = trueres;
   return (rel <= tol || nf == 0) ? NFL_OK : NFL_NOT_CONVERGED;
+}
+
+int krr_solve(nfl_plan *P, double beta, const double *f_dev, double *alpha_dev, int warm,
+              double tol, int maxit, int *iters, double *relres) {
+  const int64_t n = P->n;
+  LBuf<float> x32, t32;
+  NFL_TRY(x32.ensure(n));
+  NFL_TRY(t32.ensure(n));
+  if (warm != NFL_WARM_USER)
+    hipLaunchKernelGGL(k_fill64, dim3(grid_for(n)), dim3(VT), 0, P->stream, alpha_dev, n, 0.0);
+  KrrOp op{P, beta, x32.p, t32.p};
+  const int rc = cg_core(P, op, f_dev, alpha_dev, tol, maxit, iters, relres);
+  NFL_HIP(hipStreamSynchronize(P->stream));
+  return rc;
+}
+
+int cg(nfl_plan *P, double tau, const double *f_dev, double *u_dev, int warm, double tol,
+       int maxit, int *iters, double *relres) {
+  const int64_t n = P->n;
+  hipStream_t s = P->stream;
+  LBuf<double> f, u;
+  NFL_TRY(f.ensure(n));
+  NFL_TRY(u.ensure(n));
+  const int gb = grid_for(n);
+  hipLaunchKernelGGL(k_gather64, dim3(gb), dim3(VT), 0, s, f_dev, P->perm.p, n, f.p);
+  if (warm == NFL_WARM_USER) {
+    hipLaunchKernelGGL(k_gather64, dim3(gb), dim3(VT), 0, s, u_dev, P->perm.p, n, u.p);
+  } else if (warm == NFL_WARM_MLP) {
+    NFL_TRY(mlp_warm_start(P, f.p, u.p));
+  } else {
+    hipLaunchKernelGGL(k_fill64, dim3(gb), dim3(VT), 0, s, u.p, n, 0.0);
+  }
+  SslOp op{P, tau};
+  const int rc = cg_core(P, op, f.p, u.p, tol, maxit, iters, relres);
+  if (rc < 0) return rc;
+  hipLaunchKernelGGL(k_scatter64, dim3(gb), dim3(VT), 0, s, u.p, P->perm.p, n, u_dev);
+  NFL_HIP(hipGetLastError());
+  NFL_HIP(hipStreamSynchronize(s));
+  return rc;
 }
 
 }  // namespace nfl
