@@ -20,7 +20,10 @@ resident in HBM.  Also reported:
     on the paper's spiral workload (n = 1e5, L = 50, M = k = 10), against
     Lanczos on the same plan, and at n = 1M on the benchmark plan;
   * L_s products with the inverse multiquadric and multiquadric kernels on the
-    same cloud, with their accuracy on sampled rows.
+    same cloud, with their accuracy on sampled rows, and kernel ridge
+    regression (K + beta I) alpha = f (two-class labels, tol 1e-6) with the
+    Gaussian (beta = 1) and the inverse multiquadric kernel (beta = 1000: its
+    Gram matrix reaches ~5e6 at n = 1M, K(0) = 20).
 
 Usage: python bench.py [--gpus 1] [--steps 200] [--warmup 10] [--no-cpu] [--no-cg]
                        [--no-batched] [--no-nystrom] [--no-kernels]
@@ -189,7 +192,21 @@ def nystrom_leg(nfl, synth, torch, dev, P_main=None, reps=3):
     return out
 
 
-def kernels_leg(nfl, synth, torch, dev, v, x, reps=50, rows=64):
+def krr_leg(P, torch, f, beta=1.0, tol=1e-6, maxit=3000):
+    """Kernel ridge regression (Section 6.3) on plan P: (K + beta I) alpha = f
+    by CG, timed whole (one solve after a warm-up solve)."""
+    P.krr_solve(f, beta, tol=tol, maxit=maxit)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = P.krr_solve(f, beta, tol=tol, maxit=maxit)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0
+    return {"beta": beta, "tol": tol, "ms": round(ms, 2), "iters": r["iters"],
+            "relres": r["relres"], "converged": r["converged"],
+            "ms_per_iter": round(ms / max(1, r["iters"]), 4)}
+
+
+def kernels_leg(nfl, synth, torch, dev, v, x, lab, reps=50, rows=64):
     """L_s products with the inverse multiquadric and multiquadric kernels
     (eq. W_general) on the n = 1M benchmark cloud, c = 0.05, N = 64, m = 6,
     eps_B = 1/8, and the relative error of W x on sampled rows against direct
@@ -212,6 +229,10 @@ def kernels_leg(nfl, synth, torch, dev, v, x, reps=50, rows=64):
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1000.0 / reps
         Wx = P.apply_W(xd).cpu().numpy().astype(np.float64)[sel]
+        if kind == "inverse_multiquadric":
+            f = np.where(lab == 0, 1.0, -1.0)
+            out["krr_" + kind] = krr_leg(P, torch, torch.as_tensor(f, device=dev), beta=1000.0)
+            log("krr %s: %s" % (kind, out["krr_" + kind]))
         P.close()
         ref = np.empty(rows)
         for i, r in enumerate(sel):
@@ -407,7 +428,10 @@ def main():
     # --- other kernels of eq. W_general ------------------------------------------
     kern = None
     if not args.no_kernels:
-        kern = kernels_leg(nfl, synth, torch, dev, v, x)
+        kern = kernels_leg(nfl, synth, torch, dev, v, x, lab)
+        f = np.where(lab == 0, 1.0, -1.0)
+        kern["krr_gaussian"] = krr_leg(P, torch, torch.as_tensor(f, device=dev))
+        log("krr gaussian: %s" % kern["krr_gaussian"])
 
     # --- CPU oracle baseline (bounded sample) ----------------------------------
     cpu = None
