@@ -55,6 +55,9 @@ typedef struct nfl_mlp *nfl_mlp_handle;
 #define NFL_OPT_KERNEL     5   /* d = 3 spread/interp: 0 = matrix-core (MFMA) kernels (default; tile-stationary
                                    where tile + 2m - 1 <= 16, else per-cell runs), 1 = vector-ALU kernels,
                                    2 = matrix-core kernels with per-cell runs only; takes effect immediately */
+#define NFL_OPT_RESTARTS   6   /* thick restarts of nfl_lanczos_smallest (0 = none, default): with r > 0,
+                                   maxit is the basis size and up to r restarts keep the leading Ritz
+                                   vectors (see nfl_lanczos_smallest); takes effect immediately */
 
 /* Create a plan for nodes in R^d, d in {1, 2, 3}.  `hip_stream` is a
  * hipStream_t (NULL = the default stream).  Allocates nothing on the device
@@ -129,7 +132,13 @@ int nfl_apply_A(nfl_handle h, const float *x_dev, float *y_dev, int nvec, int64_
  * (block > 1 runs a block Lanczos of that block size, 1..8).
  * evals_host: k doubles, ascending eigenvalues of L_s.  evecs_dev: n x k
  * FP64 column-major in caller order (NULL to skip).  iters, max_resid: host,
- * may be NULL.  Synchronises.  1 <= k < n, k <= maxit. */
+ * may be NULL.  Synchronises.  1 <= k < n, k <= maxit.
+ * With NFL_OPT_RESTARTS r > 0 (any block size, 1 included) the basis holds at
+ * most maxit columns (maxit >= k + 2 block); when it is full and the wanted
+ * pairs have not converged, a thick restart (Wu and Simon 2000, block form)
+ * keeps the l = min(J - b, max(k + b, J/2)) leading Ritz vectors and the next
+ * block, with the projection diag(theta) plus the coupling R s_last, and the
+ * iteration goes on; at most r restarts.  iters then counts A products. */
 int nfl_lanczos_smallest(nfl_handle h, int k, int block, double tol, int maxit,
                          double *evals_host, double *evecs_dev, int *iters, double *max_resid);
 

@@ -29,6 +29,7 @@ OPT_TILE = 2
 OPT_CHUNK = 3
 OPT_EPS_B_DEFAULT = 4
 OPT_KERNEL = 5
+OPT_RESTARTS = 6
 KERNELS = {"gaussian": 0, "multiquadric": 1, "inverse_multiquadric": 2}
 
 WARM_ZERO = 0
@@ -238,8 +239,11 @@ class Plan:
 
     # -- solvers ------------------------------------------------------------
     def lanczos_smallest(self, k: int, tol: float = 1e-8, maxit: int = 300, block: int = 1,
-                         vectors: bool = True):
+                         vectors: bool = True, restarts: int = 0):
+        """k smallest eigenpairs of L_s; restarts > 0 bounds the basis at maxit
+        columns and allows that many thick restarts."""
         torch = self._torch
+        self.set_option(OPT_RESTARTS, int(restarts))
         ev = np.empty(k, dtype=np.float64)
         V = torch.empty((k, self.n), dtype=torch.float64, device=self.device) if vectors else None
         it = ctypes.c_int()

@@ -112,6 +112,11 @@ int nfl_destroy(nfl_handle P) {
 
 int nfl_set_option(nfl_handle P, int opt, double value) {
   if (!P) { set_error("null handle"); return NFL_ERR_ARG; }
+  if (opt == NFL_OPT_RESTARTS) {   // a solver setting: the operator is unchanged
+    if (value < 0 || value > 1000 || value != std::floor(value)) { set_error("restarts must be an integer in [0, 1000]"); return NFL_ERR_ARG; }
+    P->opt_restarts = (int)value;
+    return NFL_OK;
+  }
   ++P->gen;
   switch (opt) {
     case NFL_OPT_P:

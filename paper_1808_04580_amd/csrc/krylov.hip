@@ -457,6 +457,50 @@ __global__ __launch_bounds__(JAC_THREADS) void k_sym_jacobi(const double *__rest
   if (tid == 0) status[0] = st;
 }
 
+// ---- out = X C (X: n x a, C: a x b row-major with row length ldc >= the
+// column count rounded up to TILE, zero-padded) -------------------------------
+// One thread per row of X; the coefficient row C[k][j0 .. j0 + TILE) is the
+// same for the whole workgroup and is read through scalar loads.
+template <int TILE>
+__global__ __launch_bounds__(VT) void k_rowmul(const double *__restrict__ X, int64_t ldx, int a,
+                                               const double *__restrict__ C, int ldc, int b,
+                                               int64_t n, double *__restrict__ out,
+                                               int64_t ldo) {
+  const int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x;
+  if (i >= n) return;
+  for (int j0 = 0; j0 < b; j0 += TILE) {
+    double acc[TILE];
+#pragma unroll
+    for (int jj = 0; jj < TILE; ++jj) acc[jj] = 0.0;
+#pragma unroll 4
+    for (int k = 0; k < a; ++k) {
+      const double x = X[(int64_t)k * ldx + i];
+      const double *c = C + (int64_t)k * ldc + j0;
+#pragma unroll
+      for (int jj = 0; jj < TILE; ++jj) acc[jj] += x * c[jj];
+    }
+#pragma unroll
+    for (int jj = 0; jj < TILE; ++jj)
+      if (j0 + jj < b) out[(int64_t)(j0 + jj) * ldo + i] = acc[jj];
+  }
+}
+
+int rowmul_dev(hipStream_t s, const double *X, int64_t ldx, int a, const double *C, int ldc, int b,
+               int64_t n, double *out, int64_t ldo) {
+  const dim3 grid((unsigned)((n + VT - 1) / VT));
+  for (int c0 = 0; c0 < b; c0 += 32) {
+    const int bc = std::min(32, b - c0);
+    if (bc <= 16)
+      hipLaunchKernelGGL(k_rowmul<16>, grid, dim3(VT), 0, s, X, ldx, a, C + c0, ldc, bc, n,
+                         out + (int64_t)c0 * ldo, ldo);
+    else
+      hipLaunchKernelGGL(k_rowmul<32>, grid, dim3(VT), 0, s, X, ldx, a, C + c0, ldc, bc, n,
+                         out + (int64_t)c0 * ldo, ldo);
+  }
+  NFL_HIP(hipGetLastError());
+  return NFL_OK;
+}
+
 int colsum(hipStream_t s, const double *part, int nb, int width, double *out) {
   hipLaunchKernelGGL(k_colsum, dim3((width + CS_E - 1) / CS_E), dim3(VT), 0, s, part, nb, width,
                      out);
@@ -500,13 +544,27 @@ __global__ __launch_bounds__(VT) void k_add_col(double *__restrict__ h,
 // so the leading J x J part of H is the projection Q^T A_E Q and the b x b
 // block below it the R factor of the next block.  Ritz residual of (theta, s):
 // || R s_last || with s_last the last b components of s.
-static int block_lanczos(nfl_plan *P, int k, int b, double tol, int maxit, double *evals_host,
-                         double *evecs_dev, int *iters, double *max_resid) {
+//
+// Thick restart (restarts > 0; Wu and Simon, "Thick-restart Lanczos method for
+// large symmetric eigenvalue problems", SIAM J. Matrix Anal. Appl. 2000, in its
+// block form): when the basis is full and the wanted pairs have not
+// converged, the l = min(J - b, max(k + b, J / 2)) leading Ritz vectors
+// Q S_l replace the basis, the already orthonormalised next block follows
+// them, and the projection becomes diag(theta_l) with the coupling rows
+// R s_last (b x l) to that block; the iteration then continues from it.
+// `maxit` is then the basis size, and products may reach
+// maxit + restarts (maxit - l).
+static int block_lanczos(nfl_plan *P, int k, int b, double tol, int maxit, int restarts,
+                         double *evals_host, double *evecs_dev, int *iters, double *max_resid) {
   const int64_t n = P->n;
   maxit = (int)std::min<int64_t>(maxit, n - b);
   const int maxblk = maxit / b;
   if (maxblk < 1 || k > maxblk * b) {
     set_error("block lanczos: need k <= maxit and room for one block");
+    return NFL_ERR_ARG;
+  }
+  if (restarts > 0 && maxblk * b < k + 2 * b) {
+    set_error("restarted lanczos: the basis (maxit) must hold k + 2 blocks");
     return NFL_ERR_ARG;
   }
   const int mcols = maxblk * b;          // columns whose products are formed
@@ -529,6 +587,12 @@ static int block_lanczos(nfl_plan *P, int k, int b, double tol, int maxit, doubl
   NFL_TRY(ev.ensure(mcols));
   NFL_TRY(st.ensure(1));
   NFL_TRY(sel.ensure(k));
+  const int ldc = (mcols + 31) & ~31;     // row length of the restart coefficients
+  LBuf<double> Cr, Qt;
+  if (restarts > 0) {
+    NFL_TRY(Cr.ensure((size_t)mcols * ldc));
+    NFL_TRY(Qt.ensure((size_t)n * mcols));
+  }
   const int gb = grid_for(n);
   hipStream_t s = P->stream;
   hipLaunchKernelGGL(k_fill64, dim3(256), dim3(VT), 0, s, H.p, (int64_t)(ldH * ldH), 0.0);
@@ -562,23 +626,25 @@ static int block_lanczos(nfl_plan *P, int k, int b, double tol, int maxit, doubl
   }
 
   std::vector<double> h_eval, h_V, h_R((size_t)b * b);
-  std::vector<int> h_sel(k);
-  int Jc = 0, nblk = 0;
+  std::vector<int> h_sel(k), order;
+  int Jc = 0, since = 0, done_restarts = 0;
+  int64_t nprod = 0;
   bool converged = false;
   double worst = INFINITY;
-  while (nblk < maxblk) {
-    const int J0 = nblk * b;
+  while (Jc + b <= mcols) {
+    const int J0 = Jc;
     for (int c = 0; c < b; ++c) NFL_TRY(apply_A64(P, Q.p + (int64_t)(J0 + c) * ld, W.p + (int64_t)c * n));
     for (int c = 0; c < b; ++c) {
       const int ncol = J0 + b + c;
       double *hcol = H.p + (int64_t)(J0 + c) * ldH;
       NFL_TRY(orth_next(W.p + (int64_t)c * n, ncol, hcol, hcol + ncol));
     }
-    ++nblk;
-    Jc = nblk * b;
-    const bool last = nblk == maxblk;
+    nprod += b;
+    ++since;
+    Jc = J0 + b;
+    const bool full = Jc + b > mcols;
     const int every = Jc <= 100 ? std::max(1, 8 / b) : std::max(1, 16 / b);
-    if (Jc >= k && (nblk % every == 0 || last)) {
+    if (Jc >= k && (since % every == 0 || full)) {
       NFL_TRY(sym_eig(s, H.p, ldH, Jc, Aw.p, Vw.p, ev.p, st.p));
       h_eval.resize(Jc);
       h_V.resize((size_t)Jc * Jc);
@@ -595,17 +661,22 @@ static int block_lanczos(nfl_plan *P, int k, int b, double tol, int maxit, doubl
         set_error("block lanczos: Jacobi eigensolver did not converge");
         return NFL_ERR_HIP;
       }
-      std::vector<int> order(Jc);
+      order.resize(Jc);
       std::iota(order.begin(), order.end(), 0);
       std::sort(order.begin(), order.end(), [&](int a, int bb) { return h_eval[a] > h_eval[bb]; });
+      // coupling of Ritz vector `col` to the next block: R s_last
+      auto coupling = [&](int col, int r) {
+        const double *sv = h_V.data() + (size_t)col * Jc;
+        double t = 0.0;
+        for (int q = 0; q < b; ++q) t += h_R[(size_t)q * b + r] * sv[Jc - b + q];
+        return t;
+      };
       worst = 0.0;
       for (int c = 0; c < k; ++c) {
         h_sel[c] = order[c];
-        const double *sv = h_V.data() + (size_t)order[c] * Jc;
         double r2 = 0.0;
         for (int r = 0; r < b; ++r) {
-          double t = 0.0;
-          for (int q = 0; q < b; ++q) t += h_R[(size_t)q * b + r] * sv[Jc - b + q];
+          const double t = coupling(order[c], r);
           r2 += t * t;
         }
         worst = std::max(worst, std::sqrt(r2));
@@ -613,6 +684,33 @@ static int block_lanczos(nfl_plan *P, int k, int b, double tol, int maxit, doubl
       if (worst <= tol) {
         converged = true;
         break;
+      }
+      if (full && done_restarts < restarts) {
+        // thick restart: Q[:, :l] = Q[:, :Jc] S_l, next block to columns l..l+b-1
+        const int l = std::min(Jc - b, std::max(k + b, Jc / 2));
+        std::vector<double> hC((size_t)Jc * ldc, 0.0);
+        for (int c = 0; c < l; ++c)
+          for (int j = 0; j < Jc; ++j) hC[(size_t)j * ldc + c] = h_V[(size_t)order[c] * Jc + j];
+        NFL_HIP(hipMemcpyAsync(Cr.p, hC.data(), hC.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        NFL_TRY(rowmul_dev(s, Q.p, ld, Jc, Cr.p, ldc, l, n, Qt.p, n));
+        NFL_HIP(hipMemcpyAsync(Q.p, Qt.p, (size_t)n * l * sizeof(double), hipMemcpyDeviceToDevice, s));
+        NFL_HIP(hipMemcpyAsync(Q.p + (int64_t)l * ld, Q.p + (int64_t)Jc * ld,
+                               (size_t)n * b * sizeof(double), hipMemcpyDeviceToDevice, s));
+        // projection: diag(theta_l), coupling rows l..l+b-1 (and, by symmetry,
+        // the next block's projections onto the Ritz vectors, formed anew
+        // when its products are orthogonalised)
+        std::vector<double> hH((size_t)ldH * l, 0.0);
+        for (int c = 0; c < l; ++c) {
+          hH[(size_t)c * ldH + c] = h_eval[order[c]];
+          for (int r = 0; r < b; ++r) hH[(size_t)c * ldH + l + r] = coupling(order[c], r);
+        }
+        hipLaunchKernelGGL(k_fill64, dim3(256), dim3(VT), 0, s, H.p, (int64_t)(ldH * ldH), 0.0);
+        NFL_HIP(hipMemcpyAsync(H.p, hH.data(), hH.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        NFL_HIP(hipGetLastError());
+        NFL_HIP(hipStreamSynchronize(s));   // host arrays go out of scope
+        ++done_restarts;
+        since = 0;
+        Jc = l;
       }
     }
   }
@@ -628,15 +726,16 @@ static int block_lanczos(nfl_plan *P, int k, int b, double tol, int maxit, doubl
     NFL_HIP(hipGetLastError());
     NFL_HIP(hipStreamSynchronize(s));
   }
-  if (iters) *iters = Jc;
+  if (iters) *iters = (int)nprod;
   if (max_resid) *max_resid = worst;
   return converged ? NFL_OK : NFL_NOT_CONVERGED;
 }
 
 int lanczos(nfl_plan *P, int k, int block, double tol, int maxit, double *evals_host,
             double *evecs_dev, int *iters, double *max_resid) {
-  if (block > 1)
-    return block_lanczos(P, k, block, tol, maxit, evals_host, evecs_dev, iters, max_resid);
+  if (block > 1 || P->opt_restarts > 0)
+    return block_lanczos(P, k, block, tol, maxit, P->opt_restarts, evals_host, evecs_dev, iters,
+                         max_resid);
   const int64_t n = P->n;
   maxit = (int)std::min<int64_t>(maxit, n);
   if (k < 1 || k > maxit) {

@@ -129,6 +129,7 @@ struct nfl_plan {
   // FFT / filter
   nfl::DBuf<float> wcoef;       // window polynomials, WIN_MAXW x WIN_NC
   int opt_kernel = 0;           // 0: MFMA (tile-stationary where possible), 1: VALU, 2: MFMA per-cell runs
+  int opt_restarts = 0;         // thick restarts of nfl_lanczos_smallest (0: none)
   nfl::DBuf<float> filt;        // half spectrum, FP32
   std::vector<double> filt_host;
   nfl::DBuf<float2> tw;         // e^{-2 pi i k / nos}, k < nos/2
@@ -214,6 +215,12 @@ int krr_solve(nfl_plan *P, double beta, const double *f_dev, double *alpha_dev, 
               double tol, int maxit, int *iters, double *relres);
 int gather64(nfl_plan *P, const double *src_user, double *dst_sorted);
 int scatter64(nfl_plan *P, const double *src_sorted, double *dst_user);
+// out[:, j] = sum_k X[:, k] C[k * ldc + j] for j < b (X: n x a column-major,
+// leading dimension ldx; C row-major, each row readable up to the next
+// multiple of 16 or 32 beyond the columns used, zero-padded; out: n x b with
+// leading dimension ldo, not overlapping X).  Asynchronous on s.
+int rowmul_dev(hipStream_t s, const double *X, int64_t ldx, int a, const double *C, int ldc, int b,
+               int64_t n, double *out, int64_t ldo);
 // out[e] = sum_{w < nb} part[w * width + e] for e < width, in a fixed order.
 int colsum(hipStream_t s, const double *part, int nb, int width, double *out);
 // Eigendecomposition of the symmetric part of the leading m x m block of H

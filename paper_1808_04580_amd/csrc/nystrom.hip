@@ -97,34 +97,6 @@ __global__ __launch_bounds__(NT) void k_gram_partial(const double *__restrict__ 
       if (i0 + p < a && j0 + q < b) out[(int64_t)(j0 + q) * a + i0 + p] = acc[p][q];
 }
 
-// ---- out = X C (X: n x a, C: a x b row-major with row length ldc >= the
-// column count rounded up to TILE, zero-padded) -------------------------------
-// One thread per row of X; the coefficient row C[k][j0 .. j0 + TILE) is the
-// same for the whole workgroup and is read through scalar loads.
-template <int TILE>
-__global__ __launch_bounds__(NT) void k_rowmul(const double *__restrict__ X, int64_t ldx, int a,
-                                               const double *__restrict__ C, int ldc, int b,
-                                               int64_t n, double *__restrict__ out,
-                                               int64_t ldo) {
-  const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
-  if (i >= n) return;
-  for (int j0 = 0; j0 < b; j0 += TILE) {
-    double acc[TILE];
-#pragma unroll
-    for (int jj = 0; jj < TILE; ++jj) acc[jj] = 0.0;
-#pragma unroll 4
-    for (int k = 0; k < a; ++k) {
-      const double x = X[(int64_t)k * ldx + i];
-      const double *c = C + (int64_t)k * ldc + j0;
-#pragma unroll
-      for (int jj = 0; jj < TILE; ++jj) acc[jj] += x * c[jj];
-    }
-#pragma unroll
-    for (int jj = 0; jj < TILE; ++jj)
-      if (j0 + jj < b) out[(int64_t)(j0 + jj) * ldo + i] = acc[jj];
-  }
-}
-
 // ---- small dense kernels (one workgroup) -------------------------------------
 constexpr int SM_PITCH = NYS_MAXL + 1;
 
@@ -287,14 +259,7 @@ int gram(nfl_plan *P, NysWork &W, const double *X, int a, const double *Y, int b
 }
 
 int rowmul(nfl_plan *P, const double *X, int a, const double *C, int ldc, int b, double *out) {
-  const int64_t n = P->n;
-  const dim3 grid((unsigned)((n + NT - 1) / NT));
-  if (b <= 16)
-    hipLaunchKernelGGL(k_rowmul<16>, grid, dim3(NT), 0, P->stream, X, n, a, C, ldc, b, n, out, n);
-  else
-    hipLaunchKernelGGL(k_rowmul<32>, grid, dim3(NT), 0, P->stream, X, n, a, C, ldc, b, n, out, n);
-  NFL_HIP(hipGetLastError());
-  return NFL_OK;
+  return rowmul_dev(P->stream, X, P->n, a, C, ldc, b, P->n, out, P->n);
 }
 
 // Shifted CholeskyQR3 of the n x a block X (overwritten), with T as the second
