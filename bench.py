@@ -18,7 +18,9 @@ resident in HBM.  Also reported:
     launch, against the same products issued plan by plan.
   * the Nystrom-Gaussian-NFFT eigenvalue approximation (Alg. nystrom_hybrid)
     on the paper's spiral workload (n = 1e5, L = 50, M = k = 10), against
-    Lanczos on the same plan, and at n = 1M on the benchmark plan;
+    Lanczos on the same plan, and at n = 1M on the benchmark plan; at n = 1M
+    also the 20 smallest eigenpairs by block Lanczos (block 4) with a full
+    basis and with a 48-column basis and thick restarts;
   * L_s products with the inverse multiquadric and multiquadric kernels on the
     same cloud, with their accuracy on sampled rows, and kernel ridge
     regression (K + beta I) alpha = f (two-class labels, tol 1e-6) with the
@@ -189,6 +191,19 @@ def nystrom_leg(nfl, synth, torch, dev, P_main=None, reps=3):
         out["n1M"] = {"ms": round(ms2, 3), "m_used": r2["m_used"],
                       "evals": [round(float(e), 6) for e in r2["evals"]]}
         log("nystrom n=1e6: %.2f ms" % ms2)
+        # 20 smallest of L_s at n = 1M, block 4: full basis vs a 48-column basis
+        # with thick restarts
+        lp, msp = timed(lambda: P_main.lanczos_smallest(20, tol=1e-6, maxit=400, block=4))
+        lr, msr = timed(lambda: P_main.lanczos_smallest(20, tol=1e-6, maxit=48, block=4,
+                                                        restarts=200))
+        P_main.set_option(nfl.OPT_RESTARTS, 0)
+        out["lanczos_n1M_k20"] = {
+            "full_basis": {"ms": round(msp, 2), "products": lp["iters"], "converged": lp["converged"]},
+            "restarted_basis48": {"ms": round(msr, 2), "products": lr["iters"],
+                                  "converged": lr["converged"]},
+            "max_abs_eval_diff": float(np.abs(lp["evals"] - lr["evals"]).max())}
+        log("lanczos n=1e6 k=20 block 4: full basis %.1f ms (%d products), basis 48 with restarts "
+            "%.1f ms (%d products)" % (msp, lp["iters"], msr, lr["iters"]))
     return out
 
 
