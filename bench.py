@@ -13,6 +13,9 @@ resident in HBM.  Also reported:
     plain (u0 = 0) and, when a trained warm-start network is available,
     learned;
   * the oracle timed on the host cores on a bounded sample (cpu_baseline);
+  * clustering sensitivity (uniform ball, 10-component mixture) and the
+    m = 4 operating point at n = 1M; the small configurations (2-D blobs,
+    n = 5,000; RGB image, n = 99,856) with Lanczos for 10 eigenpairs;
   * the batched workload: 64 Gaussian-mixture graphs of uneven size, each
     autotuned to rel err 1e-5, L_s on 8 vectors per graph in one graph
     launch, against the same products issued plan by plan.
@@ -262,6 +265,81 @@ def kernels_leg(nfl, synth, torch, dev, v, x, lab, reps=50, rows=64):
     return out
 
 
+def variants_leg(nfl, synth, torch, dev, steps=50, rows=256):
+    """Clustering sensitivity and the FP32 operating point at n = 1M,
+    sigma = 0.04, N = 64: a uniform ball and a 10-component mixture (std
+    U[0.005, 0.03]) with m = 6, and the benchmark cloud with m = 4.  Time per
+    L_s product (HIP events on the library stream), spread / interp stage
+    times, and the relative error of W x on sampled rows against the direct
+    FP64 oracle."""
+    from oracle import graph
+    out = {}
+    x = synth.normal_vectors(N_POINTS, seed=12345)
+    xd = torch.as_tensor(x, device=dev)
+    yd = torch.empty_like(xd)
+    sel = np.sort(np.random.default_rng(11).choice(N_POINTS, size=rows, replace=False))
+    cases = [("uniform_ball_m6", lambda: synth.uniform_ball(N_POINTS, seed=2), MCUT),
+             ("gmm10_m6", lambda: synth.gmm(N_POINTS, d=3, k=10, seed=0), MCUT),
+             ("moons_roll_m4", lambda: synth.moons_and_roll(N_POINTS, seed=1)[0], 4)]
+    for name, make, m in cases:
+        v = make()
+        P = nfl.plan(torch.as_tensor(v, device=dev), SIGMA, N=NBW, m=m, eps_B=EPS_B)
+        for _ in range(5):
+            P.apply_Ls(xd, out=yd)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(P.stream)
+        for _ in range(steps):
+            P.apply_Ls(xd, out=yd)
+        e1.record(P.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        st = P.profile_stages(xd, nrep=20)
+        Wx = P.apply_W(xd).cpu().numpy().astype(np.float64)[sel]
+        P.close()
+        ref = graph.w_rows(v, SIGMA, x.astype(np.float64), sel)
+        out[name] = {"m": m, "ms_per_Ls": round(ms, 4), "Ls_per_s": round(1000.0 / ms, 1),
+                     "spread_us": round(st["spread"] * 1e3, 1),
+                     "interp_us": round(st["interp"] * 1e3, 1),
+                     "rel_err_Wx_rows": float(np.abs(Wx - ref).max() / np.abs(ref).max())}
+        log("variant %s: %s" % (name, out[name]))
+    return out
+
+
+def small_configs_leg(nfl, synth, torch, dev, steps=100):
+    """The survey's small configurations: (1) two 2-D blobs, n = 5,000,
+    sigma = 0.05, N = 32, m = 4, eps_B = 1/16; (2) the 316 x 316 RGB image,
+    n = 99,856, sigma = 0.1, N = 64, m = 5.  Time per L_s product and the 10
+    smallest eigenpairs by Lanczos (tol 1e-6)."""
+    out = {}
+    cases = [("blobs2d_n5000", synth.blobs2d(5000, seed=0), 0.05, 32, 4, 1.0 / 16),
+             ("image_n99856", synth.image_rgb(316, seed=0), 0.1, 64, 5, 0.0)]
+    for name, v, sig, N, m, eps in cases:
+        P = nfl.plan(torch.as_tensor(v, device=dev), sig, N=N, m=m, eps_B=eps)
+        xd = torch.as_tensor(synth.normal_vectors(v.shape[0], seed=3), device=dev)
+        yd = torch.empty_like(xd)
+        for _ in range(5):
+            P.apply_Ls(xd, out=yd)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(P.stream)
+        for _ in range(steps):
+            P.apply_Ls(xd, out=yd)
+        e1.record(P.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        P.lanczos_smallest(10, tol=1e-6, maxit=300, vectors=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lz = P.lanczos_smallest(10, tol=1e-6, maxit=300)
+        torch.cuda.synchronize()
+        ml = (time.perf_counter() - t0) * 1000.0
+        P.close()
+        out[name] = {"ms_per_Ls": round(ms, 4), "lanczos10_ms": round(ml, 2),
+                     "lanczos10_steps": lz["iters"], "converged": lz["converged"],
+                     "evals": [round(float(e), 7) for e in lz["evals"]]}
+        log("config %s: %s" % (name, out[name]))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -269,11 +347,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-cg", action="store_true")
-    ap.add_argument("--rows", type=int, default=256, help="sampled rows for the accuracy check")
+    ap.add_argument("--rows", type=int, default=4096, help="sampled rows for the accuracy check")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-graph batched leg")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the 64-graph batched leg and print its JSON record")
     ap.add_argument("--no-nystrom", action="store_true", help="skip the Nystrom eigenvalue leg")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the clustering / m = 4 variants and the small configurations")
     ap.add_argument("--no-kernels", action="store_true",
                     help="skip the (inverse) multiquadric kernel leg")
     ap.add_argument("--nystrom-only", action="store_true",
@@ -341,6 +421,19 @@ def main():
     ms_step = ms_total / args.steps
     value = 1000.0 / ms_step
     log("timed %d steps: %.4f ms/step -> %.1f matvecs/s" % (args.steps, ms_step, value))
+    # per-step distribution (one event after each product; a separate pass so
+    # that the events do not enter the timed region above)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    evs[0].record(stream)
+    for i in range(args.steps):
+        P.apply_Ls(xd, out=yd)
+        evs[i + 1].record(stream)
+    torch.cuda.synchronize()
+    per = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
+    step_pct = {"p10": round(float(np.percentile(per, 10)), 5),
+                "median": round(float(np.median(per)), 5),
+                "p90": round(float(np.percentile(per, 90)), 5)}
+    log("per-step ms: %s" % step_pct)
 
     st = P.profile_stages(xd, nrep=max(10, min(50, args.steps)))
     log("stages (ms): " + ", ".join("%s %.4f" % kv for kv in st.items()))
@@ -406,6 +499,11 @@ def main():
             torch.cuda.synchronize()
             res["plain"].append((r0["iters"], (time.time() - t0) * 1e3, r0["relres"]))
             if net is not None:
+                # initial relative residual of the learned start (u0 = 0 starts at 1)
+                u0 = net.predict(Pt, f, c)
+                Mu0 = u0 + TAU * Pt.apply_Ls(u0.float()).double()
+                res.setdefault("learned_initial_relres", []).append(
+                    (torch.linalg.vector_norm(f - Mu0) / torch.linalg.vector_norm(f)).item())
                 net.attach(Pt, c)
                 torch.cuda.synchronize()
                 t0 = time.time()
@@ -425,6 +523,7 @@ def main():
         cg = {"tau": TAU, "tol": 1e-6, "cloud_seed": 100001,
               "rhs": "one-vs-rest, 2% labelled, classes 0..2",
               "plain": summ(res["plain"]), "learned": summ(res["learned"]),
+              "initial_relres": {"plain": 1.0, "learned": res.get("learned_initial_relres")},
               "learned_vs_plain_solution_rel_diff": res.get("rel_diff_solution")}
         log("CG plain: %s" % cg["plain"])
         log("CG learned: %s" % cg["learned"])
@@ -447,6 +546,12 @@ def main():
         f = np.where(lab == 0, 1.0, -1.0)
         kern["krr_gaussian"] = krr_leg(P, torch, torch.as_tensor(f, device=dev))
         log("krr gaussian: %s" % kern["krr_gaussian"])
+
+    # --- clustering sensitivity, m = 4, small configurations ---------------------
+    variants = small = None
+    if not args.no_variants:
+        variants = variants_leg(nfl, synth, torch, dev)
+        small = small_configs_leg(nfl, synth, torch, dev)
 
     # --- CPU oracle baseline (bounded sample) ----------------------------------
     cpu = None
@@ -479,6 +584,7 @@ def main():
                                "N=64 (grid 128^3), m=6, eps_B=0, FP32 L_s product",
                    "n": N_POINTS, "d": 3, "sigma": SIGMA, "N": NBW, "m": MCUT, "eps_B": EPS_B},
         "stages_ms": {k: round(v_, 5) for k, v_ in st.items()},
+        "step_ms_percentiles": step_pct,
         "setup_s": round(setup_s, 3),
         "accuracy": acc,
         "cg": cg,
@@ -487,6 +593,8 @@ def main():
         "batched": batched,
         "nystrom": nys,
         "kernels": kern,
+        "variants": variants,
+        "small_configs": small,
     }
     print(json.dumps(out), flush=True)
     P.close()
