@@ -262,83 +262,139 @@ __global__ __launch_bounds__(256) void k_interp3_tile(const Item *__restrict__ i
 // ---------------------------------------------------------------------------
 // d = 1, 2: one thread per node, direct global accumulation / gathering.
 // ---------------------------------------------------------------------------
+// Spread for d = 1, 2, one work item (nodes of one T^d tile) per workgroup,
+// without per-node atomics: batches of 256 nodes stage their window weights
+// in LDS, then each thread owns cells of the padded tile ((T + W - 1)^d
+// cells) and sums the contributions of the batch's nodes whose windows cover
+// them; the padded tile is added into the grid once per item.
 template <int IN>
-__global__ __launch_bounds__(256) void k_spread12(const float4 *__restrict__ pts, int n, KArgs ka,
+__global__ __launch_bounds__(256) void k_spread12(const Item *__restrict__ items,
+                                                  const float4 *__restrict__ pts, KArgs ka,
                                                   float *__restrict__ grid, int d, int nos,
-                                                  int m, const float *__restrict__ wcoef) {
+                                                  int m, int tshift,
+                                                  const float *__restrict__ wcoef) {
   __shared__ float sc[WIN_MAXW * WIN_NC];
-  for (int q = threadIdx.x; q < WIN_MAXW * WIN_NC; q += 256) sc[q] = wcoef[q];
-  __syncthreads();
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  const float4 q = pts[i];
-  const uint32_t cell = __float_as_uint(q.w);
-  const int cx = cell & 1023u, cy = (cell >> 10) & 1023u;
-  const float xv = load_in<IN>(ka, i);
-  const int W = 2 * m, mask = nos - 1;
-  float wx[WIN_MAXW], wy[WIN_MAXW];
-  const float gx0 = fmaf(2.f, q.x, -1.f), gy0 = fmaf(2.f, q.y, -1.f);
-  for (int a = 0; a < W; ++a) {
-    float px = sc[a * WIN_NC + WIN_NC - 1], py = px;
-    for (int k = WIN_NC - 2; k >= 0; --k) {
-      px = fmaf(px, gx0, sc[a * WIN_NC + k]);
-      py = fmaf(py, gy0, sc[a * WIN_NC + k]);
-    }
-    wx[a] = px;
-    wy[a] = d == 2 ? py : 1.f;
-  }
-  for (int a = 0; a < W; ++a) {
-    const int gx = (cx - (m - 1) + a) & mask;
-    if (d == 1) {
-      unsafeAtomicAdd(&grid[gx], xv * wx[a]);
-    } else {
-      for (int c = 0; c < W; ++c) {
-        const int gy = (cy - (m - 1) + c) & mask;
-        unsafeAtomicAdd(&grid[(size_t)gx * nos + gy], xv * wx[a] * wy[c]);
+  __shared__ float wxs[256 * (WIN_MAXW + 1)], wys[256 * (WIN_MAXW + 1)];
+  __shared__ float xs[256];
+  __shared__ int loc[256];                     // local cell offsets lx | ly << 8
+  const int t = threadIdx.x;
+  for (int q = t; q < WIN_MAXW * WIN_NC; q += 256) sc[q] = wcoef[q];
+  const Item it = items[blockIdx.x];
+  const int W = 2 * m, mask = nos - 1, T = 1 << tshift, Pd = T + W - 1;
+  const int ntd = nos >> tshift;
+  const int tx0 = (d == 2 ? it.tile / ntd : it.tile) << tshift;
+  const int ty0 = d == 2 ? (it.tile % ntd) << tshift : 0;
+  const int ncell = d == 2 ? Pd * Pd : Pd;
+  constexpr int CPT = (WIN_MAXW + 4 - 1) * (WIN_MAXW + 4 - 1) / 256 + 1;   // cells per thread
+  float acc[CPT];
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) acc[c] = 0.f;
+  for (int b0 = it.start; b0 < it.end; b0 += 256) {
+    const int cnt = min(256, it.end - b0);
+    __syncthreads();
+    if (t < cnt) {
+      const int i = b0 + t;
+      const float4 q = pts[i];
+      const uint32_t cell = __float_as_uint(q.w);
+      const int cx = cell & 1023u, cy = (cell >> 10) & 1023u;
+      xs[t] = load_in<IN>(ka, i);
+      loc[t] = (cx - tx0) | ((d == 2 ? cy - ty0 : 0) << 8);
+      const float gx0 = fmaf(2.f, q.x, -1.f), gy0 = fmaf(2.f, q.y, -1.f);
+      for (int a = 0; a < W; ++a) {
+        float px = sc[a * WIN_NC + WIN_NC - 1], py = px;
+        for (int k = WIN_NC - 2; k >= 0; --k) {
+          px = fmaf(px, gx0, sc[a * WIN_NC + k]);
+          py = fmaf(py, gy0, sc[a * WIN_NC + k]);
+        }
+        wxs[t * (WIN_MAXW + 1) + a] = px;
+        wys[t * (WIN_MAXW + 1) + a] = d == 2 ? py : 1.f;
       }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      const int e = t + 256 * c;
+      if (e >= ncell) break;
+      const int px = d == 2 ? e / Pd : e, py = d == 2 ? e % Pd : 0;
+      float sacc = acc[c];
+      for (int j = 0; j < cnt; ++j) {
+        const int l = loc[j];
+        const int a = px - (l & 255), bb = py - (l >> 8);
+        if (a >= 0 && a < W && bb >= 0 && bb < W)
+          sacc = fmaf(xs[j] * wxs[j * (WIN_MAXW + 1) + a], wys[j * (WIN_MAXW + 1) + bb], sacc);
+      }
+      acc[c] = sacc;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    const int e = t + 256 * c;
+    if (e >= ncell) break;
+    const int px = d == 2 ? e / Pd : e, py = d == 2 ? e % Pd : 0;
+    const int gx = (tx0 - (m - 1) + px) & mask;
+    if (acc[c] != 0.f) {
+      if (d == 1)
+        unsafeAtomicAdd(&grid[gx], acc[c]);
+      else
+        unsafeAtomicAdd(&grid[(size_t)gx * nos + ((ty0 - (m - 1) + py) & mask)], acc[c]);
     }
   }
 }
 
+// Interpolation for d = 1, 2, the transpose of k_spread12: one work item per
+// workgroup; its padded tile is staged in LDS once, then each node sums its
+// window from there.
 template <int IN, int OUT>
-__global__ __launch_bounds__(256) void k_interp12(const float4 *__restrict__ pts, int n, KArgs ka,
+__global__ __launch_bounds__(256) void k_interp12(const Item *__restrict__ items,
+                                                  const float4 *__restrict__ pts, KArgs ka,
                                                   const float *__restrict__ grid, int d, int nos,
-                                                  int m, const float *__restrict__ wcoef) {
+                                                  int m, int tshift,
+                                                  const float *__restrict__ wcoef) {
   __shared__ float sc[WIN_MAXW * WIN_NC];
-  for (int q = threadIdx.x; q < WIN_MAXW * WIN_NC; q += 256) sc[q] = wcoef[q];
+  __shared__ float tile[(WIN_MAXW + 4 - 1) * (WIN_MAXW + 4 - 1)];
+  const int t = threadIdx.x;
+  for (int q = t; q < WIN_MAXW * WIN_NC; q += 256) sc[q] = wcoef[q];
+  const Item it = items[blockIdx.x];
+  const int W = 2 * m, mask = nos - 1, T = 1 << tshift, Pd = T + W - 1;
+  const int ntd = nos >> tshift;
+  const int tx0 = (d == 2 ? it.tile / ntd : it.tile) << tshift;
+  const int ty0 = d == 2 ? (it.tile % ntd) << tshift : 0;
+  const int ncell = d == 2 ? Pd * Pd : Pd;
+  for (int e = t; e < ncell; e += 256) {
+    const int px = d == 2 ? e / Pd : e, py = d == 2 ? e % Pd : 0;
+    const int gx = (tx0 - (m - 1) + px) & mask;
+    tile[e] = d == 1 ? grid[gx] : grid[(size_t)gx * nos + ((ty0 - (m - 1) + py) & mask)];
+  }
   __syncthreads();
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  const float4 q = pts[i];
-  const uint32_t cell = __float_as_uint(q.w);
-  const int cx = cell & 1023u, cy = (cell >> 10) & 1023u;
-  const int W = 2 * m, mask = nos - 1;
-  float wx[WIN_MAXW], wy[WIN_MAXW];
-  const float gx0 = fmaf(2.f, q.x, -1.f), gy0 = fmaf(2.f, q.y, -1.f);
-  for (int a = 0; a < W; ++a) {
-    float px = sc[a * WIN_NC + WIN_NC - 1], py = px;
-    for (int k = WIN_NC - 2; k >= 0; --k) {
-      px = fmaf(px, gx0, sc[a * WIN_NC + k]);
-      py = fmaf(py, gy0, sc[a * WIN_NC + k]);
-    }
-    wx[a] = px;
-    wy[a] = d == 2 ? py : 1.f;
-  }
-  float f = 0.f;
-  for (int a = 0; a < W; ++a) {
-    const int gx = (cx - (m - 1) + a) & mask;
-    if (d == 1) {
-      f = fmaf(wx[a], grid[gx], f);
-    } else {
-      float t = 0.f;
-      for (int c = 0; c < W; ++c) {
-        const int gy = (cy - (m - 1) + c) & mask;
-        t = fmaf(wy[c], grid[(size_t)gx * nos + gy], t);
+  for (int i = it.start + t; i < it.end; i += 256) {
+    const float4 q = pts[i];
+    const uint32_t cell = __float_as_uint(q.w);
+    const int lx = (int)(cell & 1023u) - tx0;
+    const int ly = d == 2 ? (int)((cell >> 10) & 1023u) - ty0 : 0;
+    float wx[WIN_MAXW], wy[WIN_MAXW];
+    const float gx0 = fmaf(2.f, q.x, -1.f), gy0 = fmaf(2.f, q.y, -1.f);
+    for (int a = 0; a < W; ++a) {
+      float px = sc[a * WIN_NC + WIN_NC - 1], py = px;
+      for (int k = WIN_NC - 2; k >= 0; --k) {
+        px = fmaf(px, gx0, sc[a * WIN_NC + k]);
+        py = fmaf(py, gy0, sc[a * WIN_NC + k]);
       }
-      f = fmaf(wx[a], t, f);
+      wx[a] = px;
+      wy[a] = d == 2 ? py : 1.f;
     }
+    float f = 0.f;
+    for (int a = 0; a < W; ++a) {
+      if (d == 1) {
+        f = fmaf(wx[a], tile[lx + a], f);
+      } else {
+        const float *row = tile + (lx + a) * Pd + ly;
+        float r = 0.f;
+        for (int c = 0; c < W; ++c) r = fmaf(wy[c], row[c], r);
+        f = fmaf(wx[a], r, f);
+      }
+    }
+    store_out<OUT>(ka, i, f);
   }
-  store_out<OUT>(ka, i, f);
 }
 
 
@@ -557,9 +613,13 @@ static int spread_in(nfl_plan *P, const KArgs &k, float *grid) {
       default: set_error("spread: m out of range"); return NFL_ERR_UNSUPPORTED;
     }
   }
-  const int nb = (int)((P->n + 255) / 256);
-  hipLaunchKernelGGL((k_spread12<IN>), dim3(nb), dim3(256), 0, P->stream, P->pts.p, (int)P->n, k,
-                     grid, P->d, P->nos, P->m, P->wcoef.p);
+  if ((1 << P->tshift) + 2 * P->m - 1 > WIN_MAXW + 4 - 1) {
+    set_error("spread: tile too large for the d <= 2 kernel (tile + 2m - 1 must be <= 19)");
+    return NFL_ERR_UNSUPPORTED;
+  }
+  if (P->nitems == 0) return NFL_OK;
+  hipLaunchKernelGGL((k_spread12<IN>), dim3(P->nitems), dim3(256), 0, P->stream, P->items.p,
+                     P->pts.p, k, grid, P->d, P->nos, P->m, P->tshift, P->wcoef.p);
   NFL_HIP(hipGetLastError());
   return NFL_OK;
 }
@@ -593,9 +653,13 @@ static int interp_io(nfl_plan *P, const KArgs &k, const float *grid) {
       default: set_error("interp: m out of range"); return NFL_ERR_UNSUPPORTED;
     }
   }
-  const int nb = (int)((P->n + 255) / 256);
-  hipLaunchKernelGGL((k_interp12<IN, OUT>), dim3(nb), dim3(256), 0, P->stream, P->pts.p,
-                     (int)P->n, k, grid, P->d, P->nos, P->m, P->wcoef.p);
+  if ((1 << P->tshift) + 2 * P->m - 1 > WIN_MAXW + 4 - 1) {
+    set_error("interp: tile too large for the d <= 2 kernel (tile + 2m - 1 must be <= 19)");
+    return NFL_ERR_UNSUPPORTED;
+  }
+  if (P->nitems == 0) return NFL_OK;
+  hipLaunchKernelGGL((k_interp12<IN, OUT>), dim3(P->nitems), dim3(256), 0, P->stream,
+                     P->items.p, P->pts.p, k, grid, P->d, P->nos, P->m, P->tshift, P->wcoef.p);
   NFL_HIP(hipGetLastError());
   return NFL_OK;
 }

@@ -351,6 +351,9 @@ int build_sorted_nodes(nfl_plan *P) {
       return (size_t)4 * px * p * 4 + 4 * 16 * 80 * 4;
     };
     while (T > 4 && lds_need(T) > 160 * 1024) T >>= 1;
+  } else {
+    // the d <= 2 spread sums one padded tile of T + 2m - 1 <= 19 cells per axis
+    while (T > 1 && T + 2 * P->m - 1 > 19) T >>= 1;
   }
   int tshift = 0;
   while ((1 << tshift) < T) ++tshift;
@@ -405,14 +408,17 @@ int build_sorted_nodes(nfl_plan *P) {
     }
   }
   // Work items: each occupied tile split into near-equal chunks of at most
-  // opt_chunk nodes.
+  // opt_chunk nodes (at most 64 for d <= 2, whose spread loops over every
+  // node of an item for each cell of the padded tile: short items keep that
+  // loop short and give more workgroups to small clustered problems).
+  const int64_t chunk = d == 3 ? P->opt_chunk : std::min(P->opt_chunk, 64);
   std::vector<Item> items;
   int64_t start = 0;
   int maxlen = 0;
   for (int64_t t = 0; t < ntiles; ++t) {
     const int64_t c = hc[(size_t)t];
     if (c == 0) continue;
-    const int64_t nch = (c + P->opt_chunk - 1) / P->opt_chunk;
+    const int64_t nch = (c + chunk - 1) / chunk;
     for (int64_t k = 0; k < nch; ++k) {
       Item it;
       it.tile = (int)t;

@@ -106,6 +106,11 @@ CASES = [
     (3, 1500, 32, 8, 8, 300, 0),
     (2, 2999, 32, 5, None, None, 0),
     (1, 777, 64, 3, None, None, 0),
+    # d <= 2 spread sums padded tiles of tile + 2m - 1 <= 19 cells per item
+    (2, 3001, 32, 8, 4, 64, 0),
+    (2, 5000, 16, 2, 16, 300, 0),
+    (2, 2000, 64, 4, 32, 128, 0),      # tile 32 is clamped so that the padded tile fits
+    (1, 1500, 128, 6, 8, 64, 0),
 ]
 
 
