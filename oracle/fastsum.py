@@ -249,21 +249,26 @@ def _outer_rest(E, rows):
     return P
 
 
-def trig_operator(vt, x, bhat: np.ndarray, N: int, chunk: int = 1024):
-    """f_j = Re sum_{l in I_N^d} b_l xhat_l exp(2 pi i l.v_j), with the adjoint
+def trig_operator(vt, x, bhat: np.ndarray, N: int, chunk: int = 1024, targets=None):
+    """f_j = Re sum_{l in I_N^d} b_l xhat_l exp(2 pi i l.t_j), with the adjoint
     sum xhat_l = sum_i x_i exp(-2 pi i l.v_i) (steps 1-3 of Alg. nfft_fastsum
-    with both nonequispaced sums done exactly).  This approximates W~ x.
+    with both nonequispaced sums done exactly).  With the targets t_j equal to
+    the sources (default) this approximates W~ x; otherwise
+    sum_i x_i K(t_j - v_i).
 
-    vt: scaled nodes (n x d); x: (n,) or (nvec, n)."""
+    vt: scaled source nodes (n x d); x: (n,) or (nvec, n); targets: scaled
+    target nodes (n_t x d) or None."""
     vt = np.asarray(vt, dtype=np.float64)
     if vt.ndim == 1:
         vt = vt[:, None]
     n, d = vt.shape
+    tt = vt if targets is None else np.asarray(targets, dtype=np.float64).reshape(-1, d)
+    nt = tt.shape[0]
     X = np.asarray(x, dtype=np.float64)
     single = X.ndim == 1
     X = X.reshape(1, n) if single else X
     Em = _phases(vt, N, -1.0)
-    Ep = _phases(vt, N, +1.0)
+    Ep = _phases(tt, N, +1.0)
     outs = []
     B = bhat.reshape(N, -1)
     for xv in X:
@@ -273,9 +278,9 @@ def trig_operator(vt, x, bhat: np.ndarray, N: int, chunk: int = 1024):
             P = _outer_rest(Em, rows)
             xhat += (xv[rows, None] * Em[0][rows]).T @ P
         F = B * xhat
-        f = np.empty(n)
-        for s in range(0, n, chunk):
-            rows = np.arange(s, min(n, s + chunk))
+        f = np.empty(nt)
+        for s in range(0, nt, chunk):
+            rows = np.arange(s, min(nt, s + chunk))
             P = _outer_rest(Ep, rows)
             Q = P @ F.T                                   # (rows, N)
             f[rows] = (Ep[0][rows] * Q).sum(axis=1).real

@@ -233,6 +233,26 @@ def test_trig_operator_on_grid_nodes_is_the_direct_sum():
     np.testing.assert_allclose(f, graph.apply_W(g, s, x) + x, atol=1e-12)
 
 
+def test_trig_operator_with_targets_on_grid_nodes_is_the_direct_cross_sum():
+    """Sources and distinct targets on the lattice j/N inside the ball of radius
+    1/4 - eps_B/2: every difference is a lattice node where K_RF = K_R = K, so
+    the operator with targets is sum_i x_i K(t_j - v_i) exactly; with targets
+    equal to the sources it is the operator without targets."""
+    N, d, s = 32, 2, 0.09
+    j = fastsum.index_set(N)
+    g = np.stack(np.meshgrid(j / N, j / N, indexing="ij"), axis=-1).reshape(-1, 2)
+    g = g[np.linalg.norm(g, axis=1) <= 0.25 - 1.0 / 16]
+    rng = np.random.default_rng(4)
+    src, tgt = g[::2], g[1::3]
+    x = rng.standard_normal(src.shape[0])
+    b = fastsum.coefficients(s, N, d, 1.0 / 8, 4)
+    f = fastsum.trig_operator(src, x, b, N, targets=tgt)
+    D = np.exp(-((tgt[:, None, :] - src[None, :, :]) ** 2).sum(axis=2) / s ** 2)
+    np.testing.assert_allclose(f, D @ x, atol=1e-12)
+    np.testing.assert_allclose(fastsum.trig_operator(src, x, b, N, targets=src),
+                               fastsum.trig_operator(src, x, b, N), atol=1e-13)
+
+
 def test_trig_operator_matches_matrix_and_kerr_bound():
     """Two code paths for the same operator agree; and |f - f_RF| <=
     ||x||_1 ||K_ERR||_inf (eq. KERR_estimate) against the direct sum."""
