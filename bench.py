@@ -271,7 +271,8 @@ def variants_leg(nfl, synth, torch, dev, steps=50, rows=256):
     U[0.005, 0.03]) with m = 6, and the benchmark cloud with m = 4.  Time per
     L_s product (HIP events on the library stream), spread / interp stage
     times, and the relative error of W x on sampled rows against the direct
-    FP64 oracle."""
+    FP64 oracle; and the configuration the autotuner picks for rel err 1e-5
+    on the benchmark cloud (no cache), timed the same way."""
     from oracle import graph
     out = {}
     x = synth.normal_vectors(N_POINTS, seed=12345)
@@ -302,6 +303,31 @@ def variants_leg(nfl, synth, torch, dev, steps=50, rows=256):
                      "interp_us": round(st["interp"] * 1e3, 1),
                      "rel_err_Wx_rows": float(np.abs(Wx - ref).max() / np.abs(ref).max())}
         log("variant %s: %s" % (name, out[name]))
+    # the autotuned minimal configuration meeting rel err 1e-5 on the benchmark cloud
+    v = synth.moons_and_roll(N_POINTS, seed=1)[0]
+    P = nfl.Plan(3)
+    P.set_points(torch.as_tensor(v, device=dev))
+    t0 = time.perf_counter()
+    tuned = P.autotune(SIGMA, target=1e-5, rows=256, seed=1)
+    tune_s = time.perf_counter() - t0
+    for _ in range(5):
+        P.apply_Ls(xd, out=yd)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(P.stream)
+    for _ in range(steps):
+        P.apply_Ls(xd, out=yd)
+    e1.record(P.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    Wx = P.apply_W(xd).cpu().numpy().astype(np.float64)[sel]
+    P.close()
+    ref = graph.w_rows(v, SIGMA, x.astype(np.float64), sel)
+    out["autotuned"] = {"N": tuned["N"], "m": tuned["m"], "eps_B": tuned["eps_B"],
+                        "tile": tuned["tile"], "probe_err": tuned["err"],
+                        "tune_s": round(tune_s, 2), "ms_per_Ls": round(ms, 4),
+                        "Ls_per_s": round(1000.0 / ms, 1),
+                        "rel_err_Wx_rows": float(np.abs(Wx - ref).max() / np.abs(ref).max())}
+    log("variant autotuned: %s" % out["autotuned"])
     return out
 
 

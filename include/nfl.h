@@ -107,6 +107,28 @@ int nfl_set_kernel_ex(nfl_handle h, int kind, double param, int N, int m, double
 
 int nfl_set_option(nfl_handle h, int opt, double value);
 
+/* Target nodes for nfl_evaluate: n >= 1 points (n x d FP32 row-major on the
+ * device, copied) placed in the frame of the plan `src` (its centre and
+ * scaling, Alg. nfft_normalized_matvec steps 1-2), which must hold its own
+ * points.  Every target must lie in the ball of the source points around
+ * their centre (then all source-target differences stay inside the torus of
+ * the fast summation); NFL_ERR_ARG otherwise.  Then call nfl_set_kernel(_ex)
+ * on h with the source plan's kernel, N, m and eps_B (and the same
+ * NFL_OPT_P): it sorts the targets and skips the degree pass.  Such a plan
+ * only serves nfl_evaluate and the raw steps; operator and solver calls on it
+ * return NFL_ERR_ORDER.  Synchronises. */
+int nfl_set_points_frame(nfl_handle h, int64_t n, const float *v_dev, nfl_handle src);
+
+/* y_j = sum_i x_i K(t_j - v_i): the fast summation of Alg. nfft_fastsum with
+ * the adjoint NFFT at the source nodes v_i of plan src and the NFFT at the
+ * target nodes t_j of plan tgt (made with nfl_set_points_frame(tgt, .., src),
+ * same kernel parameters; tgt == src gives W~ x = W x + K(0) x).  This is the
+ * kernel ridge regression prediction F(t) = sum_i alpha_i K(t - v_i)
+ * (Section 6.3) for x = alpha.  x_dev: src->n FP32 in the sources' caller
+ * order; y_dev: tgt->n FP32 in the targets' caller order.  Asynchronous on
+ * src's stream (the target plan's stream is synchronised first). */
+int nfl_evaluate(nfl_handle src, const float *x_dev, nfl_handle tgt, float *y_dev);
+
 /* d_E (step 4 of Alg. nfft_normalized_matvec): n float32 in caller order. */
 int nfl_degree(nfl_handle h, float *d_dev);
 

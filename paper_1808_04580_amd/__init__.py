@@ -46,6 +46,8 @@ SIGNATURES = {
     "nfl_set_points": (_i, [_p, _i64, _p]),
     "nfl_set_kernel": (_i, [_p, _d, _i, _i, _d]),
     "nfl_set_kernel_ex": (_i, [_p, _i, _d, _i, _i, _d]),
+    "nfl_set_points_frame": (_i, [_p, _i64, _p, _p]),
+    "nfl_evaluate": (_i, [_p, _p, _p, _p]),
     "nfl_set_option": (_i, [_p, _i, _d]),
     "nfl_degree": (_i, [_p, _p]),
     "nfl_apply_W": (_i, [_p, _p, _p, _i, _i64]),
@@ -185,6 +187,8 @@ class Plan:
     # -- setup --------------------------------------------------------------
     def set_option(self, opt: int, value: float):
         _check(lib().nfl_set_option(self._h, opt, float(value)), "nfl_set_option")
+        if opt == OPT_P:
+            self._options = dict(getattr(self, "_options", {}), **{opt: value})
 
     def set_points(self, v):
         torch = self._torch
@@ -201,7 +205,31 @@ class Plan:
         (inverse) multiquadric kernel)."""
         _check(lib().nfl_set_kernel_ex(self._h, KERNELS[kind], float(sigma), int(N), int(m),
                                        float(eps_B)), "nfl_set_kernel_ex")
+        self._kernel = (float(sigma), int(N), int(m), float(eps_B), kind)
         self._N = int(N)
+
+    def set_points_frame(self, v, src: "Plan"):
+        """Target nodes in the frame of plan `src` (nfl_set_points_frame)."""
+        torch = self._torch
+        v = torch.as_tensor(v, dtype=torch.float32, device=self.device).contiguous()
+        _check(lib().nfl_set_points_frame(self._h, v.shape[0], _ptr(v), src._h),
+               "nfl_set_points_frame")
+        self.n = int(v.shape[0])
+
+    def evaluate(self, x, tgt: "Plan" = None, out=None):
+        """y_j = sum_i x_i K(t_j - v_i) at the nodes of target plan tgt
+        (default: this plan's own nodes, y = W x + K(0) x)."""
+        torch = self._torch
+        tgt = self if tgt is None else tgt
+        x = torch.as_tensor(x, dtype=torch.float32, device=self.device).contiguous()
+        y = torch.empty(tgt.n, dtype=torch.float32, device=self.device) if out is None else out
+        _check(lib().nfl_evaluate(self._h, _ptr(x), tgt._h, _ptr(y)), "nfl_evaluate")
+        return y
+
+    def krr_predict(self, alpha, tgt: "Plan"):
+        """Kernel ridge regression prediction F(t) = sum_i alpha_i K(t - v_i)
+        (Section 6.3) at the target plan's nodes, FP32."""
+        return self.evaluate(alpha, tgt)
 
     def info(self) -> dict:
         vals = [ctypes.c_double() for _ in range(5)]
@@ -381,6 +409,21 @@ class Plan:
         out = np.empty(count, dtype=np.float64)
         _check(lib().nfl_get_filter(self._h, out.ctypes.data_as(_p), count), "nfl_get_filter")
         return out
+
+
+def target_plan(points, src: "Plan", stream=None):
+    """A plan of target nodes in the frame of `src`, with src's kernel and NFFT
+    parameters (for Plan.evaluate / Plan.krr_predict)."""
+    import torch
+    v = torch.as_tensor(points)
+    d = 1 if v.dim() == 1 else int(v.shape[1])
+    T = Plan(d, stream)
+    for opt, val in getattr(src, "_options", {}).items():
+        T.set_option(opt, val)
+    T.set_points_frame(v.reshape(-1, d), src)
+    sigma, N, m, eps_B, kind = src._kernel
+    T.set_kernel(sigma, N, m, eps_B, kind=kind)
+    return T
 
 
 def plan(points, sigma: float, N: int, m: int, eps_B: float = 0.0, stream=None,

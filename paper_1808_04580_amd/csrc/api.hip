@@ -39,6 +39,7 @@ static bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
 static int check_vec_args(nfl_plan *P, const void *x, const void *y, int nvec, int64_t ld) {
   if (!P) { set_error("null handle"); return NFL_ERR_ARG; }
   if (!P->have_kernel) { set_error("apply before a successful nfl_set_kernel"); return NFL_ERR_ORDER; }
+  if (P->frame_only) { set_error("apply on a plan of target nodes (nfl_set_points_frame): it has no degrees"); return NFL_ERR_ORDER; }
   if (!x || !y) { set_error("null vector pointer"); return NFL_ERR_ARG; }
   if (nvec < 1) { set_error("nvec < 1"); return NFL_ERR_ARG; }
   if (ld < P->n) { set_error("ld < n"); return NFL_ERR_ARG; }
@@ -152,6 +153,7 @@ int nfl_set_points(nfl_handle P, int64_t n, const float *v_dev) {
   ++P->gen;
   P->have_points = false;
   P->have_kernel = false;
+  P->frame_only = false;
   P->n = n;
   NFL_TRY(P->pts_user.ensure((size_t)n * P->d));
   NFL_HIP(hipMemcpyAsync(P->pts_user.p, v_dev, (size_t)n * P->d * sizeof(float),
@@ -159,6 +161,75 @@ int nfl_set_points(nfl_handle P, int64_t n, const float *v_dev) {
   NFL_TRY(bbox_and_radius(P));
   if (!std::isfinite(P->radius)) { set_error("non-finite coordinates"); return NFL_ERR_ARG; }
   P->have_points = true;
+  return NFL_OK;
+}
+
+int nfl_set_points_frame(nfl_handle P, int64_t n, const float *v_dev, nfl_handle src) {
+  if (!P || !src) { set_error("null handle"); return NFL_ERR_ARG; }
+  if (P == src) { set_error("a plan cannot be its own frame"); return NFL_ERR_ARG; }
+  if (!src->have_points || src->frame_only) { set_error("frame plan without its own points"); return NFL_ERR_ORDER; }
+  if (P->d != src->d) { set_error("dimension differs from the frame plan"); return NFL_ERR_ARG; }
+  if (n < 1) { set_error("need n >= 1 target points"); return NFL_ERR_ARG; }
+  if (n > (int64_t)1 << 30) { set_error("n above 2^30 is not supported"); return NFL_ERR_UNSUPPORTED; }
+  if (!v_dev) { set_error("null point pointer"); return NFL_ERR_ARG; }
+  ++P->gen;
+  P->have_points = false;
+  P->have_kernel = false;
+  P->frame_only = true;
+  P->n = n;
+  NFL_TRY(P->pts_user.ensure((size_t)n * P->d));
+  NFL_HIP(hipMemcpyAsync(P->pts_user.p, v_dev, (size_t)n * P->d * sizeof(float),
+                         hipMemcpyDeviceToDevice, P->stream));
+  double r = 0.0;
+  NFL_TRY(radius_about(P, src->centre, &r));
+  if (!std::isfinite(r)) { set_error("non-finite coordinates"); return NFL_ERR_ARG; }
+  if (r > src->radius * (1.0 + 1e-6)) {
+    set_error("target points outside the ball of the source points (all differences must stay "
+              "inside the torus of the fast summation)");
+    return NFL_ERR_ARG;
+  }
+  for (int t = 0; t < 3; ++t) P->centre[t] = src->centre[t];
+  P->radius = src->radius;
+  P->have_points = true;
+  return NFL_OK;
+}
+
+int nfl_evaluate(nfl_handle S, const float *x_dev, nfl_handle T, float *y_dev) {
+  if (!S || !T) { set_error("null handle"); return NFL_ERR_ARG; }
+  if (!S->have_kernel || !T->have_kernel) { set_error("evaluate before a successful nfl_set_kernel on both plans"); return NFL_ERR_ORDER; }
+  if (S->frame_only) { set_error("the source plan must hold its own points"); return NFL_ERR_ARG; }
+  if (T != S && !T->frame_only) { set_error("the target plan must be made with nfl_set_points_frame"); return NFL_ERR_ARG; }
+  if (T != S && (T->centre[0] != S->centre[0] || T->centre[1] != S->centre[1] ||
+                 T->centre[2] != S->centre[2] || T->radius != S->radius || T->d != S->d ||
+                 T->kind != S->kind || T->sigma != S->sigma || T->N != S->N || T->m != S->m ||
+                 T->p != S->p || T->eps_B != S->eps_B)) {
+    set_error("target plan and source plan differ in frame or kernel parameters");
+    return NFL_ERR_ARG;
+  }
+  if (!x_dev || !y_dev) { set_error("null vector pointer"); return NFL_ERR_ARG; }
+  if (T->stream != S->stream) NFL_HIP(hipStreamSynchronize(T->stream));
+  // Alg. nfft_fastsum with the adjoint NFFT at the sources and the NFFT at the
+  // targets: spread (sources), filter, interpolation (targets)
+  VecArgs a;
+  a.x32 = x_dev;
+  const bool clear = !S->grid_clean;
+  S->grid_clean = false;
+  NFL_TRY(spread(S, IN_USER_F32, a, S->grid.p, clear));
+  NFL_TRY(convolve(S, S->grid.p, S->grid2.p, true));
+  S->grid_clean = true;
+  VecArgs b;
+  b.y32 = y_dev;
+  hipStream_t keep = T->stream;
+  T->stream = S->stream;               // one stream orders the three steps
+  const int rc = interp(T, S->grid2.p, IN_USER_F32, OUT_USER_RAW, b);
+  T->stream = keep;
+  if (rc < 0) return rc;
+  if (S->wscale != 1.0) {
+    const int blocks = (int)std::min<int64_t>(4096, (T->n + 255) / 256);
+    hipLaunchKernelGGL(k_scale_f32, dim3(blocks), dim3(256), 0, S->stream, y_dev, T->n,
+                       (float)S->wscale);
+    NFL_HIP(hipGetLastError());
+  }
   return NFL_OK;
 }
 
@@ -237,6 +308,10 @@ int nfl_set_kernel_ex(nfl_handle P, int kind, double sigma, int N, int m, double
   NFL_TRY(P->deg.ensure(P->n));
   NFL_TRY(P->dinv.ensure(P->n));
 
+  if (P->frame_only) {   // target nodes: no degree pass
+    P->have_kernel = true;
+    return NFL_OK;
+  }
   // step 4 of Alg. nfft_normalized_matvec: D_E = diag(W~_E 1 - K(0) 1)
   VecArgs a;
   NFL_TRY(fastsum(P, IN_ONES, OUT_DEGREE, a));
@@ -252,6 +327,7 @@ int nfl_set_kernel_ex(nfl_handle P, int kind, double sigma, int N, int m, double
 int nfl_degree(nfl_handle P, float *d_dev) {
   if (!P) { set_error("null handle"); return NFL_ERR_ARG; }
   if (!P->have_kernel) { set_error("degree before a successful nfl_set_kernel"); return NFL_ERR_ORDER; }
+  if (P->frame_only) { set_error("degree on a plan of target nodes (nfl_set_points_frame): it has no degrees"); return NFL_ERR_ORDER; }
   if (!d_dev) { set_error("null output"); return NFL_ERR_ARG; }
   NFL_TRY(scatter_f32(P, P->deg.p, d_dev));
   return scale_out(P, d_dev);
@@ -287,6 +363,7 @@ int nfl_lanczos_smallest(nfl_handle P, int k, int block, double tol, int maxit, 
                          double *evecs_dev, int *iters, double *max_resid) {
   if (!P) { set_error("null handle"); return NFL_ERR_ARG; }
   if (!P->have_kernel) { set_error("lanczos before a successful nfl_set_kernel"); return NFL_ERR_ORDER; }
+  if (P->frame_only) { set_error("lanczos on a plan of target nodes (nfl_set_points_frame): it has no degrees"); return NFL_ERR_ORDER; }
   if (!evals_host) { set_error("null eigenvalue output"); return NFL_ERR_ARG; }
   if (k < 1 || k >= P->n || maxit < k || !(tol > 0)) { set_error("need 1 <= k < n, maxit >= k, tol > 0"); return NFL_ERR_ARG; }
   if (block < 1 || block > 8) { set_error("block must be in 1..8"); return NFL_ERR_ARG; }
@@ -297,6 +374,7 @@ int nfl_nystrom(nfl_handle P, const double *G_dev, int64_t ldg, int L, int M, in
                 double *evals_host, double *evecs_dev, int *m_used) {
   if (!P) { set_error("null handle"); return NFL_ERR_ARG; }
   if (!P->have_kernel) { set_error("nystrom before a successful nfl_set_kernel"); return NFL_ERR_ORDER; }
+  if (P->frame_only) { set_error("nystrom on a plan of target nodes (nfl_set_points_frame): it has no degrees"); return NFL_ERR_ORDER; }
   if (!G_dev || !evals_host) { set_error("null G or eigenvalue output"); return NFL_ERR_ARG; }
   if (k < 1 || M < k || L < M || L > P->n) { set_error("need 1 <= k <= M <= L <= n"); return NFL_ERR_ARG; }
   if (ldg < P->n) { set_error("ldg < n"); return NFL_ERR_ARG; }
@@ -307,6 +385,7 @@ int nfl_cg_solve(nfl_handle P, double tau, const double *f_dev, double *u_dev, i
                  int maxit, int *iters, double *relres) {
   if (!P) { set_error("null handle"); return NFL_ERR_ARG; }
   if (!P->have_kernel) { set_error("cg before a successful nfl_set_kernel"); return NFL_ERR_ORDER; }
+  if (P->frame_only) { set_error("cg on a plan of target nodes (nfl_set_points_frame): it has no degrees"); return NFL_ERR_ORDER; }
   if (!f_dev || !u_dev) { set_error("null vector pointer"); return NFL_ERR_ARG; }
   if (!(tau >= 0) || !(tol > 0) || maxit < 0) { set_error("need tau >= 0, tol > 0, maxit >= 0"); return NFL_ERR_ARG; }
   if (warm < NFL_WARM_ZERO || warm > NFL_WARM_MLP) { set_error("bad warm-start mode"); return NFL_ERR_ARG; }
@@ -317,6 +396,7 @@ int nfl_krr_solve(nfl_handle P, double beta, const double *f_dev, double *alpha_
                   double tol, int maxit, int *iters, double *relres) {
   if (!P) { set_error("null handle"); return NFL_ERR_ARG; }
   if (!P->have_kernel) { set_error("krr before a successful nfl_set_kernel"); return NFL_ERR_ORDER; }
+  if (P->frame_only) { set_error("krr on a plan of target nodes (nfl_set_points_frame): it has no degrees"); return NFL_ERR_ORDER; }
   if (!f_dev || !alpha_dev) { set_error("null vector pointer"); return NFL_ERR_ARG; }
   if (!(beta >= 0) || !std::isfinite(beta) || !(tol > 0) || maxit < 0) { set_error("need beta >= 0, tol > 0, maxit >= 0"); return NFL_ERR_ARG; }
   if (warm != NFL_WARM_ZERO && warm != NFL_WARM_USER) { set_error("krr warm start: NFL_WARM_ZERO or NFL_WARM_USER"); return NFL_ERR_ARG; }

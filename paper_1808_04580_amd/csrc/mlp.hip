@@ -587,7 +587,7 @@ int nfl_mlp_gradient(nfl_mlp_handle M, const float *feat_dev, const float *targe
 int nfl_mlp_train_step(nfl_mlp_handle M, nfl_handle P, const double *f_dev, const double *u_dev,
                        int cls, int64_t nsample, uint64_t seed, double lr, double *loss_host) {
   if (!M || !P || !f_dev || !u_dev || nsample < 1 || !(lr > 0)) { set_error("bad arguments"); return NFL_ERR_ARG; }
-  if (!P->have_kernel) { set_error("plan has no kernel"); return NFL_ERR_ORDER; }
+  if (!P->have_kernel || P->frame_only) { set_error("plan has no kernel or no degrees"); return NFL_ERR_ORDER; }
   if (cls < 0 || cls >= M->ncls) { set_error("class out of range"); return NFL_ERR_ARG; }
   const int64_t ns = std::min<int64_t>(nsample, P->n);
   // sample without replacement: a random window of a seeded shuffle is not
@@ -616,7 +616,7 @@ int nfl_mlp_train_step(nfl_mlp_handle M, nfl_handle P, const double *f_dev, cons
 
 int nfl_mlp_predict(nfl_mlp_handle M, nfl_handle P, const double *f_dev, int cls, double *u_dev) {
   if (!M || !P || !f_dev || !u_dev) { set_error("bad arguments"); return NFL_ERR_ARG; }
-  if (!P->have_kernel) { set_error("plan has no kernel"); return NFL_ERR_ORDER; }
+  if (!P->have_kernel || P->frame_only) { set_error("plan has no kernel or no degrees"); return NFL_ERR_ORDER; }
   if (cls < 0 || cls >= M->ncls) { set_error("class out of range"); return NFL_ERR_ARG; }
   LBuf<double> fs, us;
   NFL_TRY(fs.ensure(P->n));

@@ -101,6 +101,7 @@ struct nfl_plan {
   double centre[3] = {0, 0, 0};
   double radius = 0;
   bool have_points = false;
+  bool frame_only = false;      // target nodes in another plan's frame (nfl_set_points_frame): no degrees
 
   // options
   int opt_p = 0;                // 0 -> p = m
@@ -162,6 +163,7 @@ namespace nfl {
 
 // ---- setup (setup.hip) -------------------------------------------------------
 int bbox_and_radius(nfl_plan *P);                       // sets centre, radius
+int radius_about(nfl_plan *P, const double *centre, double *radius);  // max ||v - centre||
 int build_sorted_nodes(nfl_plan *P);                    // keys, sort, items
 int build_filter_host(nfl_plan *P);                     // filt_host (FP64)
 int exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t len, hipStream_t s,

@@ -94,6 +94,21 @@ __global__ __launch_bounds__(64) void k_radius_final(double *part, int nparts, d
   }
 }
 
+int radius_about(nfl_plan *P, const double *centre, double *radius) {
+  const int nb = (int)std::min<int64_t>(1024, (P->n + RED_THREADS - 1) / RED_THREADS);
+  NFL_TRY(P->red.ensure((size_t)nb * 6 + 8));
+  double *part = P->red.p;
+  double *res = P->red.p + (size_t)nb * 6;
+  NFL_HIP(hipMemcpyAsync(res, centre, 3 * sizeof(double), hipMemcpyHostToDevice, P->stream));
+  hipLaunchKernelGGL(k_radius_partial, dim3(nb), dim3(RED_THREADS), 0, P->stream, P->pts_user.p,
+                     P->n, P->d, res, part);
+  hipLaunchKernelGGL(k_radius_final, dim3(1), dim3(64), 0, P->stream, part, nb, res + 3);
+  NFL_HIP(hipGetLastError());
+  NFL_HIP(hipMemcpyAsync(radius, res + 3, sizeof(double), hipMemcpyDeviceToHost, P->stream));
+  NFL_HIP(hipStreamSynchronize(P->stream));
+  return NFL_OK;
+}
+
 int bbox_and_radius(nfl_plan *P) {
   const int nb = (int)std::min<int64_t>(1024, (P->n + RED_THREADS - 1) / RED_THREADS);
   NFL_TRY(P->red.ensure((size_t)nb * 6 + 8));

@@ -59,6 +59,8 @@ def test_error_codes_without_gpu():
     assert L.nfl_nystrom(None, None, 0, 1, 1, 1, None, None, None) == nfl.NFL_ERR_ARG
     assert L.nfl_set_kernel_ex(None, 1, 0.1, 32, 4, 0.0) == nfl.NFL_ERR_ARG
     assert L.nfl_krr_solve(None, 1.0, None, None, 0, 1e-6, 10, None, None) == nfl.NFL_ERR_ARG
+    assert L.nfl_set_points_frame(None, 1, None, None) == nfl.NFL_ERR_ARG
+    assert L.nfl_evaluate(None, None, None, None) == nfl.NFL_ERR_ARG
 
 
 def kb_hat_quadrature(xi, m, b=1.5 * math.pi, nq=2001):
