@@ -572,6 +572,31 @@ def main():
         f = np.where(lab == 0, 1.0, -1.0)
         kern["krr_gaussian"] = krr_leg(P, torch, torch.as_tensor(f, device=dev))
         log("krr gaussian: %s" % kern["krr_gaussian"])
+        # prediction at 1M new points (uniform in 0.95 of the sources' ball)
+        V = v.astype(np.float64)
+        c0 = 0.5 * (V.min(axis=0) + V.max(axis=0))
+        R = np.sqrt(((V - c0) ** 2).sum(axis=1)).max()
+        u = synth.uniform_ball(N_POINTS, d=3, seed=77).astype(np.float64)
+        u /= np.sqrt((u * u).sum(axis=1)).max()
+        tgt = torch.as_tensor((c0 + 0.95 * R * u).astype(np.float32), device=dev)
+        t0 = time.perf_counter()
+        T = nfl.target_plan(tgt, P)
+        torch.cuda.synchronize()
+        setup_t = (time.perf_counter() - t0) * 1000.0
+        xd32 = torch.as_tensor(x, device=dev)
+        yt = torch.empty(N_POINTS, dtype=torch.float32, device=dev)
+        for _ in range(3):
+            P.evaluate(xd32, T, out=yt)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(P.stream)
+        for _ in range(20):
+            P.evaluate(xd32, T, out=yt)
+        e1.record(P.stream)
+        torch.cuda.synchronize()
+        kern["evaluate_1M_targets"] = {"ms": round(e0.elapsed_time(e1) / 20, 4),
+                                       "target_setup_ms": round(setup_t, 2)}
+        log("evaluate at 1M targets: %s" % kern["evaluate_1M_targets"])
+        T.close()
 
     # --- clustering sensitivity, m = 4, small configurations ---------------------
     variants = small = None
