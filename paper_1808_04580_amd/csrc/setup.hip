@@ -75,7 +75,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_radius_partial(const float *__r
       double x = (double)v[i * d + t] - c[t];
       a += x * x;
     }
-    r2 = fmax(r2, a);
+    r2 = a == a ? fmax(r2, a) : INFINITY;   // a NaN coordinate makes the radius infinite
   }
   s[threadIdx.x] = r2;
   __syncthreads();
