@@ -101,7 +101,7 @@ def two_point_taylor(a: float, b: float, A, B):
 
 # ---- other radial kernels of eq. W_general -----------------------------------
 
-KINDS = ("gaussian", "multiquadric", "inverse_multiquadric")
+KINDS = ("gaussian", "multiquadric", "inverse_multiquadric", "laplacian_rbf")
 _ALPHA = {"multiquadric": 0.5, "inverse_multiquadric": -0.5}
 
 
@@ -111,6 +111,8 @@ def radial_kernel(kind: str, param: float):
     multiquadric), param = c."""
     if kind == "gaussian":
         return lambda r: gaussian(r, param)
+    if kind == "laplacian_rbf":
+        return lambda r: np.exp(-np.asarray(r, dtype=np.float64) / param)
     a = _ALPHA[kind]
     return lambda r: (np.asarray(r, dtype=np.float64) ** 2 + param * param) ** a
 
@@ -143,6 +145,9 @@ def power_radial_derivs(r0: float, c: float, alpha: float, p: int):
 def radial_derivs(kind: str, r0: float, param: float, p: int):
     if kind == "gaussian":
         return gaussian_radial_derivs(r0, param, p)
+    if kind == "laplacian_rbf":
+        # d^k/dr^k exp(-r/s) = (-1/s)^k exp(-r/s)
+        return [(-1.0 / param) ** k * math.exp(-r0 / param) for k in range(p)]
     return power_radial_derivs(r0, param, _ALPHA[kind], p)
 
 
@@ -153,17 +158,25 @@ def scaled_param(kind: str, param: float, rho: float) -> float:
 
 def output_scale(kind: str, rho: float) -> float:
     """K(y; param) = output_scale * K(rho y; rho param) (homogeneity)."""
-    return {"gaussian": 1.0, "multiquadric": 1.0 / rho, "inverse_multiquadric": rho}[kind]
+    return {"gaussian": 1.0, "multiquadric": 1.0 / rho, "inverse_multiquadric": rho,
+            "laplacian_rbf": 1.0}[kind]
 
 
 class RegKernel:
     """K_R of the regularisation ansatz, as a radial function (Gaussian by
     default; `kind` selects another kernel of eq. W_general, `sigma` is then
-    its parameter c)."""
+    its parameter c).  With eps_I > 0 (the Laplacian RBF kernel, not smooth at
+    0) K_R is also replaced near the origin: on r <= eps_I by the even
+    polynomial T_I of degree 2p - 1 that matches K and its first p - 1 radial
+    derivatives at r = +-eps_I (two-point Taylor on [-eps_I, eps_I] of the even
+    extension of K), the near-origin regularisation the paper takes from its
+    reference on fast summation with singular kernels."""
 
-    def __init__(self, sigma: float, eps_B: float, p: int, kind: str = "gaussian"):
+    def __init__(self, sigma: float, eps_B: float, p: int, kind: str = "gaussian",
+                 eps_I: float = 0.0):
         self.sigma, self.eps_B, self.p = float(sigma), float(eps_B), int(p)
         self.kind = kind
+        self.eps_I = float(eps_I)
         self.K = radial_kernel(kind, self.sigma)
         self.r0 = 0.5 - self.eps_B
         self.k_half = float(self.K(0.5))
@@ -173,6 +186,23 @@ class RegKernel:
             self.coef = two_point_taylor(self.r0, 0.5, A, B)
         else:
             self.coef = None
+        if self.eps_I > 0:
+            D = radial_derivs(kind, self.eps_I, self.sigma, self.p)
+            Dm = [(-1.0) ** k * D[k] for k in range(self.p)]   # even extension at -eps_I
+            self.coef_I = two_point_taylor(-self.eps_I, self.eps_I, Dm, D)
+        else:
+            self.coef_I = None
+
+    def T_I(self, r):
+        t = (np.asarray(r, dtype=np.float64) + self.eps_I) / (2.0 * self.eps_I)
+        return np.polynomial.polynomial.polyval(t, self.coef_I)
+
+    def near(self, r):
+        """K - K_R on r <= eps_I (the near-field correction), 0 elsewhere."""
+        r = np.asarray(r, dtype=np.float64)
+        if self.coef_I is None:
+            return np.zeros_like(r)
+        return np.where(r <= self.eps_I, self.K(r) - self.T_I(np.minimum(r, self.eps_I)), 0.0)
 
     def T_B(self, r):
         t = (np.asarray(r, dtype=np.float64) - self.r0) / (0.5 - self.r0)
@@ -181,6 +211,8 @@ class RegKernel:
     def __call__(self, r):
         r = np.asarray(r, dtype=np.float64)
         out = self.K(r)
+        if self.coef_I is not None:
+            out = np.where(r <= self.eps_I, self.T_I(np.minimum(r, self.eps_I)), out)
         if self.coef is None:
             # eps_B = 0: no transition region; constant K(1/2) beyond radius 1/2
             return np.where(r <= 0.5, out, self.k_half)
@@ -198,12 +230,12 @@ def index_set(N: int):
 
 
 def coefficients(sigma: float, N: int, d: int, eps_B: float, p: int,
-                 kind: str = "gaussian") -> np.ndarray:
+                 kind: str = "gaussian", eps_I: float = 0.0) -> np.ndarray:
     """b_l for l in I_N^d, array of shape (N,)*d indexed by l + N/2.
 
     b_l = N^{-d} sum_{j in I_N^d} K_R(j/N) exp(-2 pi i j.l/N), computed as a DFT
     (numpy's FFT as the library primitive) of the samples placed at j mod N."""
-    K = RegKernel(sigma, eps_B, p, kind)
+    K = RegKernel(sigma, eps_B, p, kind, eps_I)
     j = index_set(N)
     grids = np.meshgrid(*([j / N] * d), indexing="ij")
     r = np.sqrt(sum(g * g for g in grids))
@@ -309,20 +341,35 @@ class TrigGraph:
     by its exact trigonometric operator.  apply_Wt approximates W~ = W + K(0) I
     in the original coordinates (for the Gaussian K(0) = 1)."""
 
-    def __init__(self, v, sigma: float, N: int, eps_B: float, p: int, kind: str = "gaussian"):
+    def __init__(self, v, sigma: float, N: int, eps_B: float, p: int, kind: str = "gaussian",
+                 eps_I: float = 0.0):
         self.c, self.rho, self.vt = scaling(v, eps_B)
         self.kind = kind
         self.sigma_t = scaled_param(kind, sigma, self.rho)
         self.scale = output_scale(kind, self.rho)
         self.K0 = float(radial_kernel(kind, sigma)(0.0))
         self.N = N
-        self.bhat = coefficients(self.sigma_t, N, self.vt.shape[1], eps_B, p, kind)
+        self.reg = RegKernel(self.sigma_t, eps_B, p, kind, eps_I)
+        self.bhat = coefficients(self.sigma_t, N, self.vt.shape[1], eps_B, p, kind, eps_I)
         ones = np.ones(self.vt.shape[0])
         self.d = self.apply_Wt(ones) - self.K0                       # step 4
         self.dinv = 1.0 / np.sqrt(self.d)
 
     def apply_Wt(self, x):
-        return self.scale * trig_operator(self.vt, x, self.bhat, self.N)
+        f = trig_operator(self.vt, x, self.bhat, self.N)
+        if self.reg.coef_I is not None:
+            f = f + self.near_field(x)
+        return self.scale * f
+
+    def near_field(self, x):
+        """sum over pairs with ||v~_j - v~_i|| <= eps_I (i = j included) of
+        x_i (K - K_R)(v~_j - v~_i): the correction that restores K near 0."""
+        X = np.asarray(x, dtype=np.float64)
+        out = np.zeros(self.vt.shape[0])
+        for s in range(0, self.vt.shape[0], 512):
+            r = np.sqrt(((self.vt[s:s + 512, None, :] - self.vt[None, :, :]) ** 2).sum(axis=2))
+            out[s:s + 512] = self.reg.near(r) @ X
+        return out
 
     def apply_W(self, x):
         return self.apply_Wt(x) - self.K0 * np.asarray(x, dtype=np.float64)

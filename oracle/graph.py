@@ -94,7 +94,8 @@ def Ls_rows(v, sigma, x, rows, d):
 def kernel_matrix(v, param: float, kind: str = "gaussian") -> np.ndarray:
     """K(v_i - v_j) for all i, j including the diagonal K(0) (eq. W_general):
     exp(-r^2/param^2) for the Gaussian, sqrt(r^2 + param^2) for the
-    multiquadric, 1/sqrt(r^2 + param^2) for the inverse multiquadric kernel
+    multiquadric, 1/sqrt(r^2 + param^2) for the inverse multiquadric kernel,
+    exp(-r/param) for the Laplacian RBF kernel (eq. W_laplacian_rbf)
     (small n only)."""
     V = _v64(v)
     diff = V[:, None, :] - V[None, :, :]
@@ -105,6 +106,8 @@ def kernel_matrix(v, param: float, kind: str = "gaussian") -> np.ndarray:
         return np.sqrt(r2 + param * param)
     if kind == "inverse_multiquadric":
         return 1.0 / np.sqrt(r2 + param * param)
+    if kind == "laplacian_rbf":
+        return np.exp(-np.sqrt(r2) / param)
     raise ValueError(kind)
 
 

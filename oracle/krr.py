@@ -35,6 +35,8 @@ def predict(v, alpha, x_new, param: float, kind: str = "gaussian") -> np.ndarray
         Kx = np.exp(-d2 / (param * param))
     elif kind == "multiquadric":
         Kx = np.sqrt(d2 + param * param)
+    elif kind == "laplacian_rbf":
+        Kx = np.exp(-np.sqrt(d2) / param)
     else:
         Kx = 1.0 / np.sqrt(d2 + param * param)
     return Kx @ np.asarray(alpha, dtype=np.float64)

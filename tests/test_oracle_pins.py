@@ -215,6 +215,51 @@ def test_other_kernels_scaled_operator_matches_direct_sums(kind, c):
     assert np.abs(wrong - T.K0 * x - W @ x).max() > 100 * bound
 
 
+def test_laplacian_rbf_derivatives_and_inner_regularisation():
+    """exp(-r/s): derivatives against central differences; T_I is even and
+    meets the Hermite conditions at +-eps_I (so K_R is C^{p-1} across the
+    junction), and the near-field correction K - K_R vanishes beyond eps_I."""
+    s, p, eps_I = 0.05, 6, 0.09
+    D = fastsum.radial_derivs("laplacian_rbf", 0.07, s, p)
+    h = 1e-6
+    K = fastsum.radial_kernel("laplacian_rbf", s)
+    assert abs(D[1] - (K(0.07 + h) - K(0.07 - h)) / (2 * h)) <= 1e-7 * abs(D[1])
+    R = fastsum.RegKernel(s, 1.0 / 8, p, "laplacian_rbf", eps_I)
+    r = np.linspace(0.0, eps_I, 7)
+    np.testing.assert_allclose(R.T_I(r), R.T_I(-r), rtol=1e-12, atol=1e-14)
+    poly = np.polynomial.Polynomial(R.coef_I)
+    h2 = 2 * eps_I
+    A = fastsum.radial_derivs("laplacian_rbf", eps_I, s, p)
+    for k in range(p):
+        dk = poly.deriv(k) if k else poly
+        scale = sum(abs(c) * q ** k for q, c in enumerate(R.coef_I)) / h2 ** k
+        assert abs(dk(1.0) / h2 ** k - A[k]) <= 1e-11 * scale + 1e-13, k
+    assert np.all(R.near(np.array([eps_I * 1.01, 0.2, 0.4])) == 0.0)
+    assert R.near(np.array([0.0]))[0] == pytest.approx(1.0 - R.T_I(0.0))
+
+
+def test_laplacian_rbf_near_field_restores_the_direct_sums():
+    """Trigonometric operator of the regularised kernel plus the near-field sum
+    equals the direct sums of eq. W_laplacian_rbf within
+    ||x||_1 max |K_R - K_RF| (the near field restores K exactly on r <= eps_I);
+    without the near field the kink of K at 0 leaves errors ~1e-2."""
+    v = synth.gmm(800, d=3, k=4, seed=3)
+    s, N, m, eps_B = 0.05, 64, 6, 1.0 / 8
+    T = fastsum.TrigGraph(v, s, N, eps_B, m, "laplacian_rbf", eps_I=m / N)
+    x = np.random.default_rng(5).standard_normal(800)
+    W = graph.dense_W(v, s, "laplacian_rbf")
+    rng = np.random.default_rng(0)
+    g = rng.normal(size=(20000, 3))
+    g /= np.linalg.norm(g, axis=1, keepdims=True)
+    rr = (0.5 - eps_B) * rng.uniform(0.0, 1.0, size=20000) ** (1.0 / 3)
+    kerr = np.abs(T.reg(rr) - fastsum.K_RF(g * rr[:, None], T.bhat, N).real).max()
+    err = np.abs(T.apply_W(x) - W @ x).max()
+    assert err <= 2.0 * kerr * np.abs(x).sum()
+    assert err <= 1e-4 * np.abs(W @ x).max()
+    T0 = fastsum.TrigGraph(v, s, N, eps_B, m, "laplacian_rbf")
+    assert np.abs(T0.apply_W(x) - W @ x).max() > 1e-3 * np.abs(W @ x).max()
+
+
 # ---- Oracle B: the exact trigonometric operator -----------------------------
 
 def test_trig_operator_on_grid_nodes_is_the_direct_sum():
