@@ -55,6 +55,9 @@ typedef struct nfl_mlp *nfl_mlp_handle;
 #define NFL_OPT_KERNEL     5   /* d = 3 spread/interp: 0 = matrix-core (MFMA) kernels (default; tile-stationary
                                    where tile + 2m - 1 <= 16, else per-cell runs), 1 = vector-ALU kernels,
                                    2 = matrix-core kernels with per-cell runs only; takes effect immediately */
+#define NFL_OPT_EPS_I      7   /* inner regularisation radius eps_I of the Laplacian RBF kernel in the
+                                   scaled coordinates (0 = default p/N); eps_I + eps_B < 1/2; takes effect
+                                   at the next nfl_set_kernel */
 #define NFL_OPT_RESTARTS   6   /* thick restarts of nfl_lanczos_smallest (0 = none, default): with r > 0,
                                    maxit is the basis size and up to r restarts keep the leading Ritz
                                    vectors (see nfl_lanczos_smallest); takes effect immediately */
@@ -90,6 +93,9 @@ int nfl_set_kernel(nfl_handle h, double sigma, int N, int m, double eps_B);
 #define NFL_KERNEL_GAUSSIAN               0  /* exp(-r^2 / param^2), K(0) = 1 */
 #define NFL_KERNEL_MULTIQUADRIC           1  /* (r^2 + param^2)^{1/2}, K(0) = param */
 #define NFL_KERNEL_INVERSE_MULTIQUADRIC   2  /* (r^2 + param^2)^{-1/2}, K(0) = 1/param */
+#define NFL_KERNEL_LAPLACIAN_RBF          3  /* exp(-r / param) (eq. W_laplacian_rbf), K(0) = 1: not
+                                                 smooth at 0, so K is regularised on r <= eps_I and a
+                                                 near-field sum over pairs closer than eps_I restores it */
 
 /* nfl_set_kernel for any kernel of eq. W_general above (Alg.
  * nfft_normalized_matvec, steps 1-4): W_ij = K(v_i - v_j) for i != j, W_ii = 0,
@@ -102,7 +108,16 @@ int nfl_set_kernel(nfl_handle h, double sigma, int N, int m, double eps_B);
  * degree range in the original units.  The kernel-approximation error of
  * these slowly decaying kernels is much larger than the Gaussian's at the same
  * N (choose N = 64 or more and eps_B around 1/8); nfl_autotune and
- * nfl_direct_rows are for the Gaussian only. */
+ * nfl_direct_rows are for the Gaussian only.
+ * NFL_KERNEL_LAPLACIAN_RBF: the regularised kernel K_R equals the even
+ * polynomial T_I (degree 2p - 1, matching K and p - 1 radial derivatives at
+ * r = +-eps_I) on r <= eps_I, the near-origin regularisation of the fast
+ * summation for kernels that are not smooth at 0; every product then adds the
+ * near-field sum over pairs with ||v~_i - v~_j|| <= eps_I of
+ * x_j (K - T_I)(v~_i - v~_j) (diagonal included), computed directly from the
+ * sorted nodes (cost grows with the number of such pairs: eps_I = p/N).
+ * Batches and nfl_evaluate do not carry the near field and refuse this
+ * kernel (NFL_ERR_UNSUPPORTED). */
 int nfl_set_kernel_ex(nfl_handle h, int kind, double param, int N, int m, double eps_B);
 
 int nfl_set_option(nfl_handle h, int opt, double value);
@@ -301,9 +316,10 @@ int nfl_compute_filter(int d, int N, int m, int p, double eps_B, double sigma_ti
                        double *filter_host, int64_t count);
 
 /* nfl_compute_filter for a kernel kind (NFL_KERNEL_*): the filter of the
- * kernel divided by K(0), sigma_tilde = the scaled parameter. */
+ * kernel divided by K(0), sigma_tilde = the scaled parameter, eps_I = the
+ * inner regularisation radius (Laplacian RBF kernel only; 0 otherwise). */
 int nfl_compute_filter_ex(int kind, int d, int N, int m, int p, double eps_B, double sigma_tilde,
-                          double *filter_host, int64_t count);
+                          double eps_I, double *filter_host, int64_t count);
 
 /* The window the kernels apply (host, no GPU): for each of the 2m grid
  * offsets c of a node's window, NFL_WIN_NC float32 coefficients of the

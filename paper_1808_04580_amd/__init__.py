@@ -30,7 +30,8 @@ OPT_CHUNK = 3
 OPT_EPS_B_DEFAULT = 4
 OPT_KERNEL = 5
 OPT_RESTARTS = 6
-KERNELS = {"gaussian": 0, "multiquadric": 1, "inverse_multiquadric": 2}
+KERNELS = {"gaussian": 0, "multiquadric": 1, "inverse_multiquadric": 2, "laplacian_rbf": 3}
+OPT_EPS_I = 7
 
 WARM_ZERO = 0
 WARM_USER = 1
@@ -64,7 +65,7 @@ SIGNATURES = {
     "nfl_interp": (_i, [_p, _p, _p]),
     "nfl_get_filter": (_i, [_p, _p, _i64]),
     "nfl_compute_filter": (_i, [_i, _i, _i, _i, _d, _d, _p, _i64]),
-    "nfl_compute_filter_ex": (_i, [_i, _i, _i, _i, _i, _d, _d, _p, _i64]),
+    "nfl_compute_filter_ex": (_i, [_i, _i, _i, _i, _i, _d, _d, _d, _p, _i64]),
     "nfl_profile_stages": (_i, [_p, _p, _p, _i, _p]),
     "nfl_window_coefficients": (_i, [_i, _p, _i64]),
     "nfl_mlp_create": (_i, [ctypes.POINTER(_p), _i, ctypes.c_uint64, _p]),
@@ -124,13 +125,14 @@ def strerror(code: int) -> str:
 
 
 def compute_filter(d: int, N: int, m: int, p: int, eps_B: float, sigma_tilde: float,
-                   kind: str = "gaussian") -> np.ndarray:
+                   kind: str = "gaussian", eps_I: float = 0.0) -> np.ndarray:
     """The half-spectrum filter (host FP64, no GPU needed); for kernels other
     than the Gaussian, of the kernel divided by K(0)."""
     count = (N + 1) ** (d - 1) * (N // 2 + 1)
     out = np.empty(count, dtype=np.float64)
     _check(lib().nfl_compute_filter_ex(KERNELS[kind], d, N, m, p, float(eps_B),
-                                       float(sigma_tilde), out.ctypes.data_as(_p), count),
+                                       float(sigma_tilde), float(eps_I), out.ctypes.data_as(_p),
+                                       count),
            "nfl_compute_filter_ex")
     shape = tuple([N + 1] * (d - 1) + [N // 2 + 1])
     return out.reshape(shape)
@@ -434,7 +436,8 @@ def plan(points, sigma: float, N: int, m: int, eps_B: float = 0.0, stream=None,
     d = 1 if v.dim() == 1 else int(v.shape[1])
     P = Plan(d, stream)
     for k, val in options.items():
-        P.set_option({"p": OPT_P, "tile": OPT_TILE, "chunk": OPT_CHUNK, "kernel": OPT_KERNEL}[k],
+        P.set_option({"p": OPT_P, "tile": OPT_TILE, "chunk": OPT_CHUNK, "kernel": OPT_KERNEL,
+                      "eps_I": OPT_EPS_I}[k],
                      val)
     P.set_points(v)
     P.set_kernel(sigma, N, m, eps_B, kind=kind)

@@ -16,7 +16,7 @@ static thread_local std::string g_last_error;
 void set_error(const std::string &msg) { g_last_error = msg; }
 
 int compute_filter(int d, int N, int m, int p, double eps_B, double sigma_t,
-                   std::vector<double> &out, int kind);
+                   std::vector<double> &out, int kind, double eps_I);
 
 // y[i] *= s, i < n (W and degree outputs of non-Gaussian kernels: the NFFT
 // works with K / K(0))
@@ -113,6 +113,12 @@ int nfl_destroy(nfl_handle P) {
 
 int nfl_set_option(nfl_handle P, int opt, double value) {
   if (!P) { set_error("null handle"); return NFL_ERR_ARG; }
+  if (opt == NFL_OPT_EPS_I) {
+    if (!(value >= 0 && value < 0.5)) { set_error("eps_I must be in [0, 1/2) (0 = p/N)"); return NFL_ERR_ARG; }
+    ++P->gen;
+    P->opt_eps_I = value;
+    return NFL_OK;
+  }
   if (opt == NFL_OPT_RESTARTS) {   // a solver setting: the operator is unchanged
     if (value < 0 || value > 1000 || value != std::floor(value)) { set_error("restarts must be an integer in [0, 1000]"); return NFL_ERR_ARG; }
     P->opt_restarts = (int)value;
@@ -198,6 +204,7 @@ int nfl_evaluate(nfl_handle S, const float *x_dev, nfl_handle T, float *y_dev) {
   if (!S || !T) { set_error("null handle"); return NFL_ERR_ARG; }
   if (!S->have_kernel || !T->have_kernel) { set_error("evaluate before a successful nfl_set_kernel on both plans"); return NFL_ERR_ORDER; }
   if (S->frame_only) { set_error("the source plan must hold its own points"); return NFL_ERR_ARG; }
+  if (S->kind == NFL_KERNEL_LAPLACIAN_RBF) { set_error("evaluate: the Laplacian RBF kernel needs a near-field sum between the two node sets, not built"); return NFL_ERR_UNSUPPORTED; }
   if (T != S && !T->frame_only) { set_error("the target plan must be made with nfl_set_points_frame"); return NFL_ERR_ARG; }
   if (T != S && (T->centre[0] != S->centre[0] || T->centre[1] != S->centre[1] ||
                  T->centre[2] != S->centre[2] || T->radius != S->radius || T->d != S->d ||
@@ -240,7 +247,7 @@ int nfl_set_kernel(nfl_handle P, double sigma, int N, int m, double eps_B) {
 int nfl_set_kernel_ex(nfl_handle P, int kind, double sigma, int N, int m, double eps_B) {
   if (!P) { set_error("null handle"); return NFL_ERR_ARG; }
   if (!P->have_points) { set_error("set_kernel before set_points"); return NFL_ERR_ORDER; }
-  if (kind < NFL_KERNEL_GAUSSIAN || kind > NFL_KERNEL_INVERSE_MULTIQUADRIC) { set_error("unknown kernel kind"); return NFL_ERR_ARG; }
+  if (kind < NFL_KERNEL_GAUSSIAN || kind > NFL_KERNEL_LAPLACIAN_RBF) { set_error("unknown kernel kind"); return NFL_ERR_ARG; }
   if (!(sigma > 0) || !std::isfinite(sigma)) { set_error("kernel parameter must be > 0"); return NFL_ERR_ARG; }
   if (N < 2 || (N & 1)) { set_error("N must be even and >= 2"); return NFL_ERR_ARG; }
   if (m < 1) { set_error("m must be >= 1"); return NFL_ERR_ARG; }
@@ -252,9 +259,16 @@ int nfl_set_kernel_ex(nfl_handle P, int kind, double sigma, int N, int m, double
   if (2 * m > N) { set_error("window wider than half the grid (need m <= N/2)"); return NFL_ERR_UNSUPPORTED; }
   ++P->gen;
   P->have_kernel = false;
+  double eps_I = 0.0;
+  if (kind == NFL_KERNEL_LAPLACIAN_RBF) {
+    eps_I = P->opt_eps_I > 0 ? P->opt_eps_I : (double)p / N;
+    if (!(eps_I + eps_B < 0.5)) { set_error("need eps_I + eps_B < 1/2"); return NFL_ERR_ARG; }
+  }
   P->kind = kind;
   P->sigma = sigma;
-  P->wscale = kind == NFL_KERNEL_GAUSSIAN ? 1.0 : (kind == NFL_KERNEL_MULTIQUADRIC ? sigma : 1.0 / sigma);
+  P->eps_I = eps_I;
+  P->wscale = (kind == NFL_KERNEL_GAUSSIAN || kind == NFL_KERNEL_LAPLACIAN_RBF)
+                  ? 1.0 : (kind == NFL_KERNEL_MULTIQUADRIC ? sigma : 1.0 / sigma);
   P->N = N;
   P->m = m;
   P->p = p;
@@ -274,6 +288,14 @@ int nfl_set_kernel_ex(nfl_handle P, int kind, double sigma, int N, int m, double
                            hipMemcpyHostToDevice, P->stream));
   }
   NFL_TRY(build_filter_host(P));
+  if (kind == NFL_KERNEL_LAPLACIAN_RBF) {
+    std::vector<double> c;
+    NFL_TRY(inner_poly(P->sigma_t, P->eps_I, p, c));
+    std::vector<float> cf(c.begin(), c.end());
+    NFL_TRY(P->ti_coef.ensure(cf.size()));
+    NFL_HIP(hipMemcpyAsync(P->ti_coef.p, cf.data(), cf.size() * sizeof(float),
+                           hipMemcpyHostToDevice, P->stream));
+  }
   NFL_TRY(P->filt.ensure(P->filt_host.size()));
   {
     std::vector<float> f32(P->filt_host.size());
@@ -452,21 +474,22 @@ int nfl_get_filter(nfl_handle P, double *filter_host, int64_t count) {
 
 int nfl_compute_filter(int d, int N, int m, int p, double eps_B, double sigma_tilde,
                        double *filter_host, int64_t count) {
-  return nfl_compute_filter_ex(NFL_KERNEL_GAUSSIAN, d, N, m, p, eps_B, sigma_tilde, filter_host,
-                               count);
+  return nfl_compute_filter_ex(NFL_KERNEL_GAUSSIAN, d, N, m, p, eps_B, sigma_tilde, 0.0,
+                               filter_host, count);
 }
 
 int nfl_compute_filter_ex(int kind, int d, int N, int m, int p, double eps_B, double sigma_tilde,
-                          double *filter_host, int64_t count) {
+                          double eps_I, double *filter_host, int64_t count) {
   if (!filter_host) { set_error("null output"); return NFL_ERR_ARG; }
-  if (kind < NFL_KERNEL_GAUSSIAN || kind > NFL_KERNEL_INVERSE_MULTIQUADRIC) { set_error("unknown kernel kind"); return NFL_ERR_ARG; }
+  if (kind < NFL_KERNEL_GAUSSIAN || kind > NFL_KERNEL_LAPLACIAN_RBF) { set_error("unknown kernel kind"); return NFL_ERR_ARG; }
+  if (kind == NFL_KERNEL_LAPLACIAN_RBF && !(eps_I > 0 && eps_I + eps_B < 0.5)) { set_error("need 0 < eps_I, eps_I + eps_B < 1/2"); return NFL_ERR_ARG; }
   if (d < 1 || d > 3 || N < 2 || (N & 1) || !is_pow2(N) || m < 1 || p < 1 ||
       !(eps_B >= 0 && eps_B < 0.5) || !(sigma_tilde > 0)) {
     set_error("bad filter arguments");
     return NFL_ERR_ARG;
   }
   std::vector<double> f;
-  NFL_TRY(compute_filter(d, N, m, p, eps_B, sigma_tilde, f, kind));
+  NFL_TRY(compute_filter(d, N, m, p, eps_B, sigma_tilde, f, kind, eps_I));
   if (count < (int64_t)f.size()) { set_error("filter buffer too small"); return NFL_ERR_ARG; }
   std::memcpy(filter_host, f.data(), f.size() * sizeof(double));
   return NFL_OK;

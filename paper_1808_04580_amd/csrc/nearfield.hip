@@ -1,0 +1,178 @@
+// Near-field correction of the fast summation for the Laplacian RBF kernel
+// exp(-r / sigma) (eq. W_laplacian_rbf).  The kernel is not smooth at 0, so the
+// regularised kernel K_R is the even polynomial T_I on r <= eps_I (the
+// near-origin regularisation of the fast summation); the trigonometric sum then
+// misses sum_{||v~_i - v~_j|| <= eps_I} x~_j (K - T_I)(||v~_i - v~_j||) for every
+// node i (the node itself included), which this kernel adds directly.
+//
+// One work item (the nodes of one grid tile) per workgroup: the item's nodes
+// are the targets (one per thread), and the nodes of every tile within eps_I
+// are staged in LDS, 256 at a time, with their input values.  Distances are
+// formed in grid-cell units from exact integer cell differences plus the
+// differences of the float fractions.  Every output mode is affine in the fast
+// sum f (y = alpha x + beta f), so the correction adds beta * delta to the
+// output the interpolation already wrote; the degree pass also recomputes
+// d^{-1/2}.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "nfl_internal.h"
+#include "nfft_device.h"
+
+namespace nfl {
+
+namespace {
+
+constexpr int NT = 256;
+constexpr int NF_MAXP = 16;
+
+template <int OUT>
+__device__ __forceinline__ void add_out(const KArgs &a, int i, float d) {
+  if constexpr (OUT == OUT_USER_RAW || OUT == OUT_USER_W) {
+    a.y32[a.perm[i]] += d;
+  } else if constexpr (OUT == OUT_USER_LS) {
+    a.y32[a.perm[i]] -= a.dinv[i] * d;
+  } else if constexpr (OUT == OUT_USER_A) {
+    a.y32[a.perm[i]] += a.dinv[i] * d;
+  } else if constexpr (OUT == OUT_DEGREE) {
+    const float dg = a.deg_out[i] + d;
+    a.deg_out[i] = dg;
+    a.dinv_out[i] = dg > 0.f ? 1.0f / __builtin_sqrtf(dg) : 0.f;
+  } else if constexpr (OUT == OUT_SORTED_F64_A) {
+    a.y64[i] += (double)a.dinv[i] * (double)d;
+  } else {  // OUT_SORTED_F64_SSL
+    a.y64[i] -= a.tau * (double)a.dinv[i] * (double)d;
+  }
+}
+
+template <int IN, int OUT>
+__global__ __launch_bounds__(NT) void k_near(const Item *__restrict__ items,
+                                             const float4 *__restrict__ pts,
+                                             const int *__restrict__ tile_start, KArgs ka, int d,
+                                             int ntd, int R, float eps_cells2, float inv_nos,
+                                             float inv_sigma, float inv_eps,
+                                             const float *__restrict__ coef, int p) {
+  __shared__ int scell[NT];
+  __shared__ float sfx[NT], sfy[NT], sfz[NT], sval[NT];
+  __shared__ float cf[NF_MAXP];
+  const int t = threadIdx.x;
+  if (t < p) cf[t] = coef[t];
+  const Item it = items[blockIdx.x];
+  int tc[3] = {0, 0, 0};
+  {
+    int r = it.tile;
+    for (int a = d - 1; a >= 0; --a) {
+      tc[a] = r % ntd;
+      r /= ntd;
+    }
+  }
+  int lo[3], hi[3];
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = a < d ? max(0, tc[a] - R) : 0;
+    hi[a] = a < d ? min(ntd - 1, tc[a] + R) : 0;
+  }
+  for (int b0 = it.start; b0 < it.end; b0 += NT) {
+    const int i = b0 + t;
+    const bool act = i < it.end;
+    int tcx = 0, tcy = 0, tcz = 0;
+    float tfx = 0.f, tfy = 0.f, tfz = 0.f;
+    if (act) {
+      const float4 q = pts[i];
+      const uint32_t cell = __float_as_uint(q.w);
+      tcx = (int)(cell & 1023u);
+      tcy = (int)((cell >> 10) & 1023u);
+      tcz = (int)((cell >> 20) & 1023u);
+      tfx = q.x;
+      tfy = q.y;
+      tfz = q.z;
+    }
+    float acc = 0.f;
+    for (int ax = lo[0]; ax <= hi[0]; ++ax)
+      for (int ay = lo[1]; ay <= hi[1]; ++ay)
+        for (int az = lo[2]; az <= hi[2]; ++az) {
+          const int tile = d == 3 ? (ax * ntd + ay) * ntd + az : (d == 2 ? ax * ntd + ay : ax);
+          const int s0 = tile_start[tile], s1 = tile_start[tile + 1];
+          for (int c0 = s0; c0 < s1; c0 += NT) {
+            const int cnt = min(NT, s1 - c0);
+            __syncthreads();
+            if (t < cnt) {
+              const int j = c0 + t;
+              const float4 q = pts[j];
+              scell[t] = (int)__float_as_uint(q.w);
+              sfx[t] = q.x;
+              sfy[t] = q.y;
+              sfz[t] = q.z;
+              sval[t] = load_in<IN>(ka, j);
+            }
+            __syncthreads();
+            if (act) {
+              for (int k = 0; k < cnt; ++k) {
+                const uint32_t sc = (uint32_t)scell[k];
+                const float dx = (float)(tcx - (int)(sc & 1023u)) + (tfx - sfx[k]);
+                const float dy = d > 1 ? (float)(tcy - (int)((sc >> 10) & 1023u)) + (tfy - sfy[k]) : 0.f;
+                const float dz = d > 2 ? (float)(tcz - (int)((sc >> 20) & 1023u)) + (tfz - sfz[k]) : 0.f;
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                if (r2 <= eps_cells2) {
+                  const float r = __builtin_sqrtf(r2) * inv_nos;   // scaled coordinates
+                  const float u = r * inv_eps;
+                  const float u2 = u * u;
+                  float tp = cf[p - 1];
+                  for (int c = p - 2; c >= 0; --c) tp = fmaf(tp, u2, cf[c]);
+                  acc = fmaf(sval[k], expf(-r * inv_sigma) - tp, acc);
+                }
+              }
+            }
+          }
+        }
+    if (act) add_out<OUT>(ka, i, acc);
+  }
+}
+
+template <int IN, int OUT>
+int launch_near(nfl_plan *P, const KArgs &k) {
+  const int T = 1 << P->tshift;
+  const double eps_cells = P->eps_I * P->nos;
+  const int R = (int)std::ceil(eps_cells / T) + 1;
+  const int ntd = P->nos >> P->tshift;
+  hipLaunchKernelGGL((k_near<IN, OUT>), dim3(P->nitems), dim3(NT), 0, P->stream, P->items.p,
+                     P->pts.p, P->tile_start.p, k, P->d, ntd, R, (float)(eps_cells * eps_cells),
+                     (float)(1.0 / P->nos), (float)(1.0 / P->sigma_t), (float)(1.0 / P->eps_I),
+                     P->ti_coef.p, P->p);
+  NFL_HIP(hipGetLastError());
+  return NFL_OK;
+}
+
+}  // namespace
+
+int near_field(nfl_plan *P, int in_mode, int out_mode, const VecArgs &a) {
+  if (P->kind != NFL_KERNEL_LAPLACIAN_RBF || P->nitems == 0) return NFL_OK;
+  if (P->p > NF_MAXP) {
+    set_error("near field: p above 16 is not supported");
+    return NFL_ERR_UNSUPPORTED;
+  }
+  KArgs k;
+  k.x32 = a.x32;
+  k.y32 = a.y32;
+  k.x64 = a.x64;
+  k.y64 = a.y64;
+  k.tau = a.tau;
+  k.perm = P->perm.p;
+  k.dinv = P->dinv.p;
+  k.deg_out = P->deg.p;
+  k.dinv_out = P->dinv.p;
+  if (in_mode == IN_USER_F32 && out_mode == OUT_USER_RAW) return launch_near<IN_USER_F32, OUT_USER_RAW>(P, k);
+  if (in_mode == IN_USER_F32 && out_mode == OUT_USER_W) return launch_near<IN_USER_F32, OUT_USER_W>(P, k);
+  if (in_mode == IN_USER_F32_DINV && out_mode == OUT_USER_LS) return launch_near<IN_USER_F32_DINV, OUT_USER_LS>(P, k);
+  if (in_mode == IN_USER_F32_DINV && out_mode == OUT_USER_A) return launch_near<IN_USER_F32_DINV, OUT_USER_A>(P, k);
+  if (in_mode == IN_ONES && out_mode == OUT_DEGREE) return launch_near<IN_ONES, OUT_DEGREE>(P, k);
+  if (in_mode == IN_SORTED_F64_DINV && out_mode == OUT_SORTED_F64_A)
+    return launch_near<IN_SORTED_F64_DINV, OUT_SORTED_F64_A>(P, k);
+  if (in_mode == IN_SORTED_F64_DINV && out_mode == OUT_SORTED_F64_SSL)
+    return launch_near<IN_SORTED_F64_DINV, OUT_SORTED_F64_SSL>(P, k);
+  set_error("near field: this pair of input and output modes is not supported");
+  return NFL_ERR_UNSUPPORTED;
+}
+
+}  // namespace nfl

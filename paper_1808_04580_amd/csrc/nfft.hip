@@ -740,6 +740,7 @@ int fastsum(nfl_plan *P, int in_mode, int out_mode, const VecArgs &a) {
   P->grid_clean = true;
   if (P->prof_ev) NFL_HIP(hipEventRecord(P->prof_ev[3], P->stream));
   NFL_TRY(interp(P, P->grid2.p, in_mode, out_mode, a));
+  NFL_TRY(near_field(P, in_mode, out_mode, a));   // Laplacian RBF kernel only
   if (P->prof_ev) NFL_HIP(hipEventRecord(P->prof_ev[4], P->stream));
   return NFL_OK;
 }

@@ -115,6 +115,11 @@ struct nfl_plan {
   // degrees come out divided by wscale = K(0) (L_s and A do not change)
   int kind = NFL_KERNEL_GAUSSIAN;
   double wscale = 1.0;
+  double eps_I = 0.0;           // inner regularisation radius (Laplacian RBF kernel), scaled coordinates
+  double opt_eps_I = 0.0;       // 0: p/N
+  nfl::DBuf<float> ti_coef;     // T_I(r) = sum_k c_k (r / eps_I)^(2k), k < p
+  nfl::DBuf<int> tile_start;    // sorted-node offset of each grid tile, ntiles + 1 entries
+  int64_t ntiles = 0;
   double sigma = 0, eps_B = 0, rho = 1, sigma_t = 0;
   int N = 0, m = 0, p = 0, nos = 0, tshift = 3;
   bool have_kernel = false;
@@ -206,6 +211,12 @@ int interp(nfl_plan *P, const float *grid, int in_mode, int out_mode, const VecA
 // whole fast summation with the given input/output modes (grid = plan grid)
 int fastsum(nfl_plan *P, int in_mode, int out_mode, const VecArgs &a);
 int fill_f32(float *p, int64_t n, float v, hipStream_t s);
+// Near-field correction of the Laplacian RBF kernel (nearfield.hip): adds the
+// contribution of sum_{||v~_i - v~_j|| <= eps_I} x~_j (K - T_I)(v~_i - v~_j) to
+// the output of the given mode, as the post-operation would have done.
+int near_field(nfl_plan *P, int in_mode, int out_mode, const VecArgs &a);
+// Monomial coefficients of the inner polynomial T_I in (r / eps_I)^2 (setup.hip).
+int inner_poly(double sigma_t, double eps_I, int p, std::vector<double> &c);
 int scatter_f32(nfl_plan *P, const float *src_sorted, float *dst_user);
 
 // ---- Krylov (krylov.hip) -------------------------------------------------------

@@ -453,6 +453,21 @@ int build_sorted_nodes(nfl_plan *P) {
   for (Item &it : items) it.pad = 0;
   P->nitems = (int)items.size();
   P->max_item_len = maxlen;
+  // sorted-node offset of every tile (the near-field sum walks neighbour tiles)
+  {
+    std::vector<int> ts((size_t)ntiles + 1);
+    int64_t acc = 0;
+    for (int64_t t = 0; t < ntiles; ++t) {
+      ts[(size_t)t] = (int)acc;
+      acc += hc[(size_t)t];
+    }
+    ts[(size_t)ntiles] = (int)acc;
+    P->ntiles = ntiles;
+    NFL_TRY(P->tile_start.ensure(ts.size()));
+    NFL_HIP(hipMemcpyAsync(P->tile_start.p, ts.data(), ts.size() * sizeof(int),
+                           hipMemcpyHostToDevice, P->stream));
+    NFL_HIP(hipStreamSynchronize(P->stream));
+  }
   NFL_TRY(P->items.ensure(items.size()));
   NFL_HIP(hipMemcpyAsync(P->items.p, items.data(), items.size() * sizeof(Item),
                          hipMemcpyHostToDevice, P->stream));
@@ -651,10 +666,63 @@ int window_coefficients(int m, std::vector<float> &coef) {
   return NFL_OK;
 }
 
+// Radial derivatives of exp(-r/s): (-1/s)^k exp(-r/s), k < p.
+static void laplace_derivs(double r, double s, int p, double *out) {
+  double f = std::exp(-r / s);
+  for (int k = 0; k < p; ++k) {
+    out[k] = f;
+    f *= -1.0 / s;
+  }
+}
+
+// The inner polynomial T_I of the Laplacian RBF kernel exp(-r/s): the
+// two-point Taylor interpolant on [-eps_I, eps_I] of the even extension of the
+// kernel (p conditions at each end), which is even of degree <= 2p - 2; its
+// coefficients c_k in (r / eps_I)^(2k), k < p, by interpolation at p points
+// in (0, 1] (exact for such a polynomial up to rounding).
+int inner_poly(double s, double eps_I, int p, std::vector<double> &c) {
+  if (!(eps_I > 0) || p < 1 || p > 16) return NFL_ERR_ARG;
+  std::vector<double> fb(p), fa(p);
+  laplace_derivs(eps_I, s, p, fb.data());
+  for (int k = 0; k < p; ++k) fa[k] = (k & 1) ? -fb[k] : fb[k];
+  std::vector<double> A((size_t)p * p), rhs(p);
+  for (int i = 0; i < p; ++i) {
+    const double u = std::cos(M_PI * (i + 0.5) / (2 * p));   // u = r / eps_I in (0, 1)
+    rhs[i] = two_point_taylor(u * eps_I, -eps_I, eps_I, fa.data(), fb.data(), p);
+    double w = 1.0;
+    for (int k = 0; k < p; ++k) {
+      A[(size_t)i * p + k] = w;
+      w *= u * u;
+    }
+  }
+  // Gaussian elimination with partial pivoting
+  for (int col = 0; col < p; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < p; ++r)
+      if (std::fabs(A[(size_t)r * p + col]) > std::fabs(A[(size_t)piv * p + col])) piv = r;
+    if (A[(size_t)piv * p + col] == 0.0) return NFL_ERR_ARG;
+    for (int k = 0; k < p; ++k) std::swap(A[(size_t)col * p + k], A[(size_t)piv * p + k]);
+    std::swap(rhs[col], rhs[piv]);
+    for (int r = col + 1; r < p; ++r) {
+      const double f = A[(size_t)r * p + col] / A[(size_t)col * p + col];
+      for (int k = col; k < p; ++k) A[(size_t)r * p + k] -= f * A[(size_t)col * p + k];
+      rhs[r] -= f * rhs[col];
+    }
+  }
+  c.assign(p, 0.0);
+  for (int r = p - 1; r >= 0; --r) {
+    double t = rhs[r];
+    for (int k = r + 1; k < p; ++k) t -= A[(size_t)r * p + k] * c[k];
+    c[r] = t / A[(size_t)r * p + r];
+  }
+  return NFL_OK;
+}
+
 int compute_filter(int d, int N, int m, int p, double eps_B, double sigma_t,
-                   std::vector<double> &out, int kind) {
+                   std::vector<double> &out, int kind, double eps_I) {
   if (d < 1 || d > 3 || N < 2 || (N & 1) || m < 1 || p < 1 || 2 * m > WIN_MAXW) return NFL_ERR_ARG;
-  if (kind < NFL_KERNEL_GAUSSIAN || kind > NFL_KERNEL_INVERSE_MULTIQUADRIC) return NFL_ERR_ARG;
+  if (kind < NFL_KERNEL_GAUSSIAN || kind > NFL_KERNEL_LAPLACIAN_RBF) return NFL_ERR_ARG;
+  if (kind == NFL_KERNEL_LAPLACIAN_RBF && !(eps_I > 0 && eps_I + eps_B < 0.5)) return NFL_ERR_ARG;
   const int nos = 2 * N;
   std::vector<float> wcoef;
   window_poly(m, M_PI * (2.0 - 0.5), wcoef);
@@ -665,16 +733,27 @@ int compute_filter(int d, int N, int m, int p, double eps_B, double sigma_t,
   const double alpha = kind == NFL_KERNEL_MULTIQUADRIC ? 0.5 : -0.5;
   auto Kn = [&](double r) -> double {
     if (kind == NFL_KERNEL_GAUSSIAN) return std::exp(-(r * r) / (sigma_t * sigma_t));
+    if (kind == NFL_KERNEL_LAPLACIAN_RBF) return std::exp(-r / sigma_t);
     return std::pow(1.0 + (r * r) / (sigma_t * sigma_t), alpha);
   };
   std::vector<double> fa(p), fb(p, 0.0);
   if (kind == NFL_KERNEL_GAUSSIAN)
     gauss_derivs(r0, sigma_t, p, fa.data());
+  else if (kind == NFL_KERNEL_LAPLACIAN_RBF)
+    laplace_derivs(r0, sigma_t, p, fa.data());
   else
     power_derivs(r0, sigma_t, alpha, p, fa.data());
   fb[0] = Kn(0.5);
   const double k_half = fb[0];
+  // inner region (Laplacian RBF kernel): T_I on r <= eps_I
+  std::vector<double> ia(p), ib(p);
+  if (kind == NFL_KERNEL_LAPLACIAN_RBF) {
+    laplace_derivs(eps_I, sigma_t, p, ib.data());
+    for (int k = 0; k < p; ++k) ia[k] = (k & 1) ? -ib[k] : ib[k];
+  }
   auto KR = [&](double r) -> double {
+    if (kind == NFL_KERNEL_LAPLACIAN_RBF && r <= eps_I)
+      return two_point_taylor(r, -eps_I, eps_I, ia.data(), ib.data(), p);
     if (r <= r0) return Kn(r);
     if (eps_B <= 0.0) return k_half;  // no transition region
     if (r <= 0.5) return two_point_taylor(r, r0, 0.5, fa.data(), fb.data(), p);
@@ -738,7 +817,8 @@ int compute_filter(int d, int N, int m, int p, double eps_B, double sigma_t,
 }
 
 int build_filter_host(nfl_plan *P) {
-  return compute_filter(P->d, P->N, P->m, P->p, P->eps_B, P->sigma_t, P->filt_host, P->kind);
+  return compute_filter(P->d, P->N, P->m, P->p, P->eps_B, P->sigma_t, P->filt_host, P->kind,
+                        P->eps_I);
 }
 
 }  // namespace nfl

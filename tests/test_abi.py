@@ -144,7 +144,8 @@ def test_filter_equals_coefficients_over_window_transform(d, N, m, eps):
 
 
 @pytest.mark.parametrize("kind,d,N,m,eps", [("multiquadric", 2, 16, 4, 0.125),
-                                            ("inverse_multiquadric", 3, 8, 3, 0.25)])
+                                            ("inverse_multiquadric", 3, 8, 3, 0.25),
+                                            ("laplacian_rbf", 2, 16, 4, 0.125)])
 def test_filter_other_kernels_equals_coefficients_over_window_transform(kind, d, N, m, eps):
     """The library's host filter for the other kernels (derivatives by a
     power-series recurrence) against the oracle's coefficients (derivatives
@@ -152,9 +153,10 @@ def test_filter_other_kernels_equals_coefficients_over_window_transform(kind, d,
     transform, at the interior frequencies."""
     c = 0.12
     p = m
-    F = nfl.compute_filter(d, N, m, p, eps, c, kind=kind)
+    eps_I = p / N if kind == "laplacian_rbf" else 0.0    # inner regularisation (Laplacian RBF)
+    F = nfl.compute_filter(d, N, m, p, eps, c, kind=kind, eps_I=eps_I)
     K0 = float(fastsum.radial_kernel(kind, c)(0.0))
-    b = fastsum.coefficients(c, N, d, eps, p, kind) / K0
+    b = fastsum.coefficients(c, N, d, eps, p, kind, eps_I) / K0
     nos = 2 * N
     coef = nfl.window_coefficients(m)
     wh = np.array([poly_window_hat(coef, m, l / nos) for l in range(-N // 2, N // 2 + 1)])

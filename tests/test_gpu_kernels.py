@@ -83,3 +83,52 @@ def test_other_kernels_lanczos(nfl, kind, c):
     tol = fastsum.lemma_bound(eps, eta) + 1e-5
     assert tol < 1e-2
     np.testing.assert_allclose(r["evals"], ref, atol=tol)
+
+
+LAPLACE_CASES = [
+    # d, n, sigma, N, m, eps_B
+    (3, 1500, 0.05, 64, 6, 1 / 8),
+    (2, 2000, 0.04, 64, 5, 1 / 8),
+]
+
+
+@pytest.mark.parametrize("d,n,s,N,m,eps_B", LAPLACE_CASES)
+def test_laplacian_rbf_with_near_field(nfl, d, n, s, N, m, eps_B):
+    """Laplacian RBF kernel (eq. W_laplacian_rbf): the regularised kernel's
+    products plus the near-field sum on r <= eps_I = p/N.  Against the oracle's
+    exact trigonometric operator of the same regularised kernel plus its dense
+    near-field sum (1e-5: window, FFT and FP32 error), and against the direct
+    sums within ||x||_1 max|K_R - K_RF|."""
+    import torch
+    v = synth.gmm(n, d=d, k=4, seed=40 + d)
+    x = synth.normal_vectors(n, seed=6)
+    eps_I = m / N
+    T = fastsum.TrigGraph(v, s, N, eps_B, m, "laplacian_rbf", eps_I=eps_I)
+    P = nfl.plan(torch.as_tensor(v, device="cuda"), s, N=N, m=m, eps_B=eps_B,
+                 kind="laplacian_rbf")
+    xd = torch.as_tensor(x, device="cuda")
+    dg = P.degree().cpu().numpy().astype(np.float64)
+    Wx = P.apply_W(xd).cpu().numpy().astype(np.float64)
+    Lx = P.apply_Ls(xd).cpu().numpy().astype(np.float64)
+    r = P.lanczos_smallest(4, tol=1e-7, maxit=200)
+    with pytest.raises(nfl.NFLError):               # no near field between two node sets
+        P.evaluate(xd, nfl.target_plan(torch.as_tensor(v[:10], device="cuda"), P))
+    P.close()
+    x64 = x.astype(np.float64)
+    assert _rel(dg, T.d) <= 1e-5
+    assert _rel(Wx, T.apply_W(x64)) <= 1e-5
+    assert _rel(Lx, T.apply_Ls(x64)) <= 1e-5
+    W = graph.dense_W(v, s, "laplacian_rbf")
+    rng = np.random.default_rng(0)
+    g = rng.normal(size=(20000, d))
+    g /= np.linalg.norm(g, axis=1, keepdims=True)
+    rr = (0.5 - eps_B) * rng.uniform(0.0, 1.0, size=20000) ** (1.0 / d)
+    kerr = np.abs(T.reg(rr) - fastsum.K_RF(g * rr[:, None], T.bhat, N).real).max()
+    assert np.abs(Wx - W @ x64).max() <= 2.0 * kerr * np.abs(x64).sum() + 1e-5 * np.abs(W @ x64).max()
+    assert r["converged"]
+    if d < 3:      # the Lemma bound is too loose at this N to say anything in 2-D
+        return
+    ref = np.linalg.eigvalsh(graph.dense_Ls(v, s, "laplacian_rbf"))[:4]
+    Wn = W.sum(axis=1).max()
+    tol = fastsum.lemma_bound(2.0 * kerr * n / Wn, W.sum(axis=1).min() / Wn) + 1e-5
+    np.testing.assert_allclose(r["evals"], ref, atol=tol)
