@@ -262,6 +262,36 @@ def kernels_leg(nfl, synth, torch, dev, v, x, lab, reps=50, rows=64):
         log("kernel %s: %.4f ms per L_s product, rel err of W x on %d rows %.2e" % (
             kind, ms, rows, out[kind]["rel_err_Wx_rows"]))
     out["config"] = "n=1,000,000 (benchmark cloud), c=0.05, N=64, m=6, eps_B=1/8"
+    # Laplacian RBF kernel (eq. W_laplacian_rbf) at the paper's size: n = 1e5
+    # points of the benchmark kind, sigma = 0.05, near field on r <= eps_I = p/N
+    vl, _ = synth.moons_and_roll(100_000, seed=3)
+    xl = synth.normal_vectors(100_000, seed=4)
+    xld = torch.as_tensor(xl, device=dev)
+    yld = torch.empty_like(xld)
+    sel_l = np.sort(np.random.default_rng(8).choice(100_000, size=rows, replace=False))
+    vl64, xl64 = vl.astype(np.float64), xl.astype(np.float64)
+    ref_l = np.empty(rows)
+    for q, r in enumerate(sel_l):
+        k = np.exp(-np.sqrt(((vl64 - vl64[r]) ** 2).sum(axis=1)) / 0.05)
+        k[r] = 0.0
+        ref_l[q] = k @ xl64
+    for N in (64, 128):
+        P = nfl.plan(torch.as_tensor(vl, device=dev), 0.05, N=N, m=6, eps_B=0.125,
+                     kind="laplacian_rbf")
+        for _ in range(3):
+            P.apply_Ls(xld, out=yld)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(10):
+            P.apply_Ls(xld, out=yld)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 100.0
+        Wx = P.apply_W(xld).cpu().numpy().astype(np.float64)[sel_l]
+        P.close()
+        key = "laplacian_rbf_n1e5_N%d" % N
+        out[key] = {"ms_per_Ls": round(ms, 3), "eps_I": 6.0 / N,
+                    "rel_err_Wx_rows": float(np.abs(Wx - ref_l).max() / np.abs(ref_l).max())}
+        log("kernel laplacian_rbf N=%d: %s" % (N, out[key]))
     return out
 
 

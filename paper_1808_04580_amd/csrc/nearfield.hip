@@ -27,6 +27,7 @@ namespace {
 
 constexpr int NT = 256;
 constexpr int NF_MAXP = 16;
+constexpr int NF_MAXTILES = 1024;   // neighbour tiles per item, (2R + 1)^d
 
 template <int OUT>
 __device__ __forceinline__ void add_out(const KArgs &a, int i, float d) {
@@ -51,12 +52,13 @@ template <int IN, int OUT>
 __global__ __launch_bounds__(NT) void k_near(const Item *__restrict__ items,
                                              const float4 *__restrict__ pts,
                                              const int *__restrict__ tile_start, KArgs ka, int d,
-                                             int ntd, int R, float eps_cells2, float inv_nos,
+                                             int ntd, int tsize, int R, float eps_cells2, float inv_nos,
                                              float inv_sigma, float inv_eps,
                                              const float *__restrict__ coef, int p) {
   __shared__ int scell[NT];
   __shared__ float sfx[NT], sfy[NT], sfz[NT], sval[NT];
   __shared__ float cf[NF_MAXP];
+  __shared__ int ns0[NF_MAXTILES], ns1[NF_MAXTILES];   // node ranges of the neighbour tiles
   const int t = threadIdx.x;
   if (t < p) cf[t] = coef[t];
   const Item it = items[blockIdx.x];
@@ -68,11 +70,36 @@ __global__ __launch_bounds__(NT) void k_near(const Item *__restrict__ items,
       r /= ntd;
     }
   }
-  int lo[3], hi[3];
-  for (int a = 0; a < 3; ++a) {
-    lo[a] = a < d ? max(0, tc[a] - R) : 0;
-    hi[a] = a < d ? min(ntd - 1, tc[a] + R) : 0;
+  // neighbour tiles: the (2R + 1)^d cube around the item's tile, without the
+  // tiles whose nearest cell is farther than eps_I from the item's tile and
+  // those outside the grid; their node ranges are read once, in parallel
+  const int side = 2 * R + 1;
+  const int nnb = d == 3 ? side * side * side : (d == 2 ? side * side : side);
+  for (int q = t; q < nnb; q += NT) {
+    int o[3] = {0, 0, 0};
+    int r = q;
+    for (int a = d - 1; a >= 0; --a) {
+      o[a] = r % side - R;
+      r /= side;
+    }
+    int tt[3], gap2 = 0;
+    bool in = true;
+    for (int a = 0; a < 3; ++a) {
+      tt[a] = tc[a] + o[a];
+      if (a < d && (tt[a] < 0 || tt[a] >= ntd)) in = false;
+      const int g = max(0, abs(o[a]) - 1) * tsize;
+      gap2 += g * g;
+    }
+    int a0 = 0, a1 = 0;
+    if (in && (float)gap2 <= eps_cells2) {
+      const int tile = d == 3 ? (tt[0] * ntd + tt[1]) * ntd + tt[2] : (d == 2 ? tt[0] * ntd + tt[1] : tt[0]);
+      a0 = tile_start[tile];
+      a1 = tile_start[tile + 1];
+    }
+    ns0[q] = a0;
+    ns1[q] = a1;
   }
+  __syncthreads();
   for (int b0 = it.start; b0 < it.end; b0 += NT) {
     const int i = b0 + t;
     const bool act = i < it.end;
@@ -89,43 +116,40 @@ __global__ __launch_bounds__(NT) void k_near(const Item *__restrict__ items,
       tfz = q.z;
     }
     float acc = 0.f;
-    for (int ax = lo[0]; ax <= hi[0]; ++ax)
-      for (int ay = lo[1]; ay <= hi[1]; ++ay)
-        for (int az = lo[2]; az <= hi[2]; ++az) {
-          const int tile = d == 3 ? (ax * ntd + ay) * ntd + az : (d == 2 ? ax * ntd + ay : ax);
-          const int s0 = tile_start[tile], s1 = tile_start[tile + 1];
-          for (int c0 = s0; c0 < s1; c0 += NT) {
-            const int cnt = min(NT, s1 - c0);
-            __syncthreads();
-            if (t < cnt) {
-              const int j = c0 + t;
-              const float4 q = pts[j];
-              scell[t] = (int)__float_as_uint(q.w);
-              sfx[t] = q.x;
-              sfy[t] = q.y;
-              sfz[t] = q.z;
-              sval[t] = load_in<IN>(ka, j);
-            }
-            __syncthreads();
-            if (act) {
-              for (int k = 0; k < cnt; ++k) {
-                const uint32_t sc = (uint32_t)scell[k];
-                const float dx = (float)(tcx - (int)(sc & 1023u)) + (tfx - sfx[k]);
-                const float dy = d > 1 ? (float)(tcy - (int)((sc >> 10) & 1023u)) + (tfy - sfy[k]) : 0.f;
-                const float dz = d > 2 ? (float)(tcz - (int)((sc >> 20) & 1023u)) + (tfz - sfz[k]) : 0.f;
-                const float r2 = dx * dx + dy * dy + dz * dz;
-                if (r2 <= eps_cells2) {
-                  const float r = __builtin_sqrtf(r2) * inv_nos;   // scaled coordinates
-                  const float u = r * inv_eps;
-                  const float u2 = u * u;
-                  float tp = cf[p - 1];
-                  for (int c = p - 2; c >= 0; --c) tp = fmaf(tp, u2, cf[c]);
-                  acc = fmaf(sval[k], expf(-r * inv_sigma) - tp, acc);
-                }
-              }
+    for (int q = 0; q < nnb; ++q) {
+      const int s0 = ns0[q], s1 = ns1[q];
+      for (int c0 = s0; c0 < s1; c0 += NT) {
+        const int cnt = min(NT, s1 - c0);
+        __syncthreads();
+        if (t < cnt) {
+          const int j = c0 + t;
+          const float4 q = pts[j];
+          scell[t] = (int)__float_as_uint(q.w);
+          sfx[t] = q.x;
+          sfy[t] = q.y;
+          sfz[t] = q.z;
+          sval[t] = load_in<IN>(ka, j);
+        }
+        __syncthreads();
+        if (act) {
+          for (int k = 0; k < cnt; ++k) {
+            const uint32_t sc = (uint32_t)scell[k];
+            const float dx = (float)(tcx - (int)(sc & 1023u)) + (tfx - sfx[k]);
+            const float dy = d > 1 ? (float)(tcy - (int)((sc >> 10) & 1023u)) + (tfy - sfy[k]) : 0.f;
+            const float dz = d > 2 ? (float)(tcz - (int)((sc >> 20) & 1023u)) + (tfz - sfz[k]) : 0.f;
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 <= eps_cells2) {
+              const float r = __builtin_sqrtf(r2) * inv_nos;   // scaled coordinates
+              const float u = r * inv_eps;
+              const float u2 = u * u;
+              float tp = cf[p - 1];
+              for (int c = p - 2; c >= 0; --c) tp = fmaf(tp, u2, cf[c]);
+              acc = fmaf(sval[k], expf(-r * inv_sigma) - tp, acc);
             }
           }
         }
+      }
+    }
     if (act) add_out<OUT>(ka, i, acc);
   }
 }
@@ -134,10 +158,18 @@ template <int IN, int OUT>
 int launch_near(nfl_plan *P, const KArgs &k) {
   const int T = 1 << P->tshift;
   const double eps_cells = P->eps_I * P->nos;
-  const int R = (int)std::ceil(eps_cells / T) + 1;
+  // a source within eps_I of a node of tile tc lies in a tile at most
+  // ceil(eps_I / T) tiles away along every axis
+  const int R = (int)std::ceil(eps_cells / T);
+  int nnb = 1;
+  for (int a = 0; a < P->d; ++a) nnb *= 2 * R + 1;
+  if (nnb > NF_MAXTILES) {
+    set_error("near field: eps_I spans too many tiles (raise the tile size or lower eps_I)");
+    return NFL_ERR_UNSUPPORTED;
+  }
   const int ntd = P->nos >> P->tshift;
   hipLaunchKernelGGL((k_near<IN, OUT>), dim3(P->nitems), dim3(NT), 0, P->stream, P->items.p,
-                     P->pts.p, P->tile_start.p, k, P->d, ntd, R, (float)(eps_cells * eps_cells),
+                     P->pts.p, P->tile_start.p, k, P->d, ntd, T, R, (float)(eps_cells * eps_cells),
                      (float)(1.0 / P->nos), (float)(1.0 / P->sigma_t), (float)(1.0 / P->eps_I),
                      P->ti_coef.p, P->p);
   NFL_HIP(hipGetLastError());
