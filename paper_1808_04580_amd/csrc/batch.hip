@@ -93,8 +93,9 @@ void kb_interp(const BItem *__restrict__ list, const BJob *__restrict__ jobs,
                                                           J.nos, J.tshift, J.wcoef);
 }
 
+// the tile-stationary kernels run three waves per SIMD, as the single-plan ones
 template <int W, int T, int NW>
-__global__ __launch_bounds__(64 * NW) void kb_spread_tile(const BItem *__restrict__ list,
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) void kb_spread_tile(const BItem *__restrict__ list,
                                                           const BJob *__restrict__ jobs,
                                                           const BIO *__restrict__ io) {
   const BItem b = list[blockIdx.x];
@@ -108,7 +109,7 @@ __global__ __launch_bounds__(64 * NW) void kb_spread_tile(const BItem *__restric
 }
 
 template <int W, int T, int NW>
-__global__ __launch_bounds__(64 * NW) void kb_interp_tile(const BItem *__restrict__ list,
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) void kb_interp_tile(const BItem *__restrict__ list,
                                                           const BJob *__restrict__ jobs,
                                                           const BIO *__restrict__ io) {
   const BItem b = list[blockIdx.x];

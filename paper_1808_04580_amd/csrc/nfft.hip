@@ -242,20 +242,20 @@ void k_interp3_mfma(const Item *__restrict__ items,
   interp3_mfma_body<W, IN, OUT>(items, blockIdx.x, pts, ka, grid, nos, tshift, wcoef);
 }
 
-// Tile-stationary forms (T + W - 1 <= 16), one workgroup per item.
+// Tile-stationary forms (T + W - 1 <= 16), one workgroup per item.  Both run
+// three waves per SIMD: within the register budget that allows (168 per lane)
+// they keep their accumulators in VGPRs, without spills.
 template <int W, int T, int IN>
-__global__ __launch_bounds__(256) void k_spread3_tile(const Item *__restrict__ items,
-                                                      const float4 *__restrict__ pts, KArgs ka,
-                                                      float *__restrict__ grid, int nos,
-                                                      const float *__restrict__ wcoef) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+void k_spread3_tile(const Item *__restrict__ items, const float4 *__restrict__ pts, KArgs ka,
+                    float *__restrict__ grid, int nos, const float *__restrict__ wcoef) {
   spread3_tile_body<W, T, IN>(items[blockIdx.x], pts, ka, grid, nos, wcoef);
 }
 
 template <int W, int T, int IN, int OUT>
-__global__ __launch_bounds__(256) void k_interp3_tile(const Item *__restrict__ items,
-                                                      const float4 *__restrict__ pts, KArgs ka,
-                                                      const float *__restrict__ grid, int nos,
-                                                      const float *__restrict__ wcoef) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+void k_interp3_tile(const Item *__restrict__ items, const float4 *__restrict__ pts, KArgs ka,
+                    const float *__restrict__ grid, int nos, const float *__restrict__ wcoef) {
   interp3_tile_body<W, T, IN, OUT>(items, blockIdx.x, pts, ka, grid, nos, wcoef);
 }
 

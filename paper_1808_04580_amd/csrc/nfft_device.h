@@ -87,6 +87,85 @@ __device__ __forceinline__ void store_out(const KArgs &a, int i, float f) {
   }
 }
 
+// Output-side operands of one node (permutation entry, caller-order input,
+// d^{-1/2}), loaded ahead of the node's store: the caller-order input is a
+// gather behind the permutation, two dependent loads that would otherwise
+// stall the wave right after its matrix-core work.  store_pre computes what
+// store_out computes, from these values.
+struct OutPre {
+  int j;
+  float xu, di;
+  double xd;
+};
+
+template <int OUT>
+constexpr bool pre_user() {
+  return OUT == OUT_USER_RAW || OUT == OUT_USER_W || OUT == OUT_USER_LS || OUT == OUT_USER_A;
+}
+
+template <int OUT>
+__device__ __forceinline__ void pre_index(const KArgs &a, int i, bool ok, OutPre &p) {
+  p.j = 0;
+  p.xu = 0.f;
+  p.di = 0.f;
+  p.xd = 0.0;
+  if (!ok) return;
+  if constexpr (pre_user<OUT>()) p.j = a.perm[i];
+  if constexpr (OUT == OUT_USER_LS || OUT == OUT_USER_A || OUT == OUT_SORTED_F64_A ||
+                OUT == OUT_SORTED_F64_SSL)
+    p.di = a.dinv[i];
+  if constexpr (OUT == OUT_SORTED_F64_A || OUT == OUT_SORTED_F64_SSL) p.xd = a.x64[i];
+}
+
+template <int OUT>
+__device__ __forceinline__ void pre_gather(const KArgs &a, bool ok, OutPre &p) {
+  if constexpr (OUT == OUT_USER_W || OUT == OUT_USER_LS || OUT == OUT_USER_A) {
+    if (ok) p.xu = a.x32[p.j];
+  }
+}
+
+// the operands of lane src's node
+template <int OUT>
+__device__ __forceinline__ OutPre pre_from(const OutPre &p, int src) {
+  OutPre q = p;
+  if constexpr (pre_user<OUT>()) q.j = __shfl(p.j, src);
+  if constexpr (OUT == OUT_USER_W || OUT == OUT_USER_LS || OUT == OUT_USER_A) q.xu = __shfl(p.xu, src);
+  if constexpr (OUT == OUT_USER_LS || OUT == OUT_USER_A || OUT == OUT_SORTED_F64_A ||
+                OUT == OUT_SORTED_F64_SSL)
+    q.di = __shfl(p.di, src);
+  if constexpr (OUT == OUT_SORTED_F64_A || OUT == OUT_SORTED_F64_SSL) q.xd = __shfl(p.xd, src);
+  return q;
+}
+
+template <int OUT>
+__device__ __forceinline__ void store_pre(const KArgs &a, int i, float f, const OutPre &p) {
+  if constexpr (OUT == OUT_USER_RAW) {
+    a.y32[p.j] = f;
+  } else if constexpr (OUT == OUT_USER_W) {
+    a.y32[p.j] = f - p.xu;
+  } else if constexpr (OUT == OUT_USER_LS) {
+    const float xt = p.di * p.xu;
+    a.y32[p.j] = p.xu - p.di * (f - xt);
+  } else if constexpr (OUT == OUT_USER_A) {
+    const float xt = p.di * p.xu;
+    a.y32[p.j] = p.di * (f - xt);
+  } else if constexpr (OUT == OUT_DEGREE) {
+    const float dg = f - 1.0f;
+    a.deg_out[i] = dg;
+    a.dinv_out[i] = dg > 0.f ? 1.0f / __builtin_sqrtf(dg) : 0.f;
+  } else if constexpr (OUT == OUT_SORTED_F64_A) {
+    const double di = (double)p.di;
+    const float xt = (float)(di * p.xd);
+    a.y64[i] = di * ((double)f - (double)xt);
+  } else {
+    const double di = (double)p.di;
+    const double xv = p.xd;
+    const float xt = (float)(di * xv);
+    const double av = di * ((double)f - (double)xt);
+    a.y64[i] = xv + a.tau * (xv - av);
+  }
+}
+
 __device__ __forceinline__ float readlane_f(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
@@ -509,7 +588,6 @@ __device__ __forceinline__ void fill_shifted(const float4 &qb, float xb, int sub
 #pragma unroll
       for (int z = 0; z < T; z += 4)
         *reinterpret_cast<float4 *>(row + 32 * a + z) = make_float4(0.f, 0.f, 0.f, 0.f);
-    row[96] = __int_as_float(ly);   // the node's y-window is padded y in [ly, ly + W)
   }
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
@@ -560,15 +638,15 @@ __device__ __forceinline__ void spread3_tile_body(const Item it, const float4 *_
       fill_shifted<T, true, TS_PITCH>(qb, xb, sb, cnt, lane, cf, wt, ox, oy, oz);
       wave_sync_lds();
       // steps of 4 nodes; the operands of step st + 1 are loaded while the
-      // matrix instructions of step st issue
+      // matrix instructions of step st issue.  Every y-slice is issued: slices
+      // outside the 4 nodes' windows add zero products, and skipping them
+      // behind per-slice branches measured slower than the straight-line loop.
       const int nst = (cnt + 3) >> 2;
       float a, wz, wy[16];
-      int ly;
-      auto load_step = [&](int st, float &a_, float &wz_, float (&wy_)[16], int &ly_) {
+      auto load_step = [&](int st, float &a_, float &wz_, float (&wy_)[16]) {
         const float *w = wt + (4 * st + p4) * TS_PITCH;
         a_ = w[c16];
         wz_ = w[64 + c16];
-        ly_ = __float_as_int(w[96]);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const float4 v = *reinterpret_cast<const float4 *>(w + 32 + 4 * q);
@@ -578,22 +656,15 @@ __device__ __forceinline__ void spread3_tile_body(const Item it, const float4 *_
           wy_[4 * q + 3] = v.w;
         }
       };
-      load_step(0, a, wz, wy, ly);
+      load_step(0, a, wz, wy);
       for (int st = 0; st < nst; ++st) {
         float an = 0.f, wzn = 0.f, wyn[16];
-        int lyn = 0;
-        if (st + 1 < nst) load_step(st + 1, an, wzn, wyn, lyn);
-        // y-slices touched by the step's 4 nodes (lanes 0, 16, 32, 48 hold them)
-        const int l0 = __builtin_amdgcn_readlane(ly, 0), l1 = __builtin_amdgcn_readlane(ly, 16),
-                  l2 = __builtin_amdgcn_readlane(ly, 32), l3 = __builtin_amdgcn_readlane(ly, 48);
-        const int ylo = min(min(l0, l1), min(l2, l3)), yhi = max(max(l0, l1), max(l2, l3)) + W;
+        if (st + 1 < nst) load_step(st + 1, an, wzn, wyn);
 #pragma unroll
         for (int y = 0; y < P; ++y)
-          if (y >= ylo && y < yhi)
-            acc[y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, wy[y] * wz, acc[y], 0, 0, 0);
+          acc[y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, wy[y] * wz, acc[y], 0, 0, 0);
         a = an;
         wz = wzn;
-        ly = lyn;
 #pragma unroll
         for (int q = 0; q < 16; ++q) wy[q] = wyn[q];
       }
@@ -707,13 +778,19 @@ __device__ __forceinline__ void interp3_tile_body(const Item *__restrict__ items
   }
   float4 qb, qn;
   float xb, xn;
+  OutPre ob, on;
   load_batch<IN, false>(pts, ka, s, e, lane, qb, xb);
+  pre_index<OUT>(ka, s + lane, s + lane < e, ob);
+  pre_gather<OUT>(ka, s + lane < e, ob);
   for (int b0 = s; b0 < e; b0 += 64) {
-    load_batch<IN, false>(pts, ka, b0 + 64, e, lane, qn, xn);  // prefetch the next batch
+    // prefetch the next batch: records, permutation entries, d^{-1/2}
+    load_batch<IN, false>(pts, ka, b0 + 64, e, lane, qn, xn);
+    pre_index<OUT>(ka, b0 + 64 + lane, b0 + 64 + lane < e, on);
     const int bcnt = min(64, e - b0);
     for (int sb = 0; sb * 16 < bcnt; ++sb) {
       const int cnt = min(16, bcnt - sb * 16);
       const int i0 = b0 + sb * 16;
+      const OutPre op = pre_from<OUT>(ob, sb * 16 + c16);
       fill_shifted<T, false, TS_PITCH_I>(qb, xb, sb, cnt, lane, cf, wt, ox, oy, oz);
       wave_sync_lds();
       const float *w = wt + c16 * TS_PITCH_I;    // column c16 = node c16
@@ -743,11 +820,14 @@ __device__ __forceinline__ void interp3_tile_body(const Item *__restrict__ items
       }
       part += __shfl_xor(part, 16);
       part += __shfl_xor(part, 32);
-      if (p4 == 0 && c16 < cnt) store_out<OUT>(ka, i0 + c16, part);
+      if (p4 == 0 && c16 < cnt) store_pre<OUT>(ka, i0 + c16, part, op);
       wave_sync_lds();
     }
     qb = qn;
     xb = xn;
+    // the next batch's caller-order gather lands during its first sub-batch
+    ob = on;
+    pre_gather<OUT>(ka, b0 + 64 + lane < e, ob);
   }
 }
 
