@@ -637,12 +637,15 @@ __device__ __forceinline__ void spread3_tile_body(const Item it, const float4 *_
       const int cnt = min(16, bcnt - sb * 16);
       fill_shifted<T, true, TS_PITCH>(qb, xb, sb, cnt, lane, cf, wt, ox, oy, oz);
       wave_sync_lds();
-      // steps of 4 nodes; the operands of step st + 1 are loaded while the
-      // matrix instructions of step st issue.  Every y-slice is issued: slices
-      // outside the 4 nodes' windows add zero products, and skipping them
-      // behind per-slice branches measured slower than the straight-line loop.
+      // four steps of 4 nodes, unrolled, with two operand sets: the operands
+      // of step st + 1 are loaded (always: rows 4 (st + 1) + p4 < 16 lie in
+      // the table) while the matrix instructions of step st issue, so the
+      // wait before step st covers exactly its own loads.  Steps past cnt
+      // are skipped whole.  Every y-slice is issued: slices outside the 4
+      // nodes' windows add zero products, and skipping them behind
+      // per-slice branches measured slower than the straight-line block.
       const int nst = (cnt + 3) >> 2;
-      float a, wz, wy[16];
+      float a[2], wz[2], wy[2][16];
       auto load_step = [&](int st, float &a_, float &wz_, float (&wy_)[16]) {
         const float *w = wt + (4 * st + p4) * TS_PITCH;
         a_ = w[c16];
@@ -656,17 +659,16 @@ __device__ __forceinline__ void spread3_tile_body(const Item it, const float4 *_
           wy_[4 * q + 3] = v.w;
         }
       };
-      load_step(0, a, wz, wy);
-      for (int st = 0; st < nst; ++st) {
-        float an = 0.f, wzn = 0.f, wyn[16];
-        if (st + 1 < nst) load_step(st + 1, an, wzn, wyn);
+      load_step(0, a[0], wz[0], wy[0]);
 #pragma unroll
-        for (int y = 0; y < P; ++y)
-          acc[y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, wy[y] * wz, acc[y], 0, 0, 0);
-        a = an;
-        wz = wzn;
+      for (int st = 0; st < 4; ++st) {
+        const int c = st & 1;
+        if (st + 1 < 4) load_step(st + 1, a[c ^ 1], wz[c ^ 1], wy[c ^ 1]);
+        if (st < nst) {
 #pragma unroll
-        for (int q = 0; q < 16; ++q) wy[q] = wyn[q];
+          for (int y = 0; y < P; ++y)
+            acc[y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], wy[c][y] * wz[c], acc[y], 0, 0, 0);
+        }
       }
       wave_sync_lds();
     }
