@@ -166,6 +166,17 @@ __device__ __forceinline__ void store_pre(const KArgs &a, int i, float f, const 
   }
 }
 
+// v[l] + v[l ^ 16] + v[l ^ 32] + v[l ^ 48] on every lane, summed in the
+// order (v + v^16) + (v + v^16)^32, with the cross-row lane swaps of the
+// vector ALU (no LDS round trip): a swap of a value with itself returns, in
+// its two halves, the lane's own value and its partner's.
+__device__ __forceinline__ float sum_rows4(float v) {
+  const auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  const float s = __uint_as_float(a[0]) + __uint_as_float(a[1]);
+  const auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(s), __float_as_uint(s), false, false);
+  return __uint_as_float(b[0]) + __uint_as_float(b[1]);
+}
+
 __device__ __forceinline__ float readlane_f(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
@@ -516,8 +527,7 @@ __device__ __forceinline__ void interp3_mfma_body(const Item *__restrict__ items
 #pragma unroll
         for (int r = 0; r < 4; ++r)
           if (4 * k4 + r < W) part = fmaf(wxv[r], d[r], part);
-        part += __shfl_xor(part, 16);
-        part += __shfl_xor(part, 32);
+        part = sum_rows4(part);
         if (k4 == 0 && c16 < k) store_out<OUT>(ka, i0 + j + c16, part);
         j += k;
       }
@@ -820,8 +830,7 @@ __device__ __forceinline__ void interp3_tile_body(const Item *__restrict__ items
         const float dr = (d[0][r] + d[1][r]) + (d[2][r] + d[3][r]);
         part = fmaf(w[4 * p4 + r], dr, part);
       }
-      part += __shfl_xor(part, 16);
-      part += __shfl_xor(part, 32);
+      part = sum_rows4(part);
       if (p4 == 0 && c16 < cnt) store_pre<OUT>(ka, i0 + c16, part, op);
       wave_sync_lds();
     }
