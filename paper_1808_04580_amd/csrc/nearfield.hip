@@ -6,8 +6,11 @@
 // node i (the node itself included), which this kernel adds directly.
 //
 // One work item (the nodes of one grid tile) per workgroup: the item's nodes
-// are the targets (one per thread), and the nodes of every tile within eps_I
-// are staged in LDS, 256 at a time, with their input values.  Distances are
+// are the targets, and the nodes of every tile within eps_I, taken as one
+// list (node ranges of the tiles and their prefix sums in LDS), are staged in
+// LDS 256 at a time with their input values.  Items shorter than the
+// workgroup give each target several thread groups, each taking every G-th
+// staged source; the groups' sums are added at the end.  Distances are
 // formed in grid-cell units from exact integer cell differences plus the
 // differences of the float fractions.  Every output mode is affine in the fast
 // sum f (y = alpha x + beta f), so the correction adds beta * delta to the
@@ -29,22 +32,32 @@ constexpr int NT = 256;
 constexpr int NF_MAXP = 16;
 constexpr int NF_MAXTILES = 1024;   // neighbour tiles per item, (2R + 1)^d
 
+// Adds one workgroup's part of the correction: every output mode is affine in
+// the fast sum, so the parts of several workgroups add up.  The degree pass
+// adds into the degree only; d^{-1/2} is recomputed afterwards (k_near_dinv).
 template <int OUT>
 __device__ __forceinline__ void add_out(const KArgs &a, int i, float d) {
   if constexpr (OUT == OUT_USER_RAW || OUT == OUT_USER_W) {
-    a.y32[a.perm[i]] += d;
+    unsafeAtomicAdd(&a.y32[a.perm[i]], d);
   } else if constexpr (OUT == OUT_USER_LS) {
-    a.y32[a.perm[i]] -= a.dinv[i] * d;
+    unsafeAtomicAdd(&a.y32[a.perm[i]], -(a.dinv[i] * d));
   } else if constexpr (OUT == OUT_USER_A) {
-    a.y32[a.perm[i]] += a.dinv[i] * d;
+    unsafeAtomicAdd(&a.y32[a.perm[i]], a.dinv[i] * d);
   } else if constexpr (OUT == OUT_DEGREE) {
-    const float dg = a.deg_out[i] + d;
-    a.deg_out[i] = dg;
-    a.dinv_out[i] = dg > 0.f ? 1.0f / __builtin_sqrtf(dg) : 0.f;
+    unsafeAtomicAdd(&a.deg_out[i], d);
   } else if constexpr (OUT == OUT_SORTED_F64_A) {
-    a.y64[i] += (double)a.dinv[i] * (double)d;
+    unsafeAtomicAdd(&a.y64[i], (double)a.dinv[i] * (double)d);
   } else {  // OUT_SORTED_F64_SSL
-    a.y64[i] -= a.tau * (double)a.dinv[i] * (double)d;
+    unsafeAtomicAdd(&a.y64[i], -(a.tau * (double)a.dinv[i] * (double)d));
+  }
+}
+
+// d^{-1/2} from the corrected degrees (the formula of the degree pass).
+__global__ __launch_bounds__(256) void k_near_dinv(const float *__restrict__ deg,
+                                                   float *__restrict__ dinv, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const float dg = deg[i];
+    dinv[i] = dg > 0.f ? 1.0f / __builtin_sqrtf(dg) : 0.f;
   }
 }
 
@@ -58,7 +71,10 @@ __global__ __launch_bounds__(NT) void k_near(const Item *__restrict__ items,
   __shared__ int scell[NT];
   __shared__ float sfx[NT], sfy[NT], sfz[NT], sval[NT];
   __shared__ float cf[NF_MAXP];
-  __shared__ int ns0[NF_MAXTILES], ns1[NF_MAXTILES];   // node ranges of the neighbour tiles
+  __shared__ int ns0[NF_MAXTILES];         // first node of each neighbour tile
+  __shared__ int pref[NF_MAXTILES + 1];    // prefix sums of their node counts
+  __shared__ int bsum[NT + 1];
+  __shared__ float part[NT];
   const int t = threadIdx.x;
   if (t < p) cf[t] = coef[t];
   const Item it = items[blockIdx.x];
@@ -72,37 +88,70 @@ __global__ __launch_bounds__(NT) void k_near(const Item *__restrict__ items,
   }
   // neighbour tiles: the (2R + 1)^d cube around the item's tile, without the
   // tiles whose nearest cell is farther than eps_I from the item's tile and
-  // those outside the grid; their node ranges are read once, in parallel
+  // those outside the grid
   const int side = 2 * R + 1;
   const int nnb = d == 3 ? side * side * side : (d == 2 ? side * side : side);
-  for (int q = t; q < nnb; q += NT) {
-    int o[3] = {0, 0, 0};
-    int r = q;
-    for (int a = d - 1; a >= 0; --a) {
-      o[a] = r % side - R;
-      r /= side;
-    }
-    int tt[3], gap2 = 0;
-    bool in = true;
-    for (int a = 0; a < 3; ++a) {
-      tt[a] = tc[a] + o[a];
-      if (a < d && (tt[a] < 0 || tt[a] >= ntd)) in = false;
-      const int g = max(0, abs(o[a]) - 1) * tsize;
-      gap2 += g * g;
-    }
+  constexpr int PER = NF_MAXTILES / NT;    // tiles per thread in the scan
+  int cnts[PER], run = 0;
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int q = t * PER + u;
     int a0 = 0, a1 = 0;
-    if (in && (float)gap2 <= eps_cells2) {
-      const int tile = d == 3 ? (tt[0] * ntd + tt[1]) * ntd + tt[2] : (d == 2 ? tt[0] * ntd + tt[1] : tt[0]);
-      a0 = tile_start[tile];
-      a1 = tile_start[tile + 1];
+    if (q < nnb) {
+      int o[3] = {0, 0, 0};
+      int r = q;
+      for (int a = d - 1; a >= 0; --a) {
+        o[a] = r % side - R;
+        r /= side;
+      }
+      int tt[3], gap2 = 0;
+      bool in = true;
+      for (int a = 0; a < 3; ++a) {
+        tt[a] = tc[a] + o[a];
+        if (a < d && (tt[a] < 0 || tt[a] >= ntd)) in = false;
+        const int g = max(0, abs(o[a]) - 1) * tsize;
+        gap2 += g * g;
+      }
+      if (in && (float)gap2 <= eps_cells2) {
+        const int tile = d == 3 ? (tt[0] * ntd + tt[1]) * ntd + tt[2] : (d == 2 ? tt[0] * ntd + tt[1] : tt[0]);
+        a0 = tile_start[tile];
+        a1 = tile_start[tile + 1];
+      }
+      ns0[q] = a0;
     }
-    ns0[q] = a0;
-    ns1[q] = a1;
+    cnts[u] = a1 - a0;
+    run += a1 - a0;
+  }
+  // exclusive scan of the per-thread totals (Hillis-Steele over NT threads)
+  bsum[t] = run;
+  __syncthreads();
+  for (int o = 1; o < NT; o <<= 1) {
+    const int v = t >= o ? bsum[t - o] : 0;
+    __syncthreads();
+    bsum[t] += v;
+    __syncthreads();
+  }
+  {
+    int acc = bsum[t] - run;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int q = t * PER + u;
+      if (q < nnb) pref[q] = acc;
+      acc += cnts[u];
+    }
+    if (t == NT - 1) pref[nnb] = bsum[NT - 1];   // all nodes of the neighbour tiles
   }
   __syncthreads();
-  for (int b0 = it.start; b0 < it.end; b0 += NT) {
-    const int i = b0 + t;
-    const bool act = i < it.end;
+  const int total = pref[nnb];
+  // Targets: one per thread for items of at least NT nodes; shorter items
+  // give each target G thread groups, group g taking every G-th source.
+  const int len = it.end - it.start;
+  const int G = len >= NT ? 1 : min(NT / max(len, 1), 32);
+  const int TB = NT / G;
+  const int ti = t % TB, gi = t / TB;
+  for (int b0 = it.start; b0 < it.end; b0 += TB) {
+    const int i = b0 + ti;
+    const bool act = gi < G && i < it.end;
     int tcx = 0, tcy = 0, tcz = 0;
     float tfx = 0.f, tfy = 0.f, tfz = 0.f;
     if (act) {
@@ -116,41 +165,55 @@ __global__ __launch_bounds__(NT) void k_near(const Item *__restrict__ items,
       tfz = q.z;
     }
     float acc = 0.f;
-    for (int q = 0; q < nnb; ++q) {
-      const int s0 = ns0[q], s1 = ns1[q];
-      for (int c0 = s0; c0 < s1; c0 += NT) {
-        const int cnt = min(NT, s1 - c0);
-        __syncthreads();
-        if (t < cnt) {
-          const int j = c0 + t;
-          const float4 q = pts[j];
-          scell[t] = (int)__float_as_uint(q.w);
-          sfx[t] = q.x;
-          sfy[t] = q.y;
-          sfz[t] = q.z;
-          sval[t] = load_in<IN>(ka, j);
+    // the neighbour tiles' nodes as one list, staged NT at a time; slice
+    // blockIdx.y of gridDim.y takes every gridDim.y-th chunk
+    for (int c0 = blockIdx.y * NT; c0 < total; c0 += gridDim.y * NT) {
+      const int cnt = min(NT, total - c0);
+      __syncthreads();
+      if (t < cnt) {
+        const int v = c0 + t;
+        int lo = 0, hi = nnb;   // the last q with pref[q] <= v
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (pref[mid] <= v) lo = mid;
+          else hi = mid;
         }
-        __syncthreads();
-        if (act) {
-          for (int k = 0; k < cnt; ++k) {
-            const uint32_t sc = (uint32_t)scell[k];
-            const float dx = (float)(tcx - (int)(sc & 1023u)) + (tfx - sfx[k]);
-            const float dy = d > 1 ? (float)(tcy - (int)((sc >> 10) & 1023u)) + (tfy - sfy[k]) : 0.f;
-            const float dz = d > 2 ? (float)(tcz - (int)((sc >> 20) & 1023u)) + (tfz - sfz[k]) : 0.f;
-            const float r2 = dx * dx + dy * dy + dz * dz;
-            if (r2 <= eps_cells2) {
-              const float r = __builtin_sqrtf(r2) * inv_nos;   // scaled coordinates
-              const float u = r * inv_eps;
-              const float u2 = u * u;
-              float tp = cf[p - 1];
-              for (int c = p - 2; c >= 0; --c) tp = fmaf(tp, u2, cf[c]);
-              acc = fmaf(sval[k], expf(-r * inv_sigma) - tp, acc);
-            }
+        const int j = ns0[lo] + (v - pref[lo]);
+        const float4 q = pts[j];
+        scell[t] = (int)__float_as_uint(q.w);
+        sfx[t] = q.x;
+        sfy[t] = q.y;
+        sfz[t] = q.z;
+        sval[t] = load_in<IN>(ka, j);
+      }
+      __syncthreads();
+      if (act) {
+        for (int k = gi; k < cnt; k += G) {
+          const uint32_t sc = (uint32_t)scell[k];
+          const float dx = (float)(tcx - (int)(sc & 1023u)) + (tfx - sfx[k]);
+          const float dy = d > 1 ? (float)(tcy - (int)((sc >> 10) & 1023u)) + (tfy - sfy[k]) : 0.f;
+          const float dz = d > 2 ? (float)(tcz - (int)((sc >> 20) & 1023u)) + (tfz - sfz[k]) : 0.f;
+          const float r2 = dx * dx + dy * dy + dz * dz;
+          if (r2 <= eps_cells2) {
+            const float r = __builtin_sqrtf(r2) * inv_nos;   // scaled coordinates
+            const float u = r * inv_eps;
+            const float u2 = u * u;
+            float tp = cf[p - 1];
+            for (int c = p - 2; c >= 0; --c) tp = fmaf(tp, u2, cf[c]);
+            acc = fmaf(sval[k], expf(-r * inv_sigma) - tp, acc);
           }
         }
       }
     }
-    if (act) add_out<OUT>(ka, i, acc);
+    // the groups' partial sums of each target, added in group order
+    part[t] = acc;
+    __syncthreads();
+    if (gi == 0 && act) {
+      float s = part[ti];
+      for (int g = 1; g < G; ++g) s += part[g * TB + ti];
+      if (s != 0.f) add_out<OUT>(ka, i, s);
+    }
+    __syncthreads();   // part is rewritten by the next batch of targets
   }
 }
 
@@ -168,11 +231,19 @@ int launch_near(nfl_plan *P, const KArgs &k) {
     return NFL_ERR_UNSUPPORTED;
   }
   const int ntd = P->nos >> P->tshift;
-  hipLaunchKernelGGL((k_near<IN, OUT>), dim3(P->nitems), dim3(NT), 0, P->stream, P->items.p,
-                     P->pts.p, P->tile_start.p, k, P->d, ntd, T, R, (float)(eps_cells * eps_cells),
-                     (float)(1.0 / P->nos), (float)(1.0 / P->sigma_t), (float)(1.0 / P->eps_I),
-                     P->ti_coef.p, P->p);
+  // slices per item: enough workgroups (~8192) to fill the chip when the
+  // items are few and their neighbourhoods large
+  const int slices = std::min(64, std::max(1, (8192 + P->nitems - 1) / P->nitems));
+  hipLaunchKernelGGL((k_near<IN, OUT>), dim3(P->nitems, slices), dim3(NT), 0, P->stream,
+                     P->items.p, P->pts.p, P->tile_start.p, k, P->d, ntd, T, R,
+                     (float)(eps_cells * eps_cells), (float)(1.0 / P->nos),
+                     (float)(1.0 / P->sigma_t), (float)(1.0 / P->eps_I), P->ti_coef.p, P->p);
   NFL_HIP(hipGetLastError());
+  if constexpr (OUT == OUT_DEGREE) {
+    const int nb = (int)std::min<int64_t>(4096, (P->n + 255) / 256);
+    hipLaunchKernelGGL(k_near_dinv, dim3(nb), dim3(256), 0, P->stream, P->deg.p, P->dinv.p, P->n);
+    NFL_HIP(hipGetLastError());
+  }
   return NFL_OK;
 }
 
