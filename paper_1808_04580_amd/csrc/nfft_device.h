@@ -573,13 +573,21 @@ constexpr int TS_PITCH = 112, TS_PITCH_I = 100;
 __host__ __device__ constexpr int ts_xs(int P) { return P * 16 + 4; }   // 4 rows apart = 16 banks
 
 // Fill the shifted weight rows of sub-batch nodes sub*16 .. sub*16+15: lane l
-// evaluates node l/4 at offsets 4 (l%4) .. +3 and writes them at offset + its
-// cell's position in the tile.  SPREAD: the x row carries x_p wx_p (x_p = 0
-// for nodes past cnt).
-template <int T, bool SPREAD, int PITCH>
+// evaluates node l/4 at offsets U (l%4) .. +U-1, U = ceil(W/4) (the offsets at
+// or past W have zero polynomials), and writes them at offset + its cell's
+// position in the tile.  The readers use [0, 16) of each 32-float segment: the
+// entries there outside the window are zeroed first ([0, T) and [4U, 16)), and
+// the window values written after them (one wave's LDS writes execute in
+// order).  SPREAD: the x row carries x_p wx_p (x_p = 0 for nodes past cnt).
+template <int W>
+constexpr int fill_upl() { return (W + 3) / 4; }
+
+template <int T, int W, bool SPREAD, int PITCH>
 __device__ __forceinline__ void fill_shifted(const float4 &qb, float xb, int sub, int cnt,
-                                             int lane, const float (&cf)[4][WIN_NC], float *wt,
-                                             int ox, int oy, int oz) {
+                                             int lane, const float (&cf)[fill_upl<W>()][WIN_NC],
+                                             float *wt, int ox, int oy, int oz) {
+  constexpr int U = fill_upl<W>();
+  static_assert(T % 4 == 0 && T + 16 <= 32, "row segment layout");
   const int node = lane >> 2, part = lane & 3;
   const int src = sub * 16 + min(node, cnt - 1);
   const float qx = __shfl(qb.x, src), qy = __shfl(qb.y, src), qz = __shfl(qb.z, src);
@@ -594,14 +602,18 @@ __device__ __forceinline__ void fill_shifted(const float4 &qb, float xb, int sub
   float *row = wt + node * PITCH;
   if (part == 0) {
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
+    for (int a = 0; a < 3; ++a) {
 #pragma unroll
       for (int z = 0; z < T; z += 4)
         *reinterpret_cast<float4 *>(row + 32 * a + z) = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int z = 4 * U; z < 16; z += 4)
+        *reinterpret_cast<float4 *>(row + 32 * a + z) = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
   }
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int o = 4 * part + u;
+  for (int u = 0; u < U; ++u) {
+    const int o = U * part + u;
     row[lx + o] = xv * win_poly(cf[u], qx);
     row[32 + ly + o] = win_poly(cf[u], qy);
     row[64 + lz + o] = win_poly(cf[u], qz);
@@ -626,10 +638,11 @@ __device__ __forceinline__ void spread3_tile_body(const Item it, const float4 *_
   const int len = it.end - it.start, per = (len + NW - 1) / NW;
   const int s = it.start + min(len, wave * per), e = it.start + min(len, (wave + 1) * per);
 
-  float cf[4][WIN_NC];
+  constexpr int U = fill_upl<W>();
+  float cf[U][WIN_NC];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int o = 4 * (lane & 3) + u;
+  for (int u = 0; u < U; ++u) {
+    const int o = U * (lane & 3) + u;
 #pragma unroll
     for (int k = 0; k < WIN_NC; ++k) cf[u][k] = wcoef[o * WIN_NC + k];   // rows 2m..15 of the table are 0
   }
@@ -645,7 +658,7 @@ __device__ __forceinline__ void spread3_tile_body(const Item it, const float4 *_
     const int bcnt = min(64, e - b0);
     for (int sb = 0; sb * 16 < bcnt; ++sb) {
       const int cnt = min(16, bcnt - sb * 16);
-      fill_shifted<T, true, TS_PITCH>(qb, xb, sb, cnt, lane, cf, wt, ox, oy, oz);
+      fill_shifted<T, W, true, TS_PITCH>(qb, xb, sb, cnt, lane, cf, wt, ox, oy, oz);
       wave_sync_lds();
       // four steps of 4 nodes, unrolled, with two operand sets: the operands
       // of step st + 1 are loaded (always: rows 4 (st + 1) + p4 < 16 lie in
@@ -781,10 +794,11 @@ __device__ __forceinline__ void interp3_tile_body(const Item *__restrict__ items
   float *wt = lds + P * XS + wave * (16 * TS_PITCH_I);
   const int len = it.end - it.start, per = (len + NW - 1) / NW;
   const int s = it.start + min(len, wave * per), e = it.start + min(len, (wave + 1) * per);
-  float cf[4][WIN_NC];
+  constexpr int U = fill_upl<W>();
+  float cf[U][WIN_NC];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int o = 4 * (lane & 3) + u;
+  for (int u = 0; u < U; ++u) {
+    const int o = U * (lane & 3) + u;
 #pragma unroll
     for (int k = 0; k < WIN_NC; ++k) cf[u][k] = wcoef[o * WIN_NC + k];   // rows 2m..15 of the table are 0
   }
@@ -803,7 +817,7 @@ __device__ __forceinline__ void interp3_tile_body(const Item *__restrict__ items
       const int cnt = min(16, bcnt - sb * 16);
       const int i0 = b0 + sb * 16;
       const OutPre op = pre_from<OUT>(ob, sb * 16 + c16);
-      fill_shifted<T, false, TS_PITCH_I>(qb, xb, sb, cnt, lane, cf, wt, ox, oy, oz);
+      fill_shifted<T, W, false, TS_PITCH_I>(qb, xb, sb, cnt, lane, cf, wt, ox, oy, oz);
       wave_sync_lds();
       const float *w = wt + c16 * TS_PITCH_I;    // column c16 = node c16
       float wz4[4], wy[16];
