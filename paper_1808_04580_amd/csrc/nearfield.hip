@@ -200,7 +200,7 @@ __global__ __launch_bounds__(NT) void k_near(const Item *__restrict__ items,
             const float u2 = u * u;
             float tp = cf[p - 1];
             for (int c = p - 2; c >= 0; --c) tp = fmaf(tp, u2, cf[c]);
-            acc = fmaf(sval[k], expf(-r * inv_sigma) - tp, acc);
+            acc = fmaf(sval[k], __expf(-r * inv_sigma) - tp, acc);
           }
         }
       }
