@@ -154,7 +154,10 @@ static int fft_blocks(int stage, int L, int N) {
 template <int STAGE>
 __global__ __launch_bounds__(FFT_THREADS) void kb_fft(const int *__restrict__ first, int njobs,
                                                       const BJob *__restrict__ jobs) {
-  const int blk = blockIdx.x;
+  // the column passes take their blocks XCD-contiguous, as in the single-plan FFT
+  const int blk = (STAGE == FFT_YF || STAGE == FFT_XF || STAGE == FFT_YI)
+                      ? xcd_block(blockIdx.x, gridDim.x)
+                      : (int)blockIdx.x;
   const int j = find_job(first, njobs, blk);
   const BJob &J = jobs[j];
   const int lb = blk - __builtin_amdgcn_readfirstlane(first[j]);

@@ -418,21 +418,21 @@ __global__ __launch_bounds__(FFT_THREADS) void k_y_fwd(const float2 *__restrict_
                                                        float2 *__restrict__ H2, int L, int logL,
                                                        int lpb, int Hz, int N,
                                                        const float2 *__restrict__ tw) {
-  y_fwd_body(blockIdx.x, H1, H2, L, logL, lpb, Hz, N, tw);
+  y_fwd_body(xcd_block(blockIdx.x, gridDim.x), H1, H2, L, logL, lpb, Hz, N, tw);
 }
 
 __global__ __launch_bounds__(FFT_THREADS) void k_y_inv(const float2 *__restrict__ H2,
                                                        float2 *__restrict__ H1, int L, int logL,
                                                        int lpb, int Hz, int N,
                                                        const float2 *__restrict__ tw) {
-  y_inv_body(blockIdx.x, H2, H1, L, logL, lpb, Hz, N, tw);
+  y_inv_body(xcd_block(blockIdx.x, gridDim.x), H2, H1, L, logL, lpb, Hz, N, tw);
 }
 
 __global__ __launch_bounds__(FFT_THREADS) void k_x_filter(float2 *__restrict__ Hx,
                                                           const float *__restrict__ filt, int C,
                                                           int L, int logL, int lpb, int N,
                                                           const float2 *__restrict__ tw) {
-  x_filter_body(blockIdx.x, Hx, filt, C, L, logL, lpb, N, tw);
+  x_filter_body(xcd_block(blockIdx.x, gridDim.x), Hx, filt, C, L, logL, lpb, N, tw);
 }
 
 __global__ void k_filter1(float2 *__restrict__ H, const float *__restrict__ filt, int Hz) {
