@@ -504,7 +504,6 @@ def main():
     traffic = None
     prof_json = os.path.join(ROOT, "profiles", "traffic.json")
     if os.path.exists(prof_json):
-        import hashlib
         try:
             rec = json.load(open(prof_json))
             if rec.get("kernel_src_sha1") == kernel_src_sha1():
