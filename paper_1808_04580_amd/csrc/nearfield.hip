@@ -68,8 +68,8 @@ __global__ __launch_bounds__(NT) void k_near(const Item *__restrict__ items,
                                              int ntd, int tsize, int R, float eps_cells2, float inv_nos,
                                              float inv_sigma, float inv_eps,
                                              const float *__restrict__ coef, int p) {
-  __shared__ int scell[NT];
-  __shared__ float sfx[NT], sfy[NT], sfz[NT], sval[NT];
+  __shared__ float4 ssrc[NT];   // staged source records (fractions, packed cell)
+  __shared__ float sval[NT];
   __shared__ float cf[NF_MAXP];
   __shared__ int ns0[NF_MAXTILES];         // first node of each neighbour tile
   __shared__ int pref[NF_MAXTILES + 1];    // prefix sums of their node counts
@@ -179,20 +179,18 @@ __global__ __launch_bounds__(NT) void k_near(const Item *__restrict__ items,
           else hi = mid;
         }
         const int j = ns0[lo] + (v - pref[lo]);
-        const float4 q = pts[j];
-        scell[t] = (int)__float_as_uint(q.w);
-        sfx[t] = q.x;
-        sfy[t] = q.y;
-        sfz[t] = q.z;
+        ssrc[t] = pts[j];
         sval[t] = load_in<IN>(ka, j);
       }
       __syncthreads();
       if (act) {
+#pragma unroll 4
         for (int k = gi; k < cnt; k += G) {
-          const uint32_t sc = (uint32_t)scell[k];
-          const float dx = (float)(tcx - (int)(sc & 1023u)) + (tfx - sfx[k]);
-          const float dy = d > 1 ? (float)(tcy - (int)((sc >> 10) & 1023u)) + (tfy - sfy[k]) : 0.f;
-          const float dz = d > 2 ? (float)(tcz - (int)((sc >> 20) & 1023u)) + (tfz - sfz[k]) : 0.f;
+          const float4 sq = ssrc[k];
+          const uint32_t sc = __float_as_uint(sq.w);
+          const float dx = (float)(tcx - (int)(sc & 1023u)) + (tfx - sq.x);
+          const float dy = d > 1 ? (float)(tcy - (int)((sc >> 10) & 1023u)) + (tfy - sq.y) : 0.f;
+          const float dz = d > 2 ? (float)(tcz - (int)((sc >> 20) & 1023u)) + (tfz - sq.z) : 0.f;
           const float r2 = dx * dx + dy * dy + dz * dz;
           if (r2 <= eps_cells2) {
             const float r = __builtin_sqrtf(r2) * inv_nos;   // scaled coordinates
