@@ -25,6 +25,10 @@
  *   threads at once.
  * - The kernel is the Gaussian K(y) = exp(-||y||^2 / sigma^2), K(0) = 1
  *   (eq. W_gaussian).  W has zero diagonal (Section 2).
+ * - Products are reproducible up to rounding order only: the spread (and,
+ *   for the Laplacian RBF kernel, the near-field sum) add floating-point
+ *   contributions with atomic operations whose order varies from run to run
+ *   (differences at the FP32 rounding level of the sums).
  */
 #ifndef NFL_H
 #define NFL_H
