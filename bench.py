@@ -362,7 +362,7 @@ def variants_leg(nfl, synth, torch, dev, steps=50, rows=256):
 
 
 def small_configs_leg(nfl, synth, torch, dev, steps=100):
-    """The survey's small configurations: (1) two 2-D blobs, n = 5,000,
+    """Small configurations: (1) two 2-D blobs, n = 5,000,
     sigma = 0.05, N = 32, m = 4, eps_B = 1/16; (2) the 316 x 316 RGB image,
     n = 99,856, sigma = 0.1, N = 64, m = 5.  Time per L_s product and the 10
     smallest eigenpairs by Lanczos (tol 1e-6)."""
