@@ -56,6 +56,20 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def golden_degree(v):
+    """Exact FP64 degrees of the benchmark cloud (tests/golden, written by an
+    oracle-only script), or None if absent or written for other coordinates."""
+    import hashlib
+    stem = os.path.join(ROOT, "tests", "golden", "degree_moons_roll_n1000000_seed1_sigma0.04")
+    if not (os.path.exists(stem + ".npy") and os.path.exists(stem + ".json")):
+        return None
+    meta = json.load(open(stem + ".json"))
+    sha = hashlib.sha1(np.ascontiguousarray(v, dtype=np.float32).tobytes()).hexdigest()
+    if meta.get("coords_sha1") != sha or meta.get("sigma") != SIGMA:
+        return None
+    return np.load(stem + ".npy")
+
+
 def kernel_src_sha1():
     """SHA-1 of the sources of the spread / FFT / interpolation kernels."""
     import hashlib
@@ -510,12 +524,33 @@ def main():
                 traffic = rec.get(dom)
         except Exception:
             traffic = None
+    # achieved HBM bandwidth of the spread and the interpolation: counter
+    # bytes per launch over the stage time, next to the algorithmic bytes
+    # (28 B per node + the grid: record 16 B, input, permutation, d^{-1/2},
+    # plus the interpolation's output; 4 B per grid cell read or written)
+    grid_bytes = 4.0 * (2 * NBW) ** 3
+    alg_bytes = {"spread": 28.0 * N_POINTS + grid_bytes, "interp": 32.0 * N_POINTS + grid_bytes}
+    hbm = {}
+    for k in ("spread", "interp"):
+        t = st[k] * 1e-3
+        ent = {"alg_bytes": alg_bytes[k], "alg_GBps": round(alg_bytes[k] / t / 1e9, 1)}
+        cnt = rec.get(k) if (traffic is not None and os.path.exists(prof_json)) else None
+        if cnt:
+            ent.update({"counter_bytes": cnt, "GBps": round(cnt / t / 1e9, 1),
+                        "frac_of_peak": round(cnt / t / 1e9 / PEAK_HBM_GBS, 4)})
+        hbm[k] = ent
     roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 3),
                 "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic}
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
+                "hbm": {"peak_GBps": PEAK_HBM_GBS, **hbm}}
+    log("HBM: %s" % hbm)
 
-    # --- accuracy on sampled rows against the FP64 direct oracle ---------------
+    # --- accuracy against the FP64 direct oracle ---------------------------------
+    # L_s x of the timed product itself (yd holds the last timed output) on
+    # sampled rows, with the exact degrees of all nodes (direct FP64 sums
+    # cached under tests/golden by an oracle-only script); W x and d rows too
     from oracle import graph
+    Ls_out = yd.cpu().numpy().astype(np.float64)
     rng = np.random.default_rng(7)
     rows = np.sort(rng.choice(N_POINTS, size=args.rows, replace=False))
     yW = P.apply_W(xd).cpu().numpy().astype(np.float64)
@@ -523,14 +558,24 @@ def main():
     t0 = time.time()
     refW = graph.w_rows(v, SIGMA, x.astype(np.float64), rows)
     refd = graph.degree(v, SIGMA, rows)
-    cpu_rows_s = time.time() - t0
     dmax_ref = refd.max()
     acc = {
         "rows": int(args.rows),
         "rel_inf_deg": float(np.abs(dg[rows] - refd).max() / np.abs(refd).max()),
         "eps_W": float(np.abs(yW[rows] - refW).max() / (dmax_ref * np.abs(x).max())),
         "rel_inf_Wx": float(np.abs(yW[rows] - refW).max() / np.abs(refW).max()),
+        "rel_inf_Ls": None,
     }
+    dfull = golden_degree(v)
+    if dfull is not None:
+        refL = graph.Ls_rows(v, SIGMA, x.astype(np.float64), rows, dfull)
+        acc["rel_inf_Ls"] = float(np.abs(Ls_out[rows] - refL).max() / np.abs(refL).max())
+        acc["rel_inf_deg_all_nodes"] = float(np.abs(dg - dfull).max() / np.abs(dfull).max())
+        acc["Ls_output"] = "the last timed apply_Ls product"
+    cpu_rows_s = time.time() - t0
+    est = P.error_estimate(samples=20000, seed=1)
+    acc["aposteriori"] = {"eta": est["eta"], "kerr_inf_sampled": est["kerr_inf"],
+                          "eps_est": est["eps_est"], "lemma_bound": est["lemma_bound"]}
     log("accuracy on %d sampled rows: %s (oracle %.1fs)" % (args.rows, acc, cpu_rows_s))
 
     # --- CG time-to-tolerance: plain vs learned warm start, held-out cloud ------

@@ -278,6 +278,29 @@ int nfl_mlp_gradient(nfl_mlp_handle m, const float *feat_dev, const float *targe
 int nfl_get_info(nfl_handle h, double *rho, double *sigma_tilde, double *dmin, double *dmax,
                  double *eps_B, int *p);
 
+/* A-posteriori error quantities of Section 3.1 (host outputs, any may be
+ * NULL), for monitoring the accuracy of a plan:
+ *   eta      = d_min / ||W||_inf, the quantity of the Lemma on normalisation
+ *              (thm. normalization_propagation), from the plan's approximate
+ *              degrees d_E (the kernels here are positive, so ||W||_inf is the
+ *              largest degree);
+ *   kerr_inf ~ ||K_ERR||_inf = max |K_R(y) - K_RF(y)| over ||y|| <= 1/2 - eps_B
+ *              in the scaled coordinates (eq. KERR_estimate), the maximum taken
+ *              over nsamples points y; K_RF(y) = sum_{l in I_N^d} b_l cos(2 pi l.y)
+ *              with the plan's coefficients b_l (eq. b_l::K_RF), K_R the
+ *              regularised kernel divided by K(0) (for the Laplacian RBF kernel
+ *              K_R = T_I near 0, which the near field corrects exactly);
+ *   eps_est  = n kerr_inf / ||W||_inf (eq. epsilon_KERR_estimate), the estimate
+ *              of eps = ||E||_inf / ||W||_inf that ignores the NFFT's own error;
+ *   lemma_bound = eps_est (1 + eta) / (eta (eta - eps_est)), the Lemma's bound
+ *              on ||A - A_E||_inf with eps = eps_est (+infinity if eps_est >= eta).
+ * The sample points are y_host (nsamples x d doubles, row-major, each inside
+ * the ball, NFL_ERR_ARG otherwise) or, if y_host is NULL, nsamples points
+ * uniform in the ball drawn from a splitmix64 stream seeded with seed.
+ * 1 <= nsamples <= 2^20.  O(nsamples N^d) work on the GPU.  Synchronises. */
+int nfl_error_estimate(nfl_handle h, int nsamples, uint64_t seed, const double *y_host,
+                       double *eta, double *kerr_inf, double *eps_est, double *lemma_bound);
+
 /* ---- the individual NFFT steps (for testing; same stream rules) ---------- */
 
 /* Size of the oversampled grid: (2N)^d float32 cells, index ((x*2N)+y)*2N+z

@@ -59,6 +59,7 @@ SIGNATURES = {
     "nfl_nystrom": (_i, [_p, _p, _i64, _i, _i, _i, _p, _p, _p]),
     "nfl_krr_solve": (_i, [_p, _d, _p, _p, _i, _d, _i, _p, _p]),
     "nfl_get_info": (_i, [_p, _p, _p, _p, _p, _p, _p]),
+    "nfl_error_estimate": (_i, [_p, _i, ctypes.c_uint64, _p, _p, _p, _p, _p]),
     "nfl_grid_size": (_i64, [_p]),
     "nfl_spread": (_i, [_p, _p, _p]),
     "nfl_convolve": (_i, [_p, _p, _p]),
@@ -240,6 +241,21 @@ class Plan:
                "nfl_get_info")
         return dict(rho=vals[0].value, sigma_tilde=vals[1].value, dmin=vals[2].value,
                     dmax=vals[3].value, eps_B=vals[4].value, p=p.value)
+
+    def error_estimate(self, samples: int = 4096, seed: int = 0, points=None) -> dict:
+        """eta, the sampled ||K_ERR||_inf, eps_est = n ||K_ERR||_inf / ||W||_inf
+        and the Lemma's bound (nfl_error_estimate); points: optional (S, d)
+        sample points in the scaled coordinates."""
+        y = None
+        if points is not None:
+            y = np.ascontiguousarray(np.asarray(points, dtype=np.float64).reshape(-1, self.d))
+            samples = y.shape[0]
+        vals = [ctypes.c_double() for _ in range(4)]
+        _check(lib().nfl_error_estimate(self._h, int(samples), int(seed),
+                                        y.ctypes.data_as(_p) if y is not None else None,
+                                        *[ctypes.byref(x) for x in vals]), "nfl_error_estimate")
+        return dict(eta=vals[0].value, kerr_inf=vals[1].value, eps_est=vals[2].value,
+                    lemma_bound=vals[3].value)
 
     # -- operators ----------------------------------------------------------
     def degree(self):
@@ -581,7 +597,10 @@ class WarmStart:
         return u
 
     def attach(self, plan: "Plan", cls: int):
+        """Use this network for plan.cg_solve(..., warm=WARM_MLP); the plan keeps
+        a reference to it, and closing the network detaches it from the plan."""
         _check(lib().nfl_mlp_attach(plan._h, self._h, int(cls)), "nfl_mlp_attach")
+        plan._warm = self
 
     def save(self, path: str):
         _check(lib().nfl_mlp_save(self._h, path.encode()), "nfl_mlp_save")

@@ -90,24 +90,8 @@ int nfl_create(nfl_handle *h, int d, void *hip_stream) {
 int nfl_destroy(nfl_handle P) {
   if (!P) return NFL_OK;
   (void)hipStreamSynchronize(P->stream);
-  P->pts_user.release();
-  P->pts.release();
-  P->perm.release();
-  P->items.release();
-  P->filt.release();
-  P->wcoef.release();
-  P->tw.release();
-  P->grid.release();
-  P->grid2.release();
-  P->spec1.release();
-  P->spec2.release();
-  P->deg.release();
-  P->dinv.release();
-  P->xs.release();
-  P->fs.release();
-  P->red.release();
-  P->tmp.release();
-  delete P;
+  mlp_detach_plan(P);
+  delete P;   // every device buffer of the plan is freed by its destructor
   return NFL_OK;
 }
 

@@ -18,6 +18,8 @@
 //   b3 @9344, W4 [64] @9408, b4 @9472; total 9473.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <cmath>
 #include <cstdio>
 #include <algorithm>
@@ -415,9 +417,22 @@ struct nfl_mlp {
   nfl::DBuf<uint16_t> wbf;
   nfl::DBuf<int> idx;
   int64_t step = 0;
+  // plans whose nfl_cg_solve(..., NFL_WARM_MLP) reads this network: destroying
+  // the network detaches them, destroying a plan removes it from this list
+  std::vector<nfl_plan *> attached;
 };
 
 namespace nfl {
+
+// Remove plan P from the attachment list of its network (if any).
+void mlp_detach_plan(nfl_plan *P) {
+  nfl_mlp *M = P->mlp;
+  if (!M) return;
+  auto &a = M->attached;
+  a.erase(std::remove(a.begin(), a.end(), P), a.end());
+  P->mlp = nullptr;
+  P->mlp_cls = 0;
+}
 
 static int mlp_refresh(nfl_mlp *M) {
   hipLaunchKernelGGL(k_mlp_tobf16, dim3(16), dim3(256), 0, M->stream, M->prm.p, M->wbf.p);
@@ -537,9 +552,15 @@ int nfl_mlp_create(nfl_mlp_handle *h, int n_classes, uint64_t seed, void *hip_st
 int nfl_mlp_destroy(nfl_mlp_handle M) {
   if (!M) return NFL_OK;
   (void)hipStreamSynchronize(M->stream);
-  M->prm.release(); M->m1.release(); M->m2.release(); M->grad.release(); M->part.release();
-  M->feat.release(); M->target.release(); M->wbf.release(); M->idx.release();
-  delete M;
+  // a later warm-started solve on these plans fails with NFL_ERR_ORDER
+  // instead of reading freed memory
+  for (nfl_plan *P : M->attached) {
+    (void)hipStreamSynchronize(P->stream);
+    P->mlp = nullptr;
+    P->mlp_cls = 0;
+  }
+  M->attached.clear();
+  delete M;   // the device buffers are freed by their destructors
   return NFL_OK;
 }
 
@@ -631,8 +652,12 @@ int nfl_mlp_predict(nfl_mlp_handle M, nfl_handle P, const double *f_dev, int cls
 int nfl_mlp_attach(nfl_handle P, nfl_mlp_handle M, int cls) {
   if (!P) { set_error("null plan"); return NFL_ERR_ARG; }
   if (M && (cls < 0 || cls >= M->ncls)) { set_error("class out of range"); return NFL_ERR_ARG; }
-  P->mlp = M;
-  P->mlp_cls = cls;
+  mlp_detach_plan(P);
+  if (M) {
+    P->mlp = M;
+    P->mlp_cls = cls;
+    M->attached.push_back(P);
+  }
   return NFL_OK;
 }
 

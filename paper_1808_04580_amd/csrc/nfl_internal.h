@@ -29,11 +29,17 @@ void set_error(const std::string &msg);
     if (rc_ < 0) return rc_;                                                       \
   } while (0)
 
-// A device buffer owned by a plan.
+// A device buffer owned by its holder (a plan, a batch, a network, a
+// function): freed by release() or at destruction (hipFree waits for the
+// device work still using it).  Not copyable, so no second owner exists.
 template <class T>
 struct DBuf {
   T *p = nullptr;
   size_t n = 0;
+  DBuf() = default;
+  DBuf(const DBuf &) = delete;
+  DBuf &operator=(const DBuf &) = delete;
+  ~DBuf() { release(); }
   int ensure(size_t count) {
     if (count <= n && p) return NFL_OK;
     if (p) (void)hipFree(p);
@@ -56,15 +62,9 @@ struct DBuf {
   }
 };
 
-// A function-local device buffer, freed when it goes out of scope (hipFree
-// waits for the device work still using it).  Not copyable.
+// A function-local device buffer (the same ownership as DBuf).
 template <class T>
-struct LBuf : DBuf<T> {
-  LBuf() = default;
-  LBuf(const LBuf &) = delete;
-  LBuf &operator=(const LBuf &) = delete;
-  ~LBuf() { this->release(); }
-};
+using LBuf = DBuf<T>;
 
 // One unit of spread/interp work: a contiguous range of sorted nodes inside
 // one grid tile.
@@ -215,6 +215,19 @@ int fill_f32(float *p, int64_t n, float v, hipStream_t s);
 // contribution of sum_{||v~_i - v~_j|| <= eps_I} x~_j (K - T_I)(v~_i - v~_j) to
 // the output of the given mode, as the post-operation would have done.
 int near_field(nfl_plan *P, int in_mode, int out_mode, const VecArgs &a);
+// The regularised kernel K_R / K(0) in the scaled coordinates (setup.hip).
+struct RegKernel {
+  int kind;
+  double sigma_t, eps_B, eps_I;
+  int p;
+  double r0, alpha, k_half = 0.0;
+  std::vector<double> fa, fb, ia, ib;
+  RegKernel(int kind, double sigma_t, double eps_B, double eps_I, int p);
+  double K(double r) const;            // the kernel itself
+  double operator()(double r) const;   // K_R
+};
+// b_l of eq. b_l::K_RF (normalised by N^d) for l in I_N^d, axis index l mod N.
+void kernel_bhat(int d, int N, const RegKernel &KR, std::vector<double> &bhat);
 // Monomial coefficients of the inner polynomial T_I in (r / eps_I)^2 (setup.hip).
 int inner_poly(double sigma_t, double eps_I, int p, std::vector<double> &c);
 int scatter_f32(nfl_plan *P, const float *src_sorted, float *dst_user);
@@ -249,6 +262,8 @@ int nystrom(nfl_plan *P, const double *G_user, int64_t ldg, int L, int M, int k,
 
 // ---- learned warm start (mlp.hip) -------------------------------------------
 int mlp_warm_start(nfl_plan *P, const double *f_sorted, double *u_sorted);
+// Remove plan P from the attachment list of its warm-start network, if any.
+void mlp_detach_plan(nfl_plan *P);
 int mlp_forward_explicit(nfl_mlp *M, int64_t B, float *out);
 
 }  // namespace nfl

@@ -718,47 +718,47 @@ int inner_poly(double s, double eps_I, int p, std::vector<double> &c) {
   return NFL_OK;
 }
 
-int compute_filter(int d, int N, int m, int p, double eps_B, double sigma_t,
-                   std::vector<double> &out, int kind, double eps_I) {
-  if (d < 1 || d > 3 || N < 2 || (N & 1) || m < 1 || p < 1 || 2 * m > WIN_MAXW) return NFL_ERR_ARG;
-  if (kind < NFL_KERNEL_GAUSSIAN || kind > NFL_KERNEL_LAPLACIAN_RBF) return NFL_ERR_ARG;
-  if (kind == NFL_KERNEL_LAPLACIAN_RBF && !(eps_I > 0 && eps_I + eps_B < 0.5)) return NFL_ERR_ARG;
-  const int nos = 2 * N;
-  std::vector<float> wcoef;
-  window_poly(m, M_PI * (2.0 - 0.5), wcoef);
-  // ---- samples of K_R on I_N^d, stored at j mod N
-  const double r0 = 0.5 - eps_B;
-  // the kernel in the scaled coordinates, divided by its value at 0 (sigma_t
-  // is the scaled width or the scaled multiquadric parameter c)
-  const double alpha = kind == NFL_KERNEL_MULTIQUADRIC ? 0.5 : -0.5;
-  auto Kn = [&](double r) -> double {
-    if (kind == NFL_KERNEL_GAUSSIAN) return std::exp(-(r * r) / (sigma_t * sigma_t));
-    if (kind == NFL_KERNEL_LAPLACIAN_RBF) return std::exp(-r / sigma_t);
-    return std::pow(1.0 + (r * r) / (sigma_t * sigma_t), alpha);
-  };
-  std::vector<double> fa(p), fb(p, 0.0);
+// The regularised kernel K_R of the fast summation in the scaled coordinates,
+// divided by K(0) (sigma_t is the scaled width or the scaled multiquadric
+// parameter c): K on r <= 1/2 - eps_B (and, for the Laplacian RBF kernel, the
+// inner polynomial T_I on r <= eps_I), the two-point Taylor transition to the
+// constant K(1/2) on (1/2 - eps_B, 1/2], that constant beyond 1/2.
+RegKernel::RegKernel(int kind_, double sigma_t_, double eps_B_, double eps_I_, int p_)
+    : kind(kind_), sigma_t(sigma_t_), eps_B(eps_B_), eps_I(eps_I_), p(p_), r0(0.5 - eps_B_),
+      alpha(kind_ == NFL_KERNEL_MULTIQUADRIC ? 0.5 : -0.5), fa(p_), fb(p_, 0.0), ia(p_), ib(p_) {
   if (kind == NFL_KERNEL_GAUSSIAN)
     gauss_derivs(r0, sigma_t, p, fa.data());
   else if (kind == NFL_KERNEL_LAPLACIAN_RBF)
     laplace_derivs(r0, sigma_t, p, fa.data());
   else
     power_derivs(r0, sigma_t, alpha, p, fa.data());
-  fb[0] = Kn(0.5);
-  const double k_half = fb[0];
-  // inner region (Laplacian RBF kernel): T_I on r <= eps_I
-  std::vector<double> ia(p), ib(p);
+  fb[0] = K(0.5);
+  k_half = fb[0];
   if (kind == NFL_KERNEL_LAPLACIAN_RBF) {
     laplace_derivs(eps_I, sigma_t, p, ib.data());
     for (int k = 0; k < p; ++k) ia[k] = (k & 1) ? -ib[k] : ib[k];
   }
-  auto KR = [&](double r) -> double {
-    if (kind == NFL_KERNEL_LAPLACIAN_RBF && r <= eps_I)
-      return two_point_taylor(r, -eps_I, eps_I, ia.data(), ib.data(), p);
-    if (r <= r0) return Kn(r);
-    if (eps_B <= 0.0) return k_half;  // no transition region
-    if (r <= 0.5) return two_point_taylor(r, r0, 0.5, fa.data(), fb.data(), p);
-    return two_point_taylor(0.5, r0, 0.5, fa.data(), fb.data(), p);
-  };
+}
+
+double RegKernel::K(double r) const {
+  if (kind == NFL_KERNEL_GAUSSIAN) return std::exp(-(r * r) / (sigma_t * sigma_t));
+  if (kind == NFL_KERNEL_LAPLACIAN_RBF) return std::exp(-r / sigma_t);
+  return std::pow(1.0 + (r * r) / (sigma_t * sigma_t), alpha);
+}
+
+double RegKernel::operator()(double r) const {
+  if (kind == NFL_KERNEL_LAPLACIAN_RBF && r <= eps_I)
+    return two_point_taylor(r, -eps_I, eps_I, ia.data(), ib.data(), p);
+  if (r <= r0) return K(r);
+  if (eps_B <= 0.0) return k_half;  // no transition region
+  if (r <= 0.5) return two_point_taylor(r, r0, 0.5, fa.data(), fb.data(), p);
+  return two_point_taylor(0.5, r0, 0.5, fa.data(), fb.data(), p);
+}
+
+// b_l of eq. b_l::K_RF for l in I_N^d, normalised by N^d: the DFT of the
+// samples K_R(j/N), j in I_N^d, each axis stored at index j mod N (so b_l sits
+// at l mod N).  K_R is even, so b_l is real.
+void kernel_bhat(int d, int N, const RegKernel &KR, std::vector<double> &bhat) {
   size_t tot = 1;
   for (int t = 0; t < d; ++t) tot *= (size_t)N;
   std::vector<std::complex<double>> S(tot);
@@ -773,7 +773,6 @@ int compute_filter(int d, int N, int m, int p, double eps_B, double sigma_t,
     }
     S[q] = KR(std::sqrt(rr) / N);
   }
-  // ---- b_l = N^{-d} DFT (separable)
   size_t stride = 1;
   for (int t = d - 1; t >= 0; --t) {
     const size_t outer = tot / ((size_t)N * stride);
@@ -782,6 +781,21 @@ int compute_filter(int d, int N, int m, int p, double eps_B, double sigma_t,
     stride *= N;
   }
   const double norm = std::pow((double)N, -d);
+  bhat.resize(tot);
+  for (size_t q = 0; q < tot; ++q) bhat[q] = S[q].real() * norm;
+}
+
+int compute_filter(int d, int N, int m, int p, double eps_B, double sigma_t,
+                   std::vector<double> &out, int kind, double eps_I) {
+  if (d < 1 || d > 3 || N < 2 || (N & 1) || m < 1 || p < 1 || 2 * m > WIN_MAXW) return NFL_ERR_ARG;
+  if (kind < NFL_KERNEL_GAUSSIAN || kind > NFL_KERNEL_LAPLACIAN_RBF) return NFL_ERR_ARG;
+  if (kind == NFL_KERNEL_LAPLACIAN_RBF && !(eps_I > 0 && eps_I + eps_B < 0.5)) return NFL_ERR_ARG;
+  const int nos = 2 * N;
+  std::vector<float> wcoef;
+  window_poly(m, M_PI * (2.0 - 0.5), wcoef);
+  const RegKernel KR(kind, sigma_t, eps_B, eps_I, p);
+  std::vector<double> S;
+  kernel_bhat(d, N, KR, S);
   // ---- window transform at l = -N/2..N/2
   std::vector<double> wh(N + 1);
   for (int l = -N / 2; l <= N / 2; ++l) wh[l + N / 2] = window_hat((double)l / nos, m, wcoef);
@@ -811,7 +825,7 @@ int compute_filter(int d, int N, int m, int p, double eps_B, double sigma_t,
       den *= w * w;
     }
     const double share = 0.5 * ((has_pos ? 0.0 : 1.0) + (has_neg ? 0.0 : 1.0));
-    out[q] = share * S[si].real() * norm / den;
+    out[q] = share * S[si] / den;
   }
   return NFL_OK;
 }

@@ -7,6 +7,10 @@ direct FP64 sum one row at a time, and (b) properties that hold at any size:
 L_s D^{1/2} 1 = 0, symmetry, the spectrum in [0, 2], eigen-residuals and
 orthonormality of the returned vectors.
 """
+import hashlib
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -14,6 +18,19 @@ import synth
 from oracle import graph
 
 pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                      "degree_moons_roll_n1000000_seed1_sigma0.04")
+
+
+def golden_degree(v):
+    """The exact FP64 degrees of the n = 1e6 cloud, written by
+    tests/golden/make_degree_moons_roll_1m.py from the oracle's direct sums;
+    refused if the generator's coordinates changed since."""
+    meta = json.load(open(GOLDEN + ".json"))
+    sha = hashlib.sha1(np.ascontiguousarray(v, dtype=np.float32).tobytes()).hexdigest()
+    assert meta["coords_sha1"] == sha, "the cloud changed since the degrees were written"
+    return np.load(GOLDEN + ".npy")
 
 
 def _sampled_rows(P, v, sigma, x, rows):
@@ -49,6 +66,31 @@ def test_moons_and_roll_1M_full_size(nfl):
     a = torch.dot(xt.double(), P.apply_Ls(y).double()).item()
     b = torch.dot(y.double(), P.apply_Ls(xt).double()).item()
     assert abs(a - b) <= 1e-5 * (abs(a) + abs(b)) / 2 + 1e-3, (a, b)
+    P.close()
+
+
+def test_moons_and_roll_1M_Ls_rows_against_the_direct_oracle(nfl):
+    """eq. nomlap at the benchmark's launch configuration (n = 1e6, sigma =
+    0.04, N = 64, m = 6, eps_B = 0, tile 4, items of <= 512 nodes): L_s x of
+    one product against (L_s x)_j = x_j - d_j^{-1/2} sum_{i != j} W_ji
+    d_i^{-1/2} x_i on 4096 seeded rows, with the exact degree vector of all
+    1e6 nodes (direct FP64 sums, cached); rel_inf <= 1e-5.  And the
+    approximate degrees d_E against all 1e6 exact ones."""
+    import torch
+    n, sigma = 1_000_000, 0.04
+    v, _ = synth.moons_and_roll(n, seed=1)
+    dref = golden_degree(v)
+    P = nfl.plan(torch.as_tensor(v, device="cuda"), sigma, N=64, m=6, eps_B=0.0)
+    dg = P.degree().double().cpu().numpy()
+    rd = np.abs(dg - dref).max() / np.abs(dref).max()
+    assert rd <= 1e-5, rd
+    x = synth.normal_vectors(n, seed=12345)
+    y = P.apply_Ls(torch.as_tensor(x, device="cuda")).double().cpu().numpy()
+    rows = np.sort(np.random.default_rng(7).choice(n, size=4096, replace=False))
+    ref = graph.Ls_rows(v, sigma, x.astype(np.float64), rows, dref)
+    rel = np.abs(y[rows] - ref).max() / np.abs(ref).max()
+    print("n = 1e6: rel_inf(d) %.3g over all nodes, rel_inf(L_s x) %.3g on 4096 rows" % (rd, rel))
+    assert rel <= 1e-5, rel
     P.close()
 
 

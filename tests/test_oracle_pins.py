@@ -351,6 +351,45 @@ def test_lemma_bound_holds():
     assert fastsum.lemma_bound(eps, eta) < 1.0
 
 
+def test_lemma_bound_hand_values_and_proof_chain():
+    """The Lemma's bound eps (1 + eta) / (eta (eta - eps)) at hand-computed
+    points (eps = 0.01, eta = 0.1: 0.011 / 0.009 = 11/9; eps = 0.2, eta = 0.5:
+    0.3 / 0.15 = 2), infinite where eps >= eta, and equal to the unsimplified
+    sum of the three terms in the proof of the Lemma (Section 3.1):
+    ((eta-eps)^{-1/2} - eta^{-1/2}) (eta^{-1/2} + (1+eps)(eta-eps)^{-1/2})
+    + (eta-eps)^{-1/2} eps eta^{-1/2}."""
+    assert abs(fastsum.lemma_bound(0.01, 0.1) - 11.0 / 9.0) < 1e-15
+    assert abs(fastsum.lemma_bound(0.2, 0.5) - 2.0) < 1e-15
+    assert fastsum.lemma_bound(0.3, 0.3) == np.inf and fastsum.lemma_bound(0.4, 0.3) == np.inf
+    rng = np.random.default_rng(11)
+    for _ in range(50):
+        eta = rng.uniform(1e-3, 1.0)
+        eps = eta * rng.uniform(0.0, 0.99)
+        a, b = (eta - eps) ** -0.5, eta ** -0.5
+        chain = (a - b) * (b + (1.0 + eps) * a) + a * eps * b
+        assert abs(fastsum.lemma_bound(eps, eta) - chain) <= 1e-12 * chain + 1e-300
+
+
+def test_K_RF_single_coefficient_and_kerr_of_a_constant():
+    """eq. K_RF with one nonzero coefficient b at l* is b exp(2 pi i l*.y)
+    (closed form); kerr_sampled of the constant K_RF = 3 against the Gaussian
+    of width 0.05 is 3 - min K over the samples, i.e. 3 up to e^{-80}
+    (samples reach radius ~1/2, where K ~ e^{-100})."""
+    rng = np.random.default_rng(12)
+    N = 8
+    for d in (1, 2, 3):
+        y = rng.uniform(-0.5, 0.5, size=(40, d))
+        b = np.zeros((N,) * d)
+        lstar = rng.integers(-N // 2, N // 2, size=d)
+        b[tuple(lstar + N // 2)] = 1.75
+        want = 1.75 * np.exp(2j * np.pi * (y @ lstar))
+        np.testing.assert_allclose(fastsum.K_RF(y, b, N), want, rtol=0, atol=1e-13)
+        c = np.zeros((N,) * d)
+        c[(N // 2,) * d] = 3.0
+        k = fastsum.kerr_sampled(c, N, 0.05, 0.0, d, samples=5000, seed=1)
+        assert abs(k - 3.0) < 1e-12, (d, k)
+
+
 # ---- Krylov solvers (Section 4) -----------------------------------------------
 
 def test_lanczos_matches_lapack_and_top_eigenpair():
