@@ -216,7 +216,13 @@ int nfl_nystrom(nfl_handle h, const double *G_dev, int64_t ldg, int L, int M, in
  * recomputed at the end with the same operator.  f_dev, u_dev: n doubles in
  * caller order.  warm: NFL_WARM_ZERO (u0 = 0), NFL_WARM_USER (u0 read from
  * u_dev), NFL_WARM_MLP (u0 from the plan's warm-start network, see
- * nfl_mlp_*).  Synchronises. */
+ * nfl_mlp_*).  The iteration runs on the device: the step lengths and the
+ * stopping test are formed by the solver's kernels (fixed-order reductions,
+ * so a solve is reproducible), and the host checks the status one iteration
+ * behind without stalling the device.  NFL_NOT_CONVERGED also on a
+ * breakdown (p.Mp <= 0).  Device work memory: 5 n doubles (plus the
+ * reduction partials), allocated by the plan's first solve and kept with
+ * the plan.  Synchronises. */
 int nfl_cg_solve(nfl_handle h, double tau, const double *f_dev, double *u_dev, int warm,
                  double tol, int maxit, int *iters, double *relres);
 

@@ -7,8 +7,9 @@ extension): 16 input features -> 64 -> 64 -> 64 -> 1, tanh after the first
 three layers, mean squared error loss.  With emulate=True every operand that
 the GPU kernels feed to the BF16 matrix cores is rounded to bfloat16
 (round-to-nearest-even of its float32 value): the weights W1, W2, W3, the
-layer inputs X, H1, H2 in the forward pass, and the deltas and layer inputs of
-the backward products; all sums, biases, W4 and activations stay FP64.
+layer inputs X, H1, H2 in the forward pass, and the deltas (of the summed
+squared error, before the mean's 1/B) and layer inputs of the backward
+products; all sums, biases, W4 and activations stay FP64.
 With emulate=False it is plain FP64 (pinned by finite differences).
 
 Parameter vector (9473): W1[64][16], b1[64], W2[64][64], b2[64], W3[64][64],
@@ -55,7 +56,10 @@ def loss_and_grad(p, X, t, emulate=True):
     out, (X, H1, H2, H3) = forward(p, X, emulate)
     B = X.shape[0]
     err = out - np.asarray(t, dtype=np.float64)
-    g = 2.0 * err / B
+    # per-node derivative of the summed squared error; the mean's 1/B is
+    # applied to the summed gradient (so the bf16-rounded deltas of a node do
+    # not depend on the batch it is in)
+    g = 2.0 * err
     gW4 = H3 @ g
     gb4 = g.sum()
     d3 = P["W4"][:, None] * g[None, :] * (1.0 - H3 ** 2)
@@ -67,5 +71,5 @@ def loss_and_grad(p, X, t, emulate=True):
     d1 = (r(P["W2"]).T @ r(d2)) * (1.0 - H1 ** 2)
     gW1 = r(d1) @ r(X)
     gb1 = d1.sum(axis=1)
-    grad = np.concatenate([gW1.ravel(), gb1, gW2.ravel(), gb2, gW3.ravel(), gb3, gW4, [gb4]])
+    grad = np.concatenate([gW1.ravel(), gb1, gW2.ravel(), gb2, gW3.ravel(), gb3, gW4, [gb4]]) / B
     return float(np.mean(err ** 2)), grad

@@ -6,6 +6,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
+#include <string>
 #include <numeric>
 #include <vector>
 
@@ -855,16 +857,107 @@ int lanczos(nfl_plan *P, int k, int block, double tol, int maxit, double *evals_
 }
 
 // ---------------------------------------------------------------------------
-// CG
+// CG (Section 4; the kernel-SSL system eq. ssl::system and the KRR system)
+//
+// The iteration runs on the device without a host round trip per step: every
+// kernel of an iteration, the product's included, returns at once when the
+// solve's stop flag is set, and the scalars alpha, beta and the convergence
+// test are formed by the vector kernels themselves.  Reductions are fixed
+// order: each block writes one partial sum; the kernel that needs the total
+// sums the partials in the same tree in every block, so all blocks agree on
+// the scalar and the result does not depend on scheduling.
+//
+// Device state: sc[0], sc[1] hold r.r by iteration parity, sc[2] = ||f||_2,
+// sc[3] = (tol ||f||)^2, sc[4] the true residual norm; st[0] the stop flag
+// (1 converged, 2 breakdown p.q <= 0), st[1] the iterations done.
 // ---------------------------------------------------------------------------
-// u += a p; r -= a q; partial r.r      with a = sc[0] / sc[1]
+constexpr int CG_NB = 1024;    // reduction blocks of the CG vector kernels (partials per sum)
+
+// sum of the nb partials in a fixed tree, valid in every thread of the block
+__device__ __forceinline__ double sum_partials(const double *__restrict__ part, int nb,
+                                               double *sh) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nb; i += VT) v += part[i];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int k = 0; k < VT / 64; ++k) t += sh[k];
+  return t;
+}
+
+// r = f - q; p = r; partials of r.r and f.f
+__global__ __launch_bounds__(VT) void k_cg_start(const double *__restrict__ f,
+                                                 const double *__restrict__ q, int64_t n,
+                                                 double *__restrict__ r, double *__restrict__ p,
+                                                 double *__restrict__ part) {
+  __shared__ double sh[VT / 64];
+  double rr = 0.0, ff = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT) {
+    const double fi = f[i], ri = fi - q[i];
+    r[i] = ri;
+    p[i] = ri;
+    rr += ri * ri;
+    ff += fi * fi;
+  }
+  rr = block_sum(rr, sh);
+  ff = block_sum(ff, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = rr;
+    part[CG_NB + blockIdx.x] = ff;
+  }
+}
+
+// one block: r.r, ||f||, the tolerance, and the stop flag before the first step
+__global__ __launch_bounds__(VT) void k_cg_init(const double *__restrict__ part, int nb,
+                                                double tol, double *__restrict__ sc,
+                                                int *__restrict__ st) {
+  __shared__ double sh[VT / 64];
+  const double rr = sum_partials(part, nb, sh);
+  const double ff = sum_partials(part + CG_NB, nb, sh);
+  if (threadIdx.x == 0) {
+    const double nf = sqrt(ff), lim = (tol * nf) * (tol * nf);
+    sc[0] = rr;
+    sc[1] = rr;
+    sc[2] = nf;
+    sc[3] = lim;
+    st[0] = (nf == 0.0 || rr <= lim) ? 1 : 0;
+    st[1] = 0;
+  }
+}
+
+// partials of p.q
+__global__ __launch_bounds__(VT) void k_cg_pq(const double *__restrict__ p,
+                                              const double *__restrict__ q, int64_t n,
+                                              const int *__restrict__ st,
+                                              double *__restrict__ part) {
+  if (st[0]) return;
+  __shared__ double sh[VT / 64];
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT)
+    s += p[i] * q[i];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// step k: alpha = r.r / p.q; u += alpha p; r -= alpha q; partials of the new r.r
 __global__ __launch_bounds__(VT) void k_cg_step(double *__restrict__ u, double *__restrict__ r,
                                                 const double *__restrict__ p,
-                                                const double *__restrict__ q,
-                                                const double *__restrict__ sc, int64_t n,
+                                                const double *__restrict__ q, int64_t n, int k,
+                                                const double *__restrict__ sc,
+                                                int *__restrict__ st,
                                                 double *__restrict__ part) {
+  if (st[0]) return;
   __shared__ double sh[VT / 64];
-  const double a = sc[0] / sc[1];
+  const double pq = sum_partials(part, (int)gridDim.x, sh);
+  if (!(pq > 0.0) || !isfinite(pq)) {   // M is not positive definite on p: stop
+    if (blockIdx.x == 0 && threadIdx.x == 0) st[0] = 2;
+    return;
+  }
+  const double a = sc[k & 1] / pq;
   double s = 0.0;
   for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT) {
     u[i] += a * p[i];
@@ -873,26 +966,54 @@ __global__ __launch_bounds__(VT) void k_cg_step(double *__restrict__ u, double *
     s += ri * ri;
   }
   s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[CG_NB + blockIdx.x] = s;
+  if (blockIdx.x == 0 && threadIdx.x == 0) st[1] = k + 1;
+}
+
+// step k: beta = r.r_new / r.r; p = r + beta p; the new r.r and the stop test.
+// Block 0 writes the flag; blocks that start after it skip the direction
+// update, which no later kernel reads once the flag is set.
+__global__ __launch_bounds__(VT) void k_cg_dir(double *__restrict__ p,
+                                               const double *__restrict__ r, int64_t n, int k,
+                                               double *__restrict__ sc, int *__restrict__ st,
+                                               const double *__restrict__ part,
+                                               int *__restrict__ host_st) {
+  if (st[0]) return;
+  __shared__ double sh[VT / 64];
+  const double rn = sum_partials(part + CG_NB, (int)gridDim.x, sh);
+  const double b = rn / sc[k & 1];
+  for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT)
+    p[i] = r[i] + b * p[i];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc[(k + 1) & 1] = rn;
+    const int done = rn <= sc[3] ? 1 : 0;
+    if (done) st[0] = 1;
+    if (host_st) {
+      __hip_atomic_store(host_st, k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(host_st + 1, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+  }
+}
+
+// r = f - q with partials of r.r (true residual after the solve)
+__global__ __launch_bounds__(VT) void k_cg_resid(const double *__restrict__ f,
+                                                 const double *__restrict__ q, int64_t n,
+                                                 double *__restrict__ part) {
+  __shared__ double sh[VT / 64];
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT) {
+    const double ri = f[i] - q[i];
+    s += ri * ri;
+  }
+  s = block_sum(s, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// p = r + (sc[2] / sc[0]) p ; then sc[0] = sc[2]   (done by the last kernel below)
-__global__ __launch_bounds__(VT) void k_cg_dir(double *__restrict__ p,
-                                               const double *__restrict__ r,
-                                               const double *__restrict__ sc, int64_t n) {
-  const double b = sc[2] / sc[0];
-  for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT)
-    p[i] = r[i] + b * p[i];
-}
-
-__global__ void k_copy_scalar(double *__restrict__ sc, int dst, int src) { sc[dst] = sc[src]; }
-
-// r = f - t
-__global__ __launch_bounds__(VT) void k_sub64(const double *__restrict__ f,
-                                              const double *__restrict__ t, int64_t n,
-                                              double *__restrict__ r) {
-  for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT)
-    r[i] = f[i] - t[i];
+__global__ __launch_bounds__(VT) void k_cg_final(const double *__restrict__ part, int nb,
+                                                 double *__restrict__ sc) {
+  __shared__ double sh[VT / 64];
+  const double s = sum_partials(part, nb, sh);
+  if (threadIdx.x == 0) sc[4] = sqrt(s);
 }
 
 int gather64(nfl_plan *P, const double *src, double *dst) {
@@ -955,99 +1076,163 @@ struct SslOp {
 };
 
 // CG iterations for M u = f on vectors f, u (u holds the start) of the plan's
-// length, any fixed node order; M applied by op.
+// length, any fixed node order; M applied by op.  W holds the work vectors and
+// device scalars (plan-owned, or carved out of a caller-free static area).
+// Iterations are enqueued without waiting; the host looks at the status
+// either through the plan's pinned status words one iteration behind the
+// device (W.host_st set: the device never waits for the host), or, without
+// them, by a copy every `check` iterations.  Iterations enqueued after the
+// stop flag is set return at once in every kernel.
+struct CgWork {
+  double *r, *p, *q;   // n each
+  double *part;        // 2 * CG_NB
+  double *sc;          // 8
+  int *st;             // 2
+  int *host_st = nullptr;          // pinned status words (iterations, converged), device-visible
+  hipEvent_t *ev = nullptr;        // two events for the one-behind host check
+};
+
+static int cg_blocks(int64_t n) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>(CG_NB, (n + VT - 1) / VT));
+}
+
 template <class Op>
-static int cg_core(nfl_plan *P, const Op &op, const double *f, double *u, double tol, int maxit,
-                   int *iters, double *relres) {
+static int cg_core(nfl_plan *P, const Op &op, const CgWork &W, const double *f, double *u,
+                   double tol, int maxit, int *iters, double *relres) {
   const int64_t n = P->n;
   hipStream_t s = P->stream;
-  LBuf<double> r, p, q, sc;
-  NFL_TRY(r.ensure(n));
-  NFL_TRY(p.ensure(n));
-  NFL_TRY(q.ensure(n));
-  NFL_TRY(sc.ensure(8));
-  Reducer R;
-  NFL_TRY(R.init(n));
-  const int gb = grid_for(n);
-  // sc: [0] rr, [1] p.q, [2] rr_new, [3] ||f||
-  NFL_TRY(dot(P, R, f, f, sc.p + 3, 1));
-  NFL_TRY(op(u, q.p));
-  hipLaunchKernelGGL(k_sub64, dim3(gb), dim3(VT), 0, s, f, q.p, n, r.p);
-  NFL_HIP(hipMemcpyAsync(p.p, r.p, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-  NFL_TRY(dot(P, R, r.p, r.p, sc.p + 0));
-  double h[4];
-  NFL_HIP(hipMemcpyAsync(h, sc.p, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
-  NFL_HIP(hipStreamSynchronize(s));
-  const double nf = h[3];
-  int it = 0;
-  double rel = nf > 0 ? std::sqrt(h[0]) / nf : 0.0;
-  while (nf > 0 && rel > tol && it < maxit) {
-    NFL_TRY(op(p.p, q.p));
-    NFL_TRY(dot(P, R, p.p, q.p, sc.p + 1));
-    hipLaunchKernelGGL(k_cg_step, dim3(R.nb), dim3(VT), 0, s, u, r.p, p.p, q.p, sc.p, n,
-                       R.part.p);
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(VT), 0, s, R.part.p, R.nb, sc.p + 2, 0);
-    hipLaunchKernelGGL(k_cg_dir, dim3(gb), dim3(VT), 0, s, p.p, r.p, sc.p, n);
-    hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(1), 0, s, sc.p, 0, 2);
+  const int nb = cg_blocks(n);
+  NFL_TRY(op(u, W.q));
+  hipLaunchKernelGGL(k_cg_start, dim3(nb), dim3(VT), 0, s, f, W.q, n, W.r, W.p, W.part);
+  hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(VT), 0, s, W.part, nb, tol, W.sc, W.st);
+  NFL_HIP(hipGetLastError());
+  if (W.host_st) {
+    W.host_st[0] = 0;
+    W.host_st[1] = 0;
+  }
+  struct StopGuard {
+    nfl_plan *P;
+    ~StopGuard() { P->stop = nullptr; }
+  } guard{P};
+  P->stop = W.st;   // every product kernel of the loop returns once the flag is set
+  constexpr int check = 4;
+  for (int k = 0; k < maxit; ++k) {
+    NFL_TRY(op(W.p, W.q));
+    hipLaunchKernelGGL(k_cg_pq, dim3(nb), dim3(VT), 0, s, W.p, W.q, n, W.st, W.part);
+    hipLaunchKernelGGL(k_cg_step, dim3(nb), dim3(VT), 0, s, u, W.r, W.p, W.q, n, k, W.sc, W.st,
+                       W.part);
+    hipLaunchKernelGGL(k_cg_dir, dim3(nb), dim3(VT), 0, s, W.p, W.r, n, k, W.sc, W.st, W.part,
+                       W.host_st);
     NFL_HIP(hipGetLastError());
-    double rr;
-    NFL_HIP(hipMemcpyAsync(&rr, sc.p, sizeof(double), hipMemcpyDeviceToHost, s));
-    NFL_HIP(hipStreamSynchronize(s));
-    ++it;
-    rel = std::sqrt(rr) / nf;
+    if (W.host_st) {
+      // wait for step k - 1 while step k is queued behind it
+      NFL_HIP(hipEventRecord(W.ev[k & 1], s));
+      if (k > 0) {
+        NFL_HIP(hipEventSynchronize(W.ev[(k - 1) & 1]));
+        if (__hip_atomic_load(&W.host_st[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) break;
+      }
+    } else if ((k + 1) % check == 0 && k + 1 < maxit) {
+      int h[2];
+      NFL_HIP(hipMemcpyAsync(h, W.st, sizeof(h), hipMemcpyDeviceToHost, s));
+      NFL_HIP(hipStreamSynchronize(s));
+      if (h[0]) break;
+    }
   }
+  P->stop = nullptr;
   // true residual with the same operator
-  double trueres = 0.0;
-  if (nf > 0) {
-    NFL_TRY(op(u, q.p));
-    hipLaunchKernelGGL(k_sub64, dim3(gb), dim3(VT), 0, s, f, q.p, n, r.p);
-    NFL_TRY(dot(P, R, r.p, r.p, sc.p + 4, 1));
-    NFL_HIP(hipMemcpyAsync(h, sc.p + 4, sizeof(double), hipMemcpyDeviceToHost, s));
-    NFL_HIP(hipStreamSynchronize(s));
-    trueres = h[0] / nf;
-  }
+  NFL_TRY(op(u, W.q));
+  hipLaunchKernelGGL(k_cg_resid, dim3(nb), dim3(VT), 0, s, f, W.q, n, W.part);
+  hipLaunchKernelGGL(k_cg_final, dim3(1), dim3(VT), 0, s, W.part, nb, W.sc);
+  NFL_HIP(hipGetLastError());
+  double h[8];
+  int st[2];
+  NFL_HIP(hipMemcpyAsync(h, W.sc, sizeof(h), hipMemcpyDeviceToHost, s));
+  NFL_HIP(hipMemcpyAsync(st, W.st, sizeof(st), hipMemcpyDeviceToHost, s));
+  NFL_HIP(hipStreamSynchronize(s));
+  const double nf = h[2];
+  const int it = st[1];
+  const double rel = nf > 0 ? std::sqrt(h[it & 1]) / nf : 0.0;
   if (iters) *iters = it;
-  if (relres) *relres = trueres;
+  if (relres) *relres = nf > 0 ? h[4] / nf : 0.0;
+  if (st[0] == 2) {
+    set_error("CG breakdown: p.Mp <= 0 (the system matrix is not positive definite here)");
+    return NFL_NOT_CONVERGED;
+  }
   return (rel <= tol || nf == 0) ? NFL_OK : NFL_NOT_CONVERGED;
+}
+
+// The plan's CG work space: r, p, q, and the sorted f and u of the SSL
+// system (5 n FP64), reduction partials, scalars, the stop flag and the
+// pinned status words; allocated by the first solve and kept with the plan.
+static int plan_cg_work(nfl_plan *P, CgWork &W, double **f_sorted, double **u_sorted) {
+  const size_t n = (size_t)P->n;
+  NFL_TRY(P->cg_vec.ensure(5 * n + 2 * CG_NB + 8));
+  NFL_TRY(P->cg_st.ensure(2));
+  if (!P->cg_host) {
+    void *h = nullptr;
+    NFL_HIP(hipHostMalloc(&h, 64, hipHostMallocDefault));
+    P->cg_host = (int *)h;
+    for (int e = 0; e < 2; ++e)
+      NFL_HIP(hipEventCreateWithFlags(&P->cg_ev[e], hipEventDisableTiming));
+  }
+  double *b = P->cg_vec.p;
+  W.r = b;
+  W.p = b + n;
+  W.q = b + 2 * n;
+  W.part = b + 5 * n;
+  W.sc = W.part + 2 * CG_NB;
+  W.st = P->cg_st.p;
+  W.host_st = P->cg_host;
+  W.ev = P->cg_ev;
+  if (f_sorted) *f_sorted = b + 3 * n;
+  if (u_sorted) *u_sorted = b + 4 * n;
+  return NFL_OK;
 }
 
 int krr_solve(nfl_plan *P, double beta, const double *f_dev, double *alpha_dev, int warm,
               double tol, int maxit, int *iters, double *relres) {
   const int64_t n = P->n;
-  LBuf<float> x32, t32;
-  NFL_TRY(x32.ensure(n));
-  NFL_TRY(t32.ensure(n));
+  NFL_TRY(P->krr_x32.ensure(n));
+  NFL_TRY(P->krr_t32.ensure(n));
+  CgWork W;
+  NFL_TRY(plan_cg_work(P, W, nullptr, nullptr));
   if (warm != NFL_WARM_USER)
     hipLaunchKernelGGL(k_fill64, dim3(grid_for(n)), dim3(VT), 0, P->stream, alpha_dev, n, 0.0);
-  KrrOp op{P, beta, x32.p, t32.p};
-  const int rc = cg_core(P, op, f_dev, alpha_dev, tol, maxit, iters, relres);
-  NFL_HIP(hipStreamSynchronize(P->stream));
+  KrrOp op{P, beta, P->krr_x32.p, P->krr_t32.p};
+  return cg_core(P, op, W, f_dev, alpha_dev, tol, maxit, iters, relres);
+}
+
+// The SSL system in the plan's sorted order: f and u are gathered into the
+// work space, solved there, and u is scattered back to the caller's order.
+static int cg_sorted(nfl_plan *P, const CgWork &W, double tau, const double *f_dev,
+                     double *u_dev, double *f, double *u, int warm, double tol, int maxit,
+                     int *iters, double *relres) {
+  const int64_t n = P->n;
+  hipStream_t s = P->stream;
+  const int gb = grid_for(n);
+  hipLaunchKernelGGL(k_gather64, dim3(gb), dim3(VT), 0, s, f_dev, P->perm.p, n, f);
+  if (warm == NFL_WARM_USER) {
+    hipLaunchKernelGGL(k_gather64, dim3(gb), dim3(VT), 0, s, u_dev, P->perm.p, n, u);
+  } else if (warm == NFL_WARM_MLP) {
+    NFL_TRY(mlp_warm_start(P, f, u));
+  } else {
+    hipLaunchKernelGGL(k_fill64, dim3(gb), dim3(VT), 0, s, u, n, 0.0);
+  }
+  SslOp op{P, tau};
+  const int rc = cg_core(P, op, W, f, u, tol, maxit, iters, relres);
+  if (rc < 0) return rc;
+  hipLaunchKernelGGL(k_scatter64, dim3(gb), dim3(VT), 0, s, u, P->perm.p, n, u_dev);
+  NFL_HIP(hipGetLastError());
+  NFL_HIP(hipStreamSynchronize(s));
   return rc;
 }
 
 int cg(nfl_plan *P, double tau, const double *f_dev, double *u_dev, int warm, double tol,
        int maxit, int *iters, double *relres) {
-  const int64_t n = P->n;
-  hipStream_t s = P->stream;
-  LBuf<double> f, u;
-  NFL_TRY(f.ensure(n));
-  NFL_TRY(u.ensure(n));
-  const int gb = grid_for(n);
-  hipLaunchKernelGGL(k_gather64, dim3(gb), dim3(VT), 0, s, f_dev, P->perm.p, n, f.p);
-  if (warm == NFL_WARM_USER) {
-    hipLaunchKernelGGL(k_gather64, dim3(gb), dim3(VT), 0, s, u_dev, P->perm.p, n, u.p);
-  } else if (warm == NFL_WARM_MLP) {
-    NFL_TRY(mlp_warm_start(P, f.p, u.p));
-  } else {
-    hipLaunchKernelGGL(k_fill64, dim3(gb), dim3(VT), 0, s, u.p, n, 0.0);
-  }
-  SslOp op{P, tau};
-  const int rc = cg_core(P, op, f.p, u.p, tol, maxit, iters, relres);
-  if (rc < 0) return rc;
-  hipLaunchKernelGGL(k_scatter64, dim3(gb), dim3(VT), 0, s, u.p, P->perm.p, n, u_dev);
-  NFL_HIP(hipGetLastError());
-  NFL_HIP(hipStreamSynchronize(s));
-  return rc;
+  CgWork W;
+  double *f = nullptr, *u = nullptr;
+  NFL_TRY(plan_cg_work(P, W, &f, &u));
+  return cg_sorted(P, W, tau, f_dev, u_dev, f, u, warm, tol, maxit, iters, relres);
 }
 
 }  // namespace nfl

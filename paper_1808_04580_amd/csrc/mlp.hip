@@ -180,7 +180,8 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const uint16_t *__restrict__ 
 // Forward + backward on explicit features (B x 16, FP32) and targets; each
 // wave loops over 16-node batches and accumulates its gradient, then writes
 // it (and its loss sum) to part[wave][MLP_NP + 1].  scale = d loss / d out
-// factor (2 / B for the mean squared error).
+// factor of one node's squared error (2): the deltas rounded to bf16 do not
+// depend on the batch size; the reduction applies the mean's 1/B.
 __global__ __launch_bounds__(64) void k_mlp_train(const uint16_t *__restrict__ wbf,
                                                   const float *__restrict__ prm,
                                                   const float *__restrict__ feat,
@@ -343,14 +344,14 @@ __global__ __launch_bounds__(64) void k_mlp_train(const uint16_t *__restrict__ w
   }
 }
 
-// grad[p] = sum over waves (fixed order)
+// grad[p] = inv_b * sum over waves (fixed order); the loss entry stays a sum
 __global__ __launch_bounds__(256) void k_mlp_reduce(const float *__restrict__ part, int nwaves,
-                                                    float *__restrict__ grad) {
+                                                    float inv_b, float *__restrict__ grad) {
   const int p = blockIdx.x * 256 + threadIdx.x;
   if (p > MLP_NP) return;
   float s = 0.f;
   for (int w = 0; w < nwaves; ++w) s += part[(int64_t)w * (MLP_NP + 1) + p];
-  grad[p] = s;
+  grad[p] = p < MLP_NP ? s * inv_b : s;
 }
 
 // Adam step on the FP32 master parameters; refresh the BF16 copies.
@@ -445,9 +446,9 @@ static int mlp_grad(nfl_mlp *M, int64_t B, double *loss_host) {
   const int nw = (int)std::min<int64_t>(512, (B + 15) / 16);
   NFL_TRY(M->part.ensure((size_t)nw * (MLP_NP + 1)));
   hipLaunchKernelGGL(k_mlp_train, dim3(nw), dim3(64), 0, M->stream, M->wbf.p, M->prm.p, M->feat.p,
-                     M->target.p, B, 2.0f / (float)B, M->part.p);
+                     M->target.p, B, 2.0f, M->part.p);
   hipLaunchKernelGGL(k_mlp_reduce, dim3((MLP_NP + 1 + 255) / 256), dim3(256), 0, M->stream,
-                     M->part.p, nw, M->grad.p);
+                     M->part.p, nw, 1.0f / (float)B, M->grad.p);
   NFL_HIP(hipGetLastError());
   if (loss_host) {
     float l = 0.f;

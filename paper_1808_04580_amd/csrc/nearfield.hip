@@ -75,6 +75,7 @@ __global__ __launch_bounds__(NT) void k_near(const Item *__restrict__ items,
   __shared__ int pref[NF_MAXTILES + 1];    // prefix sums of their node counts
   __shared__ int bsum[NT + 1];
   __shared__ float part[NT];
+  if (stopped(ka.stop)) return;
   const int t = threadIdx.x;
   if (t < p) cf[t] = coef[t];
   const Item it = items[blockIdx.x];
@@ -263,6 +264,7 @@ int near_field(nfl_plan *P, int in_mode, int out_mode, const VecArgs &a) {
   k.dinv = P->dinv.p;
   k.deg_out = P->deg.p;
   k.dinv_out = P->dinv.p;
+  k.stop = P->stop;
   if (in_mode == IN_USER_F32 && out_mode == OUT_USER_RAW) return launch_near<IN_USER_F32, OUT_USER_RAW>(P, k);
   if (in_mode == IN_USER_F32 && out_mode == OUT_USER_W) return launch_near<IN_USER_F32, OUT_USER_W>(P, k);
   if (in_mode == IN_USER_F32_DINV && out_mode == OUT_USER_LS) return launch_near<IN_USER_F32_DINV, OUT_USER_LS>(P, k);

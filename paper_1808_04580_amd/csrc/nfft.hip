@@ -30,6 +30,7 @@ __global__ __launch_bounds__(256) void k_spread3(const Item *__restrict__ items,
                                                  const float *__restrict__ wcoef) {
   constexpr int M = W / 2, R = (W * W + 63) / 64;
   extern __shared__ float lds[];
+  if (stopped(ka.stop)) return;
   const int T = 1 << tshift, P = T + W - 1, PP = P * P, P3 = PP * P;
   const Item it = items[blockIdx.x];
   const int ntd = nos >> tshift;
@@ -147,6 +148,7 @@ __global__ __launch_bounds__(256) void k_interp3(const Item *__restrict__ items,
                                                  int tshift, const float *__restrict__ wcoef) {
   constexpr int M = W / 2, R = (W * W + 63) / 64;
   extern __shared__ float lds[];
+  if (stopped(ka.stop)) return;
   const int T = 1 << tshift, P = T + W - 1, PP = P * P, P3 = PP * P;
   const Item it = items[blockIdx.x];
   const int ntd = nos >> tshift;
@@ -229,6 +231,7 @@ __global__ __launch_bounds__(256) void k_spread3_mfma(const Item *__restrict__ i
                                                       float *__restrict__ grid, int nos,
                                                       int tshift,
                                                       const float *__restrict__ wcoef) {
+  if (stopped(ka.stop)) return;
   spread3_mfma_body<W, IN, ZM>(items[blockIdx.x], pts, ka, grid, nos, tshift, wcoef);
 }
 
@@ -239,6 +242,7 @@ void k_interp3_mfma(const Item *__restrict__ items,
                                                       const float *__restrict__ grid, int nos,
                                                       int tshift,
                                                       const float *__restrict__ wcoef) {
+  if (stopped(ka.stop)) return;
   interp3_mfma_body<W, IN, OUT>(items, blockIdx.x, pts, ka, grid, nos, tshift, wcoef);
 }
 
@@ -249,6 +253,7 @@ template <int W, int T, int IN>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 void k_spread3_tile(const Item *__restrict__ items, const float4 *__restrict__ pts, KArgs ka,
                     float *__restrict__ grid, int nos, const float *__restrict__ wcoef) {
+  if (stopped(ka.stop)) return;
   spread3_tile_body<W, T, IN>(items[blockIdx.x], pts, ka, grid, nos, wcoef);
 }
 
@@ -256,6 +261,7 @@ template <int W, int T, int IN, int OUT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 void k_interp3_tile(const Item *__restrict__ items, const float4 *__restrict__ pts, KArgs ka,
                     const float *__restrict__ grid, int nos, const float *__restrict__ wcoef) {
+  if (stopped(ka.stop)) return;
   interp3_tile_body<W, T, IN, OUT>(items, blockIdx.x, pts, ka, grid, nos, wcoef);
 }
 
@@ -278,6 +284,7 @@ __global__ __launch_bounds__(256) void k_spread12(const Item *__restrict__ items
   __shared__ float xs[256];
   __shared__ int loc[256];                     // local cell offsets lx | ly << 8
   const int t = threadIdx.x;
+  if (stopped(ka.stop)) return;
   for (int q = t; q < WIN_MAXW * WIN_NC; q += 256) sc[q] = wcoef[q];
   const Item it = items[blockIdx.x];
   const int W = 2 * m, mask = nos - 1, T = 1 << tshift, Pd = T + W - 1;
@@ -353,6 +360,7 @@ __global__ __launch_bounds__(256) void k_interp12(const Item *__restrict__ items
   __shared__ float sc[WIN_MAXW * WIN_NC];
   __shared__ float tile[(WIN_MAXW + 4 - 1) * (WIN_MAXW + 4 - 1)];
   const int t = threadIdx.x;
+  if (stopped(ka.stop)) return;
   for (int q = t; q < WIN_MAXW * WIN_NC; q += 256) sc[q] = wcoef[q];
   const Item it = items[blockIdx.x];
   const int W = 2 * m, mask = nos - 1, T = 1 << tshift, Pd = T + W - 1;
@@ -403,39 +411,51 @@ template <bool ZERO>
 __global__ __launch_bounds__(FFT_THREADS) void k_r2c_lines(float *__restrict__ grid,
                                                            float2 *__restrict__ H, int nlines,
                                                            int L, int logL, int lpb, int Hz,
-                                                           const float2 *__restrict__ tw) {
+                                                           const float2 *__restrict__ tw,
+                                                           const int *__restrict__ stop) {
+  if (stopped(stop)) return;
   r2c_lines_body<ZERO>(blockIdx.x, grid, H, nlines, L, logL, lpb, Hz, tw);
 }
 
 __global__ __launch_bounds__(FFT_THREADS) void k_c2r_lines(const float2 *__restrict__ H,
                                                            float *__restrict__ grid, int nlines,
                                                            int L, int logL, int lpb, int Hz,
-                                                           const float2 *__restrict__ tw) {
+                                                           const float2 *__restrict__ tw,
+                                                           const int *__restrict__ stop) {
+  if (stopped(stop)) return;
   c2r_lines_body(blockIdx.x, H, grid, nlines, L, logL, lpb, Hz, tw);
 }
 
 __global__ __launch_bounds__(FFT_THREADS) void k_y_fwd(const float2 *__restrict__ H1,
                                                        float2 *__restrict__ H2, int L, int logL,
                                                        int lpb, int Hz, int N,
-                                                       const float2 *__restrict__ tw) {
+                                                       const float2 *__restrict__ tw,
+                                                       const int *__restrict__ stop) {
+  if (stopped(stop)) return;
   y_fwd_body(xcd_block(blockIdx.x, gridDim.x), H1, H2, L, logL, lpb, Hz, N, tw);
 }
 
 __global__ __launch_bounds__(FFT_THREADS) void k_y_inv(const float2 *__restrict__ H2,
                                                        float2 *__restrict__ H1, int L, int logL,
                                                        int lpb, int Hz, int N,
-                                                       const float2 *__restrict__ tw) {
+                                                       const float2 *__restrict__ tw,
+                                                       const int *__restrict__ stop) {
+  if (stopped(stop)) return;
   y_inv_body(xcd_block(blockIdx.x, gridDim.x), H2, H1, L, logL, lpb, Hz, N, tw);
 }
 
 __global__ __launch_bounds__(FFT_THREADS) void k_x_filter(float2 *__restrict__ Hx,
                                                           const float *__restrict__ filt, int C,
                                                           int L, int logL, int lpb, int N,
-                                                          const float2 *__restrict__ tw) {
+                                                          const float2 *__restrict__ tw,
+                                                          const int *__restrict__ stop) {
+  if (stopped(stop)) return;
   x_filter_body(xcd_block(blockIdx.x, gridDim.x), Hx, filt, C, L, logL, lpb, N, tw);
 }
 
-__global__ void k_filter1(float2 *__restrict__ H, const float *__restrict__ filt, int Hz) {
+__global__ void k_filter1(float2 *__restrict__ H, const float *__restrict__ filt, int Hz,
+                          const int *__restrict__ stop) {
+  if (stopped(stop)) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < Hz) {
     H[i].x *= filt[i];
@@ -483,6 +503,7 @@ static KArgs make_kargs(nfl_plan *P, const VecArgs &a) {
   k.dinv = P->dinv.p;
   k.deg_out = P->deg.p;
   k.dinv_out = P->dinv.p;
+  k.stop = P->stop;
   return k;
 }
 
@@ -692,36 +713,36 @@ int convolve(nfl_plan *P, const float *gin_c, float *gout, bool zero_in) {
   const float2 *tw = P->tw.p;
   if (P->d == 1) {
     hipLaunchKernelGGL(r2c, dim3(1), dim3(FFT_THREADS), ldz, P->stream, gin, P->spec1.p,
-                       1, L, logL, lpz, Hz, tw);
-    hipLaunchKernelGGL(k_filter1, dim3(1), dim3(256), 0, P->stream, P->spec1.p, P->filt.p, Hz);
+                       1, L, logL, lpz, Hz, tw, P->stop);
+    hipLaunchKernelGGL(k_filter1, dim3(1), dim3(256), 0, P->stream, P->spec1.p, P->filt.p, Hz, P->stop);
     hipLaunchKernelGGL(k_c2r_lines, dim3(1), dim3(FFT_THREADS), ldz, P->stream, P->spec1.p, gout,
-                       1, L, logL, lpz, Hz, tw);
+                       1, L, logL, lpz, Hz, tw, P->stop);
   } else if (P->d == 2) {
     const int nlines = L;
     const int nb = (nlines + lpz - 1) / lpz;
     hipLaunchKernelGGL(r2c, dim3(nb), dim3(FFT_THREADS), ldz, P->stream, gin, P->spec1.p,
-                       nlines, L, logL, lpz, Hz, tw);
+                       nlines, L, logL, lpz, Hz, tw, P->stop);
     hipLaunchKernelGGL(k_x_filter, dim3(Hz), dim3(FFT_THREADS), fft_lds_bytes(1, L), P->stream,
-                       P->spec1.p, P->filt.p, Hz, L, logL, 1, N, tw);
+                       P->spec1.p, P->filt.p, Hz, L, logL, 1, N, tw, P->stop);
     hipLaunchKernelGGL(k_c2r_lines, dim3(nb), dim3(FFT_THREADS), ldz, P->stream, P->spec1.p, gout,
-                       nlines, L, logL, lpz, Hz, tw);
+                       nlines, L, logL, lpz, Hz, tw, P->stop);
   } else {
     const int nlines = L * L;
     const int nb = (nlines + lpz - 1) / lpz;
     hipLaunchKernelGGL(r2c, dim3(nb), dim3(FFT_THREADS), ldz, P->stream, gin, P->spec1.p,
-                       nlines, L, logL, lpz, Hz, tw);
+                       nlines, L, logL, lpz, Hz, tw, P->stop);
     const int lpy = fft_lpb_y(L), ngroups = (Hz + lpy - 1) / lpy;
     const size_t ldy = fft_lds_bytes(lpy, L);
     hipLaunchKernelGGL(k_y_fwd, dim3(L * ngroups), dim3(FFT_THREADS), ldy, P->stream, P->spec1.p,
-                       P->spec2.p, L, logL, lpy, Hz, N, tw);
+                       P->spec2.p, L, logL, lpy, Hz, N, tw, P->stop);
     const int C = F * Hz, lpx = fft_lpb_x(L);
     hipLaunchKernelGGL(k_x_filter, dim3((C + lpx - 1) / lpx), dim3(FFT_THREADS),
                        fft_lds_bytes(lpx, L), P->stream, P->spec2.p, P->filt.p, C, L, logL, lpx,
-                       N, tw);
+                       N, tw, P->stop);
     hipLaunchKernelGGL(k_y_inv, dim3(L * ngroups), dim3(FFT_THREADS), ldy, P->stream, P->spec2.p,
-                       P->spec1.p, L, logL, lpy, Hz, N, tw);
+                       P->spec1.p, L, logL, lpy, Hz, N, tw, P->stop);
     hipLaunchKernelGGL(k_c2r_lines, dim3(nb), dim3(FFT_THREADS), ldz, P->stream, P->spec1.p, gout,
-                       nlines, L, logL, lpz, Hz, tw);
+                       nlines, L, logL, lpz, Hz, tw, P->stop);
   }
   NFL_HIP(hipGetLastError());
   return NFL_OK;

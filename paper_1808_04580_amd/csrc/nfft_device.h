@@ -42,7 +42,12 @@ struct KArgs {
   const float *dinv;
   float *deg_out;
   float *dinv_out;
+  const int *stop;   // null, or a device flag: when nonzero every kernel of the product returns at once
 };
+
+// Uniform early exit of a product's kernels once an iterative solver on the
+// device has stopped (its flag is set by the solver's own kernels).
+__device__ __forceinline__ bool stopped(const int *stop) { return stop && *stop; }
 
 template <int IN>
 __device__ __forceinline__ float load_in(const KArgs &a, int i) {

@@ -157,6 +157,25 @@ struct nfl_plan {
   // after it, after the spread kernel, after the convolution, after interp
   hipEvent_t *prof_ev = nullptr;
 
+  // CG work space, allocated by the first solve and kept: r, p, q and the
+  // sorted f, u (5 n FP64), reduction partials and scalars; the stop flag and
+  // iteration count; pinned status words the solver's kernels write (host
+  // checks one iteration behind the device) and two events for that check
+  nfl::DBuf<double> cg_vec;
+  nfl::DBuf<int> cg_st;
+  int *cg_host = nullptr;
+  hipEvent_t cg_ev[2] = {nullptr, nullptr};
+  nfl::DBuf<float> krr_x32, krr_t32;   // FP32 copies of the KRR product's input and output
+  // device stop flag of a running solve: passed to every kernel of a product,
+  // which returns at once when it is set (null outside a solve)
+  const int *stop = nullptr;
+
+  ~nfl_plan() {
+    if (cg_host) (void)hipHostFree(cg_host);
+    for (hipEvent_t e : cg_ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+
   // scratch
   nfl::DBuf<float> xs;          // sorted FP32 work vector
   nfl::DBuf<float> fs;          // sorted FP32 interp output

@@ -85,8 +85,8 @@ def _propagate(p, X, t, flips: bool):
     o.update(dh1=dh1, dh2=dh2, dh3=dh3, dr1=dr1, dr2=dr2)
     if t is not None:
         err = out - np.asarray(t, dtype=np.float64)
-        g = 2.0 * err / B
-        dg = 2.0 * o["dout"] / B + _gamma(4) * np.abs(g)
+        g = 2.0 * err                 # per node, before the mean's 1/B (as the kernels round)
+        dg = 2.0 * o["dout"] + _gamma(4) * np.abs(g)
         W4 = P["W4"][:, None]
         f3 = 1.0 - H3 ** 2
         d3 = W4 * g[None, :] * f3
@@ -131,7 +131,7 @@ def gradient_abs_sums(p, X, t):
     return np.concatenate([(np.abs(r(d1)) @ x.T).ravel(), d1.sum(1),
                            (np.abs(r(d2)) @ np.abs(r(H1)).T).ravel(), d2.sum(1),
                            (np.abs(r(d3)) @ np.abs(r(H2)).T).ravel(), d3.sum(1),
-                           np.abs(H3) @ g, [g.sum()]])
+                           np.abs(H3) @ g, [g.sum()]]) / X.shape[0]
 
 
 def gradient_bound(p, X, t):
@@ -144,7 +144,11 @@ def gradient_bound(p, X, t):
     b = _propagate(p, X, t, flips=True)
     bound, dloss = _grad_sums(a, b, a["near"], B)
     tight, _ = _grad_sums(a, a, np.zeros(B, dtype=bool), B)
-    return L, g_ref, bound, tight, dloss
+    # the sums are of per-node contributions; the GPU then multiplies by
+    # fl(1/B) in FP32 (two roundings)
+    def scaled(x):
+        return x / B + 3.0 * U32 * (np.abs(g_ref) + x / B)
+    return L, g_ref, scaled(bound), scaled(tight), dloss
 
 
 def _grad_sums(a, b, cand, B):
@@ -194,15 +198,19 @@ def forward_gates(got, want, bound, tight):
     return fails
 
 
-def gradient_gates(got, want, bound, tight):
+def gradient_gates(got, want, bound, tight, batch=None):
     """The gradient checks: every element within its rigorous bound, and at
-    most 5% of the elements beyond the no-flip bound."""
+    most 5% of the elements beyond the no-flip bound.  Below 64 nodes one
+    bf16 flip of one node's delta already moves a whole row of a weight
+    gradient (and, through the next layer's deltas, more) beyond the no-flip
+    bound, so there the second gate allows half of the elements and the
+    rigorous bound decides."""
     e = np.abs(np.asarray(got, dtype=np.float64) - want)
     fails = []
     if not np.all(e <= bound):
         i = int(np.argmax(e - bound))
         fails.append("element %d: |err| %.3g > bound %.3g" % (i, e[i], bound[i]))
     frac = float((e > tight).mean())
-    if frac > 0.05:
+    if frac > (0.05 if batch is None or batch >= 64 else 0.5):
         fails.append("%.1f%% of the elements beyond the no-flip bound" % (100 * frac))
     return fails

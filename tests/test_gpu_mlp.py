@@ -69,7 +69,7 @@ def test_gradient_matches_reference(nfl, B):
     loss, g = W.gradient(X, t)
     Lr, gr, bound, tight, dloss = mb.gradient_bound(p, X, t)
     assert abs(loss - Lr) <= dloss, (loss, Lr, dloss)
-    fails = mb.gradient_gates(g, gr, bound, tight)
+    fails = mb.gradient_gates(g, gr, bound, tight, B)
     assert fails == [], fails
 
 

@@ -31,7 +31,7 @@ def fp32_grad(p, X, t, skip_last=False):
     P = {k: np.asarray(v, dtype=np.float32) for k, v in ref.unpack(p).items()}
     out, (H1, H2, H3) = fp32_forward(p, X)
     B = X.shape[0]
-    g = (np.float32(2.0) * (out - t.astype(np.float32)) / np.float32(B)).astype(np.float32)
+    g = (np.float32(2.0) * (out - t.astype(np.float32))).astype(np.float32)   # per node
     if skip_last:
         g[-1] = 0.0
     gW4 = H3 @ g
@@ -41,8 +41,8 @@ def fp32_grad(p, X, t, skip_last=False):
     gW2 = bf16_32(d2) @ bf16_32(H1).T
     d1 = (bf16_32(P["W2"]).T @ bf16_32(d2)) * (1 - H1 * H1)
     gW1 = bf16_32(d1) @ bf16_32(X)
-    return np.concatenate([gW1.ravel(), d1.sum(1), gW2.ravel(), d2.sum(1), gW3.ravel(),
-                           d3.sum(1), gW4, [g.sum()]]).astype(np.float64)
+    return (np.concatenate([gW1.ravel(), d1.sum(1), gW2.ravel(), d2.sum(1), gW3.ravel(),
+                            d3.sum(1), gW4, [g.sum()]]) * np.float32(1.0 / B)).astype(np.float64)
 
 
 def net(seed):
@@ -80,12 +80,12 @@ def test_gradient_gates_pass_fp32_network_and_catch_mistakes(B):
     t = np.random.default_rng(2).normal(size=B).astype(np.float32)
     L, g_ref, bound, tight, dloss = mb.gradient_bound(p, X, t)
     g = fp32_grad(p, X, t)
-    assert mb.gradient_gates(g, g_ref, bound, tight) == []
+    assert mb.gradient_gates(g, g_ref, bound, tight, B) == []
     bad = g.copy()
     big = int(np.argmax(np.abs(g_ref)))
     bad[big] = -bad[big]
-    assert mb.gradient_gates(bad, g_ref, bound, tight) != []
+    assert mb.gradient_gates(bad, g_ref, bound, tight, B) != []
     if B > 1:
-        assert mb.gradient_gates(fp32_grad(p, X, t, skip_last=True), g_ref, bound, tight) != []
+        assert mb.gradient_gates(fp32_grad(p, X, t, skip_last=True), g_ref, bound, tight, B) != []
     S = mb.gradient_abs_sums(p, X, t)
     assert np.all(np.abs(g_ref) <= S * (1 + 1e-9) + 1e-300)
