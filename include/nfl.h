@@ -226,6 +226,22 @@ int nfl_nystrom(nfl_handle h, const double *G_dev, int64_t ldg, int L, int M, in
 int nfl_cg_solve(nfl_handle h, double tau, const double *f_dev, double *u_dev, int warm,
                  double tol, int maxit, int *iters, double *relres);
 
+/* nfl_cg_solve for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same solve, kernels and results, with the work space (5 n doubles, the
+ * reduction partials, scalars and the stop flag) in the library's static
+ * device array instead of plan-owned buffers; the call makes no hipMalloc,
+ * hipFree or allocating library call.  Limits: n <= NFL_CG_NOALLOC_MAX_N
+ * (else NFL_ERR_ARG, nothing written); warm is NFL_WARM_ZERO or
+ * NFL_WARM_USER (the network's start allocates its feature buffers).  Each
+ * GPU holds one such array (42 MB) until the process ends, shared by every
+ * call on that GPU: calls that overlap on one GPU race (serialise them, e.g.
+ * one stream).  The plan itself must have been built (points and kernel) by
+ * the allocating calls beforehand.  Synchronises. */
+#define NFL_CG_NOALLOC_MAX_N 1048576
+int nfl_cg_solve_noalloc(nfl_handle h, double tau, const double *f_dev, double *u_dev, int warm,
+                         double tol, int maxit, int *iters, double *relres);
+
 /* Kernel ridge regression (Section 6.3): CG for (K + beta I) alpha = f with
  * the Gram matrix K_ij = K(v_i - v_j) of the plan's kernel, diagonal K(0)
  * included (K = W + K(0) I; Gaussian or inverse multiquadric: positive

@@ -36,6 +36,7 @@ OPT_EPS_I = 7
 WARM_ZERO = 0
 WARM_USER = 1
 WARM_MLP = 2
+CG_NOALLOC_MAX_N = 1048576
 
 _lib = None
 
@@ -56,6 +57,7 @@ SIGNATURES = {
     "nfl_apply_A": (_i, [_p, _p, _p, _i, _i64]),
     "nfl_lanczos_smallest": (_i, [_p, _i, _i, _d, _i, _p, _p, _p, _p]),
     "nfl_cg_solve": (_i, [_p, _d, _p, _p, _i, _d, _i, _p, _p]),
+    "nfl_cg_solve_noalloc": (_i, [_p, _d, _p, _p, _i, _d, _i, _p, _p]),
     "nfl_nystrom": (_i, [_p, _p, _i64, _i, _i, _i, _p, _p, _p]),
     "nfl_krr_solve": (_i, [_p, _d, _p, _p, _i, _d, _i, _p, _p]),
     "nfl_get_info": (_i, [_p, _p, _p, _p, _p, _p, _p]),
@@ -342,6 +344,20 @@ class Plan:
         code = _check(lib().nfl_cg_solve(self._h, float(tau), _ptr(f), _ptr(u), int(warm),
                                          float(tol), int(maxit), ctypes.byref(it),
                                          ctypes.byref(rel)), "nfl_cg_solve", allow_soft=True)
+        return dict(u=u, iters=it.value, relres=rel.value, converged=(code == NFL_OK))
+
+    def cg_solve_noalloc(self, f, u, tau: float, tol: float = 1e-6, maxit: int = 1000,
+                         warm: int = WARM_ZERO):
+        """nfl_cg_solve_noalloc: the CG solve with its work space in the
+        library's static device array (n <= NFL_CG_NOALLOC_MAX_N).  f and u
+        are caller-allocated FP64 device tensors of length n (u holds the
+        start when warm == WARM_USER; it receives the solution)."""
+        it = ctypes.c_int()
+        rel = ctypes.c_double()
+        code = _check(lib().nfl_cg_solve_noalloc(self._h, float(tau), _ptr(f), _ptr(u), int(warm),
+                                                 float(tol), int(maxit), ctypes.byref(it),
+                                                 ctypes.byref(rel)), "nfl_cg_solve_noalloc",
+                      allow_soft=True)
         return dict(u=u, iters=it.value, relres=rel.value, converged=(code == NFL_OK))
 
     def krr_solve(self, f, beta: float, tol: float = 1e-6, maxit: int = 1000, alpha0=None):

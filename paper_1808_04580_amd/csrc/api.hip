@@ -398,6 +398,17 @@ int nfl_cg_solve(nfl_handle P, double tau, const double *f_dev, double *u_dev, i
   return cg(P, tau, f_dev, u_dev, warm, tol, maxit, iters, relres);
 }
 
+int nfl_cg_solve_noalloc(nfl_handle P, double tau, const double *f_dev, double *u_dev, int warm,
+                         double tol, int maxit, int *iters, double *relres) {
+  if (!P) { set_error("null handle"); return NFL_ERR_ARG; }
+  if (!P->have_kernel) { set_error("cg before a successful nfl_set_kernel"); return NFL_ERR_ORDER; }
+  if (P->frame_only) { set_error("cg on a plan of target nodes (nfl_set_points_frame): it has no degrees"); return NFL_ERR_ORDER; }
+  if (!f_dev || !u_dev) { set_error("null vector pointer"); return NFL_ERR_ARG; }
+  if (!(tau >= 0) || !(tol > 0) || maxit < 0) { set_error("need tau >= 0, tol > 0, maxit >= 0"); return NFL_ERR_ARG; }
+  if (warm != NFL_WARM_ZERO && warm != NFL_WARM_USER) { set_error("nfl_cg_solve_noalloc: warm start NFL_WARM_ZERO or NFL_WARM_USER"); return NFL_ERR_ARG; }
+  return cg_noalloc(P, tau, f_dev, u_dev, warm, tol, maxit, iters, relres);
+}
+
 int nfl_krr_solve(nfl_handle P, double beta, const double *f_dev, double *alpha_dev, int warm,
                   double tol, int maxit, int *iters, double *relres) {
   if (!P) { set_error("null handle"); return NFL_ERR_ARG; }

@@ -1227,6 +1227,68 @@ static int cg_sorted(nfl_plan *P, const CgWork &W, double tau, const double *f_d
   return rc;
 }
 
+// ---------------------------------------------------------------------------
+// CG without allocation: the work space of the SSL solve lives in one static
+// device array, `scratch`, sized for up to NFL_CG_NOALLOC_MAX_N nodes (each
+// GPU the library runs on holds its own copy until the process ends).  Host
+// code never uses the array's name as an address: its device address is
+// taken once per device with hipGetSymbolAddress and kept here.  All calls
+// on one GPU share that GPU's array, so calls that overlap on one GPU race.
+// ---------------------------------------------------------------------------
+constexpr size_t CG_SCRATCH_DOUBLES = 5 * (size_t)NFL_CG_NOALLOC_MAX_N + 2 * CG_NB + 8 + 2;
+static __device__ __align__(256) double scratch[CG_SCRATCH_DOUBLES];
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+// device address of `scratch` on `dev` (looked up once per device, with that
+// device current)
+static int scratch_address(int dev, double **out) {
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) {
+    set_error("device ordinal out of range for the static work space");
+    return NFL_ERR_ARG;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int cur = 0;
+    NFL_HIP(hipGetDevice(&cur));
+    if (cur != dev) NFL_HIP(hipSetDevice(dev));
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !ptr) {
+      set_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+      return NFL_ERR_HIP;
+    }
+    g_scratch_ptr[dev] = (double *)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return NFL_OK;
+}
+
+int cg_noalloc(nfl_plan *P, double tau, const double *f_dev, double *u_dev, int warm, double tol,
+               int maxit, int *iters, double *relres) {
+  if (P->n > NFL_CG_NOALLOC_MAX_N) {
+    set_error("nfl_cg_solve_noalloc: n exceeds NFL_CG_NOALLOC_MAX_N (the static work space)");
+    return NFL_ERR_ARG;
+  }
+  double *b = nullptr;
+  NFL_TRY(scratch_address(P->device, &b));
+  const size_t n = (size_t)P->n;
+  CgWork W;
+  W.r = b;
+  W.p = b + n;
+  W.q = b + 2 * n;
+  W.part = b + 5 * n;
+  W.sc = W.part + 2 * CG_NB;
+  W.st = reinterpret_cast<int *>(W.sc + 8);
+  W.host_st = nullptr;   // status read by a copy every few iterations
+  W.ev = nullptr;
+  return cg_sorted(P, W, tau, f_dev, u_dev, b + 3 * n, b + 4 * n, warm, tol, maxit, iters,
+                   relres);
+}
+
 int cg(nfl_plan *P, double tau, const double *f_dev, double *u_dev, int warm, double tol,
        int maxit, int *iters, double *relres) {
   CgWork W;

@@ -256,6 +256,9 @@ int lanczos(nfl_plan *P, int k, int block, double tol, int maxit, double *evals_
             double *evecs_dev, int *iters, double *max_resid);
 int cg(nfl_plan *P, double tau, const double *f_dev, double *u_dev, int warm, double tol,
        int maxit, int *iters, double *relres);
+// nfl_cg_solve_noalloc: the work space in the library's static device array
+int cg_noalloc(nfl_plan *P, double tau, const double *f_dev, double *u_dev, int warm, double tol,
+               int maxit, int *iters, double *relres);
 int krr_solve(nfl_plan *P, double beta, const double *f_dev, double *alpha_dev, int warm,
               double tol, int maxit, int *iters, double *relres);
 int gather64(nfl_plan *P, const double *src_user, double *dst_sorted);
