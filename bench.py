@@ -406,8 +406,34 @@ def small_configs_leg(nfl, synth, torch, dev, steps=100):
         out[name] = {"ms_per_Ls": round(ms, 4), "lanczos10_ms": round(ml, 2),
                      "lanczos10_steps": lz["iters"], "converged": lz["converged"],
                      "evals": [round(float(e), 7) for e in lz["evals"]]}
+        out[name].update(eigen_errors(nfl, torch, dev, name, v, sig, N, m, eps, lz["evals"]))
         log("config %s: %s" % (name, out[name]))
     return out
+
+
+def eigen_errors(nfl, torch, dev, name, v, sig, N, m, eps, evals):
+    """Per-eigenvalue error |lambda_j - lambda_j*| (eq. max_ev_error) against
+    LAPACK on the dense FP64 L_s of the oracle: the blobs on all 5,000 nodes;
+    the image (too large for a dense matrix) on a seeded 5,000-pixel
+    subsample, whose 10 smallest eigenvalues the GPU's Lanczos recomputes
+    with the same sigma, N, m."""
+    from oracle import graph
+    t0 = time.perf_counter()
+    if v.shape[0] <= 5000:
+        lam_ref, _ = graph.smallest_eigs_dense(v, sig, 10)
+        got, where = np.asarray(evals, dtype=np.float64), "all %d nodes" % v.shape[0]
+    else:
+        idx = np.sort(np.random.default_rng(5).choice(v.shape[0], size=5000, replace=False))
+        vs = np.ascontiguousarray(v[idx])
+        P = nfl.plan(torch.as_tensor(vs, device=dev), sig, N=N, m=m, eps_B=eps)
+        got = np.asarray(P.lanczos_smallest(10, tol=1e-8, maxit=300, vectors=False)["evals"])
+        P.close()
+        lam_ref, _ = graph.smallest_eigs_dense(vs, sig, 10)
+        where = "seeded 5,000-pixel subsample (GPU Lanczos rerun on it)"
+    err = np.abs(got - lam_ref)
+    return {"eval_abs_err_vs_dense_eigh": [float("%.3g" % e) for e in err],
+            "max_eval_abs_err": float(err.max()), "eval_err_on": where,
+            "oracle_s": round(time.perf_counter() - t0, 1)}
 
 
 def main():
@@ -500,6 +526,24 @@ def main():
         evs[i + 1].record(stream)
     torch.cuda.synchronize()
     per = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
+    # the same product with FP32 atomic accumulation in the spread (not
+    # bitwise reproducible), to price the deterministic default
+    P.set_option(nfl.OPT_DETERMINISTIC, 0)
+    for _ in range(args.warmup):
+        P.apply_Ls(xd, out=yd)
+    e0.record(stream)
+    for _ in range(args.steps):
+        P.apply_Ls(xd, out=yd)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_float = e0.elapsed_time(e1) / args.steps
+    P.set_option(nfl.OPT_DETERMINISTIC, 1)
+    P.apply_Ls(xd, out=yd)          # yd again from the deterministic (timed) path
+    determinism = {"default": "int64 fixed-point spread accumulation (bitwise reproducible)",
+                   "ms_per_Ls_deterministic": round(ms_step, 5),
+                   "ms_per_Ls_float_atomics": round(ms_float, 5),
+                   "cost_frac": round(ms_step / ms_float - 1.0, 4)}
+    log("determinism: %s" % determinism)
     step_pct = {"p10": round(float(np.percentile(per, 10)), 5),
                 "median": round(float(np.median(per)), 5),
                 "p90": round(float(np.percentile(per, 90)), 5)}
@@ -571,7 +615,7 @@ def main():
         refL = graph.Ls_rows(v, SIGMA, x.astype(np.float64), rows, dfull)
         acc["rel_inf_Ls"] = float(np.abs(Ls_out[rows] - refL).max() / np.abs(refL).max())
         acc["rel_inf_deg_all_nodes"] = float(np.abs(dg - dfull).max() / np.abs(dfull).max())
-        acc["Ls_output"] = "the last timed apply_Ls product"
+        acc["Ls_output"] = "apply_Ls on the timed (deterministic) path: bitwise equal to the timed products"
     cpu_rows_s = time.time() - t0
     est = P.error_estimate(samples=20000, seed=1)
     acc["aposteriori"] = {"eta": est["eta"], "kerr_inf_sampled": est["kerr_inf"],
@@ -619,11 +663,16 @@ def main():
             return {"iters": [r[0] for r in rs], "ms": [round(r[1], 2) for r in rs],
                     "mean_iters": float(np.mean([r[0] for r in rs])),
                     "mean_ms": round(float(np.mean([r[1] for r in rs])), 3),
+                    # call to return over iterations (includes the final true-residual
+                    # product and, for the learned start, the network and its product)
+                    "ms_per_iter": round(float(np.sum([r[1] for r in rs]) /
+                                               max(1, np.sum([r[0] for r in rs]))), 4),
                     "max_true_relres": float(max(r[2] for r in rs))}
         cg = {"tau": TAU, "tol": 1e-6, "cloud_seed": 100001,
               "rhs": "one-vs-rest, 2% labelled, classes 0..2",
               "plain": summ(res["plain"]), "learned": summ(res["learned"]),
               "initial_relres": {"plain": 1.0, "learned": res.get("learned_initial_relres")},
+              "ms_per_Ls_product": round(ms_step, 4),
               "learned_vs_plain_solution_rel_diff": res.get("rel_diff_solution")}
         log("CG plain: %s" % cg["plain"])
         log("CG learned: %s" % cg["learned"])
@@ -710,6 +759,7 @@ def main():
                    "n": N_POINTS, "d": 3, "sigma": SIGMA, "N": NBW, "m": MCUT, "eps_B": EPS_B},
         "stages_ms": {k: round(v_, 5) for k, v_ in st.items()},
         "step_ms_percentiles": step_pct,
+        "determinism": determinism,
         "setup_s": round(setup_s, 3),
         "accuracy": acc,
         "cg": cg,

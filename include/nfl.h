@@ -65,6 +65,11 @@ typedef struct nfl_mlp *nfl_mlp_handle;
 #define NFL_OPT_RESTARTS   6   /* thick restarts of nfl_lanczos_smallest (0 = none, default): with r > 0,
                                    maxit is the basis size and up to r restarts keep the leading Ritz
                                    vectors (see nfl_lanczos_smallest); takes effect immediately */
+#define NFL_OPT_DETERMINISTIC 8 /* 1 (default): the spread into the plan's grid accumulates in int64 fixed
+                                 * point (integer addition is associative), so every product is bitwise
+                                 * reproducible run to run; 0: FP32 atomic additions, whose order (and so
+                                 * the last bits of the result) varies between runs.  The batched launch
+                                 * (nfl_batch_*) and the Laplacian RBF near field always use FP32 atomics. */
 
 /* Create a plan for nodes in R^d, d in {1, 2, 3}.  `hip_stream` is a
  * hipStream_t (NULL = the default stream).  Allocates nothing on the device

@@ -32,6 +32,7 @@ OPT_KERNEL = 5
 OPT_RESTARTS = 6
 KERNELS = {"gaussian": 0, "multiquadric": 1, "inverse_multiquadric": 2, "laplacian_rbf": 3}
 OPT_EPS_I = 7
+OPT_DETERMINISTIC = 8
 
 WARM_ZERO = 0
 WARM_USER = 1
@@ -469,7 +470,7 @@ def plan(points, sigma: float, N: int, m: int, eps_B: float = 0.0, stream=None,
     P = Plan(d, stream)
     for k, val in options.items():
         P.set_option({"p": OPT_P, "tile": OPT_TILE, "chunk": OPT_CHUNK, "kernel": OPT_KERNEL,
-                      "eps_I": OPT_EPS_I}[k],
+                      "eps_I": OPT_EPS_I, "deterministic": OPT_DETERMINISTIC}[k],
                      val)
     P.set_points(v)
     P.set_kernel(sigma, N, m, eps_B, kind=kind)

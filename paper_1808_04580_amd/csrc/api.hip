@@ -125,6 +125,11 @@ int nfl_set_option(nfl_handle P, int opt, double value) {
     case NFL_OPT_EPS_B_DEFAULT:
       P->opt_eps_default = value != 0;
       return NFL_OK;
+    case NFL_OPT_DETERMINISTIC:
+      if (value != 0 && value != 1) { set_error("deterministic must be 0 or 1"); return NFL_ERR_ARG; }
+      P->opt_det = value != 0;
+      P->grid_clean = false;   // the next spread clears the grid in the new format
+      return NFL_OK;
     case NFL_OPT_KERNEL:
       if (value != 0 && value != 1 && value != 2) { set_error("kernel must be 0 (matrix cores), 1 (vector ALU) or 2 (matrix cores, per-cell runs)"); return NFL_ERR_ARG; }
       P->opt_kernel = (int)value;
@@ -298,9 +303,15 @@ int nfl_set_kernel_ex(nfl_handle P, int kind, double sigma, int N, int m, double
   }
   int64_t gsz = 1;
   for (int t = 0; t < P->d; ++t) gsz *= P->nos;
-  NFL_TRY(P->grid.ensure(gsz));
+  NFL_TRY(P->grid.ensure(2 * gsz));   // room for the int64 fixed-point grid
   NFL_TRY(P->grid2.ensure(gsz));
   P->grid_clean = false;
+  NFL_TRY(P->fx_max.ensure(1));
+  NFL_HIP(hipMemsetAsync(P->fx_max.p, 0, sizeof(unsigned), P->stream));
+  {
+    const double b = M_PI * 1.5, m = P->m;   // Kaiser-Bessel window at t = 0
+    P->win_max = (std::sinh(b * m) / m) / (b * std::exp(b * m));
+  }
   const int Hz = N / 2 + 1, F = N + 1;
   size_t s1 = Hz, s2 = 0;
   if (P->d == 2) s1 = (size_t)P->nos * Hz;

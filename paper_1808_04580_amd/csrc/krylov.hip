@@ -889,7 +889,7 @@ __device__ __forceinline__ double sum_partials(const double *__restrict__ part, 
   return t;
 }
 
-// r = f - q; p = r; partials of r.r and f.f
+// r = f - q (q null: r = f); p = r; partials of r.r and f.f
 __global__ __launch_bounds__(VT) void k_cg_start(const double *__restrict__ f,
                                                  const double *__restrict__ q, int64_t n,
                                                  double *__restrict__ r, double *__restrict__ p,
@@ -897,7 +897,7 @@ __global__ __launch_bounds__(VT) void k_cg_start(const double *__restrict__ f,
   __shared__ double sh[VT / 64];
   double rr = 0.0, ff = 0.0;
   for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT) {
-    const double fi = f[i], ri = fi - q[i];
+    const double fi = f[i], ri = q ? fi - q[i] : fi;
     r[i] = ri;
     p[i] = ri;
     rr += ri * ri;
@@ -1098,12 +1098,13 @@ static int cg_blocks(int64_t n) {
 
 template <class Op>
 static int cg_core(nfl_plan *P, const Op &op, const CgWork &W, const double *f, double *u,
-                   double tol, int maxit, int *iters, double *relres) {
+                   bool u_zero, double tol, int maxit, int *iters, double *relres) {
   const int64_t n = P->n;
   hipStream_t s = P->stream;
   const int nb = cg_blocks(n);
-  NFL_TRY(op(u, W.q));
-  hipLaunchKernelGGL(k_cg_start, dim3(nb), dim3(VT), 0, s, f, W.q, n, W.r, W.p, W.part);
+  if (!u_zero) NFL_TRY(op(u, W.q));   // r = f - M u0 (M 0 = 0: no product for a zero start)
+  hipLaunchKernelGGL(k_cg_start, dim3(nb), dim3(VT), 0, s, f, u_zero ? nullptr : W.q, n, W.r,
+                     W.p, W.part);
   hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(VT), 0, s, W.part, nb, tol, W.sc, W.st);
   NFL_HIP(hipGetLastError());
   if (W.host_st) {
@@ -1199,7 +1200,7 @@ int krr_solve(nfl_plan *P, double beta, const double *f_dev, double *alpha_dev, 
   if (warm != NFL_WARM_USER)
     hipLaunchKernelGGL(k_fill64, dim3(grid_for(n)), dim3(VT), 0, P->stream, alpha_dev, n, 0.0);
   KrrOp op{P, beta, P->krr_x32.p, P->krr_t32.p};
-  return cg_core(P, op, W, f_dev, alpha_dev, tol, maxit, iters, relres);
+  return cg_core(P, op, W, f_dev, alpha_dev, warm != NFL_WARM_USER, tol, maxit, iters, relres);
 }
 
 // The SSL system in the plan's sorted order: f and u are gathered into the
@@ -1219,7 +1220,7 @@ static int cg_sorted(nfl_plan *P, const CgWork &W, double tau, const double *f_d
     hipLaunchKernelGGL(k_fill64, dim3(gb), dim3(VT), 0, s, u, n, 0.0);
   }
   SslOp op{P, tau};
-  const int rc = cg_core(P, op, W, f, u, tol, maxit, iters, relres);
+  const int rc = cg_core(P, op, W, f, u, warm == NFL_WARM_ZERO, tol, maxit, iters, relres);
   if (rc < 0) return rc;
   hipLaunchKernelGGL(k_scatter64, dim3(gb), dim3(VT), 0, s, u, P->perm.p, n, u_dev);
   NFL_HIP(hipGetLastError());

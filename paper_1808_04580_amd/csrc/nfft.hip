@@ -118,13 +118,14 @@ __global__ __launch_bounds__(256) void k_spread3(const Item *__restrict__ items,
   __syncthreads();
 
   const int mask = nos - 1;
+  const double fx = fx_of(ka);
   for (int c = threadIdx.x; c < P3; c += 256) {
     const float v = lds[c];
     if (v != 0.f) {
       const int px = c / PP, rem = c - px * PP, py = rem / P, pz = rem - py * P;
       const int gx = (ox - (M - 1) + px) & mask, gy = (oy - (M - 1) + py) & mask,
                 gz = (oz - (M - 1) + pz) & mask;
-      unsafeAtomicAdd(&grid[((size_t)gx * nos + gy) * nos + gz], v);
+      grid_add(grid, ((size_t)gx * nos + gy) * nos + gz, v, fx);
     }
   }
 }
@@ -333,6 +334,7 @@ __global__ __launch_bounds__(256) void k_spread12(const Item *__restrict__ items
       acc[c] = sacc;
     }
   }
+  const double fx = fx_of(ka);
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
     const int e = t + 256 * c;
@@ -341,9 +343,9 @@ __global__ __launch_bounds__(256) void k_spread12(const Item *__restrict__ items
     const int gx = (tx0 - (m - 1) + px) & mask;
     if (acc[c] != 0.f) {
       if (d == 1)
-        unsafeAtomicAdd(&grid[gx], acc[c]);
+        grid_add(grid, gx, acc[c], fx);
       else
-        unsafeAtomicAdd(&grid[(size_t)gx * nos + ((ty0 - (m - 1) + py) & mask)], acc[c]);
+        grid_add(grid, (size_t)gx * nos + ((ty0 - (m - 1) + py) & mask), acc[c], fx);
     }
   }
 }
@@ -412,17 +414,23 @@ __global__ __launch_bounds__(FFT_THREADS) void k_r2c_lines(float *__restrict__ g
                                                            float2 *__restrict__ H, int nlines,
                                                            int L, int logL, int lpb, int Hz,
                                                            const float2 *__restrict__ tw,
-                                                           const int *__restrict__ stop) {
+                                                           const int *__restrict__ stop,
+                                                           const unsigned *__restrict__ fx_max,
+                                                           float fx_mult) {
   if (stopped(stop)) return;
-  r2c_lines_body<ZERO>(blockIdx.x, grid, H, nlines, L, logL, lpb, Hz, tw);
+  r2c_lines_body<ZERO>(blockIdx.x, grid, H, nlines, L, logL, lpb, Hz, tw, fx_max, fx_mult);
 }
 
 __global__ __launch_bounds__(FFT_THREADS) void k_c2r_lines(const float2 *__restrict__ H,
                                                            float *__restrict__ grid, int nlines,
                                                            int L, int logL, int lpb, int Hz,
                                                            const float2 *__restrict__ tw,
-                                                           const int *__restrict__ stop) {
+                                                           const int *__restrict__ stop,
+                                                           unsigned *__restrict__ fx_reset) {
   if (stopped(stop)) return;
+  // the last pass of a product clears the deterministic spread's input bound
+  // for the next product's pre-pass (every reader of it has finished)
+  if (fx_reset && blockIdx.x == 0 && threadIdx.x == 0) *fx_reset = 0u;
   c2r_lines_body(blockIdx.x, H, grid, nlines, L, logL, lpb, Hz, tw);
 }
 
@@ -460,6 +468,41 @@ __global__ void k_filter1(float2 *__restrict__ H, const float *__restrict__ filt
   if (i < Hz) {
     H[i].x *= filt[i];
     H[i].y *= filt[i];
+  }
+}
+
+// Pre-pass of the deterministic spread: *out = max(*out, bits of max_i |x_i|)
+// (non-negative floats order like their bit patterns); x null: |x| = 1.
+template <class T>
+__global__ __launch_bounds__(256) void k_fx_max(const T *__restrict__ x, int64_t n,
+                                                unsigned *__restrict__ out,
+                                                const int *__restrict__ stop) {
+  if (stopped(stop)) return;
+  __shared__ float wm[4];
+  float m = x ? 0.f : 1.f;
+  if (x) {
+    // 16-byte loads where the base is aligned (torch tensors are), scalar tail
+    constexpr int V = 16 / sizeof(T);
+    const bool vec = (reinterpret_cast<uintptr_t>(x) & 15) == 0;
+    const int64_t nv = vec ? n / V : 0;
+    const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x, nt = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = tid; i < nv; i += nt) {
+      const float4 q = reinterpret_cast<const float4 *>(x)[i];
+      const T *e = reinterpret_cast<const T *>(&q);
+#pragma unroll
+      for (int k = 0; k < V; ++k) m = fmaxf(m, (float)fabs((double)e[k]));
+    }
+    for (int64_t i = nv * V + tid; i < n; i += nt) m = fmaxf(m, (float)fabs((double)x[i]));
+    m *= 1.f + 1e-6f;   // round up past the float rounding of double inputs
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  // one atomic per block: atomics on one address serialise, so few blocks
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmaxf(m, wm[w]);
+    atomicMax(out, __float_as_uint(m));
   }
 }
 
@@ -504,6 +547,8 @@ static KArgs make_kargs(nfl_plan *P, const VecArgs &a) {
   k.deg_out = P->deg.p;
   k.dinv_out = P->dinv.p;
   k.stop = P->stop;
+  k.fx_max = nullptr;
+  k.fx_mult = 0.f;
   return k;
 }
 
@@ -645,12 +690,41 @@ static int spread_in(nfl_plan *P, const KArgs &k, float *grid) {
   return NFL_OK;
 }
 
+// The bound of the deterministic spread's grid values: every cell sums at
+// most n terms x~_i psi psi psi, |x~_i| <= max |input| * (d^{-1/2} bound for
+// the normalised inputs), psi <= psi(0); with margins for rounding.
+static int fx_prepass(nfl_plan *P, int in_mode, const VecArgs &a) {
+  double factor = 1.0;
+  if (in_mode == IN_USER_F32_DINV || in_mode == IN_SORTED_F64_DINV)
+    factor = 1.01 / std::sqrt(std::max(P->dmin, 1e-300));
+  P->fx_mult = (float)(1.0625 * factor * (double)P->n * std::pow(1.01 * P->win_max, P->d));
+  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(512, (P->n + 1023) / 1024));
+  if (in_mode == IN_ONES) {
+    hipLaunchKernelGGL(k_fx_max<float>, dim3(1), dim3(64), 0, P->stream, (const float *)nullptr,
+                       (int64_t)0, P->fx_max.p, P->stop);
+  } else if (in_mode == IN_SORTED_F64_DINV) {
+    hipLaunchKernelGGL(k_fx_max<double>, dim3(nb), dim3(256), 0, P->stream, a.x64, P->n,
+                       P->fx_max.p, P->stop);
+  } else {
+    hipLaunchKernelGGL(k_fx_max<float>, dim3(nb), dim3(256), 0, P->stream, a.x32, P->n,
+                       P->fx_max.p, P->stop);
+  }
+  NFL_HIP(hipGetLastError());
+  return NFL_OK;
+}
+
 int spread(nfl_plan *P, int in_mode, const VecArgs &a, float *grid, bool clear) {
   int64_t gsz = 1;
   for (int t = 0; t < P->d; ++t) gsz *= P->nos;
-  if (clear) NFL_TRY(fill_f32(grid, gsz, 0.f, P->stream));
+  const bool fx = P->opt_det && grid == P->grid.p;
+  if (clear) NFL_TRY(fill_f32(grid, fx ? 2 * gsz : gsz, 0.f, P->stream));
+  if (fx) NFL_TRY(fx_prepass(P, in_mode, a));
   if (P->prof_ev) NFL_HIP(hipEventRecord(P->prof_ev[1], P->stream));
-  const KArgs k = make_kargs(P, a);
+  KArgs k = make_kargs(P, a);
+  if (fx) {
+    k.fx_max = P->fx_max.p;
+    k.fx_mult = P->fx_mult;
+  }
   switch (in_mode) {
     case IN_USER_F32: return spread_in<IN_USER_F32>(P, k, grid);
     case IN_USER_F32_DINV: return spread_in<IN_USER_F32_DINV>(P, k, grid);
@@ -705,6 +779,10 @@ int convolve(nfl_plan *P, const float *gin_c, float *gout, bool zero_in) {
   // the input is written only when zero_in (then it is the plan's own grid)
   float *gin = const_cast<float *>(gin_c);
   auto r2c = zero_in ? k_r2c_lines<true> : k_r2c_lines<false>;
+  const bool fx = P->opt_det && gin_c == P->grid.p;   // the spread used the fixed-point grid
+  const unsigned *fxm = fx ? P->fx_max.p : nullptr;
+  unsigned *fxr = fx ? P->fx_max.p : nullptr;
+  const float fxu = P->fx_mult;
   const int L = P->nos, N = P->N, Hz = N / 2 + 1, F = N + 1;
   int logL = 0;
   while ((1 << logL) < L) ++logL;
@@ -713,24 +791,24 @@ int convolve(nfl_plan *P, const float *gin_c, float *gout, bool zero_in) {
   const float2 *tw = P->tw.p;
   if (P->d == 1) {
     hipLaunchKernelGGL(r2c, dim3(1), dim3(FFT_THREADS), ldz, P->stream, gin, P->spec1.p,
-                       1, L, logL, lpz, Hz, tw, P->stop);
+                       1, L, logL, lpz, Hz, tw, P->stop, fxm, fxu);
     hipLaunchKernelGGL(k_filter1, dim3(1), dim3(256), 0, P->stream, P->spec1.p, P->filt.p, Hz, P->stop);
     hipLaunchKernelGGL(k_c2r_lines, dim3(1), dim3(FFT_THREADS), ldz, P->stream, P->spec1.p, gout,
-                       1, L, logL, lpz, Hz, tw, P->stop);
+                       1, L, logL, lpz, Hz, tw, P->stop, fxr);
   } else if (P->d == 2) {
     const int nlines = L;
     const int nb = (nlines + lpz - 1) / lpz;
     hipLaunchKernelGGL(r2c, dim3(nb), dim3(FFT_THREADS), ldz, P->stream, gin, P->spec1.p,
-                       nlines, L, logL, lpz, Hz, tw, P->stop);
+                       nlines, L, logL, lpz, Hz, tw, P->stop, fxm, fxu);
     hipLaunchKernelGGL(k_x_filter, dim3(Hz), dim3(FFT_THREADS), fft_lds_bytes(1, L), P->stream,
                        P->spec1.p, P->filt.p, Hz, L, logL, 1, N, tw, P->stop);
     hipLaunchKernelGGL(k_c2r_lines, dim3(nb), dim3(FFT_THREADS), ldz, P->stream, P->spec1.p, gout,
-                       nlines, L, logL, lpz, Hz, tw, P->stop);
+                       nlines, L, logL, lpz, Hz, tw, P->stop, fxr);
   } else {
     const int nlines = L * L;
     const int nb = (nlines + lpz - 1) / lpz;
     hipLaunchKernelGGL(r2c, dim3(nb), dim3(FFT_THREADS), ldz, P->stream, gin, P->spec1.p,
-                       nlines, L, logL, lpz, Hz, tw, P->stop);
+                       nlines, L, logL, lpz, Hz, tw, P->stop, fxm, fxu);
     const int lpy = fft_lpb_y(L), ngroups = (Hz + lpy - 1) / lpy;
     const size_t ldy = fft_lds_bytes(lpy, L);
     hipLaunchKernelGGL(k_y_fwd, dim3(L * ngroups), dim3(FFT_THREADS), ldy, P->stream, P->spec1.p,
@@ -742,7 +820,7 @@ int convolve(nfl_plan *P, const float *gin_c, float *gout, bool zero_in) {
     hipLaunchKernelGGL(k_y_inv, dim3(L * ngroups), dim3(FFT_THREADS), ldy, P->stream, P->spec2.p,
                        P->spec1.p, L, logL, lpy, Hz, N, tw, P->stop);
     hipLaunchKernelGGL(k_c2r_lines, dim3(nb), dim3(FFT_THREADS), ldz, P->stream, P->spec1.p, gout,
-                       nlines, L, logL, lpz, Hz, tw, P->stop);
+                       nlines, L, logL, lpz, Hz, tw, P->stop, fxr);
   }
   NFL_HIP(hipGetLastError());
   return NFL_OK;

@@ -43,7 +43,41 @@ struct KArgs {
   float *deg_out;
   float *dinv_out;
   const int *stop;   // null, or a device flag: when nonzero every kernel of the product returns at once
+  // deterministic spread (null: float atomics): bits of max |input| written
+  // by the product's pre-pass; fx_mult bounds every grid value by
+  // max |input| * fx_mult (see fx_scale)
+  const unsigned *fx_max;
+  float fx_mult;
 };
+
+// Deterministic spread: the plan's grid holds int64 fixed-point values
+// round(v * 2^e).  Integer addition is associative, so the sum a cell
+// receives does not depend on the order of the work items' atomic additions
+// (float atomics make it run-to-run dependent).  The exponent comes from a
+// bound b = max |input| * fx_mult >= every |cell sum| (number of nodes times
+// the largest window product times the input bound), so that
+// |sum| * 2^e < 2^61: no overflow, and a resolution of b 2^-61, far below
+// FP32 rounding of the values.  Spread and r2c derive the same e from the
+// same bits.
+__device__ __forceinline__ double fx_scale(unsigned maxbits, float mult) {
+  const double b = (double)__uint_as_float(maxbits) * (double)mult + 1e-300;
+  int e;
+  (void)frexp(b, &e);   // b < 2^e
+  return ldexp(1.0, 61 - e);
+}
+
+// add v into grid cell idx: a float atomic, or the fixed-point int64 atomic
+__device__ __forceinline__ void grid_add(float *grid, size_t idx, float v, double fx) {
+  if (fx != 0.0)
+    atomicAdd(reinterpret_cast<unsigned long long *>(grid) + idx,
+              (unsigned long long)__double2ll_rn((double)v * fx));
+  else
+    unsafeAtomicAdd(grid + idx, v);
+}
+
+__device__ __forceinline__ double fx_of(const KArgs &ka) {
+  return ka.fx_max ? fx_scale(*ka.fx_max, ka.fx_mult) : 0.0;
+}
 
 // Uniform early exit of a product's kernels once an iterative solver on the
 // device has stopped (its flag is set by the solver's own kernels).
@@ -427,6 +461,7 @@ __device__ __forceinline__ void spread3_mfma_body(const Item it, const float4 *_
   // sum the private tiles and add into the grid: each wave takes rows (px, py)
   // of the tile, 64 / ZL rows at a time with ZL >= P lanes along z
   const int mask = nos - 1;
+  const double fx = fx_of(ka);
   const int ZL = P <= 16 ? 16 : (P <= 32 ? 32 : 64), RL = 64 / ZL;
   const int pz = lane % ZL, rsub = lane / ZL;
   for (int row0 = wave * RL; row0 < P * P; row0 += NW * RL) {
@@ -441,7 +476,7 @@ __device__ __forceinline__ void spread3_mfma_body(const Item it, const float4 *_
       if (v != 0.f) {
         const int gx = (ox - (M - 1) + px) & mask, gy = (oy - (M - 1) + py) & mask,
                   gz = (oz - (M - 1) + pz) & mask;
-        unsafeAtomicAdd(&grid[((size_t)gx * nos + gy) * nos + gz], v);
+        grid_add(grid, ((size_t)gx * nos + gy) * nos + gz, v, fx);
       }
     }
   }
@@ -755,6 +790,7 @@ __device__ __forceinline__ void spread3_tile_body(const Item it, const float4 *_
   }
   // into the grid: each wave takes rows (px, py), four at a time, z along lanes
   const int mask = nos - 1;
+  const double fx = fx_of(ka);
   const int pz = lane & 15, rsub = lane >> 4;
   for (int row0 = wave * 4; row0 < P * P; row0 += NW * 4) {
     const int row = row0 + rsub;
@@ -765,7 +801,7 @@ __device__ __forceinline__ void spread3_tile_body(const Item it, const float4 *_
       if (v != 0.f) {
         const int gx = (ox - (M - 1) + px) & mask, gy = (oy - (M - 1) + py) & mask,
                   gz = (oz - (M - 1) + pz) & mask;
-        unsafeAtomicAdd(&grid[((size_t)gx * nos + gy) * nos + gz], v);
+        grid_add(grid, ((size_t)gx * nos + gy) * nos + gz, v, fx);
       }
     }
   }
@@ -992,26 +1028,45 @@ __host__ __device__ __forceinline__ int fft_lpb_x(int L) {
 // lpb real lines (an even number) per workgroup.  ZERO: each input element is
 // set to 0 after it is read (every element is read once, by one thread), which
 // leaves the spread grid clear for the next product.
+// fx_max non-null: the grid holds the deterministic spread's int64 fixed-point
+// values (scaled by fx_scale(*fx_max, fx_mult)), converted here.
 template <bool ZERO = false>
 __device__ __forceinline__ void r2c_lines_body(int blk, float *__restrict__ grid,
                                                float2 *__restrict__ H, int nlines, int L,
                                                int logL, int lpb, int Hz,
-                                               const float2 *__restrict__ tw) {
+                                               const float2 *__restrict__ tw,
+                                               const unsigned *__restrict__ fx_max = nullptr,
+                                               float fx_mult = 0.f) {
   extern __shared__ float2 sm[];
   const int np = lpb >> 1;
   float2 *a = sm, *b = sm + np * L, *twl = sm + 2 * np * L;
   load_twiddles(twl, tw, L);
   const int l0 = blk * lpb;
   const int nl = min(lpb, nlines - l0), npp = (nl + 1) >> 1;
-  for (int idx = threadIdx.x; idx < npp * L; idx += FFT_THREADS) {
-    const int pl = idx / L, j = idx - pl * L;
-    float *pa = grid + (size_t)(l0 + 2 * pl) * L + j;
-    const float re = *pa;
-    const float im = 2 * pl + 1 < nl ? pa[L] : 0.f;
-    a[idx] = make_float2(re, im);
-    if (ZERO) {
-      *pa = 0.f;
-      if (2 * pl + 1 < nl) pa[L] = 0.f;
+  if (fx_max) {
+    const double inv = 1.0 / fx_scale(*fx_max, fx_mult);   // a power of 2: exact
+    for (int idx = threadIdx.x; idx < npp * L; idx += FFT_THREADS) {
+      const int pl = idx / L, j = idx - pl * L;
+      long long *pa = reinterpret_cast<long long *>(grid) + (size_t)(l0 + 2 * pl) * L + j;
+      const float re = (float)((double)pa[0] * inv);
+      const float im = 2 * pl + 1 < nl ? (float)((double)pa[L] * inv) : 0.f;
+      a[idx] = make_float2(re, im);
+      if (ZERO) {
+        pa[0] = 0;
+        if (2 * pl + 1 < nl) pa[L] = 0;
+      }
+    }
+  } else {
+    for (int idx = threadIdx.x; idx < npp * L; idx += FFT_THREADS) {
+      const int pl = idx / L, j = idx - pl * L;
+      float *pa = grid + (size_t)(l0 + 2 * pl) * L + j;
+      const float re = *pa;
+      const float im = 2 * pl + 1 < nl ? pa[L] : 0.f;
+      a[idx] = make_float2(re, im);
+      if (ZERO) {
+        *pa = 0.f;
+        if (2 * pl + 1 < nl) pa[L] = 0.f;
+      }
     }
   }
   __syncthreads();

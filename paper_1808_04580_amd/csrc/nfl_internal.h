@@ -135,6 +135,10 @@ struct nfl_plan {
   // FFT / filter
   nfl::DBuf<float> wcoef;       // window polynomials, WIN_MAXW x WIN_NC
   int opt_kernel = 0;           // 0: MFMA (tile-stationary where possible), 1: VALU, 2: MFMA per-cell runs
+  bool opt_det = true;          // deterministic spread: int64 fixed-point grid (NFL_OPT_DETERMINISTIC)
+  nfl::DBuf<unsigned> fx_max;   // bits of max |input| of the current product (pre-pass; reset by c2r)
+  float fx_mult = 0.f;          // grid values <= max |input| * fx_mult (set by the spread launch)
+  double win_max = 0;           // largest window value (psi(0))
   int opt_restarts = 0;         // thick restarts of nfl_lanczos_smallest (0: none)
   nfl::DBuf<float> filt;        // half spectrum, FP32
   std::vector<double> filt_host;
