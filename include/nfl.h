@@ -65,6 +65,13 @@ typedef struct nfl_mlp *nfl_mlp_handle;
 #define NFL_OPT_RESTARTS   6   /* thick restarts of nfl_lanczos_smallest (0 = none, default): with r > 0,
                                    maxit is the basis size and up to r restarts keep the leading Ritz
                                    vectors (see nfl_lanczos_smallest); takes effect immediately */
+#define NFL_OPT_PRECISION  9   /* NFFT arithmetic, applied by the next nfl_set_kernel: 32 (default: FP32 spread,
+                                 * FFT and interpolation on the matrix cores) or 64 (all FP64: the Kaiser-Bessel
+                                 * window evaluated exactly, FP64 node fractions, degrees, FFT and filter; for
+                                 * error studies, several times slower; d = 1..3, not with the Laplacian RBF
+                                 * kernel, nfl_evaluate or the batched launch).  Inputs and outputs of the
+                                 * apply calls stay float32; the Krylov solvers' FP64 vectors go through FP64
+                                 * products. */
 #define NFL_OPT_DETERMINISTIC 8 /* 1 (default): the spread into the plan's grid accumulates in int64 fixed
                                  * point (integer addition is associative), so every product is bitwise
                                  * reproducible run to run; 0: FP32 atomic additions, whose order (and so
@@ -169,6 +176,16 @@ int nfl_apply_Ls(nfl_handle h, const float *x_dev, float *y_dev, int nvec, int64
 /* y = A_E x, A_E = D_E^{-1/2} W_E D_E^{-1/2} (step 5 of Alg.
  * nfft_normalized_matvec). */
 int nfl_apply_A(nfl_handle h, const float *x_dev, float *y_dev, int nvec, int64_t ld);
+
+/* FP64 vectors, caller order, one vector: y = A_E x = D_E^{-1/2} W_E D_E^{-1/2} x
+ * (eq. nomlap; L_s x = x - A_E x, W x = D^{1/2} A_E D^{1/2} x).  With
+ * NFL_OPT_PRECISION 64 the whole product is FP64 (the operator the Krylov
+ * solvers use); otherwise the NFFT runs in FP32 between FP64 vectors.  x_dev
+ * and y_dev must not overlap.  Device work memory: 2 n doubles (kept). */
+int nfl_apply_A64(nfl_handle h, const double *x_dev, double *y_dev);
+/* The degrees d_E (n doubles, caller order): FP64 on the FP64 path, else the
+ * float32 degrees widened. */
+int nfl_degree64(nfl_handle h, double *d_dev);
 
 /* The k smallest eigenpairs of L_s (Section 4): Lanczos on A_E for its k
  * largest eigenvalues theta, lambda = 1 - theta (end of Section 2).  FP64

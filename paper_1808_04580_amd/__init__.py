@@ -33,6 +33,7 @@ OPT_RESTARTS = 6
 KERNELS = {"gaussian": 0, "multiquadric": 1, "inverse_multiquadric": 2, "laplacian_rbf": 3}
 OPT_EPS_I = 7
 OPT_DETERMINISTIC = 8
+OPT_PRECISION = 9
 
 WARM_ZERO = 0
 WARM_USER = 1
@@ -56,6 +57,8 @@ SIGNATURES = {
     "nfl_apply_W": (_i, [_p, _p, _p, _i, _i64]),
     "nfl_apply_Ls": (_i, [_p, _p, _p, _i, _i64]),
     "nfl_apply_A": (_i, [_p, _p, _p, _i, _i64]),
+    "nfl_apply_A64": (_i, [_p, _p, _p]),
+    "nfl_degree64": (_i, [_p, _p]),
     "nfl_lanczos_smallest": (_i, [_p, _i, _i, _d, _i, _p, _p, _p, _p]),
     "nfl_cg_solve": (_i, [_p, _d, _p, _p, _i, _d, _i, _p, _p]),
     "nfl_cg_solve_noalloc": (_i, [_p, _d, _p, _p, _i, _d, _i, _p, _p]),
@@ -286,6 +289,21 @@ class Plan:
     def apply_A(self, x, out=None):
         return self._apply(lib().nfl_apply_A, "nfl_apply_A", x, out)
 
+    def apply_A64(self, x):
+        """A_E x for one FP64 vector in caller order (FP64 throughout on the
+        FP64 path, NFL_OPT_PRECISION 64)."""
+        torch = self._torch
+        x = torch.as_tensor(x, dtype=torch.float64, device=self.device).contiguous()
+        y = torch.empty_like(x)
+        _check(lib().nfl_apply_A64(self._h, _ptr(x), _ptr(y)), "nfl_apply_A64")
+        return y
+
+    def degree64(self):
+        torch = self._torch
+        d = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        _check(lib().nfl_degree64(self._h, _ptr(d)), "nfl_degree64")
+        return d
+
     # -- solvers ------------------------------------------------------------
     def lanczos_smallest(self, k: int, tol: float = 1e-8, maxit: int = 300, block: int = 1,
                          vectors: bool = True, restarts: int = 0):
@@ -470,7 +488,8 @@ def plan(points, sigma: float, N: int, m: int, eps_B: float = 0.0, stream=None,
     P = Plan(d, stream)
     for k, val in options.items():
         P.set_option({"p": OPT_P, "tile": OPT_TILE, "chunk": OPT_CHUNK, "kernel": OPT_KERNEL,
-                      "eps_I": OPT_EPS_I, "deterministic": OPT_DETERMINISTIC}[k],
+                      "eps_I": OPT_EPS_I, "deterministic": OPT_DETERMINISTIC,
+                      "precision": OPT_PRECISION}[k],
                      val)
     P.set_points(v)
     P.set_kernel(sigma, N, m, eps_B, kind=kind)

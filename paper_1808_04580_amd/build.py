@@ -15,7 +15,7 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnfl.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 SOURCES = ["api.hip", "setup.hip", "nfft.hip", "krylov.hip", "mlp.hip", "batch.hip", "tune.hip",
-           "nystrom.hip", "nearfield.hip", "errest.hip"]
+           "nystrom.hip", "nearfield.hip", "errest.hip", "fp64.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -15,8 +15,7 @@ namespace nfl {
 static thread_local std::string g_last_error;
 void set_error(const std::string &msg) { g_last_error = msg; }
 
-int compute_filter(int d, int N, int m, int p, double eps_B, double sigma_t,
-                   std::vector<double> &out, int kind, double eps_I);
+
 
 // y[i] *= s, i < n (W and degree outputs of non-Gaussian kernels: the NFFT
 // works with K / K(0))
@@ -30,6 +29,19 @@ static int scale_out(nfl_plan *P, float *y) {
   if (P->wscale == 1.0) return NFL_OK;
   const int blocks = (int)std::min<int64_t>(4096, (P->n + 255) / 256);
   hipLaunchKernelGGL(k_scale_f32, dim3(blocks), dim3(256), 0, P->stream, y, P->n, (float)P->wscale);
+  NFL_HIP(hipGetLastError());
+  return NFL_OK;
+}
+
+__global__ void k_scale_f64(double *__restrict__ y, int64_t n, double s) {
+  const int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x;
+  if (i < n) y[i] *= s;
+}
+
+static int scale_out64(nfl_plan *P, double *y) {
+  if (P->wscale == 1.0) return NFL_OK;
+  const int blocks = (int)((P->n + 255) / 256);
+  hipLaunchKernelGGL(k_scale_f64, dim3(blocks), dim3(256), 0, P->stream, y, P->n, P->wscale);
   NFL_HIP(hipGetLastError());
   return NFL_OK;
 }
@@ -125,6 +137,10 @@ int nfl_set_option(nfl_handle P, int opt, double value) {
     case NFL_OPT_EPS_B_DEFAULT:
       P->opt_eps_default = value != 0;
       return NFL_OK;
+    case NFL_OPT_PRECISION:
+      if (value != 32 && value != 64) { set_error("precision must be 32 or 64"); return NFL_ERR_ARG; }
+      P->opt_prec = (int)value;
+      return NFL_OK;
     case NFL_OPT_DETERMINISTIC:
       if (value != 0 && value != 1) { set_error("deterministic must be 0 or 1"); return NFL_ERR_ARG; }
       P->opt_det = value != 0;
@@ -194,6 +210,7 @@ int nfl_evaluate(nfl_handle S, const float *x_dev, nfl_handle T, float *y_dev) {
   if (!S->have_kernel || !T->have_kernel) { set_error("evaluate before a successful nfl_set_kernel on both plans"); return NFL_ERR_ORDER; }
   if (S->frame_only) { set_error("the source plan must hold its own points"); return NFL_ERR_ARG; }
   if (S->kind == NFL_KERNEL_LAPLACIAN_RBF) { set_error("evaluate: the Laplacian RBF kernel needs a near-field sum between the two node sets, not built"); return NFL_ERR_UNSUPPORTED; }
+  if (S->prec == 64 || T->prec == 64) { set_error("evaluate: not built for the FP64 path"); return NFL_ERR_UNSUPPORTED; }
   if (T != S && !T->frame_only) { set_error("the target plan must be made with nfl_set_points_frame"); return NFL_ERR_ARG; }
   if (T != S && (T->centre[0] != S->centre[0] || T->centre[1] != S->centre[1] ||
                  T->centre[2] != S->centre[2] || T->radius != S->radius || T->d != S->d ||
@@ -324,6 +341,11 @@ int nfl_set_kernel_ex(nfl_handle P, int kind, double sigma, int N, int m, double
   NFL_TRY(build_sorted_nodes(P));
   NFL_TRY(P->deg.ensure(P->n));
   NFL_TRY(P->dinv.ensure(P->n));
+  P->prec = 32;
+  if (P->opt_prec == 64) {
+    NFL_TRY(setup64(P));
+    P->prec = 64;
+  }
 
   if (P->frame_only) {   // target nodes: no degree pass
     P->have_kernel = true;
@@ -374,6 +396,23 @@ int nfl_apply_Ls(nfl_handle P, const float *x, float *y, int nvec, int64_t ld) {
 
 int nfl_apply_A(nfl_handle P, const float *x, float *y, int nvec, int64_t ld) {
   return apply_common(P, x, y, nvec, ld, IN_USER_F32_DINV, OUT_USER_A);
+}
+
+int nfl_apply_A64(nfl_handle P, const double *x, double *y) {
+  if (!P) { set_error("null handle"); return NFL_ERR_ARG; }
+  if (!P->have_kernel) { set_error("apply before a successful nfl_set_kernel"); return NFL_ERR_ORDER; }
+  if (P->frame_only) { set_error("apply_A64 on a plan of target nodes: it has no degrees"); return NFL_ERR_ORDER; }
+  if (!x || !y || x == y) { set_error("null or aliased vector pointer"); return NFL_ERR_ARG; }
+  return apply_A64_user(P, x, y);
+}
+
+int nfl_degree64(nfl_handle P, double *d) {
+  if (!P) { set_error("null handle"); return NFL_ERR_ARG; }
+  if (!P->have_kernel) { set_error("degree before a successful nfl_set_kernel"); return NFL_ERR_ORDER; }
+  if (P->frame_only) { set_error("degree on a plan of target nodes: it has no degrees"); return NFL_ERR_ORDER; }
+  if (!d) { set_error("null output"); return NFL_ERR_ARG; }
+  NFL_TRY(degree64_user(P, d));
+  return scale_out64(P, d);
 }
 
 int nfl_lanczos_smallest(nfl_handle P, int k, int block, double tol, int maxit, double *evals_host,

@@ -538,6 +538,7 @@ int nfl_batch_create(nfl_batch *b, const nfl_handle *plans, int nplans, int nvec
     if (P->kind == NFL_KERNEL_LAPLACIAN_RBF) { set_error("batch: the Laplacian RBF kernel's near-field sum is not part of the batched launch"); return NFL_ERR_UNSUPPORTED; }
     if (P->d != 3) { set_error("batch: plans must have d = 3"); return NFL_ERR_UNSUPPORTED; }
     if (P->opt_kernel != 0) { set_error("batch: plans must use the matrix-core kernels"); return NFL_ERR_UNSUPPORTED; }
+    if (P->prec != 32) { set_error("batch: plans must use the FP32 path"); return NFL_ERR_UNSUPPORTED; }
     if (P->device != dev) { set_error("batch: plans on another device"); return NFL_ERR_ARG; }
     if (P->nos > FFT_MAXL) { set_error("batch: grid too large"); return NFL_ERR_UNSUPPORTED; }
   }

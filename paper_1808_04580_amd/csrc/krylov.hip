@@ -1016,6 +1016,31 @@ __global__ __launch_bounds__(VT) void k_cg_final(const double *__restrict__ part
   if (threadIdx.x == 0) sc[4] = sqrt(s);
 }
 
+// nfl_apply_A64: y = A_E x for one FP64 vector in caller order
+int apply_A64_user(nfl_plan *P, const double *x, double *y) {
+  const int64_t n = P->n;
+  NFL_TRY(P->v64.ensure(2 * (size_t)n));
+  NFL_TRY(gather64(P, x, P->v64.p));
+  NFL_TRY(apply_A64(P, P->v64.p, P->v64.p + n));
+  return scatter64(P, P->v64.p + n, y);
+}
+
+__global__ __launch_bounds__(VT) void k_promote(const float *__restrict__ a, int64_t n,
+                                                double *__restrict__ b) {
+  for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT)
+    b[i] = (double)a[i];
+}
+
+// nfl_degree64: the FP64 degrees (FP64 path) or the float ones promoted, caller order
+int degree64_user(nfl_plan *P, double *d) {
+  const int64_t n = P->n;
+  if (P->prec == 64) return scatter64(P, P->deg64.p, d);
+  NFL_TRY(P->v64.ensure(2 * (size_t)n));
+  hipLaunchKernelGGL(k_promote, dim3(grid_for(n)), dim3(VT), 0, P->stream, P->deg.p, n, P->v64.p);
+  NFL_HIP(hipGetLastError());
+  return scatter64(P, P->v64.p, d);
+}
+
 int gather64(nfl_plan *P, const double *src, double *dst) {
   hipLaunchKernelGGL(k_gather64, dim3(grid_for(P->n)), dim3(VT), 0, P->stream, src, P->perm.p,
                      P->n, dst);

@@ -830,6 +830,7 @@ int convolve(nfl_plan *P, const float *gin_c, float *gout, bool zero_in) {
 // leaves zero for the next product (so no separate clear once it is clean);
 // the c2r pass writes `grid2`, which the interpolation reads.
 int fastsum(nfl_plan *P, int in_mode, int out_mode, const VecArgs &a) {
+  if (P->prec == 64) return fastsum64(P, in_mode, out_mode, a);
   if (P->prof_ev) NFL_HIP(hipEventRecord(P->prof_ev[0], P->stream));
   const bool clear = !P->grid_clean;
   P->grid_clean = false;

@@ -136,6 +136,16 @@ struct nfl_plan {
   nfl::DBuf<float> wcoef;       // window polynomials, WIN_MAXW x WIN_NC
   int opt_kernel = 0;           // 0: MFMA (tile-stationary where possible), 1: VALU, 2: MFMA per-cell runs
   bool opt_det = true;          // deterministic spread: int64 fixed-point grid (NFL_OPT_DETERMINISTIC)
+  int opt_prec = 32;            // NFFT precision: 32 (production) or 64 (NFL_OPT_PRECISION)
+  int prec = 32;                // the precision the current kernel was set up with
+  // all-FP64 path: real grid, complex grid, FP64 node fractions, degrees,
+  // filter (exact window transform) and twiddles
+  nfl::DBuf<double> grid64;
+  nfl::DBuf<double2> spec64;
+  nfl::DBuf<double4> frac64;
+  nfl::DBuf<double> deg64, dinv64, filt64;
+  nfl::DBuf<double2> tw64;
+  nfl::DBuf<double> v64;        // 2 n FP64: sorted in/out of nfl_apply_A64
   nfl::DBuf<unsigned> fx_max;   // bits of max |input| of the current product (pre-pass; reset by c2r)
   float fx_mult = 0.f;          // grid values <= max |input| * fx_mult (set by the spread launch)
   double win_max = 0;           // largest window value (psi(0))
@@ -194,6 +204,13 @@ int bbox_and_radius(nfl_plan *P);                       // sets centre, radius
 int radius_about(nfl_plan *P, const double *centre, double *radius);  // max ||v - centre||
 int build_sorted_nodes(nfl_plan *P);                    // keys, sort, items
 int build_filter_host(nfl_plan *P);                     // filt_host (FP64)
+// the half-spectrum filter (FP64); exact_window: divide by the exact transform
+// of the Kaiser-Bessel function (the FP64 path) instead of that of the
+// polynomial window the FP32 kernels apply
+int compute_filter(int d, int N, int m, int p, double eps_B, double sigma_t,
+                   std::vector<double> &out, int kind, double eps_I, bool exact_window = false);
+double kb_hat_exact(double xi, int m);                 // fp64.hip
+int setup64(nfl_plan *P);   // all-FP64 path (fp64.hip): buffers, fractions, filter, twiddles
 int exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t len, hipStream_t s,
                        DBuf<uint32_t> &scratch, size_t scratch_off);
 int radix_sort_pairs(uint32_t *keys, uint32_t *vals, int64_t n, int bits, hipStream_t s,
@@ -233,6 +250,8 @@ int convolve(nfl_plan *P, const float *gin, float *gout, bool zero_in = false);
 int interp(nfl_plan *P, const float *grid, int in_mode, int out_mode, const VecArgs &a);
 // whole fast summation with the given input/output modes (grid = plan grid)
 int fastsum(nfl_plan *P, int in_mode, int out_mode, const VecArgs &a);
+// the same fast summation with FP64 spread, FFT and interpolation (fp64.hip)
+int fastsum64(nfl_plan *P, int in_mode, int out_mode, const VecArgs &a);
 int fill_f32(float *p, int64_t n, float v, hipStream_t s);
 // Near-field correction of the Laplacian RBF kernel (nearfield.hip): adds the
 // contribution of sum_{||v~_i - v~_j|| <= eps_I} x~_j (K - T_I)(v~_i - v~_j) to
@@ -265,6 +284,8 @@ int cg_noalloc(nfl_plan *P, double tau, const double *f_dev, double *u_dev, int 
                int maxit, int *iters, double *relres);
 int krr_solve(nfl_plan *P, double beta, const double *f_dev, double *alpha_dev, int warm,
               double tol, int maxit, int *iters, double *relres);
+int apply_A64_user(nfl_plan *P, const double *x_user, double *y_user);
+int degree64_user(nfl_plan *P, double *d_user);
 int gather64(nfl_plan *P, const double *src_user, double *dst_sorted);
 int scatter64(nfl_plan *P, const double *src_sorted, double *dst_user);
 // out[:, j] = sum_k X[:, k] C[k * ldc + j] for j < b (X: n x a column-major,

@@ -786,7 +786,7 @@ void kernel_bhat(int d, int N, const RegKernel &KR, std::vector<double> &bhat) {
 }
 
 int compute_filter(int d, int N, int m, int p, double eps_B, double sigma_t,
-                   std::vector<double> &out, int kind, double eps_I) {
+                   std::vector<double> &out, int kind, double eps_I, bool exact_window) {
   if (d < 1 || d > 3 || N < 2 || (N & 1) || m < 1 || p < 1 || 2 * m > WIN_MAXW) return NFL_ERR_ARG;
   if (kind < NFL_KERNEL_GAUSSIAN || kind > NFL_KERNEL_LAPLACIAN_RBF) return NFL_ERR_ARG;
   if (kind == NFL_KERNEL_LAPLACIAN_RBF && !(eps_I > 0 && eps_I + eps_B < 0.5)) return NFL_ERR_ARG;
@@ -798,7 +798,10 @@ int compute_filter(int d, int N, int m, int p, double eps_B, double sigma_t,
   kernel_bhat(d, N, KR, S);
   // ---- window transform at l = -N/2..N/2
   std::vector<double> wh(N + 1);
-  for (int l = -N / 2; l <= N / 2; ++l) wh[l + N / 2] = window_hat((double)l / nos, m, wcoef);
+  // (the FP64 path applies the Kaiser-Bessel function itself: its exact transform)
+  for (int l = -N / 2; l <= N / 2; ++l)
+    wh[l + N / 2] = exact_window ? kb_hat_exact((double)l / nos, m)
+                                 : window_hat((double)l / nos, m, wcoef);
   // ---- half-spectrum filter: first d-1 axes l in [-N/2, N/2], last in [0, N/2]
   const int H = N / 2 + 1, F = N + 1;
   size_t cnt = (size_t)H;
