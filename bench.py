@@ -309,6 +309,51 @@ def kernels_leg(nfl, synth, torch, dev, v, x, lab, reps=50, rows=64):
     return out
 
 
+def cfg5_leg(nfl, synth, torch, dev, maxit=400):
+    """Large spectral clustering: n = 1e7, d = 3, 10-component Gaussian
+    mixture (weights Dirichlet(1), std U[0.005, 0.03]), sigma = 0.02, N = 128
+    (grid 256^3), m = 6.  Block Lanczos (block 4) for the 20 smallest
+    eigenvalues of L_s on the FP32 path (tol 1e-6) and on the all-FP64 path
+    (tol 1e-9), the per-eigenvalue difference (eq. max_ev_error with the FP64
+    run as reference), and spread / interpolation stage times with their
+    algorithmic HBM rates (record 16 B + input 4 B + permutation 4 B +
+    d^{-1/2} 4 B per node, + 4 B output for the interpolation, + the grid)."""
+    n, sigma, N, m = 10_000_000, 0.02, 128, 6
+    t0 = time.time()
+    v = synth.gmm(n, d=3, k=10, seed=0)
+    vd = torch.as_tensor(v, device=dev)
+    xd = torch.as_tensor(synth.normal_vectors(n, seed=4), device=dev)
+    out = {"workload": "10-component GMM, n=1e7, d=3, sigma=0.02, N=128 (grid 256^3), m=6; "
+                       "block Lanczos (block 4), 20 smallest of L_s"}
+    grid_bytes = 4.0 * (2 * N) ** 3
+    res = {}
+    for prec, tol in ((32, 1e-6), (64, 1e-9)):
+        P = nfl.plan(vd, sigma, N=N, m=m, eps_B=0.0, precision=prec)
+        st = P.profile_stages(xd, nrep=5)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        r = P.lanczos_smallest(20, tol=tol, maxit=maxit, block=4, vectors=False)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t1) * 1e3
+        P.close()
+        gb = (8.0 if prec == 64 else 4.0) / 4.0 * grid_bytes
+        res[prec] = np.asarray(r["evals"], dtype=np.float64)
+        out["fp%d" % prec] = {
+            "lanczos_ms": round(ms, 1), "steps": r["iters"], "converged": r["converged"],
+            "max_resid": r["max_resid"], "tol": tol,
+            "stage_ms": {k: round(v_, 4) for k, v_ in st.items()},
+            "spread_alg_GBps": round((28.0 * n + gb) / (st["spread"] * 1e-3) / 1e9, 1),
+            "interp_alg_GBps": round((32.0 * n + gb) / (st["interp"] * 1e-3) / 1e9, 1)}
+        log("cfg5 FP%d: %s" % (prec, out["fp%d" % prec]))
+    diff = np.abs(res[32] - res[64])
+    out["evals_fp64"] = [float("%.12g" % e) for e in res[64]]
+    out["abs_diff_fp32_vs_fp64"] = [float("%.3g" % e) for e in diff]
+    out["max_abs_diff"] = float(diff.max())
+    out["total_s"] = round(time.time() - t0, 1)
+    log("cfg5 per-eigenvalue |FP32 - FP64|: %s" % out["abs_diff_fp32_vs_fp64"])
+    return out
+
+
 def variants_leg(nfl, synth, torch, dev, steps=50, rows=256):
     """Clustering sensitivity and the FP32 operating point at n = 1M,
     sigma = 0.04, N = 64: a uniform ball and a 10-component mixture (std
@@ -452,6 +497,10 @@ def main():
                     help="skip the clustering / m = 4 variants and the small configurations")
     ap.add_argument("--no-kernels", action="store_true",
                     help="skip the (inverse) multiquadric kernel leg")
+    ap.add_argument("--no-cfg5", action="store_true",
+                    help="skip the n = 1e7 FP32-versus-FP64 block Lanczos leg")
+    ap.add_argument("--cfg5-only", action="store_true",
+                    help="run only the n = 1e7 FP32-versus-FP64 leg and print its JSON record")
     ap.add_argument("--nystrom-only", action="store_true",
                     help="run only the Nystrom leg (n = 1e5 spirals) and print its JSON record")
     ap.add_argument("--profile-run", action="store_true",
@@ -476,6 +525,9 @@ def main():
         return
     if args.nystrom_only:
         print(json.dumps(nystrom_leg(nfl, synth, torch, dev, reps=1)), flush=True)
+        return
+    if args.cfg5_only:
+        print(json.dumps(cfg5_leg(nfl, synth, torch, dev)), flush=True)
         return
     t0 = time.time()
     v, lab = synth.moons_and_roll(N_POINTS, seed=1)
@@ -727,6 +779,13 @@ def main():
         variants = variants_leg(nfl, synth, torch, dev)
         small = small_configs_leg(nfl, synth, torch, dev)
 
+    # --- n = 1e7: FP32 versus all-FP64 eigenvalues -------------------------------
+    cfg5 = None
+    if not args.no_cfg5:
+        P.close()          # free the metric plan's buffers first
+        P = None
+        cfg5 = cfg5_leg(nfl, synth, torch, dev)
+
     # --- CPU oracle baseline (bounded sample) ----------------------------------
     cpu = None
     if not args.no_cpu:
@@ -770,9 +829,11 @@ def main():
         "kernels": kern,
         "variants": variants,
         "small_configs": small,
+        "spectral_1e7_fp32_vs_fp64": cfg5,
     }
     print(json.dumps(out), flush=True)
-    P.close()
+    if P is not None:
+        P.close()
 
 
 if __name__ == "__main__":

@@ -715,6 +715,10 @@ int setup64(nfl_plan *P) {
 
 int fastsum64(nfl_plan *P, int in_mode, int out_mode, const VecArgs &a) {
   const K64 k = make_k64(P, a);
+  if (P->prof_ev) {   // stage events as on the FP32 path (no separate clear)
+    NFL_HIP(hipEventRecord(P->prof_ev[0], P->stream));
+    NFL_HIP(hipEventRecord(P->prof_ev[1], P->stream));
+  }
   // spread into the real FP64 grid (left zero by the first FFT pass)
   switch (in_mode) {
     case IN_USER_F32: NFL_TRY(spread64_in<IN_USER_F32>(P, k)); break;
@@ -724,17 +728,22 @@ int fastsum64(nfl_plan *P, int in_mode, int out_mode, const VecArgs &a) {
     case IN_SORTED_F64_DINV: NFL_TRY(spread64_in<IN_SORTED_F64_DINV>(P, k)); break;
     default: set_error("FP64 spread: bad input mode"); return NFL_ERR_ARG;
   }
+  if (P->prof_ev) NFL_HIP(hipEventRecord(P->prof_ev[2], P->stream));
   NFL_TRY(convolve64(P));
+  if (P->prof_ev) NFL_HIP(hipEventRecord(P->prof_ev[3], P->stream));
+  int rc;
   switch (out_mode) {
-    case OUT_USER_RAW: return interp64_io<IN_USER_F32, OUT_USER_RAW>(P, k);
-    case OUT_USER_W: return interp64_io<IN_USER_F32, OUT_USER_W>(P, k);
-    case OUT_USER_LS: return interp64_io<IN_USER_F32, OUT_USER_LS>(P, k);
-    case OUT_USER_A: return interp64_io<IN_USER_F32, OUT_USER_A>(P, k);
-    case OUT_DEGREE: return interp64_io<IN_ONES, OUT_DEGREE>(P, k);
-    case OUT_SORTED_F64_A: return interp64_io<IN_SORTED_F64_DINV, OUT_SORTED_F64_A>(P, k);
-    case OUT_SORTED_F64_SSL: return interp64_io<IN_SORTED_F64_DINV, OUT_SORTED_F64_SSL>(P, k);
+    case OUT_USER_RAW: rc = interp64_io<IN_USER_F32, OUT_USER_RAW>(P, k); break;
+    case OUT_USER_W: rc = interp64_io<IN_USER_F32, OUT_USER_W>(P, k); break;
+    case OUT_USER_LS: rc = interp64_io<IN_USER_F32, OUT_USER_LS>(P, k); break;
+    case OUT_USER_A: rc = interp64_io<IN_USER_F32, OUT_USER_A>(P, k); break;
+    case OUT_DEGREE: rc = interp64_io<IN_ONES, OUT_DEGREE>(P, k); break;
+    case OUT_SORTED_F64_A: rc = interp64_io<IN_SORTED_F64_DINV, OUT_SORTED_F64_A>(P, k); break;
+    case OUT_SORTED_F64_SSL: rc = interp64_io<IN_SORTED_F64_DINV, OUT_SORTED_F64_SSL>(P, k); break;
     default: set_error("FP64 interp: bad output mode"); return NFL_ERR_ARG;
   }
+  if (rc == NFL_OK && P->prof_ev) NFL_HIP(hipEventRecord(P->prof_ev[4], P->stream));
+  return rc;
 }
 
 }  // namespace nfl
