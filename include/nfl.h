@@ -399,7 +399,7 @@ int nfl_compute_filter_ex(int kind, int d, int N, int m, int p, double eps_B, do
  *   psi(t) = sinh(b sqrt(m^2 - t^2)) / (sqrt(m^2 - t^2) b e^{bm}), b = 3 pi / 2,
  * row-major [c][k], count >= 2m * NFL_WIN_NC.  The filter deconvolves with the
  * exact transform of this piecewise polynomial. */
-#define NFL_WIN_NC 10
+#define NFL_WIN_NC 8
 int nfl_window_coefficients(int m, float *coef_host, int64_t count);
 
 /* ---- accuracy probe and parameter search ---------------------------------- */

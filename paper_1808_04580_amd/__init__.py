@@ -145,7 +145,7 @@ def compute_filter(d: int, N: int, m: int, p: int, eps_B: float, sigma_tilde: fl
     return out.reshape(shape)
 
 
-WIN_NC = 10
+WIN_NC = 8
 
 
 def window_coefficients(m: int) -> np.ndarray:

@@ -259,7 +259,7 @@ void k_spread3_tile(const Item *__restrict__ items, const float4 *__restrict__ p
 }
 
 template <int W, int T, int IN, int OUT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 void k_interp3_tile(const Item *__restrict__ items, const float4 *__restrict__ pts, KArgs ka,
                     const float *__restrict__ grid, int nos, const float *__restrict__ wcoef) {
   if (stopped(ka.stop)) return;
@@ -588,7 +588,8 @@ static size_t tile_form_lds(int W, int T, bool spread) {
   const int Pd = T + W - 1;
   // spread: two tile copies must fit once the weight tables are free
   const size_t tables = (size_t)4 * 16 * (spread ? TS_PITCH : TS_PITCH_I);
-  const size_t need = (size_t)Pd * ts_xs(Pd) + tables;
+  // the interpolation keeps the window coefficients in LDS after the tables
+  const size_t need = (size_t)Pd * ts_xs(Pd) + tables + (spread ? 0 : WIN_MAXW * WIN_NC);
   return std::max(need, spread ? (size_t)2 * 16 * ts_xs(Pd) : need) * sizeof(float);
 }
 

@@ -675,6 +675,61 @@ __device__ __forceinline__ void fill_shifted(const float4 &qb, float xb, int sub
   }
 }
 
+// fill_shifted with the window coefficients read from LDS (cft: WIN_MAXW rows
+// of WIN_NC floats) at each use instead of being held in registers.
+// ZREL: the z weights stay relative to the node's own window (z' = offset,
+// no shift by the cell and no zero padding): for runs of nodes that share
+// their cell's z inside the tile.  `first` is the batch lane of the first
+// node of the run.
+template <int T, int W, bool SPREAD, int PITCH, bool ZREL = false>
+__device__ __forceinline__ void fill_shifted_lds(const float4 &qb, float xb, int first, int cnt,
+                                                 int lane, const float *cft, float *wt, int ox,
+                                                 int oy, int oz) {
+  constexpr int U = fill_upl<W>();
+  static_assert(T % 4 == 0 && T + 16 <= 32, "row segment layout");
+  static_assert(WIN_NC % 4 == 0, "coefficient rows are read as float4");
+  const int node = lane >> 2, part = lane & 3;
+  const int src = first + min(node, cnt - 1);
+  const float qx = __shfl(qb.x, src), qy = __shfl(qb.y, src), qz = __shfl(qb.z, src);
+  const uint32_t cell = (uint32_t)__shfl((int)__float_as_uint(qb.w), src);
+  float xv = 1.f;
+  if constexpr (SPREAD) {
+    xv = __shfl(xb, src);
+    if (node >= cnt) xv = 0.f;
+  }
+  const int lx = (int)(cell & 1023u) - ox, ly = (int)((cell >> 10) & 1023u) - oy,
+            lz = (int)(cell >> 20) - oz;
+  float *row = wt + node * PITCH;
+  if (part == 0) {
+#pragma unroll
+    for (int a = 0; a < (ZREL ? 2 : 3); ++a) {
+#pragma unroll
+      for (int z = 0; z < T; z += 4)
+        *reinterpret_cast<float4 *>(row + 32 * a + z) = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int z = 4 * U; z < 16; z += 4)
+        *reinterpret_cast<float4 *>(row + 32 * a + z) = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int o = U * part + u;
+    float c[WIN_NC];
+    const float4 *cp = reinterpret_cast<const float4 *>(cft + o * WIN_NC);
+#pragma unroll
+    for (int k = 0; k < WIN_NC / 4; ++k) {
+      const float4 t = cp[k];
+      c[4 * k] = t.x;
+      c[4 * k + 1] = t.y;
+      c[4 * k + 2] = t.z;
+      c[4 * k + 3] = t.w;
+    }
+    row[lx + o] = xv * win_poly(c, qx);
+    row[32 + ly + o] = win_poly(c, qy);
+    row[64 + (ZREL ? 0 : lz) + o] = win_poly(c, qz);
+  }
+}
+
 template <int W, int T, int IN, int NW = 4>
 __device__ __forceinline__ void spread3_tile_body(const Item it, const float4 *__restrict__ pts,
                                                   const KArgs ka, float *__restrict__ grid,
@@ -813,7 +868,7 @@ __device__ __forceinline__ void interp3_tile_body(const Item *__restrict__ items
                                                   const KArgs ka,
                                                   const float *__restrict__ grid, int nos,
                                                   const float *__restrict__ wcoef) {
-  constexpr int M = W / 2, P = T + W - 1, XS = ts_xs(P), NS = 4 * P;
+  constexpr int M = W / 2, P = T + W - 1, XS = ts_xs(P);
   static_assert(P <= 16, "tile-stationary form needs T + W - 1 <= 16");
   extern __shared__ float lds[];
   float *tile = lds;
@@ -840,24 +895,26 @@ __device__ __forceinline__ void interp3_tile_body(const Item *__restrict__ items
         tile[px * XS + py * 16 + c16] = v;
       }
     }
+    // window coefficients (rows 2m..15 are 0) after the tables
+    float *cfs = lds + P * XS + NW * 16 * TS_PITCH_I;
+    for (int q = threadIdx.x; q < WIN_MAXW * WIN_NC; q += NW * 64) cfs[q] = wcoef[q];
   }
   __syncthreads();
-  // A operand: lane (row c16, k = p4) holds G[c16][4 s + p4], s < 4P
-  float g[NS];
-#pragma unroll
-  for (int st = 0; st < NS; ++st) g[st] = c16 < P ? tile[c16 * XS + 4 * st + p4] : 0.f;
+  // Nodes are taken in runs of <= 16 that share their cell's z inside the tile
+  // (the sort orders a tile's nodes z-major, so a run is usually 16 long):
+  // their z windows coincide, so K = (padded y, z window) needs ZQ = W/4
+  // quads per y instead of the 4 of the whole padded z extent.
+  // A operand for the run's z offset lz: lane (row c16, k = p4) holds
+  // G[c16][y][lz + 4 zq + p4] at step y ZQ + zq; reloaded when lz changes.
+  constexpr int ZQ = (W + 3) / 4, NK = P * ZQ;
+  static_assert(T + 4 * ZQ <= 17, "the shifted z window stays inside a 16-wide tile row");
+  float g[NK];
+  int cur_lz = -1;
 
   float *wt = lds + P * XS + wave * (16 * TS_PITCH_I);
+  const float *cft = lds + P * XS + NW * 16 * TS_PITCH_I;   // staged with the tile
   const int len = it.end - it.start, per = (len + NW - 1) / NW;
   const int s = it.start + min(len, wave * per), e = it.start + min(len, (wave + 1) * per);
-  constexpr int U = fill_upl<W>();
-  float cf[U][WIN_NC];
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int o = U * (lane & 3) + u;
-#pragma unroll
-    for (int k = 0; k < WIN_NC; ++k) cf[u][k] = wcoef[o * WIN_NC + k];   // rows 2m..15 of the table are 0
-  }
   float4 qb, qn;
   float xb, xn;
   OutPre ob, on;
@@ -869,16 +926,32 @@ __device__ __forceinline__ void interp3_tile_body(const Item *__restrict__ items
     load_batch<IN, false>(pts, ka, b0 + 64, e, lane, qn, xn);
     pre_index<OUT>(ka, b0 + 64 + lane, b0 + 64 + lane < e, on);
     const int bcnt = min(64, e - b0);
-    for (int sb = 0; sb * 16 < bcnt; ++sb) {
-      const int cnt = min(16, bcnt - sb * 16);
-      const int i0 = b0 + sb * 16;
-      const OutPre op = pre_from<OUT>(ob, sb * 16 + c16);
-      fill_shifted<T, W, false, TS_PITCH_I>(qb, xb, sb, cnt, lane, cf, wt, ox, oy, oz);
+    const int lzl = (int)(__float_as_uint(qb.w) >> 20) - oz;   // this lane's node: z in the tile
+    int cnt;
+    for (int pos = 0; pos < bcnt; pos += cnt) {
+      const int lz0 = __builtin_amdgcn_readlane(lzl, pos);
+      const unsigned long long same = __ballot(lane < bcnt && lzl == lz0);
+      // run length from pos: the trailing ones of same >> pos (all 64 bits are
+      // ones when pos = 0 and the whole batch shares lz: ctz of 0 is undefined)
+      const unsigned long long rest = ~(same >> pos);
+      const int run = rest ? __builtin_ctzll(rest) : 64;            // >= 1: the node at pos
+      cnt = min(16, min(run, bcnt - pos));
+      if (lz0 != cur_lz) {
+        cur_lz = lz0;
+#pragma unroll
+        for (int y = 0; y < P; ++y)
+#pragma unroll
+          for (int zq = 0; zq < ZQ; ++zq)
+            g[y * ZQ + zq] = c16 < P ? tile[c16 * XS + y * 16 + lz0 + 4 * zq + p4] : 0.f;
+      }
+      const int i0 = b0 + pos;
+      const OutPre op = pre_from<OUT>(ob, pos + c16);
+      fill_shifted_lds<T, W, false, TS_PITCH_I, true>(qb, xb, pos, cnt, lane, cft, wt, ox, oy, oz);
       wave_sync_lds();
       const float *w = wt + c16 * TS_PITCH_I;    // column c16 = node c16
-      float wz4[4], wy[16];
+      float wzq[ZQ], wy[16];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) wz4[q] = w[64 + 4 * q + p4];
+      for (int q = 0; q < ZQ; ++q) wzq[q] = w[64 + 4 * q + p4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const float4 v = *reinterpret_cast<const float4 *>(w + 32 + 4 * q);
@@ -887,19 +960,18 @@ __device__ __forceinline__ void interp3_tile_body(const Item *__restrict__ items
         wy[4 * q + 2] = v.z;
         wy[4 * q + 3] = v.w;
       }
-      f32x4 d[4];
+      // two accumulator chains: a chain's next instruction comes two matrix
+      // instructions later, past the result latency
+      f32x4 d[2];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) d[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int q = 0; q < 2; ++q) d[q] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int st = 0; st < NS; ++st)
-        d[st & 3] = __builtin_amdgcn_mfma_f32_16x16x4f32(g[st], wy[st >> 2] * wz4[st & 3],
-                                                         d[st & 3], 0, 0, 0);
+      for (int st = 0; st < NK; ++st)
+        d[st & 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(g[st], wy[st / ZQ] * wzq[st % ZQ],
+                                                         d[st & 1], 0, 0, 0);
       float part = 0.f;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const float dr = (d[0][r] + d[1][r]) + (d[2][r] + d[3][r]);
-        part = fmaf(w[4 * p4 + r], dr, part);
-      }
+      for (int r = 0; r < 4; ++r) part = fmaf(w[4 * p4 + r], d[0][r] + d[1][r], part);
       part = sum_rows4(part);
       if (p4 == 0 && c16 < cnt) store_pre<OUT>(ka, i0 + c16, part, op);
       wave_sync_lds();

@@ -76,7 +76,7 @@ struct Item {
 };
 
 // Window polynomials: WIN_NC coefficients for each of up to WIN_MAXW offsets.
-constexpr int WIN_NC = 10;
+constexpr int WIN_NC = 8;   // degree 7: the float32 rounding of the coefficients already bounds the fit (~3e-8 of psi(0))
 constexpr int WIN_MAXW = 16;
 int window_coefficients(int m, std::vector<float> &coef);
 

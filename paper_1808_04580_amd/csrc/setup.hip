@@ -323,10 +323,10 @@ __global__ __launch_bounds__(256) void k_keys(const float *__restrict__ v, int64
   }
   const uint32_t T = 1u << tshift, ntd = (uint32_t)nos >> tshift;
   uint32_t tile = 0, local = 0;
-  for (int t = 0; t < d; ++t) {
-    tile = tile * ntd + ((uint32_t)cell[t] >> tshift);
-    local = local * T + ((uint32_t)cell[t] & (T - 1));
-  }
+  for (int t = 0; t < d; ++t) tile = tile * ntd + ((uint32_t)cell[t] >> tshift);
+  // inside a tile the last axis is the slowest: nodes of one z-offset (of one
+  // y-offset, then one cell) are consecutive, which the interpolation's runs use
+  for (int t = d - 1; t >= 0; --t) local = local * T + ((uint32_t)cell[t] & (T - 1));
   keys[i] = (tile << (d * tshift)) | local;
   idx[i] = (uint32_t)i;
   const uint32_t packed = (uint32_t)cell[0] | ((uint32_t)cell[1] << 10) | ((uint32_t)cell[2] << 20);

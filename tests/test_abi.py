@@ -94,12 +94,14 @@ def poly_window(coef, m, t):
 
 @pytest.mark.parametrize("m", [2, 3, 4, 5, 6, 7, 8])
 def test_window_polynomials_match_kaiser_bessel(m):
-    """The polynomial window equals the Kaiser-Bessel window to float32 level."""
+    """The polynomial window (degree 7 per unit interval) equals the
+    Kaiser-Bessel window to float32 level: within 1e-7 of psi(0) for m >= 3,
+    4e-7 for m = 2 (whose own NFFT error, ~1e-3, is far larger)."""
     coef = nfl.window_coefficients(m)
     assert coef.shape == (2 * m, nfl.WIN_NC)
     t = np.linspace(-m + 1e-9, m, 20001)
     err = np.abs(poly_window(coef, m, t) - kb_psi(t, m)).max() / kb_psi(0.0, m)
-    assert err < 3e-7, err
+    assert err < (4e-7 if m == 2 else 1e-7), err
 
 
 def poly_window_hat(coef, m, xi, nq=64):
