@@ -588,8 +588,8 @@ static size_t tile_form_lds(int W, int T, bool spread) {
   const int Pd = T + W - 1;
   // spread: two tile copies must fit once the weight tables are free
   const size_t tables = (size_t)4 * 16 * (spread ? TS_PITCH : TS_PITCH_I);
-  // the interpolation keeps the window coefficients in LDS after the tables
-  const size_t need = (size_t)Pd * ts_xs(Pd) + tables + (spread ? 0 : WIN_MAXW * WIN_NC);
+  // the window coefficients stay in LDS after the tables
+  const size_t need = (size_t)Pd * ts_xs(Pd) + tables + WIN_MAXW * WIN_NC;
   return std::max(need, spread ? (size_t)2 * 16 * ts_xs(Pd) : need) * sizeof(float);
 }
 

@@ -637,14 +637,17 @@ __host__ __device__ constexpr int ts_xs(int P) { return P * 16 + 4; }   // 4 row
 template <int W>
 constexpr int fill_upl() { return (W + 3) / 4; }
 
-template <int T, int W, bool SPREAD, int PITCH>
-__device__ __forceinline__ void fill_shifted(const float4 &qb, float xb, int sub, int cnt,
+// YREL: the y weights stay relative to the node's own window (y' = offset,
+// no shift by the cell, no zero padding), for runs of nodes that share their
+// cell's y inside the tile.  `first`: batch lane of the run's first node.
+template <int T, int W, bool SPREAD, int PITCH, bool YREL = false>
+__device__ __forceinline__ void fill_shifted(const float4 &qb, float xb, int first, int cnt,
                                              int lane, const float (&cf)[fill_upl<W>()][WIN_NC],
                                              float *wt, int ox, int oy, int oz) {
   constexpr int U = fill_upl<W>();
   static_assert(T % 4 == 0 && T + 16 <= 32, "row segment layout");
   const int node = lane >> 2, part = lane & 3;
-  const int src = sub * 16 + min(node, cnt - 1);
+  const int src = first + min(node, cnt - 1);
   const float qx = __shfl(qb.x, src), qy = __shfl(qb.y, src), qz = __shfl(qb.z, src);
   const uint32_t cell = (uint32_t)__shfl((int)__float_as_uint(qb.w), src);
   float xv = 1.f;
@@ -658,6 +661,7 @@ __device__ __forceinline__ void fill_shifted(const float4 &qb, float xb, int sub
   if (part == 0) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
+      if (YREL && a == 1) continue;
 #pragma unroll
       for (int z = 0; z < T; z += 4)
         *reinterpret_cast<float4 *>(row + 32 * a + z) = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -670,7 +674,7 @@ __device__ __forceinline__ void fill_shifted(const float4 &qb, float xb, int sub
   for (int u = 0; u < U; ++u) {
     const int o = U * part + u;
     row[lx + o] = xv * win_poly(cf[u], qx);
-    row[32 + ly + o] = win_poly(cf[u], qy);
+    row[32 + (YREL ? 0 : ly) + o] = win_poly(cf[u], qy);
     row[64 + lz + o] = win_poly(cf[u], qz);
   }
 }
@@ -681,7 +685,7 @@ __device__ __forceinline__ void fill_shifted(const float4 &qb, float xb, int sub
 // no shift by the cell and no zero padding): for runs of nodes that share
 // their cell's z inside the tile.  `first` is the batch lane of the first
 // node of the run.
-template <int T, int W, bool SPREAD, int PITCH, bool ZREL = false>
+template <int T, int W, bool SPREAD, int PITCH, bool ZREL = false, bool YREL = false>
 __device__ __forceinline__ void fill_shifted_lds(const float4 &qb, float xb, int first, int cnt,
                                                  int lane, const float *cft, float *wt, int ox,
                                                  int oy, int oz) {
@@ -702,7 +706,8 @@ __device__ __forceinline__ void fill_shifted_lds(const float4 &qb, float xb, int
   float *row = wt + node * PITCH;
   if (part == 0) {
 #pragma unroll
-    for (int a = 0; a < (ZREL ? 2 : 3); ++a) {
+    for (int a = 0; a < 3; ++a) {
+      if ((ZREL && a == 2) || (YREL && a == 1)) continue;
 #pragma unroll
       for (int z = 0; z < T; z += 4)
         *reinterpret_cast<float4 *>(row + 32 * a + z) = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -725,8 +730,55 @@ __device__ __forceinline__ void fill_shifted_lds(const float4 &qb, float xb, int
       c[4 * k + 3] = t.w;
     }
     row[lx + o] = xv * win_poly(c, qx);
-    row[32 + ly + o] = win_poly(c, qy);
+    row[32 + (YREL ? 0 : ly) + o] = win_poly(c, qy);
     row[64 + (ZREL ? 0 : lz) + o] = win_poly(c, qz);
+  }
+}
+
+// The 4-node steps of one run of the spread (nodes sharing their cell's y
+// offset L inside the tile): W y-slices per step, accumulators L .. L + W - 1.
+// Two operand sets: the operands of step st + 1 are loaded (always: rows
+// 4 (st + 1) + p4 < 16 lie in the table) while the matrix instructions of
+// step st issue, so the wait before step st covers exactly its own loads.
+// Steps past nst are skipped whole.
+template <int L, int W, int P, int PITCH>
+__device__ __forceinline__ void spread_run_steps(f32x4 (&acc)[P], const float *wt, int nst,
+                                                 int c16, int p4) {
+  static_assert(L + W <= P, "the run's window lies in the padded tile");
+  constexpr int WQ = (W + 3) / 4;
+  float a[2], wz[2], wy[2][4 * WQ];
+  auto load_step = [&](int st, float &a_, float &wz_, float (&wy_)[4 * WQ]) {
+    const float *w = wt + (4 * st + p4) * PITCH;
+    a_ = w[c16];
+    wz_ = w[64 + c16];
+#pragma unroll
+    for (int q = 0; q < WQ; ++q) {
+      const float4 v = *reinterpret_cast<const float4 *>(w + 32 + 4 * q);
+      wy_[4 * q] = v.x;
+      wy_[4 * q + 1] = v.y;
+      wy_[4 * q + 2] = v.z;
+      wy_[4 * q + 3] = v.w;
+    }
+  };
+  load_step(0, a[0], wz[0], wy[0]);
+#pragma unroll
+  for (int st = 0; st < 4; ++st) {
+    const int c = st & 1;
+    if (st + 1 < 4) load_step(st + 1, a[c ^ 1], wz[c ^ 1], wy[c ^ 1]);
+    if (st < nst) {
+#pragma unroll
+      for (int y = 0; y < W; ++y)
+        acc[L + y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], wy[c][y] * wz[c], acc[L + y], 0, 0, 0);
+    }
+  }
+}
+
+template <int W, int P, int PITCH, int L = 0>
+__device__ __forceinline__ void spread_run_dispatch(int ly0, f32x4 (&acc)[P], const float *wt,
+                                                    int nst, int c16, int p4) {
+  if constexpr (L + W <= P) {
+    if (ly0 == L) spread_run_steps<L, W, P, PITCH>(acc, wt, nst, c16, p4);
+    else spread_run_dispatch<W, P, PITCH, L + 1>(ly0, acc, wt, nst, c16, p4);
   }
 }
 
@@ -748,14 +800,11 @@ __device__ __forceinline__ void spread3_tile_body(const Item it, const float4 *_
   const int len = it.end - it.start, per = (len + NW - 1) / NW;
   const int s = it.start + min(len, wave * per), e = it.start + min(len, (wave + 1) * per);
 
-  constexpr int U = fill_upl<W>();
-  float cf[U][WIN_NC];
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int o = U * (lane & 3) + u;
-#pragma unroll
-    for (int k = 0; k < WIN_NC; ++k) cf[u][k] = wcoef[o * WIN_NC + k];   // rows 2m..15 of the table are 0
-  }
+  // window coefficients (rows 2m..15 are 0) after the weight tables, read at
+  // each use (the final tile sum reuses only the LDS below them)
+  float *cft = lds + P * XS + NW * 16 * TS_PITCH;
+  for (int q = threadIdx.x; q < WIN_MAXW * WIN_NC; q += NW * 64) cft[q] = wcoef[q];
+  __syncthreads();
   f32x4 acc[P];
 #pragma unroll
   for (int y = 0; y < P; ++y) acc[y] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -766,43 +815,21 @@ __device__ __forceinline__ void spread3_tile_body(const Item it, const float4 *_
   for (int b0 = s; b0 < e; b0 += 64) {
     load_batch<IN, true>(pts, ka, b0 + 64, e, lane, qn, xn);  // prefetch the next batch
     const int bcnt = min(64, e - b0);
-    for (int sb = 0; sb * 16 < bcnt; ++sb) {
-      const int cnt = min(16, bcnt - sb * 16);
-      fill_shifted<T, W, true, TS_PITCH>(qb, xb, sb, cnt, lane, cf, wt, ox, oy, oz);
+    // runs of <= 16 nodes sharing their cell's y offset in the tile (the sort
+    // orders a tile's nodes z-major, then by y): their y windows coincide, so
+    // a step issues W y-slices instead of all T + W - 1 of the padded tile
+    const int lyl = (int)((__float_as_uint(qb.w) >> 10) & 1023u) - oy;
+    int cnt;
+    for (int pos = 0; pos < bcnt; pos += cnt) {
+      const int ly0 = __builtin_amdgcn_readlane(lyl, pos);
+      const unsigned long long same = __ballot(lane < bcnt && lyl == ly0);
+      const unsigned long long rest = ~(same >> pos);   // 0 when the whole batch shares ly0
+      const int run = rest ? __builtin_ctzll(rest) : 64;
+      cnt = min(16, min(run, bcnt - pos));
+      fill_shifted_lds<T, W, true, TS_PITCH, false, true>(qb, xb, pos, cnt, lane, cft, wt, ox, oy,
+                                                          oz);
       wave_sync_lds();
-      // four steps of 4 nodes, unrolled, with two operand sets: the operands
-      // of step st + 1 are loaded (always: rows 4 (st + 1) + p4 < 16 lie in
-      // the table) while the matrix instructions of step st issue, so the
-      // wait before step st covers exactly its own loads.  Steps past cnt
-      // are skipped whole.  Every y-slice is issued: slices outside the 4
-      // nodes' windows add zero products, and skipping them behind
-      // per-slice branches measured slower than the straight-line block.
-      const int nst = (cnt + 3) >> 2;
-      float a[2], wz[2], wy[2][16];
-      auto load_step = [&](int st, float &a_, float &wz_, float (&wy_)[16]) {
-        const float *w = wt + (4 * st + p4) * TS_PITCH;
-        a_ = w[c16];
-        wz_ = w[64 + c16];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const float4 v = *reinterpret_cast<const float4 *>(w + 32 + 4 * q);
-          wy_[4 * q] = v.x;
-          wy_[4 * q + 1] = v.y;
-          wy_[4 * q + 2] = v.z;
-          wy_[4 * q + 3] = v.w;
-        }
-      };
-      load_step(0, a[0], wz[0], wy[0]);
-#pragma unroll
-      for (int st = 0; st < 4; ++st) {
-        const int c = st & 1;
-        if (st + 1 < 4) load_step(st + 1, a[c ^ 1], wz[c ^ 1], wy[c ^ 1]);
-        if (st < nst) {
-#pragma unroll
-          for (int y = 0; y < P; ++y)
-            acc[y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], wy[c][y] * wz[c], acc[y], 0, 0, 0);
-        }
-      }
+      spread_run_dispatch<W, P, TS_PITCH>(ly0, acc, wt, (cnt + 3) >> 2, c16, p4);
       wave_sync_lds();
     }
     qb = qn;
