@@ -323,12 +323,15 @@ static int apply_A64(nfl_plan *P, const double *q, double *w) {
   return fastsum(P, IN_SORTED_F64_DINV, OUT_SORTED_F64_A, a);
 }
 
-// w = (I + tau L_s) q
-static int apply_SSL64(nfl_plan *P, double tau, const double *q, double *w) {
+// w = (I + tau L_s) q; fx_ready: q's bound for the deterministic spread is in
+// the plan's fx_max word already (the CG direction kernels write it)
+static int apply_SSL64(nfl_plan *P, double tau, const double *q, double *w,
+                       bool fx_ready = false) {
   VecArgs a;
   a.x64 = q;
   a.y64 = w;
   a.tau = tau;
+  a.fx_ready = fx_ready;
   return fastsum(P, IN_SORTED_F64_DINV, OUT_SORTED_F64_SSL, a);
 }
 
@@ -890,18 +893,37 @@ __device__ __forceinline__ double sum_partials(const double *__restrict__ part, 
 }
 
 // r = f - q (q null: r = f); p = r; partials of r.r and f.f
+// The deterministic spread's input bound for the next product: max |p| over
+// the block as float bits (rounded up), one atomic max per block.  The word
+// was reset by the last FFT pass of the previous product.
+__device__ __forceinline__ void block_absmax_to(float m, unsigned *fx_max) {
+  __shared__ float wm[VT / 64];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < VT / 64; ++w) m = fmaxf(m, wm[w]);
+    atomicMax(fx_max, __float_as_uint(m * (1.f + 1e-6f)));
+  }
+}
+
 __global__ __launch_bounds__(VT) void k_cg_start(const double *__restrict__ f,
                                                  const double *__restrict__ q, int64_t n,
                                                  double *__restrict__ r, double *__restrict__ p,
-                                                 double *__restrict__ part) {
+                                                 double *__restrict__ part,
+                                                 unsigned *__restrict__ fx_max) {
   __shared__ double sh[VT / 64];
   double rr = 0.0, ff = 0.0;
+  float mx = 0.f;
   for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT) {
     const double fi = f[i], ri = q ? fi - q[i] : fi;
     r[i] = ri;
     p[i] = ri;
     rr += ri * ri;
     ff += fi * fi;
+    mx = fmaxf(mx, (float)fabs(ri));
   }
   rr = block_sum(rr, sh);
   ff = block_sum(ff, sh);
@@ -909,6 +931,7 @@ __global__ __launch_bounds__(VT) void k_cg_start(const double *__restrict__ f,
     part[blockIdx.x] = rr;
     part[CG_NB + blockIdx.x] = ff;
   }
+  if (fx_max) block_absmax_to(mx, fx_max);
 }
 
 // one block: r.r, ||f||, the tolerance, and the stop flag before the first step
@@ -929,12 +952,22 @@ __global__ __launch_bounds__(VT) void k_cg_init(const double *__restrict__ part,
   }
 }
 
+// The solve's stop flag as one value for the whole block: block 0 of k_cg_dir
+// (and of k_cg_step on a breakdown) writes it while other blocks of the same
+// kernel may be starting, so the waves of a block read it once, together.
+__device__ __forceinline__ bool cg_stopped(const int *st) {
+  __shared__ int s_stop;
+  if (threadIdx.x == 0) s_stop = __hip_atomic_load(st, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  return s_stop != 0;
+}
+
 // partials of p.q
 __global__ __launch_bounds__(VT) void k_cg_pq(const double *__restrict__ p,
                                               const double *__restrict__ q, int64_t n,
                                               const int *__restrict__ st,
                                               double *__restrict__ part) {
-  if (st[0]) return;
+  if (cg_stopped(st)) return;
   __shared__ double sh[VT / 64];
   double s = 0.0;
   for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT)
@@ -950,7 +983,7 @@ __global__ __launch_bounds__(VT) void k_cg_step(double *__restrict__ u, double *
                                                 const double *__restrict__ sc,
                                                 int *__restrict__ st,
                                                 double *__restrict__ part) {
-  if (st[0]) return;
+  if (cg_stopped(st)) return;
   __shared__ double sh[VT / 64];
   const double pq = sum_partials(part, (int)gridDim.x, sh);
   if (!(pq > 0.0) || !isfinite(pq)) {   // M is not positive definite on p: stop
@@ -977,13 +1010,19 @@ __global__ __launch_bounds__(VT) void k_cg_dir(double *__restrict__ p,
                                                const double *__restrict__ r, int64_t n, int k,
                                                double *__restrict__ sc, int *__restrict__ st,
                                                const double *__restrict__ part,
-                                               int *__restrict__ host_st) {
-  if (st[0]) return;
+                                               int *__restrict__ host_st,
+                                               unsigned *__restrict__ fx_max) {
+  if (cg_stopped(st)) return;
   __shared__ double sh[VT / 64];
   const double rn = sum_partials(part + CG_NB, (int)gridDim.x, sh);
   const double b = rn / sc[k & 1];
-  for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT)
-    p[i] = r[i] + b * p[i];
+  float mx = 0.f;
+  for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT) {
+    const double pi = r[i] + b * p[i];
+    p[i] = pi;
+    mx = fmaxf(mx, (float)fabs(pi));
+  }
+  if (fx_max) block_absmax_to(mx, fx_max);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     sc[(k + 1) & 1] = rn;
     const int done = rn <= sc[3] ? 1 : 0;
@@ -1077,10 +1116,11 @@ __global__ __launch_bounds__(VT) void k_krr_combine(const float *__restrict__ t,
 }
 
 struct KrrOp {
+  static constexpr bool fx_feed = false;
   nfl_plan *P;
   double beta;
   float *x32, *t32;
-  int operator()(const double *x, double *q) const {
+  int operator()(const double *x, double *q, bool = false) const {
     const int gb = grid_for(P->n);
     hipLaunchKernelGGL(k_to_f32, dim3(gb), dim3(VT), 0, P->stream, x, P->n, x32);
     VecArgs a;
@@ -1095,9 +1135,12 @@ struct KrrOp {
 };
 
 struct SslOp {
+  static constexpr bool fx_feed = true;   // products take the input bound from the CG kernels
   nfl_plan *P;
   double tau;
-  int operator()(const double *x, double *q) const { return apply_SSL64(P, tau, x, q); }
+  int operator()(const double *x, double *q, bool fx_ready = false) const {
+    return apply_SSL64(P, tau, x, q, fx_ready);
+  }
 };
 
 // CG iterations for M u = f on vectors f, u (u holds the start) of the plan's
@@ -1128,8 +1171,11 @@ static int cg_core(nfl_plan *P, const Op &op, const CgWork &W, const double *f, 
   hipStream_t s = P->stream;
   const int nb = cg_blocks(n);
   if (!u_zero) NFL_TRY(op(u, W.q));   // r = f - M u0 (M 0 = 0: no product for a zero start)
+  // the direction kernels also write the bound of the next product's input
+  // for the deterministic spread (its pre-pass is then skipped)
+  unsigned *fxw = (Op::fx_feed && P->opt_det && P->prec == 32) ? P->fx_max.p : nullptr;
   hipLaunchKernelGGL(k_cg_start, dim3(nb), dim3(VT), 0, s, f, u_zero ? nullptr : W.q, n, W.r,
-                     W.p, W.part);
+                     W.p, W.part, fxw);
   hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(VT), 0, s, W.part, nb, tol, W.sc, W.st);
   NFL_HIP(hipGetLastError());
   if (W.host_st) {
@@ -1143,12 +1189,12 @@ static int cg_core(nfl_plan *P, const Op &op, const CgWork &W, const double *f, 
   P->stop = W.st;   // every product kernel of the loop returns once the flag is set
   constexpr int check = 4;
   for (int k = 0; k < maxit; ++k) {
-    NFL_TRY(op(W.p, W.q));
+    NFL_TRY(op(W.p, W.q, fxw != nullptr));
     hipLaunchKernelGGL(k_cg_pq, dim3(nb), dim3(VT), 0, s, W.p, W.q, n, W.st, W.part);
     hipLaunchKernelGGL(k_cg_step, dim3(nb), dim3(VT), 0, s, u, W.r, W.p, W.q, n, k, W.sc, W.st,
                        W.part);
     hipLaunchKernelGGL(k_cg_dir, dim3(nb), dim3(VT), 0, s, W.p, W.r, n, k, W.sc, W.st, W.part,
-                       W.host_st);
+                       W.host_st, fxw);
     NFL_HIP(hipGetLastError());
     if (W.host_st) {
       // wait for step k - 1 while step k is queued behind it
@@ -1165,6 +1211,10 @@ static int cg_core(nfl_plan *P, const Op &op, const CgWork &W, const double *f, 
     }
   }
   P->stop = nullptr;
+  // The last direction kernel (or the start kernel, when the loop never ran a
+  // product) may have left a bound for a product that was skipped; the word
+  // must start from zero for the next pre-pass.
+  if (fxw) NFL_TRY(fill_f32(reinterpret_cast<float *>(fxw), 1, 0.f, s));
   // true residual with the same operator
   NFL_TRY(op(u, W.q));
   hipLaunchKernelGGL(k_cg_resid, dim3(nb), dim3(VT), 0, s, f, W.q, n, W.part);

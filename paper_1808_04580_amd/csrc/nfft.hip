@@ -699,6 +699,7 @@ static int fx_prepass(nfl_plan *P, int in_mode, const VecArgs &a) {
   if (in_mode == IN_USER_F32_DINV || in_mode == IN_SORTED_F64_DINV)
     factor = 1.01 / std::sqrt(std::max(P->dmin, 1e-300));
   P->fx_mult = (float)(1.0625 * factor * (double)P->n * std::pow(1.01 * P->win_max, P->d));
+  if (a.fx_ready) return NFL_OK;   // the producer of the input wrote its bound
   const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(512, (P->n + 1023) / 1024));
   if (in_mode == IN_ONES) {
     hipLaunchKernelGGL(k_fx_max<float>, dim3(1), dim3(64), 0, P->stream, (const float *)nullptr,

@@ -237,6 +237,9 @@ enum OutMode {
 };
 
 struct VecArgs {
+  // the input's bound for the deterministic spread is already in the plan's
+  // fx_max word (written by the kernel that produced the input)
+  bool fx_ready = false;
   const float *x32 = nullptr;   // caller order
   float *y32 = nullptr;         // caller order
   const double *x64 = nullptr;  // sorted order
