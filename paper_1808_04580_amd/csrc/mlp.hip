@@ -3,12 +3,19 @@
 // with BF16 operands and FP32 accumulation.
 //
 // Layers are computed in transposed form, D[unit][node] = sum_k W[unit][k] H[k][node],
-// with v_mfma_f32_16x16x16_bf16 (A = 16 units x 16 inputs, B = 16 inputs x 16
-// nodes).  Lane l holds D[unit = 4 (l/16) + r][node = l%16]; that is exactly the
-// B-operand layout of the next layer (input = 4 (l/16) + v, node = l%16), so
-// activations stay in registers from layer to layer.  Backward: the deltas
-// propagate through W^T the same way; the weight gradients (K = nodes) go
-// through a 16 x 64 LDS transpose per layer.
+// with gfx950's v_mfma_f32_16x16x32_bf16 (A = 16 units x 32 inputs, B = 32
+// inputs x 16 nodes).  Lane l holds D[unit = 4 (l/16) + r][node = l%16].  In a
+// K-reduction MFMA lane l contributes 8 K values (slots i = 0..7) of row or
+// column l%16, and A and B are paired slot by slot, so the assignment of input
+// units to (l/16, i) is free as long as both operands use it.  The one chosen,
+//   input k = 32 c + 16 (i/4) + 4 (l/16) + i%4   for K chunk c,
+// puts in lane l exactly the D values it holds from two 16-unit blocks of the
+// previous layer: activations stay in registers from layer to layer, and the
+// BF16 weight copies are stored with their columns in that order, so that an
+// A operand is one 16-byte load.  The first layer (16 inputs) fills slots
+// 0..3 and leaves 4..7 zero.  Backward: the deltas propagate through W^T the
+// same way; the weight gradients (K = nodes) take 32-node batches through
+// LDS, [row][node] per layer.
 //
 // BF16 rounding happens exactly at the MFMA operands: W1..W3 (and their
 // transposes), the layer inputs X, H1, H2 in the forward pass, the deltas and
@@ -19,10 +26,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-
 #include <cmath>
 #include <cstdio>
-#include <algorithm>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -34,11 +39,12 @@ namespace nfl {
 constexpr int MLP_NF = 16, MLP_H = 64;
 constexpr int OFF_W1 = 0, OFF_B1 = 1024, OFF_W2 = 1088, OFF_B2 = 5184, OFF_W3 = 5248,
               OFF_B3 = 9344, OFF_W4 = 9408, OFF_B4 = 9472, MLP_NP = 9473;
-// BF16 copies: W1 [64][16], W2, W3 [64][64], W2^T, W3^T [64][64]
-constexpr int BF_W1 = 0, BF_W2 = 1024, BF_W3 = 5120, BF_W2T = 9216, BF_W3T = 13312,
-              MLP_NBF = 17408;
+// BF16 copies with permuted columns: W1 [64][32] (slots 4..7 of each lane
+// group zero), W2, W3, W2^T, W3^T [64][64]
+constexpr int BF_W1 = 0, BF_W2 = 2048, BF_W3 = 6144, BF_W2T = 10240, BF_W3T = 14336,
+              MLP_NBF = 18432;
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4m __attribute__((ext_vector_type(4)));
 
 __host__ __device__ __forceinline__ uint16_t f2bf(float f) {
@@ -48,53 +54,57 @@ __host__ __device__ __forceinline__ uint16_t f2bf(float f) {
   return (uint16_t)(u >> 16);
 }
 
+// Column position of input unit k in a permuted 64-wide weight row: lane
+// group g reads positions 32 c + 8 g .. + 7, i.e. units 32 c + 16 (i/4) + 4 g + i%4.
+__host__ __device__ __forceinline__ int kpos(int k) {
+  return (k & ~31) + 8 * ((k >> 2) & 3) + 4 * ((k >> 4) & 1) + (k & 3);
+}
+
 __device__ __forceinline__ float tanh_f(float x) {
   // tanh(x) = 1 - 2 / (e^{2x} + 1), saturating cleanly for large |x|
   const float e = __expf(2.f * fminf(fmaxf(x, -15.f), 15.f));
   return 1.f - 2.f / (e + 1.f);
 }
 
-__device__ __forceinline__ bf16x4 pack4(float a, float b, float c, float d) {
-  bf16x4 r;
-  r[0] = (short)f2bf(a);
-  r[1] = (short)f2bf(b);
-  r[2] = (short)f2bf(c);
-  r[3] = (short)f2bf(d);
-  return r;
+__device__ __forceinline__ uint32_t pack2(float a, float b) {
+  return (uint32_t)f2bf(a) | ((uint32_t)f2bf(b) << 16);
 }
 
-// A operand of a 16x16 weight block: rows = units 16*ub + l%16, cols = inputs
-// 16*kb + 4*(l/16) .. +3, from a row-major [rows][ld] bf16 matrix.
-__device__ __forceinline__ bf16x4 load_a(const uint16_t *__restrict__ w, int ld, int ub, int kb,
+// B operand from two D-layout blocks: slots 0..3 from lo, 4..7 from hi
+__device__ __forceinline__ bf16x8 pack8(const f32x4m &lo, const f32x4m &hi) {
+  const uint4 w = make_uint4(pack2(lo[0], lo[1]), pack2(lo[2], lo[3]), pack2(hi[0], hi[1]),
+                             pack2(hi[2], hi[3]));
+  return __builtin_bit_cast(bf16x8, w);
+}
+
+__device__ __forceinline__ f32x4m mfma32(const bf16x8 &a, const bf16x8 &b, const f32x4m &c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// A operand: row 16 ub + l%16, K chunk c of a permuted [rows][ld] bf16 matrix
+__device__ __forceinline__ bf16x8 load_a(const uint16_t *__restrict__ w, int ld, int ub, int c,
                                         int lane) {
-  const uint16_t *p = w + (16 * ub + (lane & 15)) * ld + 16 * kb + 4 * (lane >> 4);
-  const uint2 v = *reinterpret_cast<const uint2 *>(p);
-  bf16x4 r;
-  r[0] = (short)(v.x & 0xffff);
-  r[1] = (short)(v.x >> 16);
-  r[2] = (short)(v.y & 0xffff);
-  r[3] = (short)(v.y >> 16);
-  return r;
+  const uint16_t *p = w + (16 * ub + (lane & 15)) * ld + 32 * c + 8 * (lane >> 4);
+  return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(p));
 }
 
 // Forward pass of 16 nodes (features in B layout: lane holds the 4 features
-// 4*(l/16)..+3 of node l%16).  Outputs: pre-activation-free activations
-// h1, h2, h3 (D layout, FP32) and the network output (valid in every lane for
-// node l%16).
+// 4*(l/16)..+3 of node l%16 in slots 0..3).  Outputs: the activations h1, h2,
+// h3 (D layout, FP32) and the network output (valid in every lane for node l%16).
 struct Acts {
   f32x4m h1[4], h2[4], h3[4];
   float out;
 };
 
 __device__ __forceinline__ void mlp_forward16(const uint16_t *__restrict__ wbf,
-                                              const float *__restrict__ prm, bf16x4 xb,
+                                              const float *__restrict__ prm, const bf16x8 &xb,
                                               int lane, Acts &A) {
   const int q = lane >> 4;
+  const f32x4m zero = {0.f, 0.f, 0.f, 0.f};
   // layer 1
 #pragma unroll
   for (int ub = 0; ub < 4; ++ub) {
-    f32x4m d = {0.f, 0.f, 0.f, 0.f};
-    d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(load_a(wbf + BF_W1, 16, ub, 0, lane), xb, d, 0, 0, 0);
+    f32x4m d = mfma32(load_a(wbf + BF_W1, 32, ub, 0, lane), xb, zero);
 #pragma unroll
     for (int r = 0; r < 4; ++r) d[r] = tanh_f(d[r] + prm[OFF_B1 + 16 * ub + 4 * q + r]);
     A.h1[ub] = d;
@@ -106,15 +116,11 @@ __device__ __forceinline__ void mlp_forward16(const uint16_t *__restrict__ wbf,
     f32x4m *hout = layer == 0 ? A.h2 : A.h3;
     const uint16_t *w = wbf + (layer == 0 ? BF_W2 : BF_W3);
     const float *bias = prm + (layer == 0 ? OFF_B2 : OFF_B3);
-    bf16x4 b[4];
-#pragma unroll
-    for (int kb = 0; kb < 4; ++kb) b[kb] = pack4(hin[kb][0], hin[kb][1], hin[kb][2], hin[kb][3]);
+    const bf16x8 b0 = pack8(hin[0], hin[1]), b1 = pack8(hin[2], hin[3]);
 #pragma unroll
     for (int ub = 0; ub < 4; ++ub) {
-      f32x4m d = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int kb = 0; kb < 4; ++kb)
-        d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(load_a(w, 64, ub, kb, lane), b[kb], d, 0, 0, 0);
+      f32x4m d = mfma32(load_a(w, 64, ub, 0, lane), b0, zero);
+      d = mfma32(load_a(w, 64, ub, 1, lane), b1, d);
 #pragma unroll
       for (int r = 0; r < 4; ++r) d[r] = tanh_f(d[r] + bias[16 * ub + 4 * q + r]);
       hout[ub] = d;
@@ -129,6 +135,12 @@ __device__ __forceinline__ void mlp_forward16(const uint16_t *__restrict__ wbf,
   part += __shfl_xor(part, 16);
   part += __shfl_xor(part, 32);
   A.out = part + prm[OFF_B4];
+}
+
+// B operand of the first layer: the lane's 4 features, slots 4..7 zero
+__device__ __forceinline__ bf16x8 pack_features(const float (&x)[4]) {
+  const f32x4m lo = {x[0], x[1], x[2], x[3]}, z = {0.f, 0.f, 0.f, 0.f};
+  return pack8(lo, z);
 }
 
 // ---------------------------------------------------------------------------
@@ -172,22 +184,33 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const uint16_t *__restrict__ 
 #pragma unroll
     for (int v = 0; v < 4; ++v) x[v] = node_feature(p, nos, f, dn, cls, 4 * q + v);
     Acts A;
-    mlp_forward16(wbf, prm, pack4(x[0], x[1], x[2], x[3]), lane, A);
+    mlp_forward16(wbf, prm, pack_features(x), lane, A);
     if (ok && q == 0) u0[i] = (double)A.out;
   }
 }
 
 // Forward + backward on explicit features (B x 16, FP32) and targets; each
-// wave loops over 16-node batches and accumulates its gradient, then writes
-// it (and its loss sum) to part[wave][MLP_NP + 1].  scale = d loss / d out
-// factor of one node's squared error (2): the deltas rounded to bf16 do not
-// depend on the batch size; the reduction applies the mean's 1/B.
+// wave loops over 32-node batches (two 16-node passes) and accumulates its
+// gradient, then writes it (and its loss sum) to part[wave][MLP_NP + 1].
+// scale = d loss / d out factor of one node's squared error (2): the deltas
+// rounded to bf16 do not depend on the batch size; the reduction applies the
+// mean's 1/B.
+constexpr int MLP_WB = 32;   // nodes per weight-gradient product (the MFMA's K)
+
+// 8 bf16 of row 16 blk + l%16, nodes 8 (l/16) .. + 7 of a [rows][32] LDS array
+__device__ __forceinline__ bf16x8 lds_op(const uint16_t *t, int blk, int lane) {
+  return __builtin_bit_cast(
+      bf16x8, *reinterpret_cast<const uint4 *>(t + (16 * blk + (lane & 15)) * MLP_WB + 8 * (lane >> 4)));
+}
+
 __global__ __launch_bounds__(64) void k_mlp_train(const uint16_t *__restrict__ wbf,
                                                   const float *__restrict__ prm,
                                                   const float *__restrict__ feat,
                                                   const float *__restrict__ target, int64_t B,
                                                   float scale, float *__restrict__ part) {
-  __shared__ uint16_t tA[64 * 16], tB[64 * 16];  // [unit][node] bf16 transposes
+  // bf16 operands of the weight gradients, [unit or feature][node of the batch]
+  __shared__ __align__(16) uint16_t tD3[64 * MLP_WB], tD2[64 * MLP_WB], tD1[64 * MLP_WB],
+      tH2[64 * MLP_WB], tH1[64 * MLP_WB], tX[16 * MLP_WB];
   const int lane = threadIdx.x;
   const int node = lane & 15, q = lane >> 4;
   const int64_t wave = blockIdx.x, nw = gridDim.x;
@@ -203,102 +226,89 @@ __global__ __launch_bounds__(64) void k_mlp_train(const uint16_t *__restrict__ w
   for (int k = 0; k < 16; ++k) gb1[k] = gb2[k] = gb3[k] = gw4[k] = 0.f;
   float gb4 = 0.f, loss = 0.f;
 
-  for (int64_t b = wave; b * 16 < B; b += nw) {
-    const int64_t i = b * 16 + node;
-    const bool ok = i < B;
-    float x[4];
+  for (int64_t b = wave; b * MLP_WB < B; b += nw) {
+#pragma unroll 1
+    for (int h = 0; h < MLP_WB / 16; ++h) {
+      // reload the weight operands per pass instead of holding all of them
+      // in registers next to the gradient accumulators
+      const uint16_t *wb = wbf;
+      asm volatile("" : "+s"(wb));
+      const int col = 16 * h + node;
+      const int64_t i = b * MLP_WB + col;
+      const bool ok = i < B;
+      float x[4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) x[v] = ok ? feat[i * MLP_NF + 4 * q + v] : 0.f;
-    const bf16x4 xb = pack4(x[0], x[1], x[2], x[3]);
-    Acts A;
-    mlp_forward16(wbf, prm, xb, lane, A);
-    const float err = ok ? A.out - target[i] : 0.f;
-    if (q == 0) loss += err * err;
-    const float g = scale * err;  // d loss / d out for this node
-    if (q == 0) gb4 += g;
-    // layer 4: dW4, delta3 = g W4 (1 - h3^2)
-    f32x4m d3[4];
+      for (int v = 0; v < 4; ++v) x[v] = ok ? feat[i * MLP_NF + 4 * q + v] : 0.f;
+      Acts A;
+      mlp_forward16(wb, prm, pack_features(x), lane, A);
+      const float err = ok ? A.out - target[i] : 0.f;
+      if (q == 0) loss += err * err;
+      const float g = scale * err;  // d loss / d out for this node
+      if (q == 0) gb4 += g;
+      // layer 4: dW4, delta3 = g W4 (1 - h3^2)
+      f32x4m d3[4];
 #pragma unroll
-    for (int ub = 0; ub < 4; ++ub)
+      for (int ub = 0; ub < 4; ++ub)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const float h = A.h3[ub][r];
-        gw4[4 * ub + r] = fmaf(g, h, gw4[4 * ub + r]);
-        d3[ub][r] = g * prm[OFF_W4 + 16 * ub + 4 * q + r] * (1.f - h * h);
+        for (int r = 0; r < 4; ++r) {
+          const float hv = A.h3[ub][r];
+          gw4[4 * ub + r] = fmaf(g, hv, gw4[4 * ub + r]);
+          d3[ub][r] = g * prm[OFF_W4 + 16 * ub + 4 * q + r] * (1.f - hv * hv);
+        }
+      // propagate: delta2 = (W3^T delta3) (1 - h2^2); delta1 = (W2^T delta2) (1 - h1^2)
+      f32x4m d2[4], d1[4];
+#pragma unroll
+      for (int layer = 0; layer < 2; ++layer) {
+        const f32x4m *dout = layer == 0 ? d3 : d2;
+        f32x4m *din = layer == 0 ? d2 : d1;
+        const f32x4m *hin = layer == 0 ? A.h2 : A.h1;
+        const uint16_t *wt = wb + (layer == 0 ? BF_W3T : BF_W2T);
+        const bf16x8 b0 = pack8(dout[0], dout[1]), b1 = pack8(dout[2], dout[3]);
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) {
+          f32x4m acc = mfma32(load_a(wt, 64, kb, 0, lane), b0, f32x4m{0.f, 0.f, 0.f, 0.f});
+          acc = mfma32(load_a(wt, 64, kb, 1, lane), b1, acc);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const float hv = hin[kb][r];
+            din[kb][r] = acc[r] * (1.f - hv * hv);
+          }
+        }
       }
-    // propagate: delta2 = (W3^T delta3) (1 - h2^2); delta1 = (W2^T delta2) (1 - h1^2)
-    f32x4m d2[4], d1[4];
+      // bias gradients (per lane: units 16 ub + 4 q + r of node `node`), and
+      // the bf16 operands of the weight gradients in column `col`
 #pragma unroll
-    for (int layer = 0; layer < 2; ++layer) {
-      const f32x4m *dout = layer == 0 ? d3 : d2;
-      f32x4m *din = layer == 0 ? d2 : d1;
-      const f32x4m *hin = layer == 0 ? A.h2 : A.h1;
-      const uint16_t *wt = wbf + (layer == 0 ? BF_W3T : BF_W2T);
-      bf16x4 bb[4];
+      for (int ub = 0; ub < 4; ++ub)
 #pragma unroll
-      for (int ub = 0; ub < 4; ++ub) bb[ub] = pack4(dout[ub][0], dout[ub][1], dout[ub][2], dout[ub][3]);
+        for (int r = 0; r < 4; ++r) {
+          gb3[4 * ub + r] += d3[ub][r];
+          gb2[4 * ub + r] += d2[ub][r];
+          gb1[4 * ub + r] += d1[ub][r];
+          const int row = (16 * ub + 4 * q + r) * MLP_WB + col;
+          tD3[row] = f2bf(d3[ub][r]);
+          tD2[row] = f2bf(d2[ub][r]);
+          tD1[row] = f2bf(d1[ub][r]);
+          tH2[row] = f2bf(A.h2[ub][r]);
+          tH1[row] = f2bf(A.h1[ub][r]);
+        }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) tX[(4 * q + v) * MLP_WB + col] = f2bf(x[v]);
+    }
+    __syncthreads();
+    // dW[u][k] = sum over the batch's nodes of delta[u][node] in[k][node]:
+    // A = deltas [u][node], B = inputs [node][k]
+    const bf16x8 xo = lds_op(tX, 0, lane);
+#pragma unroll
+    for (int ub = 0; ub < 4; ++ub) {
+      const bf16x8 a3 = lds_op(tD3, ub, lane), a2 = lds_op(tD2, ub, lane);
 #pragma unroll
       for (int kb = 0; kb < 4; ++kb) {
-        f32x4m acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int ub = 0; ub < 4; ++ub)
-          acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(load_a(wt, 64, kb, ub, lane), bb[ub], acc, 0, 0, 0);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const float h = hin[kb][r];
-          din[kb][r] = acc[r] * (1.f - h * h);
-        }
+        g3[ub][kb] = mfma32(a3, lds_op(tH2, kb, lane), g3[ub][kb]);
+        g2[ub][kb] = mfma32(a2, lds_op(tH1, kb, lane), g2[ub][kb]);
       }
+      g1[ub] = mfma32(lds_op(tD1, ub, lane), xo, g1[ub]);
     }
-    // bias gradients (per lane: units 16 ub + 4 q + r of node `node`)
-#pragma unroll
-    for (int ub = 0; ub < 4; ++ub)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        gb3[4 * ub + r] += d3[ub][r];
-        gb2[4 * ub + r] += d2[ub][r];
-        gb1[4 * ub + r] += d1[ub][r];
-      }
-    // weight gradients dW[u][k] = sum_node delta[u][node] in[k][node] via LDS
-    // transposes: A[u][node] from tA, B[node][k] from tB.
-    auto wgrad = [&](const f32x4m (&dl)[4], const f32x4m (&in)[4], int nkb, f32x4m (*gacc)) {
-      __syncthreads();
-#pragma unroll
-      for (int ub = 0; ub < 4; ++ub)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          tA[(16 * ub + 4 * q + r) * 16 + node] = f2bf(dl[ub][r]);
-          if (ub < nkb) tB[(16 * ub + 4 * q + r) * 16 + node] = f2bf(in[ub][r]);
-        }
-      __syncthreads();
-#pragma unroll
-      for (int ub = 0; ub < 4; ++ub) {
-        const bf16x4 a = *reinterpret_cast<const bf16x4 *>(tA + (16 * ub + (lane & 15)) * 16 + 4 * q);
-        for (int kb = 0; kb < nkb; ++kb) {
-          const bf16x4 bo = *reinterpret_cast<const bf16x4 *>(tB + (16 * kb + (lane & 15)) * 16 + 4 * q);
-          gacc[ub * 4 + kb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bo, gacc[ub * 4 + kb], 0, 0, 0);
-        }
-      }
-    };
-    wgrad(d3, A.h2, 4, &g3[0][0]);
-    wgrad(d2, A.h1, 4, &g2[0][0]);
-    {
-      // layer 1: inputs are the 16 features (one block); feature rows 4 q + v
-      __syncthreads();
-#pragma unroll
-      for (int ub = 0; ub < 4; ++ub)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) tA[(16 * ub + 4 * q + r) * 16 + node] = f2bf(d1[ub][r]);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) tB[(4 * q + v) * 16 + node] = f2bf(x[v]);
-      __syncthreads();
-      const bf16x4 bo = *reinterpret_cast<const bf16x4 *>(tB + (lane & 15) * 16 + 4 * q);
-#pragma unroll
-      for (int ub = 0; ub < 4; ++ub) {
-        const bf16x4 a = *reinterpret_cast<const bf16x4 *>(tA + (16 * ub + (lane & 15)) * 16 + 4 * q);
-        g1[ub] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bo, g1[ub], 0, 0, 0);
-      }
-    }
+    __syncthreads();   // the next batch overwrites the operands
   }
   // write the wave's partial gradient.  gacc blocks hold D[u = 4 q + r][k = l%16].
   float *out = part + wave * (MLP_NP + 1);
@@ -370,16 +380,20 @@ __global__ __launch_bounds__(256) void k_mlp_adam(float *__restrict__ prm,
   prm[p] -= lr * (a / c1) / (sqrtf(v / c2) + eps);
 }
 
+// BF16 copies in the permuted column order of the MFMA operands
 __global__ __launch_bounds__(256) void k_mlp_tobf16(const float *__restrict__ prm,
                                                     uint16_t *__restrict__ wbf) {
   const int t = blockIdx.x * 256 + threadIdx.x;
-  if (t < 1024) wbf[BF_W1 + t] = f2bf(prm[OFF_W1 + t]);
+  if (t < 2048) {   // W1: row u, slot i of lane group g = feature 4 g + i (i < 4)
+    const int u = t >> 5, g = (t >> 3) & 3, i = t & 7;
+    wbf[BF_W1 + t] = i < 4 ? f2bf(prm[OFF_W1 + u * 16 + 4 * g + i]) : (uint16_t)0;
+  }
   if (t < 4096) {
     const int u = t >> 6, k = t & 63;
-    wbf[BF_W2 + t] = f2bf(prm[OFF_W2 + t]);
-    wbf[BF_W3 + t] = f2bf(prm[OFF_W3 + t]);
-    wbf[BF_W2T + k * 64 + u] = f2bf(prm[OFF_W2 + t]);
-    wbf[BF_W3T + k * 64 + u] = f2bf(prm[OFF_W3 + t]);
+    wbf[BF_W2 + u * 64 + kpos(k)] = f2bf(prm[OFF_W2 + t]);
+    wbf[BF_W3 + u * 64 + kpos(k)] = f2bf(prm[OFF_W3 + t]);
+    wbf[BF_W2T + k * 64 + kpos(u)] = f2bf(prm[OFF_W2 + t]);
+    wbf[BF_W3T + k * 64 + kpos(u)] = f2bf(prm[OFF_W3 + t]);
   }
 }
 
@@ -443,7 +457,7 @@ static int mlp_refresh(nfl_mlp *M) {
 
 // fwd + bwd + reduce on features already in M->feat / M->target (B rows)
 static int mlp_grad(nfl_mlp *M, int64_t B, double *loss_host) {
-  const int nw = (int)std::min<int64_t>(512, (B + 15) / 16);
+  const int nw = (int)std::min<int64_t>(512, (B + MLP_WB - 1) / MLP_WB);
   NFL_TRY(M->part.ensure((size_t)nw * (MLP_NP + 1)));
   hipLaunchKernelGGL(k_mlp_train, dim3(nw), dim3(64), 0, M->stream, M->wbf.p, M->prm.p, M->feat.p,
                      M->target.p, B, 2.0f, M->part.p);
@@ -714,7 +728,7 @@ __global__ __launch_bounds__(256) void k_mlp_fwd_explicit(const uint16_t *__rest
 #pragma unroll
     for (int v = 0; v < 4; ++v) x[v] = ok ? feat[i * MLP_NF + 4 * q + v] : 0.f;
     Acts A;
-    mlp_forward16(wbf, prm, pack4(x[0], x[1], x[2], x[3]), lane, A);
+    mlp_forward16(wbf, prm, pack_features(x), lane, A);
     if (ok && q == 0) out[i] = A.out;
   }
 }

@@ -6,8 +6,9 @@ the layers, plus one bf16 ulp at each operand that lies within its error
 bound of a bf16 rounding boundary.  On top, at most a few outputs (and 5% of
 the gradient elements) may exceed the bound that assumes no bf16 operand
 flips: an FP32 implementation of the network flips an operand at ~0.05% of
-the nodes.  Partial 16-node tiles are covered by the batch sizes (1, 17,
-1000, 4097) and by comparing a batch with its parts.
+the nodes.  Partial tiles (16-node forward passes; 32-node batches of the
+weight gradients, two passes each) are covered by the batch sizes (1, 17,
+33, 48, 777, 1000, 4097) and by comparing a batch with its parts.
 """
 import gc
 
@@ -61,7 +62,7 @@ def test_forward_of_a_batch_equals_forward_of_its_parts(nfl):
     assert np.all(np.abs(full - parts) <= 1e-5 * scale)
 
 
-@pytest.mark.parametrize("B", [1, 17, 777, 4097])
+@pytest.mark.parametrize("B", [1, 17, 33, 48, 777, 4097])
 def test_gradient_matches_reference(nfl, B):
     W, p = make_net(nfl, seed=5)
     X = features(B, 9 + B)
