@@ -47,12 +47,10 @@ constexpr int BF_W1 = 0, BF_W2 = 2048, BF_W3 = 6144, BF_W2T = 10240, BF_W3T = 14
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4m __attribute__((ext_vector_type(4)));
 
-__host__ __device__ __forceinline__ uint16_t f2bf(float f) {
-  uint32_t u;
-  memcpy(&u, &f, 4);
-  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
-  return (uint16_t)(u >> 16);
-}
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// FP32 -> BF16 bits, round to nearest even (v_cvt_pk_bf16_f32)
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 
 // Column position of input unit k in a permuted 64-wide weight row: lane
 // group g reads positions 32 c + 8 g .. + 7, i.e. units 32 c + 16 (i/4) + 4 g + i%4.
@@ -61,13 +59,16 @@ __host__ __device__ __forceinline__ int kpos(int k) {
 }
 
 __device__ __forceinline__ float tanh_f(float x) {
-  // tanh(x) = 1 - 2 / (e^{2x} + 1), saturating cleanly for large |x|
-  const float e = __expf(2.f * fminf(fmaxf(x, -15.f), 15.f));
-  return 1.f - 2.f / (e + 1.f);
+  // tanh(x) = 1 - 2 / (e^{2x} + 1) with the hardware exp2 and reciprocal
+  // (absolute error below 2^-21); for large |x| e is inf or 0 and the
+  // reciprocal 0 or 1, so the result saturates at +-1 without a clamp
+  const float e = __builtin_amdgcn_exp2f(x * 2.885390081777927f);   // 2 log2(e)
+  return fmaf(-2.f, __builtin_amdgcn_rcpf(e + 1.f), 1.f);
 }
 
 __device__ __forceinline__ uint32_t pack2(float a, float b) {
-  return (uint32_t)f2bf(a) | ((uint32_t)f2bf(b) << 16);
+  const bf16x2 r = {(__bf16)a, (__bf16)b};
+  return __builtin_bit_cast(uint32_t, r);
 }
 
 // B operand from two D-layout blocks: slots 0..3 from lo, 4..7 from hi
@@ -160,6 +161,16 @@ __device__ __forceinline__ float node_feature(const float4 &q, int nos, float f,
   return (k - 5 == cls) ? 1.f : 0.f;
 }
 
+// The BF16 weight copies staged in LDS once per block (36 KB; four blocks of
+// four waves fit a CU): the A operands are then LDS reads, cheaper than
+// re-reading them from the caches and, unlike holding them in registers,
+// leaving room for four waves per SIMD to cover the MFMA -> tanh chains.
+__device__ __forceinline__ void stage_weights(const uint16_t *__restrict__ wbf, uint4 *wl) {
+  const uint4 *src = reinterpret_cast<const uint4 *>(wbf);
+  for (int t = threadIdx.x; t < MLP_NBF / 8; t += blockDim.x) wl[t] = src[t];
+  __syncthreads();
+}
+
 // Inference over all nodes (sorted order): u0[i] = net(features_i).
 __global__ __launch_bounds__(256) void k_mlp_infer(const uint16_t *__restrict__ wbf,
                                                    const float *__restrict__ prm,
@@ -168,6 +179,8 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const uint16_t *__restrict__ 
                                                    const double *__restrict__ f_sorted, int cls,
                                                    int nos, int d, int64_t n,
                                                    double *__restrict__ u0) {
+  __shared__ uint4 wl[MLP_NBF / 8];
+  stage_weights(wbf, wl);
   const int lane = threadIdx.x & 63;
   const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -184,7 +197,10 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const uint16_t *__restrict__ 
 #pragma unroll
     for (int v = 0; v < 4; ++v) x[v] = node_feature(p, nos, f, dn, cls, 4 * q + v);
     Acts A;
-    mlp_forward16(wbf, prm, pack_features(x), lane, A);
+    // (an opaque offset keeps the operand reads inside the loop)
+    int off = 0;
+    asm volatile("" : "+s"(off));
+    mlp_forward16(reinterpret_cast<const uint16_t *>(wl) + off, prm, pack_features(x), lane, A);
     if (ok && q == 0) u0[i] = (double)A.out;
   }
 }
@@ -354,14 +370,24 @@ __global__ __launch_bounds__(64) void k_mlp_train(const uint16_t *__restrict__ w
   }
 }
 
-// grad[p] = inv_b * sum over waves (fixed order); the loss entry stays a sum
+// grad[p] = inv_b * sum over waves, in a fixed order: 8 slices of the waves
+// (w = s mod 8) summed per thread, then the slices in order; 32 parameters
+// per block.  The loss entry stays a sum.
+constexpr int RED_P = 32, RED_S = 8;
 __global__ __launch_bounds__(256) void k_mlp_reduce(const float *__restrict__ part, int nwaves,
                                                     float inv_b, float *__restrict__ grad) {
-  const int p = blockIdx.x * 256 + threadIdx.x;
-  if (p > MLP_NP) return;
+  __shared__ float sl[RED_S][RED_P];
+  const int p = blockIdx.x * RED_P + (threadIdx.x % RED_P), sidx = threadIdx.x / RED_P;
   float s = 0.f;
-  for (int w = 0; w < nwaves; ++w) s += part[(int64_t)w * (MLP_NP + 1) + p];
-  grad[p] = p < MLP_NP ? s * inv_b : s;
+  if (p <= MLP_NP)
+    for (int w = sidx; w < nwaves; w += RED_S) s += part[(int64_t)w * (MLP_NP + 1) + p];
+  sl[sidx][threadIdx.x % RED_P] = s;
+  __syncthreads();
+  if (threadIdx.x < RED_P && p <= MLP_NP) {
+    float t = 0.f;
+    for (int k = 0; k < RED_S; ++k) t += sl[k][threadIdx.x];
+    grad[p] = p < MLP_NP ? t * inv_b : t;
+  }
 }
 
 // Adam step on the FP32 master parameters; refresh the BF16 copies.
@@ -461,7 +487,7 @@ static int mlp_grad(nfl_mlp *M, int64_t B, double *loss_host) {
   NFL_TRY(M->part.ensure((size_t)nw * (MLP_NP + 1)));
   hipLaunchKernelGGL(k_mlp_train, dim3(nw), dim3(64), 0, M->stream, M->wbf.p, M->prm.p, M->feat.p,
                      M->target.p, B, 2.0f, M->part.p);
-  hipLaunchKernelGGL(k_mlp_reduce, dim3((MLP_NP + 1 + 255) / 256), dim3(256), 0, M->stream,
+  hipLaunchKernelGGL(k_mlp_reduce, dim3((MLP_NP + 1 + RED_P - 1) / RED_P), dim3(256), 0, M->stream,
                      M->part.p, nw, 1.0f / (float)B, M->grad.p);
   NFL_HIP(hipGetLastError());
   if (loss_host) {
@@ -492,7 +518,7 @@ static float plan_dinvmean(nfl_plan *P, DBuf<double> &tmp) {
 int mlp_predict_sorted(nfl_mlp *M, nfl_plan *P, int cls, const double *f_sorted, double *u0) {
   LBuf<double> tmp;
   const int64_t nb16 = (P->n + 15) / 16;
-  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(2048, (nb16 + 3) / 4));
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (nb16 + 3) / 4));
   hipLaunchKernelGGL(k_mlp_infer, dim3(blocks), dim3(256), 0, P->stream, M->wbf.p, M->prm.p,
                      P->pts.p, P->deg.p, plan_dinvmean(P, tmp), f_sorted, cls, P->nos, P->d, P->n,
                      u0);
@@ -717,6 +743,8 @@ __global__ __launch_bounds__(256) void k_mlp_fwd_explicit(const uint16_t *__rest
                                                           const float *__restrict__ prm,
                                                           const float *__restrict__ feat,
                                                           int64_t B, float *__restrict__ out) {
+  __shared__ uint4 wl[MLP_NBF / 8];
+  stage_weights(wbf, wl);
   const int lane = threadIdx.x & 63;
   const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -728,14 +756,17 @@ __global__ __launch_bounds__(256) void k_mlp_fwd_explicit(const uint16_t *__rest
 #pragma unroll
     for (int v = 0; v < 4; ++v) x[v] = ok ? feat[i * MLP_NF + 4 * q + v] : 0.f;
     Acts A;
-    mlp_forward16(wbf, prm, pack_features(x), lane, A);
+    // (an opaque offset keeps the operand reads inside the loop)
+    int off = 0;
+    asm volatile("" : "+s"(off));
+    mlp_forward16(reinterpret_cast<const uint16_t *>(wl) + off, prm, pack_features(x), lane, A);
     if (ok && q == 0) out[i] = A.out;
   }
 }
 
 int mlp_forward_explicit(nfl_mlp *M, int64_t B, float *out) {
   const int64_t nb16 = (B + 15) / 16;
-  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(2048, (nb16 + 3) / 4));
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (nb16 + 3) / 4));
   hipLaunchKernelGGL(k_mlp_fwd_explicit, dim3(blocks), dim3(256), 0, M->stream, M->wbf.p, M->prm.p,
                      M->feat.p, B, out);
   NFL_HIP(hipGetLastError());
