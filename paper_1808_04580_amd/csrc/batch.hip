@@ -441,9 +441,9 @@ static int batch_build(nfl_batch_s *B) {
       size_t li = (p3 + nw * 16 * WT_INTERP) * sizeof(float);
       if (form == FORM_TILE4 || form == FORM_TILE8) {
         const size_t tile = (size_t)Pd * ts_xs(Pd);
-        const size_t copies = (nw >= 2 ? 2 : 1) * (size_t)16 * ts_xs(Pd);
+        // the spread's tables, coefficient table and tile copies
+        ls = (size_t)spread_tile_lds_floats(Pd, (int)nw) * sizeof(float);
         // + the window coefficient table the tile forms keep after the weight tables
-        ls = std::max(tile + nw * 16 * TS_PITCH + WIN_MAXW * WIN_NC, copies) * sizeof(float);
         li = (tile + nw * 16 * TS_PITCH_I + WIN_MAXW * WIN_NC) * sizeof(float);
       }
       B->groups[k].lds_spread[v] = std::max(B->groups[k].lds_spread[v], ls);

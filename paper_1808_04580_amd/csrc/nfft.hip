@@ -474,11 +474,11 @@ __global__ void k_filter1(float2 *__restrict__ H, const float *__restrict__ filt
 // Pre-pass of the deterministic spread: *out = max(*out, bits of max_i |x_i|)
 // (non-negative floats order like their bit patterns); x null: |x| = 1.
 template <class T>
-__global__ __launch_bounds__(256) void k_fx_max(const T *__restrict__ x, int64_t n,
-                                                unsigned *__restrict__ out,
-                                                const int *__restrict__ stop) {
+__global__ __launch_bounds__(1024) void k_fx_max(const T *__restrict__ x, int64_t n,
+                                                 unsigned *__restrict__ out,
+                                                 const int *__restrict__ stop) {
   if (stopped(stop)) return;
-  __shared__ float wm[4];
+  __shared__ float wm[16];
   float m = x ? 0.f : 1.f;
   if (x) {
     // 16-byte loads where the base is aligned (torch tensors are), scalar tail
@@ -486,6 +486,7 @@ __global__ __launch_bounds__(256) void k_fx_max(const T *__restrict__ x, int64_t
     const bool vec = (reinterpret_cast<uintptr_t>(x) & 15) == 0;
     const int64_t nv = vec ? n / V : 0;
     const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x, nt = (int64_t)gridDim.x * blockDim.x;
+#pragma unroll 4
     for (int64_t i = tid; i < nv; i += nt) {
       const float4 q = reinterpret_cast<const float4 *>(x)[i];
       const T *e = reinterpret_cast<const T *>(&q);
@@ -499,7 +500,8 @@ __global__ __launch_bounds__(256) void k_fx_max(const T *__restrict__ x, int64_t
   for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
   if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
   __syncthreads();
-  // one atomic per block: atomics on one address serialise, so few blocks
+  // one atomic per block: atomics on one address serialise, so few, large
+  // blocks (at most 64 of 1024 threads; 512 blocks of 256 took ~8 us at n = 1e6)
   if (threadIdx.x == 0) {
     for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmaxf(m, wm[w]);
     atomicMax(out, __float_as_uint(m));
@@ -586,11 +588,9 @@ static int launch_spread3_mfma(nfl_plan *P, const KArgs &k, float *grid) {
 
 static size_t tile_form_lds(int W, int T, bool spread) {
   const int Pd = T + W - 1;
-  // spread: two tile copies must fit once the weight tables are free
-  const size_t tables = (size_t)4 * 16 * (spread ? TS_PITCH : TS_PITCH_I);
+  if (spread) return (size_t)spread_tile_lds_floats(Pd, 4) * sizeof(float);
   // the window coefficients stay in LDS after the tables
-  const size_t need = (size_t)Pd * ts_xs(Pd) + tables + WIN_MAXW * WIN_NC;
-  return std::max(need, spread ? (size_t)2 * 16 * ts_xs(Pd) : need) * sizeof(float);
+  return ((size_t)Pd * ts_xs(Pd) + (size_t)4 * 16 * TS_PITCH_I + WIN_MAXW * WIN_NC) * sizeof(float);
 }
 
 template <int W, int T, int IN>
@@ -700,15 +700,15 @@ static int fx_prepass(nfl_plan *P, int in_mode, const VecArgs &a) {
     factor = 1.01 / std::sqrt(std::max(P->dmin, 1e-300));
   P->fx_mult = (float)(1.0625 * factor * (double)P->n * std::pow(1.01 * P->win_max, P->d));
   if (a.fx_ready) return NFL_OK;   // the producer of the input wrote its bound
-  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(512, (P->n + 1023) / 1024));
+  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(64, (P->n + 16383) / 16384));
   if (in_mode == IN_ONES) {
     hipLaunchKernelGGL(k_fx_max<float>, dim3(1), dim3(64), 0, P->stream, (const float *)nullptr,
                        (int64_t)0, P->fx_max.p, P->stop);
   } else if (in_mode == IN_SORTED_F64_DINV) {
-    hipLaunchKernelGGL(k_fx_max<double>, dim3(nb), dim3(256), 0, P->stream, a.x64, P->n,
+    hipLaunchKernelGGL(k_fx_max<double>, dim3(nb), dim3(1024), 0, P->stream, a.x64, P->n,
                        P->fx_max.p, P->stop);
   } else {
-    hipLaunchKernelGGL(k_fx_max<float>, dim3(nb), dim3(256), 0, P->stream, a.x32, P->n,
+    hipLaunchKernelGGL(k_fx_max<float>, dim3(nb), dim3(1024), 0, P->stream, a.x32, P->n,
                        P->fx_max.p, P->stop);
   }
   NFL_HIP(hipGetLastError());

@@ -735,50 +735,89 @@ __device__ __forceinline__ void fill_shifted_lds(const float4 &qb, float xb, int
   }
 }
 
-// The 4-node steps of one run of the spread (nodes sharing their cell's y
-// offset L inside the tile): W y-slices per step, accumulators L .. L + W - 1.
-// Two operand sets: the operands of step st + 1 are loaded (always: rows
-// 4 (st + 1) + p4 < 16 lie in the table) while the matrix instructions of
-// step st issue, so the wait before step st covers exactly its own loads.
+// Spread tile layout in LDS once the weight tables are free: [ax][az][ay],
+// ay fastest, z stride 17 and x stride ts_sxs(P) = 4 mod 8 words.  The
+// accumulator stores (16 consecutive ay per row of lanes, four x rows 16
+// banks apart) and the flush reads (16 consecutive az, odd stride) are then
+// free of bank conflicts.
+constexpr int TS_SZS = 17;
+__host__ __device__ constexpr int ts_sxs(int P) { return (P * TS_SZS + 3) / 8 * 8 + 4; }
+
+// LDS of the tile spread, in floats: the weight tables of NW waves and the
+// window coefficients during the accumulation, then up to two tile copies.
+__host__ __device__ constexpr int spread_tile_lds_floats(int P, int NW) {
+  const int run = NW * 16 * TS_PITCH + WIN_MAXW * WIN_NC;
+  const int sum = (NW >= 2 ? 2 : 1) * 16 * ts_sxs(P);
+  return run > sum ? run : sum;
+}
+
+// The 4-node steps of one run of the spread (nodes sharing their cell's z
+// offset L inside the tile, z rows relative to the window): W z-slices per
+// step into accumulators L .. L + W - 1 (x rows by y columns).  Two operand
+// sets: the operands of step st + 1 are loaded (always: rows 4 (st + 1) + p4
+// < 16 lie in the table) while the matrix instructions of step st issue.
 // Steps past nst are skipped whole.
 template <int L, int W, int P, int PITCH>
-__device__ __forceinline__ void spread_run_steps(f32x4 (&acc)[P], const float *wt, int nst,
-                                                 int c16, int p4) {
+__device__ __forceinline__ void spread_zrun_steps(f32x4 (&acc)[P], const float *wt, int nst,
+                                                  int c16, int p4) {
   static_assert(L + W <= P, "the run's window lies in the padded tile");
   constexpr int WQ = (W + 3) / 4;
-  float a[2], wz[2], wy[2][4 * WQ];
-  auto load_step = [&](int st, float &a_, float &wz_, float (&wy_)[4 * WQ]) {
+  float a[2], wy[2], wz[2][4 * WQ];
+  auto load_step = [&](int st, float &a_, float &wy_, float (&wz_)[4 * WQ]) {
     const float *w = wt + (4 * st + p4) * PITCH;
     a_ = w[c16];
-    wz_ = w[64 + c16];
+    wy_ = w[32 + c16];
 #pragma unroll
     for (int q = 0; q < WQ; ++q) {
-      const float4 v = *reinterpret_cast<const float4 *>(w + 32 + 4 * q);
-      wy_[4 * q] = v.x;
-      wy_[4 * q + 1] = v.y;
-      wy_[4 * q + 2] = v.z;
-      wy_[4 * q + 3] = v.w;
+      const float4 v = *reinterpret_cast<const float4 *>(w + 64 + 4 * q);
+      wz_[4 * q] = v.x;
+      wz_[4 * q + 1] = v.y;
+      wz_[4 * q + 2] = v.z;
+      wz_[4 * q + 3] = v.w;
     }
   };
-  load_step(0, a[0], wz[0], wy[0]);
+  load_step(0, a[0], wy[0], wz[0]);
 #pragma unroll
   for (int st = 0; st < 4; ++st) {
     const int c = st & 1;
-    if (st + 1 < 4) load_step(st + 1, a[c ^ 1], wz[c ^ 1], wy[c ^ 1]);
+    if (st + 1 < 4) load_step(st + 1, a[c ^ 1], wy[c ^ 1], wz[c ^ 1]);
     if (st < nst) {
 #pragma unroll
-      for (int y = 0; y < W; ++y)
-        acc[L + y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], wy[c][y] * wz[c], acc[L + y], 0, 0, 0);
+      for (int z = 0; z < W; ++z)
+        acc[L + z] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], wz[c][z] * wy[c], acc[L + z], 0, 0, 0);
     }
   }
 }
 
-template <int W, int P, int PITCH, int L = 0>
-__device__ __forceinline__ void spread_run_dispatch(int ly0, f32x4 (&acc)[P], const float *wt,
-                                                    int nst, int c16, int p4) {
-  if constexpr (L + W <= P) {
-    if (ly0 == L) spread_run_steps<L, W, P, PITCH>(acc, wt, nst, c16, p4);
-    else spread_run_dispatch<W, P, PITCH, L + 1>(ly0, acc, wt, nst, c16, p4);
+// The nodes of one 64-node batch whose cell has z offset L in the tile (a
+// contiguous range of lanes: a tile's nodes are sorted z-major), in runs of
+// up to 16.  L is a compile-time constant in each call, so every matrix
+// instruction names its accumulator statically and the accumulators stay in
+// place across the classes.
+template <int L, int T, int W, int P>
+__device__ __forceinline__ void spread_zclass(f32x4 (&acc)[P], int lzl, int bcnt, int lane,
+                                              const float4 &qb, float xb, const float *cft,
+                                              float *wt, int ox, int oy, int oz, int c16, int p4) {
+  const unsigned long long m = __ballot(lane < bcnt && lzl == L);
+  if (m == 0) return;
+  const int p0 = __builtin_ctzll(m), pe = p0 + __popcll(m);
+  for (int pos = p0; pos < pe; pos += 16) {
+    const int cnt = min(16, pe - pos);
+    fill_shifted_lds<T, W, true, TS_PITCH, true>(qb, xb, pos, cnt, lane, cft, wt, ox, oy, oz);
+    wave_sync_lds();
+    spread_zrun_steps<L, W, P, TS_PITCH>(acc, wt, (cnt + 3) >> 2, c16, p4);
+    wave_sync_lds();
+  }
+}
+
+template <int L, int T, int W, int P>
+__device__ __forceinline__ void spread_zclasses(f32x4 (&acc)[P], int lzl, int bcnt, int lane,
+                                                const float4 &qb, float xb, const float *cft,
+                                                float *wt, int ox, int oy, int oz, int c16,
+                                                int p4) {
+  if constexpr (L < T) {
+    spread_zclass<L, T, W, P>(acc, lzl, bcnt, lane, qb, xb, cft, wt, ox, oy, oz, c16, p4);
+    spread_zclasses<L + 1, T, W, P>(acc, lzl, bcnt, lane, qb, xb, cft, wt, ox, oy, oz, c16, p4);
   }
 }
 
@@ -786,8 +825,9 @@ template <int W, int T, int IN, int NW = 4>
 __device__ __forceinline__ void spread3_tile_body(const Item it, const float4 *__restrict__ pts,
                                                   const KArgs ka, float *__restrict__ grid,
                                                   int nos, const float *__restrict__ wcoef) {
-  constexpr int M = W / 2, P = T + W - 1, XS = ts_xs(P);
+  constexpr int M = W / 2, P = T + W - 1, XS = ts_sxs(P);
   static_assert(P <= 16, "tile-stationary form needs T + W - 1 <= 16");
+  static_assert(P - W + 1 == T, "z classes 0 .. T - 1");
   extern __shared__ float lds[];
   const int ntd = nos / T;
   const int tz = it.tile % ntd, ty = (it.tile / ntd) % ntd, tx = it.tile / (ntd * ntd);
@@ -796,18 +836,17 @@ __device__ __forceinline__ void spread3_tile_body(const Item it, const float4 *_
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int c16 = lane & 15, p4 = lane >> 4;
-  float *wt = lds + P * XS + wave * (16 * TS_PITCH);
+  float *wt = lds + wave * (16 * TS_PITCH);
   const int len = it.end - it.start, per = (len + NW - 1) / NW;
   const int s = it.start + min(len, wave * per), e = it.start + min(len, (wave + 1) * per);
 
-  // window coefficients (rows 2m..15 are 0) after the weight tables, read at
-  // each use (the final tile sum reuses only the LDS below them)
-  float *cft = lds + P * XS + NW * 16 * TS_PITCH;
+  // window coefficients (rows 2m..15 are 0) after the weight tables
+  float *cft = lds + NW * 16 * TS_PITCH;
   for (int q = threadIdx.x; q < WIN_MAXW * WIN_NC; q += NW * 64) cft[q] = wcoef[q];
   __syncthreads();
   f32x4 acc[P];
 #pragma unroll
-  for (int y = 0; y < P; ++y) acc[y] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int z = 0; z < P; ++z) acc[z] = f32x4{0.f, 0.f, 0.f, 0.f};
 
   float4 qb, qn;
   float xb, xn;
@@ -815,57 +854,41 @@ __device__ __forceinline__ void spread3_tile_body(const Item it, const float4 *_
   for (int b0 = s; b0 < e; b0 += 64) {
     load_batch<IN, true>(pts, ka, b0 + 64, e, lane, qn, xn);  // prefetch the next batch
     const int bcnt = min(64, e - b0);
-    // runs of <= 16 nodes sharing their cell's y offset in the tile (the sort
-    // orders a tile's nodes z-major, then by y): their y windows coincide, so
-    // a step issues W y-slices instead of all T + W - 1 of the padded tile
-    const int lyl = (int)((__float_as_uint(qb.w) >> 10) & 1023u) - oy;
-    int cnt;
-    for (int pos = 0; pos < bcnt; pos += cnt) {
-      const int ly0 = __builtin_amdgcn_readlane(lyl, pos);
-      const unsigned long long same = __ballot(lane < bcnt && lyl == ly0);
-      const unsigned long long rest = ~(same >> pos);   // 0 when the whole batch shares ly0
-      const int run = rest ? __builtin_ctzll(rest) : 64;
-      cnt = min(16, min(run, bcnt - pos));
-      fill_shifted_lds<T, W, true, TS_PITCH, false, true>(qb, xb, pos, cnt, lane, cft, wt, ox, oy,
-                                                          oz);
-      wave_sync_lds();
-      spread_run_dispatch<W, P, TS_PITCH>(ly0, acc, wt, (cnt + 3) >> 2, c16, p4);
-      wave_sync_lds();
-    }
+    const int lzl = (int)(__float_as_uint(qb.w) >> 20) - oz;
+    spread_zclasses<0, T, W, P>(acc, lzl, bcnt, lane, qb, xb, cft, wt, ox, oy, oz, c16, p4);
     qb = qn;
     xb = xn;
   }
   // Sum the waves' tiles without LDS atomics (measured far slower than plain
   // LDS traffic): once every wave is done with its weight table, waves 0 and 1
   // store their tiles into copies C0 and C1 (in the LDS of the tables), then
-  // waves 2 and 3 add theirs into C0 and C1; the flush adds C0 + C1.  The
-  // workgroup's LDS must hold 2 x 16 x ts_xs(P) floats.
+  // waves 2 and 3 add theirs into C0 and C1; the flush adds C0 + C1.
   constexpr int NC = NW >= 2 ? 2 : 1;
   static_assert(NW == 1 || NW == 2 || NW == 4, "one, two or four waves");
   __syncthreads();
   {
-    // copies of 16 x-rows (row 15 and z-columns >= P are written, never read)
+    // copies of 16 x-rows (row 15 and y-columns >= P are written, never read)
     float *cp = lds + (wave % NC) * (16 * XS) + (4 * p4) * XS + c16;
     if (wave < NC) {
 #pragma unroll
-      for (int y = 0; y < P; ++y)
+      for (int z = 0; z < P; ++z)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) cp[r * XS + y * 16] = acc[y][r];
+        for (int r = 0; r < 4; ++r) cp[r * XS + z * TS_SZS] = acc[z][r];
     }
     __syncthreads();
     if (NW == 4 && wave >= NC) {
-      // read-add-write in groups of 4 y-slices: 16 loads in flight at a time
+      // read-add-write in groups of 4 z-slices: 16 loads in flight at a time
 #pragma unroll
-      for (int y0 = 0; y0 < P; y0 += 4) {
+      for (int z0 = 0; z0 < P; z0 += 4) {
         float old[4][4];
 #pragma unroll
-        for (int y = y0; y < y0 + 4 && y < P; ++y)
+        for (int z = z0; z < z0 + 4 && z < P; ++z)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) old[y - y0][r] = cp[r * XS + y * 16];
+          for (int r = 0; r < 4; ++r) old[z - z0][r] = cp[r * XS + z * TS_SZS];
 #pragma unroll
-        for (int y = y0; y < y0 + 4 && y < P; ++y)
+        for (int z = z0; z < z0 + 4 && z < P; ++z)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) cp[r * XS + y * 16] = old[y - y0][r] + acc[y][r];
+          for (int r = 0; r < 4; ++r) cp[r * XS + z * TS_SZS] = old[z - z0][r] + acc[z][r];
       }
     }
     __syncthreads();
@@ -878,7 +901,7 @@ __device__ __forceinline__ void spread3_tile_body(const Item it, const float4 *_
     const int row = row0 + rsub;
     if (row < P * P && pz < P) {
       const int px = row / P, py = row - px * P;
-      const int o = px * XS + py * 16 + pz;
+      const int o = px * XS + pz * TS_SZS + py;
       const float v = NC == 2 ? lds[o] + lds[16 * XS + o] : lds[o];
       if (v != 0.f) {
         const int gx = (ox - (M - 1) + px) & mask, gy = (oy - (M - 1) + py) & mask,
