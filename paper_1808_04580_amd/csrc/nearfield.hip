@@ -61,23 +61,38 @@ __global__ __launch_bounds__(256) void k_near_dinv(const float *__restrict__ deg
   }
 }
 
-template <int IN, int OUT>
+// Node coordinates relative to the item's tile origin, in grid cells: the
+// integer cell difference exactly, plus the float fraction, rounded once
+// (by at most 2^-19 of a cell while |coordinate| < 64 cells; candidate
+// sources lie within R + 1 tiles of the origin).
+__device__ __forceinline__ float3 rel_cells(const float4 &q, const int (&org)[3], int d) {
+  const uint32_t c = __float_as_uint(q.w);
+  float3 r;
+  r.x = (float)((int)(c & 1023u) - org[0]) + q.x;
+  r.y = d > 1 ? (float)((int)((c >> 10) & 1023u) - org[1]) + q.y : 0.f;
+  r.z = d > 2 ? (float)((int)((c >> 20) & 1023u) - org[2]) + q.z : 0.f;
+  return r;
+}
+
+// PC: number of polynomial coefficients evaluated (>= p; the ones past p are
+// zero), a compile-time constant so that the coefficients stay in registers.
+template <int IN, int OUT, int PC>
 __global__ __launch_bounds__(NT) void k_near(const Item *__restrict__ items,
                                              const float4 *__restrict__ pts,
                                              const int *__restrict__ tile_start, KArgs ka, int d,
-                                             int ntd, int tsize, int R, float eps_cells2, float inv_nos,
-                                             float inv_sigma, float inv_eps,
+                                             int ntd, int tsize, int R, float eps_cells2,
+                                             float kexp, float ku2,
                                              const float *__restrict__ coef, int p) {
-  __shared__ float4 ssrc[NT];   // staged source records (fractions, packed cell)
-  __shared__ float sval[NT];
-  __shared__ float cf[NF_MAXP];
+  __shared__ float4 ssrc[NT];              // staged sources: tile-relative cells, value
   __shared__ int ns0[NF_MAXTILES];         // first node of each neighbour tile
   __shared__ int pref[NF_MAXTILES + 1];    // prefix sums of their node counts
   __shared__ int bsum[NT + 1];
   __shared__ float part[NT];
   if (stopped(ka.stop)) return;
   const int t = threadIdx.x;
-  if (t < p) cf[t] = coef[t];
+  float cf[PC];
+#pragma unroll
+  for (int c = 0; c < PC; ++c) cf[c] = c < p ? coef[c] : 0.f;
   const Item it = items[blockIdx.x];
   int tc[3] = {0, 0, 0};
   {
@@ -87,6 +102,7 @@ __global__ __launch_bounds__(NT) void k_near(const Item *__restrict__ items,
       r /= ntd;
     }
   }
+  const int org[3] = {tc[0] * tsize, tc[1] * tsize, tc[2] * tsize};
   // neighbour tiles: the (2R + 1)^d cube around the item's tile, without the
   // tiles whose nearest cell is farther than eps_I from the item's tile and
   // those outside the grid
@@ -144,27 +160,18 @@ __global__ __launch_bounds__(NT) void k_near(const Item *__restrict__ items,
   }
   __syncthreads();
   const int total = pref[nnb];
-  // Targets: one per thread for items of at least NT nodes; shorter items
-  // give each target G thread groups, group g taking every G-th source.
-  const int len = it.end - it.start;
-  const int G = len >= NT ? 1 : min(NT / max(len, 1), 32);
-  const int TB = NT / G;
-  const int ti = t % TB, gi = t / TB;
-  for (int b0 = it.start; b0 < it.end; b0 += TB) {
+  // Batches of targets: a full batch takes one target per thread; the last,
+  // partial batch gives each of its rem targets G thread groups, group g
+  // taking every G-th staged source, so that no batch leaves threads idle.
+  for (int b0 = it.start; b0 < it.end;) {
+    const int rem = it.end - b0;
+    const int G = rem >= NT ? 1 : min(NT / rem, 32);
+    const int TB = NT / G;
+    const int ti = t % TB, gi = t / TB;
     const int i = b0 + ti;
     const bool act = gi < G && i < it.end;
-    int tcx = 0, tcy = 0, tcz = 0;
-    float tfx = 0.f, tfy = 0.f, tfz = 0.f;
-    if (act) {
-      const float4 q = pts[i];
-      const uint32_t cell = __float_as_uint(q.w);
-      tcx = (int)(cell & 1023u);
-      tcy = (int)((cell >> 10) & 1023u);
-      tcz = (int)((cell >> 20) & 1023u);
-      tfx = q.x;
-      tfy = q.y;
-      tfz = q.z;
-    }
+    float3 tp3 = make_float3(0.f, 0.f, 0.f);
+    if (act) tp3 = rel_cells(pts[i], org, d);
     float acc = 0.f;
     // the neighbour tiles' nodes as one list, staged NT at a time; slice
     // blockIdx.y of gridDim.y takes every gridDim.y-th chunk
@@ -180,27 +187,24 @@ __global__ __launch_bounds__(NT) void k_near(const Item *__restrict__ items,
           else hi = mid;
         }
         const int j = ns0[lo] + (v - pref[lo]);
-        ssrc[t] = pts[j];
-        sval[t] = load_in<IN>(ka, j);
+        const float3 sr = rel_cells(pts[j], org, d);
+        ssrc[t] = make_float4(sr.x, sr.y, sr.z, load_in<IN>(ka, j));
       }
       __syncthreads();
       if (act) {
+        // branch-free: pairs past eps_I contribute an exact 0
 #pragma unroll 4
         for (int k = gi; k < cnt; k += G) {
           const float4 sq = ssrc[k];
-          const uint32_t sc = __float_as_uint(sq.w);
-          const float dx = (float)(tcx - (int)(sc & 1023u)) + (tfx - sq.x);
-          const float dy = d > 1 ? (float)(tcy - (int)((sc >> 10) & 1023u)) + (tfy - sq.y) : 0.f;
-          const float dz = d > 2 ? (float)(tcz - (int)((sc >> 20) & 1023u)) + (tfz - sq.z) : 0.f;
-          const float r2 = dx * dx + dy * dy + dz * dz;
-          if (r2 <= eps_cells2) {
-            const float r = __builtin_sqrtf(r2) * inv_nos;   // scaled coordinates
-            const float u = r * inv_eps;
-            const float u2 = u * u;
-            float tp = cf[p - 1];
-            for (int c = p - 2; c >= 0; --c) tp = fmaf(tp, u2, cf[c]);
-            acc = fmaf(sval[k], __expf(-r * inv_sigma) - tp, acc);
-          }
+          const float dx = tp3.x - sq.x, dy = tp3.y - sq.y, dz = tp3.z - sq.z;
+          const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+          // K(r): hardware square root and exp2 (about 1 ulp each)
+          const float e = __builtin_amdgcn_exp2f(__builtin_amdgcn_sqrtf(r2) * kexp);
+          const float u2 = fminf(r2 * ku2, 1.f);   // (r / eps_I)^2, clamped: finite past eps_I
+          float tp = cf[PC - 1];
+#pragma unroll
+          for (int c = PC - 2; c >= 0; --c) tp = fmaf(tp, u2, cf[c]);
+          acc = fmaf(r2 <= eps_cells2 ? sq.w : 0.f, e - tp, acc);
         }
       }
     }
@@ -213,6 +217,7 @@ __global__ __launch_bounds__(NT) void k_near(const Item *__restrict__ items,
       if (s != 0.f) add_out<OUT>(ka, i, s);
     }
     __syncthreads();   // part is rewritten by the next batch of targets
+    b0 += min(TB, rem);
   }
 }
 
@@ -233,10 +238,16 @@ int launch_near(nfl_plan *P, const KArgs &k) {
   // slices per item: enough workgroups (~8192) to fill the chip when the
   // items are few and their neighbourhoods large
   const int slices = std::min(64, std::max(1, (8192 + P->nitems - 1) / P->nitems));
-  hipLaunchKernelGGL((k_near<IN, OUT>), dim3(P->nitems, slices), dim3(NT), 0, P->stream,
-                     P->items.p, P->pts.p, P->tile_start.p, k, P->d, ntd, T, R,
-                     (float)(eps_cells * eps_cells), (float)(1.0 / P->nos),
-                     (float)(1.0 / P->sigma_t), (float)(1.0 / P->eps_I), P->ti_coef.p, P->p);
+  // K(r) = 2^(r_cells * kexp), (r / eps_I)^2 = r_cells^2 * ku2 (r_cells in grid cells)
+  const float kexp = (float)(-1.0 / (P->nos * P->sigma_t * std::log(2.0)));
+  const float ku2 = (float)(1.0 / (eps_cells * eps_cells));
+  auto kern = P->p <= 4   ? k_near<IN, OUT, 4>
+              : P->p <= 6 ? k_near<IN, OUT, 6>
+              : P->p <= 8 ? k_near<IN, OUT, 8>
+                          : k_near<IN, OUT, NF_MAXP>;
+  hipLaunchKernelGGL(kern, dim3(P->nitems, slices), dim3(NT), 0, P->stream, P->items.p, P->pts.p,
+                     P->tile_start.p, k, P->d, ntd, T, R, (float)(eps_cells * eps_cells), kexp, ku2,
+                     P->ti_coef.p, P->p);
   NFL_HIP(hipGetLastError());
   if constexpr (OUT == OUT_DEGREE) {
     const int nb = (int)std::min<int64_t>(4096, (P->n + 255) / 256);

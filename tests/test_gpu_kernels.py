@@ -92,6 +92,30 @@ LAPLACE_CASES = [
 ]
 
 
+def test_laplacian_near_field_items_longer_than_a_workgroup(nfl):
+    """Near field of the Laplacian RBF kernel on a clustered 2-D cloud whose
+    tiles hold up to ~2,800 nodes: work items of more than 256 targets run in
+    full batches plus a partial last batch (shared among thread groups).
+    Degrees, W x and L_s x against the oracle's exact trigonometric operator
+    plus its dense near-field sum (1e-5)."""
+    import torch
+    n, d, s, N, m, eps_B = 12000, 2, 0.04, 64, 5, 1 / 8
+    v = synth.gmm(n, d=d, k=4, seed=42)
+    x = synth.normal_vectors(n, seed=7)
+    T = fastsum.TrigGraph(v, s, N, eps_B, m, "laplacian_rbf", eps_I=m / N)
+    P = nfl.plan(torch.as_tensor(v, device="cuda"), s, N=N, m=m, eps_B=eps_B,
+                 kind="laplacian_rbf")
+    xd = torch.as_tensor(x, device="cuda")
+    dg = P.degree().cpu().numpy().astype(np.float64)
+    Wx = P.apply_W(xd).cpu().numpy().astype(np.float64)
+    Lx = P.apply_Ls(xd).cpu().numpy().astype(np.float64)
+    P.close()
+    x64 = x.astype(np.float64)
+    assert _rel(dg, T.d) <= 1e-5
+    assert _rel(Wx, T.apply_W(x64)) <= 1e-5
+    assert _rel(Lx, T.apply_Ls(x64)) <= 1e-5
+
+
 @pytest.mark.parametrize("d,n,s,N,m,eps_B", LAPLACE_CASES)
 def test_laplacian_rbf_with_near_field(nfl, d, n, s, N, m, eps_B):
     """Laplacian RBF kernel (eq. W_laplacian_rbf): the regularised kernel's
