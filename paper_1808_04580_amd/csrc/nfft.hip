@@ -416,9 +416,10 @@ __global__ __launch_bounds__(FFT_THREADS) void k_r2c_lines(float *__restrict__ g
                                                            const float2 *__restrict__ tw,
                                                            const int *__restrict__ stop,
                                                            const unsigned *__restrict__ fx_max,
-                                                           float fx_mult) {
+                                                           float fx_mult,
+                                                           const int *__restrict__ lines) {
   if (stopped(stop)) return;
-  r2c_lines_body<ZERO>(blockIdx.x, grid, H, nlines, L, logL, lpb, Hz, tw, fx_max, fx_mult);
+  r2c_lines_body<ZERO>(blockIdx.x, grid, H, nlines, L, logL, lpb, Hz, tw, fx_max, fx_mult, lines);
 }
 
 __global__ __launch_bounds__(FFT_THREADS) void k_c2r_lines(const float2 *__restrict__ H,
@@ -426,39 +427,44 @@ __global__ __launch_bounds__(FFT_THREADS) void k_c2r_lines(const float2 *__restr
                                                            int L, int logL, int lpb, int Hz,
                                                            const float2 *__restrict__ tw,
                                                            const int *__restrict__ stop,
-                                                           unsigned *__restrict__ fx_reset) {
+                                                           unsigned *__restrict__ fx_reset,
+                                                           const int *__restrict__ lines) {
   if (stopped(stop)) return;
   // the last pass of a product clears the deterministic spread's input bound
   // for the next product's pre-pass (every reader of it has finished)
   if (fx_reset && blockIdx.x == 0 && threadIdx.x == 0) *fx_reset = 0u;
-  c2r_lines_body(blockIdx.x, H, grid, nlines, L, logL, lpb, Hz, tw);
+  c2r_lines_body(blockIdx.x, H, grid, nlines, L, logL, lpb, Hz, tw, lines);
 }
 
 __global__ __launch_bounds__(FFT_THREADS) void k_y_fwd(const float2 *__restrict__ H1,
                                                        float2 *__restrict__ H2, int L, int logL,
                                                        int lpb, int Hz, int N,
                                                        const float2 *__restrict__ tw,
-                                                       const int *__restrict__ stop) {
+                                                       const int *__restrict__ stop,
+                                                       const int *__restrict__ xs) {
   if (stopped(stop)) return;
-  y_fwd_body(xcd_block(blockIdx.x, gridDim.x), H1, H2, L, logL, lpb, Hz, N, tw);
+  y_fwd_body(xcd_block(blockIdx.x, gridDim.x), H1, H2, L, logL, lpb, Hz, N, tw, xs);
 }
 
 __global__ __launch_bounds__(FFT_THREADS) void k_y_inv(const float2 *__restrict__ H2,
                                                        float2 *__restrict__ H1, int L, int logL,
                                                        int lpb, int Hz, int N,
                                                        const float2 *__restrict__ tw,
-                                                       const int *__restrict__ stop) {
+                                                       const int *__restrict__ stop,
+                                                       const int *__restrict__ xs,
+                                                       const uint8_t *__restrict__ sup) {
   if (stopped(stop)) return;
-  y_inv_body(xcd_block(blockIdx.x, gridDim.x), H2, H1, L, logL, lpb, Hz, N, tw);
+  y_inv_body(xcd_block(blockIdx.x, gridDim.x), H2, H1, L, logL, lpb, Hz, N, tw, xs, sup);
 }
 
 __global__ __launch_bounds__(FFT_THREADS) void k_x_filter(float2 *__restrict__ Hx,
                                                           const float *__restrict__ filt, int C,
                                                           int L, int logL, int lpb, int N,
                                                           const float2 *__restrict__ tw,
-                                                          const int *__restrict__ stop) {
+                                                          const int *__restrict__ stop,
+                                                          const uint8_t *__restrict__ xin) {
   if (stopped(stop)) return;
-  x_filter_body(xcd_block(blockIdx.x, gridDim.x), Hx, filt, C, L, logL, lpb, N, tw);
+  x_filter_body(xcd_block(blockIdx.x, gridDim.x), Hx, filt, C, L, logL, lpb, N, tw, xin);
 }
 
 __global__ void k_filter1(float2 *__restrict__ H, const float *__restrict__ filt, int Hz,
@@ -777,7 +783,7 @@ int interp(nfl_plan *P, const float *grid, int in_mode, int out_mode, const VecA
   return NFL_ERR_ARG;
 }
 
-int convolve(nfl_plan *P, const float *gin_c, float *gout, bool zero_in) {
+int convolve(nfl_plan *P, const float *gin_c, float *gout, bool zero_in, bool support) {
   // the input is written only when zero_in (then it is the plan's own grid)
   float *gin = const_cast<float *>(gin_c);
   auto r2c = zero_in ? k_r2c_lines<true> : k_r2c_lines<false>;
@@ -793,36 +799,49 @@ int convolve(nfl_plan *P, const float *gin_c, float *gout, bool zero_in) {
   const float2 *tw = P->tw.p;
   if (P->d == 1) {
     hipLaunchKernelGGL(r2c, dim3(1), dim3(FFT_THREADS), ldz, P->stream, gin, P->spec1.p,
-                       1, L, logL, lpz, Hz, tw, P->stop, fxm, fxu);
+                       1, L, logL, lpz, Hz, tw, P->stop, fxm, fxu, (const int *)nullptr);
     hipLaunchKernelGGL(k_filter1, dim3(1), dim3(256), 0, P->stream, P->spec1.p, P->filt.p, Hz, P->stop);
     hipLaunchKernelGGL(k_c2r_lines, dim3(1), dim3(FFT_THREADS), ldz, P->stream, P->spec1.p, gout,
-                       1, L, logL, lpz, Hz, tw, P->stop, fxr);
+                       1, L, logL, lpz, Hz, tw, P->stop, fxr, (const int *)nullptr);
   } else if (P->d == 2) {
     const int nlines = L;
     const int nb = (nlines + lpz - 1) / lpz;
     hipLaunchKernelGGL(r2c, dim3(nb), dim3(FFT_THREADS), ldz, P->stream, gin, P->spec1.p,
-                       nlines, L, logL, lpz, Hz, tw, P->stop, fxm, fxu);
+                       nlines, L, logL, lpz, Hz, tw, P->stop, fxm, fxu, (const int *)nullptr);
     hipLaunchKernelGGL(k_x_filter, dim3(Hz), dim3(FFT_THREADS), fft_lds_bytes(1, L), P->stream,
-                       P->spec1.p, P->filt.p, Hz, L, logL, 1, N, tw, P->stop);
+                       P->spec1.p, P->filt.p, Hz, L, logL, 1, N, tw, P->stop,
+                       (const uint8_t *)nullptr);
     hipLaunchKernelGGL(k_c2r_lines, dim3(nb), dim3(FFT_THREADS), ldz, P->stream, P->spec1.p, gout,
-                       nlines, L, logL, lpz, Hz, tw, P->stop, fxr);
+                       nlines, L, logL, lpz, Hz, tw, P->stop, fxr, (const int *)nullptr);
   } else {
-    const int nlines = L * L;
+    // On the plan's own grids the passes take only the support: the z-lines
+    // some node's window touches, the x-slabs holding them; the spectrum
+    // entries off the support are zero from the last clear and stay zero.
+    const bool sup = support && P->zs_nlines > 0;
+    if (sup && !P->spec_clean) {
+      NFL_TRY(fill_f32(reinterpret_cast<float *>(P->spec1.p), (int64_t)2 * L * L * Hz, 0.f, P->stream));
+      NFL_TRY(fill_f32(reinterpret_cast<float *>(P->spec2.p), (int64_t)2 * L * F * Hz, 0.f, P->stream));
+      P->spec_clean = true;
+    }
+    if (!sup) P->spec_clean = false;   // the full passes write every entry
+    const int *zl = sup ? P->zs_lines.p : nullptr, *zx = sup ? P->zs_x.p : nullptr;
+    const uint8_t *zmap = sup ? P->zs_map.p : nullptr, *zxin = sup ? P->zs_map.p + (size_t)L * L : nullptr;
+    const int nlines = sup ? P->zs_nlines : L * L, nxs = sup ? P->zs_nx : L;
     const int nb = (nlines + lpz - 1) / lpz;
     hipLaunchKernelGGL(r2c, dim3(nb), dim3(FFT_THREADS), ldz, P->stream, gin, P->spec1.p,
-                       nlines, L, logL, lpz, Hz, tw, P->stop, fxm, fxu);
+                       nlines, L, logL, lpz, Hz, tw, P->stop, fxm, fxu, zl);
     const int lpy = fft_lpb_y(L), ngroups = (Hz + lpy - 1) / lpy;
     const size_t ldy = fft_lds_bytes(lpy, L);
-    hipLaunchKernelGGL(k_y_fwd, dim3(L * ngroups), dim3(FFT_THREADS), ldy, P->stream, P->spec1.p,
-                       P->spec2.p, L, logL, lpy, Hz, N, tw, P->stop);
+    hipLaunchKernelGGL(k_y_fwd, dim3(nxs * ngroups), dim3(FFT_THREADS), ldy, P->stream, P->spec1.p,
+                       P->spec2.p, L, logL, lpy, Hz, N, tw, P->stop, zx);
     const int C = F * Hz, lpx = fft_lpb_x(L);
     hipLaunchKernelGGL(k_x_filter, dim3((C + lpx - 1) / lpx), dim3(FFT_THREADS),
                        fft_lds_bytes(lpx, L), P->stream, P->spec2.p, P->filt.p, C, L, logL, lpx,
-                       N, tw, P->stop);
-    hipLaunchKernelGGL(k_y_inv, dim3(L * ngroups), dim3(FFT_THREADS), ldy, P->stream, P->spec2.p,
-                       P->spec1.p, L, logL, lpy, Hz, N, tw, P->stop);
+                       N, tw, P->stop, zxin);
+    hipLaunchKernelGGL(k_y_inv, dim3(nxs * ngroups), dim3(FFT_THREADS), ldy, P->stream, P->spec2.p,
+                       P->spec1.p, L, logL, lpy, Hz, N, tw, P->stop, zx, zmap);
     hipLaunchKernelGGL(k_c2r_lines, dim3(nb), dim3(FFT_THREADS), ldz, P->stream, P->spec1.p, gout,
-                       nlines, L, logL, lpz, Hz, tw, P->stop, fxr);
+                       nlines, L, logL, lpz, Hz, tw, P->stop, fxr, zl);
   }
   NFL_HIP(hipGetLastError());
   return NFL_OK;
@@ -838,7 +857,7 @@ int fastsum(nfl_plan *P, int in_mode, int out_mode, const VecArgs &a) {
   P->grid_clean = false;
   NFL_TRY(spread(P, in_mode, a, P->grid.p, clear));
   if (P->prof_ev) NFL_HIP(hipEventRecord(P->prof_ev[2], P->stream));
-  NFL_TRY(convolve(P, P->grid.p, P->grid2.p, true));
+  NFL_TRY(convolve(P, P->grid.p, P->grid2.p, true, true));
   P->grid_clean = true;
   if (P->prof_ev) NFL_HIP(hipEventRecord(P->prof_ev[3], P->stream));
   NFL_TRY(interp(P, P->grid2.p, in_mode, out_mode, a));

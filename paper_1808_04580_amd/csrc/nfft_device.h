@@ -1049,7 +1049,7 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-constexpr int FFT_THREADS = 128, FFT_ELEMS = 512, FFT_MAXL = 512;
+constexpr int FFT_THREADS = 256, FFT_ELEMS = 512, FFT_MAXL = 512;
 
 __device__ __forceinline__ void load_twiddles(float2 *twl, const float2 *__restrict__ tw, int L) {
   for (int k = threadIdx.x; k < L / 2; k += FFT_THREADS) {
@@ -1152,42 +1152,50 @@ __host__ __device__ __forceinline__ int fft_lpb_x(int L) {
 // leaves the spread grid clear for the next product.
 // fx_max non-null: the grid holds the deterministic spread's int64 fixed-point
 // values (scaled by fx_scale(*fx_max, fx_mult)), converted here.
+// lines non-null: the block's lines are lines[l0 ..] (a list of line
+// indices, e.g. the lines some node's window touches) instead of l0 ...
 template <bool ZERO = false>
 __device__ __forceinline__ void r2c_lines_body(int blk, float *__restrict__ grid,
                                                float2 *__restrict__ H, int nlines, int L,
                                                int logL, int lpb, int Hz,
                                                const float2 *__restrict__ tw,
                                                const unsigned *__restrict__ fx_max = nullptr,
-                                               float fx_mult = 0.f) {
+                                               float fx_mult = 0.f,
+                                               const int *__restrict__ lines = nullptr) {
   extern __shared__ float2 sm[];
   const int np = lpb >> 1;
   float2 *a = sm, *b = sm + np * L, *twl = sm + 2 * np * L;
   load_twiddles(twl, tw, L);
   const int l0 = blk * lpb;
   const int nl = min(lpb, nlines - l0), npp = (nl + 1) >> 1;
+  auto line = [&](int li) { return lines ? lines[l0 + li] : l0 + li; };
   if (fx_max) {
     const double inv = 1.0 / fx_scale(*fx_max, fx_mult);   // a power of 2: exact
     for (int idx = threadIdx.x; idx < npp * L; idx += FFT_THREADS) {
       const int pl = idx / L, j = idx - pl * L;
-      long long *pa = reinterpret_cast<long long *>(grid) + (size_t)(l0 + 2 * pl) * L + j;
+      const bool two = 2 * pl + 1 < nl;
+      long long *pa = reinterpret_cast<long long *>(grid) + (size_t)line(2 * pl) * L + j;
+      long long *pb = two ? reinterpret_cast<long long *>(grid) + (size_t)line(2 * pl + 1) * L + j : pa;
       const float re = (float)((double)pa[0] * inv);
-      const float im = 2 * pl + 1 < nl ? (float)((double)pa[L] * inv) : 0.f;
+      const float im = two ? (float)((double)pb[0] * inv) : 0.f;
       a[idx] = make_float2(re, im);
       if (ZERO) {
         pa[0] = 0;
-        if (2 * pl + 1 < nl) pa[L] = 0;
+        if (two) pb[0] = 0;
       }
     }
   } else {
     for (int idx = threadIdx.x; idx < npp * L; idx += FFT_THREADS) {
       const int pl = idx / L, j = idx - pl * L;
-      float *pa = grid + (size_t)(l0 + 2 * pl) * L + j;
+      const bool two = 2 * pl + 1 < nl;
+      float *pa = grid + (size_t)line(2 * pl) * L + j;
+      float *pb = two ? grid + (size_t)line(2 * pl + 1) * L + j : pa;
       const float re = *pa;
-      const float im = 2 * pl + 1 < nl ? pa[L] : 0.f;
+      const float im = two ? *pb : 0.f;
       a[idx] = make_float2(re, im);
       if (ZERO) {
         *pa = 0.f;
-        if (2 * pl + 1 < nl) pa[L] = 0.f;
+        if (two) *pb = 0.f;
       }
     }
   }
@@ -1196,9 +1204,9 @@ __device__ __forceinline__ void r2c_lines_body(int blk, float *__restrict__ grid
   for (int idx = threadIdx.x; idx < nl * Hz; idx += FFT_THREADS) {
     const int li = idx / Hz, k = idx - li * Hz, pl = li >> 1;
     const float2 zk = a[pl * L + k], zm = a[pl * L + ((L - k) & (L - 1))];
-    H[(size_t)(l0 + li) * Hz + k] = (li & 1) == 0
-                                        ? make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y))
-                                        : make_float2(0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x));
+    H[(size_t)line(li) * Hz + k] = (li & 1) == 0
+                                       ? make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y))
+                                       : make_float2(0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x));
   }
 }
 
@@ -1207,19 +1215,21 @@ __device__ __forceinline__ void r2c_lines_body(int blk, float *__restrict__ grid
 __device__ __forceinline__ void c2r_lines_body(int blk, const float2 *__restrict__ H,
                                                float *__restrict__ grid, int nlines, int L,
                                                int logL, int lpb, int Hz,
-                                               const float2 *__restrict__ tw) {
+                                               const float2 *__restrict__ tw,
+                                               const int *__restrict__ lines = nullptr) {
   extern __shared__ float2 sm[];
   const int np = lpb >> 1;
   float2 *a = sm, *b = sm + np * L, *twl = sm + 2 * np * L;
   load_twiddles(twl, tw, L);
   const int l0 = blk * lpb;
   const int nl = min(lpb, nlines - l0), npp = (nl + 1) >> 1;
+  auto line = [&](int li) { return lines ? lines[l0 + li] : l0 + li; };
   for (int idx = threadIdx.x; idx < npp * L; idx += FFT_THREADS) a[idx] = make_float2(0.f, 0.f);
   __syncthreads();
   for (int idx = threadIdx.x; idx < npp * Hz; idx += FFT_THREADS) {
     const int pl = idx / Hz, k = idx - pl * Hz;
-    const float2 A = H[(size_t)(l0 + 2 * pl) * Hz + k];
-    const float2 B = 2 * pl + 1 < nl ? H[(size_t)(l0 + 2 * pl + 1) * Hz + k] : make_float2(0.f, 0.f);
+    const float2 A = H[(size_t)line(2 * pl) * Hz + k];
+    const float2 B = 2 * pl + 1 < nl ? H[(size_t)line(2 * pl + 1) * Hz + k] : make_float2(0.f, 0.f);
     a[pl * L + k] = make_float2(A.x - B.y, A.y + B.x);                  // A + i B
     if (k > 0) a[pl * L + L - k] = make_float2(A.x + B.y, B.x - A.y);   // conj A + i conj B
   }
@@ -1228,20 +1238,22 @@ __device__ __forceinline__ void c2r_lines_body(int blk, const float2 *__restrict
   for (int idx = threadIdx.x; idx < nl * L; idx += FFT_THREADS) {
     const int li = idx / L, j = idx - li * L;
     const float2 v = a[(li >> 1) * L + j];
-    grid[(size_t)l0 * L + idx] = (li & 1) ? v.y : v.x;
+    grid[(size_t)line(li) * L + j] = (li & 1) ? v.y : v.x;
   }
 }
 
 // d = 3 middle axis (y), forward: H1[(x*L + y)*Hz + lz] -> H2[(x*F + y')*Hz + lz],
 // keeping ly = y' - N/2 in [-N/2, N/2]; lpb columns lz per workgroup.
+// xs non-null: block row blk / ngroups takes slab x = xs[blk / ngroups].
 __device__ __forceinline__ void y_fwd_body(int blk, const float2 *__restrict__ H1,
                                            float2 *__restrict__ H2, int L, int logL, int lpb,
-                                           int Hz, int N, const float2 *__restrict__ tw) {
+                                           int Hz, int N, const float2 *__restrict__ tw,
+                                           const int *__restrict__ xs = nullptr) {
   extern __shared__ float2 sm[];
   float2 *a = sm, *b = sm + lpb * L, *twl = sm + 2 * lpb * L;
   load_twiddles(twl, tw, L);
   const int ngroups = (Hz + lpb - 1) / lpb;
-  const int x = blk / ngroups, lz0 = (blk % ngroups) * lpb;
+  const int x = xs ? xs[blk / ngroups] : blk / ngroups, lz0 = (blk % ngroups) * lpb;
   const int nl = min(lpb, Hz - lz0);
   const int F = N + 1;
   for (int idx = threadIdx.x; idx < nl * L; idx += FFT_THREADS) {
@@ -1257,14 +1269,18 @@ __device__ __forceinline__ void y_fwd_body(int blk, const float2 *__restrict__ H
   }
 }
 
+// xs non-null: slab x = xs[blk / ngroups]; sup non-null: only the lines
+// (x, y) with sup[x L + y] set are written (the others stay as they are).
 __device__ __forceinline__ void y_inv_body(int blk, const float2 *__restrict__ H2,
                                            float2 *__restrict__ H1, int L, int logL, int lpb,
-                                           int Hz, int N, const float2 *__restrict__ tw) {
+                                           int Hz, int N, const float2 *__restrict__ tw,
+                                           const int *__restrict__ xs = nullptr,
+                                           const uint8_t *__restrict__ sup = nullptr) {
   extern __shared__ float2 sm[];
   float2 *a = sm, *b = sm + lpb * L, *twl = sm + 2 * lpb * L;
   load_twiddles(twl, tw, L);
   const int ngroups = (Hz + lpb - 1) / lpb;
-  const int x = blk / ngroups, lz0 = (blk % ngroups) * lpb;
+  const int x = xs ? xs[blk / ngroups] : blk / ngroups, lz0 = (blk % ngroups) * lpb;
   const int nl = min(lpb, Hz - lz0);
   const int F = N + 1;
   for (int idx = threadIdx.x; idx < nl * L; idx += FFT_THREADS) a[idx] = make_float2(0.f, 0.f);
@@ -1278,16 +1294,18 @@ __device__ __forceinline__ void y_inv_body(int blk, const float2 *__restrict__ H
   lds_fft<+1>(a, b, L, logL, nl, twl);
   for (int idx = threadIdx.x; idx < nl * L; idx += FFT_THREADS) {
     const int y = idx / nl, li = idx - y * nl;
-    H1[((size_t)x * L + y) * Hz + lz0 + li] = a[li * L + y];
+    if (!sup || sup[x * L + y]) H1[((size_t)x * L + y) * Hz + lz0 + li] = a[li * L + y];
   }
 }
 
 // First axis (x): forward FFT, multiply by the filter on lx in [-N/2, N/2]
 // (zero elsewhere), inverse FFT.  Hx[x*C + c], filter[(lx + N/2)*C + c].
+// xin non-null: only the x with xin[x] set are written back.
 __device__ __forceinline__ void x_filter_body(int blk, float2 *__restrict__ Hx,
                                               const float *__restrict__ filt, int C, int L,
                                               int logL, int lpb, int N,
-                                              const float2 *__restrict__ tw) {
+                                              const float2 *__restrict__ tw,
+                                              const uint8_t *__restrict__ xin = nullptr) {
   extern __shared__ float2 sm[];
   float2 *a = sm, *b = sm + lpb * L, *twl = sm + 2 * lpb * L;
   load_twiddles(twl, tw, L);
@@ -1311,7 +1329,7 @@ __device__ __forceinline__ void x_filter_body(int blk, float2 *__restrict__ Hx,
   lds_fft<+1>(a, b, L, logL, nl, twl);
   for (int idx = threadIdx.x; idx < nl * L; idx += FFT_THREADS) {
     const int x = idx / nl, li = idx - x * nl;
-    Hx[(size_t)x * C + c0 + li] = a[li * L + x];
+    if (!xin || xin[x]) Hx[(size_t)x * C + c0 + li] = a[li * L + x];
   }
 }
 

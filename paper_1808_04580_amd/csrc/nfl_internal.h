@@ -157,6 +157,16 @@ struct nfl_plan {
   nfl::DBuf<float> grid2;       // nos^d real: c2r output, interpolation input
   bool grid_clean = false;      // `grid` is known to be zero
   nfl::DBuf<float2> spec1, spec2;
+  // d = 3: the z-lines (x, y) of the grid that some node's window touches
+  // (the padded tiles of the occupied tiles).  The spread writes and the
+  // interpolation reads only these; the FFT passes process only them, the
+  // x-slabs holding them and the spectrum entries above them; every other
+  // entry of spec1 / spec2 stays zero (spec_clean) across products.
+  nfl::DBuf<int> zs_lines;      // x * nos + y of the support lines, ascending
+  nfl::DBuf<int> zs_x;          // the x holding a support line, ascending
+  nfl::DBuf<uint8_t> zs_map;    // nos * nos line flags, then nos x flags
+  int zs_nlines = 0, zs_nx = 0;
+  bool spec_clean = false;      // spec1 / spec2 are zero off the support
 
   // degrees (sorted order)
   nfl::DBuf<float> deg;
@@ -249,7 +259,9 @@ struct VecArgs {
 
 int spread(nfl_plan *P, int in_mode, const VecArgs &a, float *grid, bool clear = true);
 // zero_in: the r2c pass sets the input grid to 0 as it reads it
-int convolve(nfl_plan *P, const float *gin, float *gout, bool zero_in = false);
+// support: the grids are the plan's own (spread and interpolation of its nodes):
+// the d = 3 passes then take only the z-line support
+int convolve(nfl_plan *P, const float *gin, float *gout, bool zero_in = false, bool support = false);
 int interp(nfl_plan *P, const float *grid, int in_mode, int out_mode, const VecArgs &a);
 // whole fast summation with the given input/output modes (grid = plan grid)
 int fastsum(nfl_plan *P, int in_mode, int out_mode, const VecArgs &a);

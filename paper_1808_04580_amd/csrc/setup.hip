@@ -471,6 +471,48 @@ int build_sorted_nodes(nfl_plan *P) {
   NFL_TRY(P->items.ensure(items.size()));
   NFL_HIP(hipMemcpyAsync(P->items.p, items.data(), items.size() * sizeof(Item),
                          hipMemcpyHostToDevice, P->stream));
+  // d = 3: the z-lines some node's window touches.  A node of cell c spreads
+  // into cells c - m + 1 .. c + m (mod nos) along each axis, so the lines of an
+  // occupied tile with origin o lie in [o - m + 1, o + T + m) along x and y.
+  P->zs_nlines = P->zs_nx = 0;
+  P->spec_clean = false;
+  if (d == 3) {
+    const int nos = P->nos, T = 1 << tshift, ntd = nos >> tshift, m = P->m;
+    std::vector<uint8_t> map((size_t)nos * nos + nos, 0);
+    for (int64_t t = 0; t < ntiles; ++t) {
+      if (hc[(size_t)t] == 0) continue;
+      const int tx = (int)(t / ((int64_t)ntd * ntd)), ty = (int)((t / ntd) % ntd);
+      for (int x = tx * T - m + 1; x < tx * T + T + m; ++x)
+        for (int y = ty * T - m + 1; y < ty * T + T + m; ++y)
+          map[(size_t)(x & (nos - 1)) * nos + (y & (nos - 1))] = 1;
+    }
+    std::vector<int> lines, xs;
+    for (int x = 0; x < nos; ++x) {
+      bool any = false;
+      for (int y = 0; y < nos; ++y)
+        if (map[(size_t)x * nos + y]) {
+          lines.push_back(x * nos + y);
+          any = true;
+        }
+      if (any) {
+        xs.push_back(x);
+        map[(size_t)nos * nos + x] = 1;
+      }
+    }
+    if (!lines.empty()) {
+      NFL_TRY(P->zs_lines.ensure(lines.size()));
+      NFL_TRY(P->zs_x.ensure(xs.size()));
+      NFL_TRY(P->zs_map.ensure(map.size()));
+      NFL_HIP(hipMemcpyAsync(P->zs_lines.p, lines.data(), lines.size() * sizeof(int),
+                             hipMemcpyHostToDevice, P->stream));
+      NFL_HIP(hipMemcpyAsync(P->zs_x.p, xs.data(), xs.size() * sizeof(int),
+                             hipMemcpyHostToDevice, P->stream));
+      NFL_HIP(hipMemcpyAsync(P->zs_map.p, map.data(), map.size(), hipMemcpyHostToDevice,
+                             P->stream));
+      P->zs_nlines = (int)lines.size();
+      P->zs_nx = (int)xs.size();
+    }
+  }
   NFL_HIP(hipStreamSynchronize(P->stream));
   return NFL_OK;
 }

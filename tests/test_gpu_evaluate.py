@@ -108,3 +108,40 @@ def test_target_plan_errors(nfl):
         P.evaluate(torch.zeros(800, device="cuda"), T)
     T.close()
     P.close()
+
+
+def test_products_around_full_transform_passes(nfl):
+    """A plan's own products run the d = 3 FFT passes on the z-lines its
+    nodes' windows touch only, keeping the rest of the spectrum zero; an
+    evaluation at other targets and a convolution of a caller's grid run the
+    full passes.  On a clustered cloud whose support leaves most lines out,
+    with targets spread over the whole ball: the targets' sums match the
+    exact trigonometric operator (1e-5), and L_s x before, between and after
+    the full passes is bitwise the same (deterministic spread)."""
+    import torch
+    d, c, N, m, eps_B, n = 3, 0.05, 32, 6, 0.0, 3000
+    v = synth.gmm(n, d=d, k=4, seed=61)
+    t = _targets(v, 700, seed=9)
+    x = synth.normal_vectors(n, seed=10)
+    xd = torch.as_tensor(x, device="cuda")
+    P = nfl.plan(torch.as_tensor(v, device="cuda"), c, N=N, m=m, eps_B=eps_B)
+    y1 = P.apply_Ls(xd).cpu().numpy()
+    T = nfl.target_plan(torch.as_tensor(t, device="cuda"), P)
+    yt = P.evaluate(xd, T).cpu().numpy().astype(np.float64)
+    y2 = P.apply_Ls(xd).cpu().numpy()
+    g = P.convolve(P.spread(xd))
+    y3 = P.apply_Ls(xd).cpu().numpy()
+    f = P.interp(g).cpu().numpy().astype(np.float64)
+    T.close()
+    P.close()
+    np.testing.assert_array_equal(y1, y2)
+    np.testing.assert_array_equal(y1, y3)
+    x64 = x.astype(np.float64)
+    c0, rho, vs = fastsum.scaling(v, eps_B)
+    vt = (t.astype(np.float64) - c0) * rho
+    b = fastsum.coefficients(c * rho, N, d, eps_B, m, "gaussian")
+    ref = fastsum.trig_operator(vs, x64, b, N, targets=vt)
+    assert np.abs(yt - ref).max() <= 1e-5 * np.abs(ref).max()
+    # the step-by-step product at the sources: the trigonometric sum itself
+    refs = fastsum.trig_operator(vs, x64, b, N)
+    assert np.abs(f - refs).max() <= 1e-5 * np.abs(refs).max()
