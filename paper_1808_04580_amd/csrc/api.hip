@@ -323,8 +323,8 @@ int nfl_set_kernel_ex(nfl_handle P, int kind, double sigma, int N, int m, double
   NFL_TRY(P->grid.ensure(2 * gsz));   // room for the int64 fixed-point grid
   NFL_TRY(P->grid2.ensure(gsz));
   P->grid_clean = false;
-  NFL_TRY(P->fx_max.ensure(1));
-  NFL_HIP(hipMemsetAsync(P->fx_max.p, 0, sizeof(unsigned), P->stream));
+  NFL_TRY(P->fx_max.ensure(FX_WORDS * FX_STRIDE));
+  NFL_HIP(hipMemsetAsync(P->fx_max.p, 0, FX_WORDS * FX_STRIDE * sizeof(unsigned), P->stream));
   {
     const double b = M_PI * 1.5, m = P->m;   // Kaiser-Bessel window at t = 0
     P->win_max = (std::sinh(b * m) / m) / (b * std::exp(b * m));

@@ -905,7 +905,7 @@ __device__ __forceinline__ void block_absmax_to(float m, unsigned *fx_max) {
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int w = 1; w < VT / 64; ++w) m = fmaxf(m, wm[w]);
-    atomicMax(fx_max, __float_as_uint(m * (1.f + 1e-6f)));
+    atomicMax(fx_max + (blockIdx.x % FX_WORDS) * FX_STRIDE, __float_as_uint(m * (1.f + 1e-6f)));
   }
 }
 
@@ -1214,7 +1214,7 @@ static int cg_core(nfl_plan *P, const Op &op, const CgWork &W, const double *f, 
   // The last direction kernel (or the start kernel, when the loop never ran a
   // product) may have left a bound for a product that was skipped; the word
   // must start from zero for the next pre-pass.
-  if (fxw) NFL_TRY(fill_f32(reinterpret_cast<float *>(fxw), 1, 0.f, s));
+  if (fxw) NFL_TRY(fill_f32(reinterpret_cast<float *>(fxw), FX_WORDS * FX_STRIDE, 0.f, s));
   // true residual with the same operator
   NFL_TRY(op(u, W.q));
   hipLaunchKernelGGL(k_cg_resid, dim3(nb), dim3(VT), 0, s, f, W.q, n, W.part);

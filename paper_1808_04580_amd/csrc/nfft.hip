@@ -432,7 +432,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_c2r_lines(const float2 *__restr
   if (stopped(stop)) return;
   // the last pass of a product clears the deterministic spread's input bound
   // for the next product's pre-pass (every reader of it has finished)
-  if (fx_reset && blockIdx.x == 0 && threadIdx.x == 0) *fx_reset = 0u;
+  if (fx_reset && blockIdx.x == 0 && threadIdx.x < FX_WORDS) fx_reset[threadIdx.x * FX_STRIDE] = 0u;
   c2r_lines_body(blockIdx.x, H, grid, nlines, L, logL, lpb, Hz, tw, lines);
 }
 
@@ -506,11 +506,11 @@ __global__ __launch_bounds__(1024) void k_fx_max(const T *__restrict__ x, int64_
   for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
   if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
   __syncthreads();
-  // one atomic per block: atomics on one address serialise, so few, large
-  // blocks (at most 64 of 1024 threads; 512 blocks of 256 took ~8 us at n = 1e6)
+  // one atomic per block, on word blockIdx mod FX_WORDS (at most 256 blocks of
+  // 1024 threads; 512 blocks of 256 on one word took ~8 us at n = 1e6)
   if (threadIdx.x == 0) {
     for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmaxf(m, wm[w]);
-    atomicMax(out, __float_as_uint(m));
+    atomicMax(fx_word(out, blockIdx.x), __float_as_uint(m));
   }
 }
 
@@ -706,7 +706,7 @@ static int fx_prepass(nfl_plan *P, int in_mode, const VecArgs &a) {
     factor = 1.01 / std::sqrt(std::max(P->dmin, 1e-300));
   P->fx_mult = (float)(1.0625 * factor * (double)P->n * std::pow(1.01 * P->win_max, P->d));
   if (a.fx_ready) return NFL_OK;   // the producer of the input wrote its bound
-  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(64, (P->n + 16383) / 16384));
+  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(256, (P->n + 4095) / 4096));
   if (in_mode == IN_ONES) {
     hipLaunchKernelGGL(k_fx_max<float>, dim3(1), dim3(64), 0, P->stream, (const float *)nullptr,
                        (int64_t)0, P->fx_max.p, P->stop);

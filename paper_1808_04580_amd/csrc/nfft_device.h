@@ -75,8 +75,22 @@ __device__ __forceinline__ void grid_add(float *grid, size_t idx, float v, doubl
     unsafeAtomicAdd(grid + idx, v);
 }
 
+// The bound is kept as FX_WORDS words FX_STRIDE apart: a producer block b
+// takes word b mod FX_WORDS for its atomic maximum (atomics on one address
+// serialise, ~10 ns each), readers take the maximum of the words.
+__device__ __forceinline__ unsigned *fx_word(unsigned *w, int block) {
+  return w + (block % FX_WORDS) * FX_STRIDE;
+}
+
+__device__ __forceinline__ unsigned fx_bits(const unsigned *w) {
+  unsigned v = 0;
+#pragma unroll
+  for (int k = 0; k < FX_WORDS; ++k) v = max(v, w[k * FX_STRIDE]);
+  return v;
+}
+
 __device__ __forceinline__ double fx_of(const KArgs &ka) {
-  return ka.fx_max ? fx_scale(*ka.fx_max, ka.fx_mult) : 0.0;
+  return ka.fx_max ? fx_scale(fx_bits(ka.fx_max), ka.fx_mult) : 0.0;
 }
 
 // Uniform early exit of a product's kernels once an iterative solver on the
@@ -1170,7 +1184,7 @@ __device__ __forceinline__ void r2c_lines_body(int blk, float *__restrict__ grid
   const int nl = min(lpb, nlines - l0), npp = (nl + 1) >> 1;
   auto line = [&](int li) { return lines ? lines[l0 + li] : l0 + li; };
   if (fx_max) {
-    const double inv = 1.0 / fx_scale(*fx_max, fx_mult);   // a power of 2: exact
+    const double inv = 1.0 / fx_scale(fx_bits(fx_max), fx_mult);   // a power of 2: exact
     for (int idx = threadIdx.x; idx < npp * L; idx += FFT_THREADS) {
       const int pl = idx / L, j = idx - pl * L;
       const bool two = 2 * pl + 1 < nl;

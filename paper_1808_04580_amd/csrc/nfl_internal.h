@@ -146,7 +146,9 @@ struct nfl_plan {
   nfl::DBuf<double> deg64, dinv64, filt64;
   nfl::DBuf<double2> tw64;
   nfl::DBuf<double> v64;        // 2 n FP64: sorted in/out of nfl_apply_A64
-  nfl::DBuf<unsigned> fx_max;   // bits of max |input| of the current product (pre-pass; reset by c2r)
+  // bits of max |input| of the current product (pre-pass; reset by c2r), as
+  // the maximum of FX_WORDS words FX_STRIDE apart
+  nfl::DBuf<unsigned> fx_max;
   float fx_mult = 0.f;          // grid values <= max |input| * fx_mult (set by the spread launch)
   double win_max = 0;           // largest window value (psi(0))
   int opt_restarts = 0;         // thick restarts of nfl_lanczos_smallest (0: none)
@@ -245,6 +247,9 @@ enum OutMode {
   OUT_SORTED_F64_A = 5, // y64[i] = dinv (f - xt), xt = (float)(dinv x64)
   OUT_SORTED_F64_SSL = 6, // y64[i] = x64 + tau (x64 - dinv (f - xt))
 };
+
+// words of the deterministic spread's input bound (128 bytes apart)
+constexpr int FX_WORDS = 8, FX_STRIDE = 32;
 
 struct VecArgs {
   // the input's bound for the deterministic spread is already in the plan's
