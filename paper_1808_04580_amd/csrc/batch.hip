@@ -41,6 +41,11 @@ struct BJob {
   int64_t xoff;   // offset of this job's vector in the packed x / y
   int nos, N, tshift, logL;
   int lpz, lpy, lpx, pad;   // FFT lines per workgroup: z (real lines), y and x passes
+  // the plan's z-line support (null: every line): lines, x-slabs, flags
+  const int *zl;
+  const int *zx;
+  const uint8_t *zmap;
+  int nzl, nzx;
 };
 
 struct BItem {
@@ -140,13 +145,13 @@ enum { FFT_R2C = 0, FFT_YF = 1, FFT_XF = 2, FFT_YI = 3, FFT_C2R = 4, FFT_STAGES 
 // Workgroups one job needs in each FFT pass.  As the single-plan convolution,
 // except for the x pass: with many jobs in flight, its workgroups take full
 // FFT_ELEMS / L columns instead of splitting one grid finely.
-static int fft_blocks(int stage, int L, int N) {
+static int fft_blocks(int stage, int L, int N, int nzl, int nzx) {
   const int Hz = N / 2 + 1, F = N + 1;
   switch (stage) {
     case FFT_R2C:
-    case FFT_C2R: return (L * L + fft_lpb_zr(L) - 1) / fft_lpb_zr(L);
+    case FFT_C2R: return (nzl + fft_lpb_zr(L) - 1) / fft_lpb_zr(L);
     case FFT_YF:
-    case FFT_YI: return L * ((Hz + fft_lpb_y(L) - 1) / fft_lpb_y(L));
+    case FFT_YI: return nzx * ((Hz + fft_lpb_y(L) - 1) / fft_lpb_y(L));
     default: return (F * Hz + fft_lpb_z(L) - 1) / fft_lpb_z(L);
   }
 }
@@ -162,16 +167,18 @@ __global__ __launch_bounds__(FFT_THREADS) void kb_fft(const int *__restrict__ fi
   const BJob &J = jobs[j];
   const int lb = blk - __builtin_amdgcn_readfirstlane(first[j]);
   const int L = J.nos, N = J.N, Hz = N / 2 + 1;
+  // passes on the plan's z-line support (the spectra are zero off it)
   if constexpr (STAGE == FFT_R2C)
-    r2c_lines_body<true>(lb, J.grid, J.spec1, L * L, L, J.logL, J.lpz, Hz, J.tw);
+    r2c_lines_body<true>(lb, J.grid, J.spec1, J.nzl, L, J.logL, J.lpz, Hz, J.tw, nullptr, 0.f, J.zl);
   else if constexpr (STAGE == FFT_YF)
-    y_fwd_body(lb, J.spec1, J.spec2, L, J.logL, J.lpy, Hz, N, J.tw);
+    y_fwd_body(lb, J.spec1, J.spec2, L, J.logL, J.lpy, Hz, N, J.tw, J.zx);
   else if constexpr (STAGE == FFT_XF)
-    x_filter_body(lb, J.spec2, J.filt, (N + 1) * Hz, L, J.logL, J.lpx, N, J.tw);
+    x_filter_body(lb, J.spec2, J.filt, (N + 1) * Hz, L, J.logL, J.lpx, N, J.tw,
+                  J.zmap ? J.zmap + (size_t)L * L : nullptr);
   else if constexpr (STAGE == FFT_YI)
-    y_inv_body(lb, J.spec2, J.spec1, L, J.logL, J.lpy, Hz, N, J.tw);
+    y_inv_body(lb, J.spec2, J.spec1, L, J.logL, J.lpy, Hz, N, J.tw, J.zx, J.zmap);
   else
-    c2r_lines_body(lb, J.spec1, J.grid2, L * L, L, J.logL, J.lpz, Hz, J.tw);
+    c2r_lines_body(lb, J.spec1, J.grid2, J.nzl, L, J.logL, J.lpz, Hz, J.tw, J.zl);
 }
 
 // The spread or interpolation launches of all jobs of one window width W and
@@ -374,8 +381,11 @@ static int batch_build(nfl_batch_s *B) {
   NFL_TRY(B->spec2.ensure((size_t)s2sum));
   B->grid_elems = gsum;
   B->arena_bytes = 2 * gsum * 4 + (s1sum + s2sum) * 8;
-  // the spread grids start clear; every replay leaves them clear again
+  // the spread grids start clear; every replay leaves them clear again.  The
+  // spectra are zero off each plan's z-line support, which no pass writes.
   NFL_TRY(fill_f32(B->grids.p, gsum, 0.f, B->stream));
+  NFL_TRY(fill_f32(reinterpret_cast<float *>(B->spec1.p), 2 * s1sum, 0.f, B->stream));
+  NFL_TRY(fill_f32(reinterpret_cast<float *>(B->spec2.p), 2 * s2sum, 0.f, B->stream));
   NFL_HIP(hipStreamSynchronize(B->stream));
 
   for (int g = 0; g < np; ++g) {
@@ -405,6 +415,12 @@ static int batch_build(nfl_batch_s *B) {
       J.lpz = fft_lpb_zr(P->nos);
       J.lpy = fft_lpb_y(P->nos);
       J.lpx = fft_lpb_z(P->nos);
+      const bool sup = P->zs_nlines > 0;
+      J.zl = sup ? P->zs_lines.p : nullptr;
+      J.zx = sup ? P->zs_x.p : nullptr;
+      J.zmap = sup ? P->zs_map.p : nullptr;
+      J.nzl = sup ? P->zs_nlines : P->nos * P->nos;
+      J.nzx = sup ? P->zs_nx : P->nos;
     }
   }
 
@@ -478,7 +494,7 @@ static int batch_build(nfl_batch_s *B) {
     int64_t acc = 0;
     for (int q = 0; q < B->njobs; ++q) {
       hf[(size_t)st * (B->njobs + 1) + q] = (int)acc;
-      acc += fft_blocks(st, hj[q].nos, hj[q].N);
+      acc += fft_blocks(st, hj[q].nos, hj[q].N, hj[q].nzl, hj[q].nzx);
     }
     if (acc > 0x7fffffff) { set_error("batch: FFT grid too large"); return NFL_ERR_UNSUPPORTED; }
     hf[(size_t)st * (B->njobs + 1) + B->njobs] = (int)acc;
