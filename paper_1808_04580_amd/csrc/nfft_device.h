@@ -1002,11 +1002,16 @@ __device__ __forceinline__ void interp3_tile_body(const Item *__restrict__ items
       cnt = min(16, min(run, bcnt - pos));
       if (lz0 != cur_lz) {
         cur_lz = lz0;
+        // rows c16 >= P read row P - 1 and are zeroed by a select (a
+        // conditional read per element costs an exec-mask save and restore)
+        const float *trow = tile + min(c16, P - 1) * XS + lz0 + p4;
 #pragma unroll
         for (int y = 0; y < P; ++y)
 #pragma unroll
-          for (int zq = 0; zq < ZQ; ++zq)
-            g[y * ZQ + zq] = c16 < P ? tile[c16 * XS + y * 16 + lz0 + 4 * zq + p4] : 0.f;
+          for (int zq = 0; zq < ZQ; ++zq) {
+            const float v = trow[y * 16 + 4 * zq];
+            g[y * ZQ + zq] = c16 < P ? v : 0.f;
+          }
       }
       const int i0 = b0 + pos;
       const OutPre op = pre_from<OUT>(ob, pos + c16);
