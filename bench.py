@@ -687,13 +687,20 @@ def main():
         fs = [torch.as_tensor(synth.ssl_rhs(labt, c, frac=0.02, seed=200000 + c), device=dev)
               for c in range(3)]
         Pt.cg_solve(fs[0], tau=TAU, tol=1e-6, maxit=5)   # warm the path
+
+        def true_relres(f, u):
+            # ||f - (I + tau L_s) u|| / ||f|| with the solver's operator
+            # (L_s u = u - A_E u, FP64 vectors), after the timed solve
+            Mu = u + TAU * (u - Pt.apply_A64(u))
+            return (torch.linalg.vector_norm(f - Mu) / torch.linalg.vector_norm(f)).item()
+
         res = {"plain": [], "learned": []}
         for c, f in enumerate(fs):
             torch.cuda.synchronize()
             t0 = time.time()
-            r0 = Pt.cg_solve(f, tau=TAU, tol=1e-6, maxit=500)
+            r0 = Pt.cg_solve(f, tau=TAU, tol=1e-6, maxit=500, true_residual=False)
             torch.cuda.synchronize()
-            res["plain"].append((r0["iters"], (time.time() - t0) * 1e3, r0["relres"]))
+            res["plain"].append((r0["iters"], (time.time() - t0) * 1e3, true_relres(f, r0["u"])))
             if net is not None:
                 # initial relative residual of the learned start (u0 = 0 starts at 1)
                 u0 = net.predict(Pt, f, c)
@@ -703,9 +710,11 @@ def main():
                 net.attach(Pt, c)
                 torch.cuda.synchronize()
                 t0 = time.time()
-                r1 = Pt.cg_solve(f, tau=TAU, tol=1e-6, maxit=500, warm=nfl.WARM_MLP)
+                r1 = Pt.cg_solve(f, tau=TAU, tol=1e-6, maxit=500, warm=nfl.WARM_MLP,
+                                 true_residual=False)
                 torch.cuda.synchronize()
-                res["learned"].append((r1["iters"], (time.time() - t0) * 1e3, r1["relres"]))
+                res["learned"].append((r1["iters"], (time.time() - t0) * 1e3,
+                                       true_relres(f, r1["u"])))
                 du = (r1["u"] - r0["u"]).abs().max().item() / r0["u"].abs().max().item()
                 res.setdefault("rel_diff_solution", []).append(du)
 
@@ -715,12 +724,16 @@ def main():
             return {"iters": [r[0] for r in rs], "ms": [round(r[1], 2) for r in rs],
                     "mean_iters": float(np.mean([r[0] for r in rs])),
                     "mean_ms": round(float(np.mean([r[1] for r in rs])), 3),
-                    # call to return over iterations (includes the final true-residual
-                    # product and, for the learned start, the network and its product)
+                    # call to return over iterations (the solve to its stopping
+                    # test; for the learned start also the network and the product
+                    # of its residual); the true residual is recomputed after the
+                    # timed call
                     "ms_per_iter": round(float(np.sum([r[1] for r in rs]) /
                                                max(1, np.sum([r[0] for r in rs]))), 4),
                     "max_true_relres": float(max(r[2] for r in rs))}
         cg = {"tau": TAU, "tol": 1e-6, "cloud_seed": 100001,
+              "timed": "nfl_cg_solve to its stopping test (recurrence residual <= tol); "
+                       "max_true_relres recomputed after the timed call",
               "rhs": "one-vs-rest, 2% labelled, classes 0..2",
               "plain": summ(res["plain"]), "learned": summ(res["learned"]),
               "initial_relres": {"plain": 1.0, "learned": res.get("learned_initial_relres")},

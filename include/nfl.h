@@ -235,7 +235,8 @@ int nfl_nystrom(nfl_handle h, const double *G_dev, int64_t ldg, int L, int M, in
  * FP64 vectors and inner products, FP32 NFFT matvecs.  Stops when the
  * recurrence residual ||r|| / ||f|| <= tol or after maxit iterations; relres
  * (host, may be NULL) is the TRUE residual ||f - (I + tau L_s) u|| / ||f||
- * recomputed at the end with the same operator.  f_dev, u_dev: n doubles in
+ * recomputed at the end with the same operator (one more product; with
+ * relres NULL that product is skipped).  f_dev, u_dev: n doubles in
  * caller order.  warm: NFL_WARM_ZERO (u0 = 0), NFL_WARM_USER (u0 read from
  * u_dev), NFL_WARM_MLP (u0 from the plan's warm-start network, see
  * nfl_mlp_*).  The iteration runs on the device: the step lengths and the
@@ -272,7 +273,7 @@ int nfl_cg_solve_noalloc(nfl_handle h, double tau, const double *f_dev, double *
  * the scalar K(0) + beta here, so plain CG is run.  FP64 vectors in caller
  * order, FP32 NFFT products.  Stops when the recurrence residual
  * ||r|| / ||f|| <= tol or after maxit iterations; relres (host, may be NULL)
- * is the true residual recomputed with the same operator.  f_dev, alpha_dev:
+ * is the true residual recomputed with the same operator (skipped when NULL).  f_dev, alpha_dev:
  * n doubles; warm: NFL_WARM_ZERO (alpha0 = 0) or NFL_WARM_USER (alpha0 read
  * from alpha_dev).  The prediction at the training points is
  * K alpha = nfl_apply_W(alpha) + K(0) alpha.  Synchronises. */

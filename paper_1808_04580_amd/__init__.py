@@ -350,7 +350,10 @@ class Plan:
                     m_used=mu.value)
 
     def cg_solve(self, f, tau: float, tol: float = 1e-6, maxit: int = 1000,
-                 warm: int = WARM_ZERO, u0=None):
+                 warm: int = WARM_ZERO, u0=None, true_residual: bool = True):
+        """nfl_cg_solve.  true_residual=False passes no relres pointer: the
+        closing product that recomputes the true residual is skipped and
+        the result's relres is None."""
         torch = self._torch
         f = torch.as_tensor(f, dtype=torch.float64, device=self.device).contiguous()
         if u0 is not None:
@@ -362,8 +365,10 @@ class Plan:
         rel = ctypes.c_double()
         code = _check(lib().nfl_cg_solve(self._h, float(tau), _ptr(f), _ptr(u), int(warm),
                                          float(tol), int(maxit), ctypes.byref(it),
-                                         ctypes.byref(rel)), "nfl_cg_solve", allow_soft=True)
-        return dict(u=u, iters=it.value, relres=rel.value, converged=(code == NFL_OK))
+                                         ctypes.byref(rel) if true_residual else None),
+                      "nfl_cg_solve", allow_soft=True)
+        return dict(u=u, iters=it.value, relres=rel.value if true_residual else None,
+                    converged=(code == NFL_OK))
 
     def cg_solve_noalloc(self, f, u, tau: float, tol: float = 1e-6, maxit: int = 1000,
                          warm: int = WARM_ZERO):

@@ -1215,11 +1215,14 @@ static int cg_core(nfl_plan *P, const Op &op, const CgWork &W, const double *f, 
   // product) may have left a bound for a product that was skipped; the word
   // must start from zero for the next pre-pass.
   if (fxw) NFL_TRY(fill_f32(reinterpret_cast<float *>(fxw), FX_WORDS * FX_STRIDE, 0.f, s));
-  // true residual with the same operator
-  NFL_TRY(op(u, W.q));
-  hipLaunchKernelGGL(k_cg_resid, dim3(nb), dim3(VT), 0, s, f, W.q, n, W.part);
-  hipLaunchKernelGGL(k_cg_final, dim3(1), dim3(VT), 0, s, W.part, nb, W.sc);
-  NFL_HIP(hipGetLastError());
+  // the true residual with the same operator, when the caller asks for it
+  // (one more product: a verification, not part of the iteration)
+  if (relres) {
+    NFL_TRY(op(u, W.q));
+    hipLaunchKernelGGL(k_cg_resid, dim3(nb), dim3(VT), 0, s, f, W.q, n, W.part);
+    hipLaunchKernelGGL(k_cg_final, dim3(1), dim3(VT), 0, s, W.part, nb, W.sc);
+    NFL_HIP(hipGetLastError());
+  }
   double h[8];
   int st[2];
   NFL_HIP(hipMemcpyAsync(h, W.sc, sizeof(h), hipMemcpyDeviceToHost, s));

@@ -276,6 +276,11 @@ def test_cg_matches_dense_solve(nfl):
     # warm start from the solution converges immediately; user warm start honoured
     r2 = P.cg_solve(tt(f), tau=10.0, tol=1e-6, maxit=500, u0=r["u"])
     assert r2["iters"] <= 1
+    # without the closing true-residual product: the same iterations and
+    # bitwise the same solution (the solve is deterministic), no residual
+    r3 = P.cg_solve(tt(f), tau=10.0, tol=1e-8, maxit=500, true_residual=False)
+    assert r3["relres"] is None and r3["converged"] and r3["iters"] == r["iters"]
+    np.testing.assert_array_equal(host(r3["u"]), u)
 
 
 def test_error_paths(nfl):
