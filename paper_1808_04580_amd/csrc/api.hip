@@ -341,6 +341,7 @@ int nfl_set_kernel_ex(nfl_handle P, int kind, double sigma, int N, int m, double
   NFL_TRY(build_sorted_nodes(P));
   NFL_TRY(P->deg.ensure(P->n));
   NFL_TRY(P->dinv.ensure(P->n));
+  NFL_TRY(P->xs32.ensure(P->n));
   P->prec = 32;
   if (P->opt_prec == 64) {
     NFL_TRY(setup64(P));

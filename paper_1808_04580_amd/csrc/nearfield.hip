@@ -276,6 +276,8 @@ int near_field(nfl_plan *P, int in_mode, int out_mode, const VecArgs &a) {
   k.deg_out = P->deg.p;
   k.dinv_out = P->dinv.p;
   k.stop = P->stop;
+  k.fx_max = nullptr;
+  k.xs = nullptr;
   if (in_mode == IN_USER_F32 && out_mode == OUT_USER_RAW) return launch_near<IN_USER_F32, OUT_USER_RAW>(P, k);
   if (in_mode == IN_USER_F32 && out_mode == OUT_USER_W) return launch_near<IN_USER_F32, OUT_USER_W>(P, k);
   if (in_mode == IN_USER_F32_DINV && out_mode == OUT_USER_LS) return launch_near<IN_USER_F32_DINV, OUT_USER_LS>(P, k);

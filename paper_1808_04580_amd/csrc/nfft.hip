@@ -557,6 +557,7 @@ static KArgs make_kargs(nfl_plan *P, const VecArgs &a) {
   k.stop = P->stop;
   k.fx_max = nullptr;
   k.fx_mult = 0.f;
+  k.xs = a.xs;
   return k;
 }
 
@@ -850,8 +851,21 @@ int convolve(nfl_plan *P, const float *gin_c, float *gout, bool zero_in, bool su
 // Two grids: the spread accumulates into `grid`, which the r2c pass reads and
 // leaves zero for the next product (so no separate clear once it is clean);
 // the c2r pass writes `grid2`, which the interpolation reads.
-int fastsum(nfl_plan *P, int in_mode, int out_mode, const VecArgs &a) {
-  if (P->prec == 64) return fastsum64(P, in_mode, out_mode, a);
+// Both tile-stationary forms run (d = 3, default kernels, T + 2m - 1 <= 16).
+static bool tile_forms(const nfl_plan *P) {
+  const int T = 1 << P->tshift, W = 2 * P->m;
+  return P->d == 3 && P->opt_kernel == 0 && ((T == 4 && W + 3 <= 16) || (T == 8 && W + 7 <= 16));
+}
+
+int fastsum(nfl_plan *P, int in_mode, int out_mode, const VecArgs &a_in) {
+  if (P->prec == 64) return fastsum64(P, in_mode, out_mode, a_in);
+  VecArgs a = a_in;
+  // the output step needs the caller-order input: the tile spread leaves a
+  // sorted copy of it for the tile interpolation
+  if ((in_mode == IN_USER_F32 || in_mode == IN_USER_F32_DINV) && a.x32 &&
+      (out_mode == OUT_USER_W || out_mode == OUT_USER_LS || out_mode == OUT_USER_A) &&
+      tile_forms(P) && P->xs32.p)
+    a.xs = P->xs32.p;
   if (P->prof_ev) NFL_HIP(hipEventRecord(P->prof_ev[0], P->stream));
   const bool clear = !P->grid_clean;
   P->grid_clean = false;

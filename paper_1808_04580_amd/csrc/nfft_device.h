@@ -48,6 +48,10 @@ struct KArgs {
   // max |input| * fx_mult (see fx_scale)
   const unsigned *fx_max;
   float fx_mult;
+  // non-null: the tile spread stores the caller-order input in sorted order
+  // here (xs[i] = x[perm[i]]), and the tile interpolation's output step reads
+  // it back instead of gathering x through the permutation again
+  float *xs;
 };
 
 // Deterministic spread: the plan's grid holds int64 fixed-point values
@@ -164,6 +168,8 @@ __device__ __forceinline__ void pre_index(const KArgs &a, int i, bool ok, OutPre
   p.xd = 0.0;
   if (!ok) return;
   if constexpr (pre_user<OUT>()) p.j = a.perm[i];
+  if constexpr (OUT == OUT_USER_W || OUT == OUT_USER_LS || OUT == OUT_USER_A)
+    if (a.xs) p.xu = a.xs[i];   // coalesced, no dependent gather
   if constexpr (OUT == OUT_USER_LS || OUT == OUT_USER_A || OUT == OUT_SORTED_F64_A ||
                 OUT == OUT_SORTED_F64_SSL)
     p.di = a.dinv[i];
@@ -173,7 +179,7 @@ __device__ __forceinline__ void pre_index(const KArgs &a, int i, bool ok, OutPre
 template <int OUT>
 __device__ __forceinline__ void pre_gather(const KArgs &a, bool ok, OutPre &p) {
   if constexpr (OUT == OUT_USER_W || OUT == OUT_USER_LS || OUT == OUT_USER_A) {
-    if (ok) p.xu = a.x32[p.j];
+    if (ok && !a.xs) p.xu = a.x32[p.j];
   }
 }
 
@@ -326,8 +332,15 @@ __device__ __forceinline__ void load_batch(const float4 *__restrict__ pts, const
   qb = make_float4(0.f, 0.f, 0.f, 0.f);
   xb = 0.f;
   if (i0 + lane < e) {
-    qb = pts[i0 + lane];
-    if (WITH_X) xb = load_in<IN>(ka, i0 + lane);
+    const int i = i0 + lane;
+    qb = pts[i];
+    if constexpr (WITH_X && (IN == IN_USER_F32 || IN == IN_USER_F32_DINV)) {
+      const float raw = ka.x32[ka.perm[i]];
+      if (ka.xs) ka.xs[i] = raw;
+      xb = IN == IN_USER_F32_DINV ? ka.dinv[i] * raw : raw;
+    } else if constexpr (WITH_X) {
+      xb = load_in<IN>(ka, i);
+    }
   }
 }
 

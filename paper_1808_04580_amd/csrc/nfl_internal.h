@@ -159,6 +159,7 @@ struct nfl_plan {
   nfl::DBuf<float> grid2;       // nos^d real: c2r output, interpolation input
   bool grid_clean = false;      // `grid` is known to be zero
   nfl::DBuf<float2> spec1, spec2;
+  nfl::DBuf<float> xs32;        // n: the product's input in sorted order (tile forms)
   // d = 3: the z-lines (x, y) of the grid that some node's window touches
   // (the padded tiles of the occupied tiles).  The spread writes and the
   // interpolation reads only these; the FFT passes process only them, the
@@ -255,6 +256,9 @@ struct VecArgs {
   // the input's bound for the deterministic spread is already in the plan's
   // fx_max word (written by the kernel that produced the input)
   bool fx_ready = false;
+  // the tile spread stores the caller-order input in sorted order here for
+  // the tile interpolation's output step (null: it gathers x again)
+  float *xs = nullptr;
   const float *x32 = nullptr;   // caller order
   float *y32 = nullptr;         // caller order
   const double *x64 = nullptr;  // sorted order
