@@ -184,6 +184,34 @@ def test_operators_match_exact_trig_operator(nfl, d, n, sigma, N, m, eps_B):
     assert np.abs(yL - refL).max() <= 1e-5 * np.abs(refL).max()
 
 
+@pytest.mark.parametrize("m,tile,kernel", [
+    (6, 4, 0),    # tile-stationary spread and interpolation (the default form)
+    (4, 8, 0),    # tile-stationary, 8-cell tiles
+    (6, 8, 0),    # padded tile 19 > 16: per-cell runs on the matrix cores
+    (6, 4, 2),    # per-cell runs forced
+    (6, 4, 1),    # vector ALU
+])
+def test_operators_across_tile_sizes_and_kernel_forms(nfl, m, tile, kernel):
+    """Products of a plan's own nodes take the FFT passes on the z-lines its
+    nodes' windows touch; the support is built from the tile size and m, and
+    every kernel form must write and read inside it.  Degrees, W x and L_s x
+    against the exact trigonometric operator (1e-5) for each form, on a
+    clustered cloud whose support leaves lines out."""
+    n, sigma, N = 2500, 0.06, 16
+    v = synth.gmm(n, d=3, k=3, seed=37)
+    P = make(nfl, v, sigma, N, m, 0.0, tile, None, kernel)
+    TG = fastsum.TrigGraph(v, sigma, N, 0.0, m)
+    x = synth.normal_vectors(n, seed=5).astype(np.float64)
+    d_gpu = host(P.degree()).astype(np.float64)
+    assert np.abs(d_gpu - TG.d).max() <= 1e-5 * np.abs(TG.d).max()
+    yW = host(P.apply_W(tt(x.astype(np.float32)))).astype(np.float64)
+    refW = TG.apply_W(x)
+    assert np.abs(yW - refW).max() <= 1e-5 * np.abs(refW).max()
+    yL = host(P.apply_Ls(tt(x.astype(np.float32)))).astype(np.float64)
+    refL = TG.apply_Ls(x)
+    assert np.abs(yL - refL).max() <= 1e-5 * np.abs(refL).max()
+
+
 def test_blobs2d_full_config_vs_direct_oracle(nfl):
     """The small workload: n = 5000 two blobs in 2-D, sigma = 0.05, eps_B = 1/16,
     m = 4.  At N = 32 the kernel approximation alone leaves ~1e-5 relative
