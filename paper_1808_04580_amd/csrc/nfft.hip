@@ -247,23 +247,36 @@ void k_interp3_mfma(const Item *__restrict__ items,
   interp3_mfma_body<W, IN, OUT>(items, blockIdx.x, pts, ka, grid, nos, tshift, wcoef);
 }
 
-// Tile-stationary forms (T + W - 1 <= 16), one workgroup per item.  Both run
-// three waves per SIMD: within the register budget that allows (168 per lane)
-// they keep their accumulators in VGPRs, without spills.
+// Tile-stationary forms (T + W - 1 <= 16), one workgroup per group of
+// segments (the plan's gitems / goff): the segments of a group are taken one
+// after the other, each with its own tile staging (interpolation) or flush
+// (spread); the barrier between two frees the LDS of the previous one.  The
+// spread keeps its accumulators in VGPRs without spills within the register
+// budget of three waves per SIMD (168 per lane); it uses 112, so four fit.
 template <int W, int T, int IN>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
-void k_spread3_tile(const Item *__restrict__ items, const float4 *__restrict__ pts, KArgs ka,
-                    float *__restrict__ grid, int nos, const float *__restrict__ wcoef) {
+void k_spread3_tile(const Item *__restrict__ items, const int *__restrict__ goff,
+                    const float4 *__restrict__ pts, KArgs ka, float *__restrict__ grid, int nos,
+                    const float *__restrict__ wcoef) {
   if (stopped(ka.stop)) return;
-  spread3_tile_body<W, T, IN>(items[blockIdx.x], pts, ka, grid, nos, wcoef);
+  const int g0 = goff[blockIdx.x], g1 = goff[blockIdx.x + 1];
+  for (int it = g0; it < g1; ++it) {
+    if (it > g0) __syncthreads();
+    spread3_tile_body<W, T, IN>(items[it], pts, ka, grid, nos, wcoef);
+  }
 }
 
 template <int W, int T, int IN, int OUT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
-void k_interp3_tile(const Item *__restrict__ items, const float4 *__restrict__ pts, KArgs ka,
-                    const float *__restrict__ grid, int nos, const float *__restrict__ wcoef) {
+void k_interp3_tile(const Item *__restrict__ items, const int *__restrict__ goff,
+                    const float4 *__restrict__ pts, KArgs ka, const float *__restrict__ grid,
+                    int nos, const float *__restrict__ wcoef) {
   if (stopped(ka.stop)) return;
-  interp3_tile_body<W, T, IN, OUT>(items, blockIdx.x, pts, ka, grid, nos, wcoef);
+  const int g0 = goff[blockIdx.x], g1 = goff[blockIdx.x + 1];
+  for (int it = g0; it < g1; ++it) {
+    if (it > g0) __syncthreads();
+    interp3_tile_body<W, T, IN, OUT>(items, it, pts, ka, grid, nos, wcoef);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -602,22 +615,69 @@ static size_t tile_form_lds(int W, int T, bool spread) {
 
 template <int W, int T, int IN>
 static int launch_spread3_tile(nfl_plan *P, const KArgs &k, float *grid) {
+  if (P->ngroups <= 0) {
+    set_error("spread: the plan has no work groups for the tile-stationary form");
+    return NFL_ERR_ORDER;
+  }
   const size_t lds = tile_form_lds(W, T, true);
   NFL_TRY(set_lds(k_spread3_tile<W, T, IN>, lds));
-  hipLaunchKernelGGL((k_spread3_tile<W, T, IN>), dim3(P->nitems), dim3(256), lds, P->stream,
-                     P->items.p, P->pts.p, k, grid, P->nos, P->wcoef.p);
+  hipLaunchKernelGGL((k_spread3_tile<W, T, IN>), dim3(P->ngroups), dim3(256), lds, P->stream,
+                     P->gitems.p, P->goff.p, P->pts.p, k, grid, P->nos, P->wcoef.p);
   NFL_HIP(hipGetLastError());
   return NFL_OK;
 }
 
 template <int W, int T, int IN, int OUT>
 static int launch_interp3_tile(nfl_plan *P, const KArgs &k, const float *grid) {
+  if (P->ngroups <= 0) {
+    set_error("interp: the plan has no work groups for the tile-stationary form");
+    return NFL_ERR_ORDER;
+  }
   const size_t lds = tile_form_lds(W, T, false);
   NFL_TRY(set_lds(k_interp3_tile<W, T, IN, OUT>, lds));
-  hipLaunchKernelGGL((k_interp3_tile<W, T, IN, OUT>), dim3(P->nitems), dim3(256), lds, P->stream,
-                     P->items.p, P->pts.p, k, grid, P->nos, P->wcoef.p);
+  hipLaunchKernelGGL((k_interp3_tile<W, T, IN, OUT>), dim3(P->ngroups), dim3(256), lds,
+                     P->stream, P->gitems.p, P->goff.p, P->pts.p, k, grid, P->nos, P->wcoef.p);
   NFL_HIP(hipGetLastError());
   return NFL_OK;
+}
+
+// Workgroups of both tile-stationary kernels (window W, tile T) that one CU
+// holds at once (the smaller of the two), times the CUs.
+// (One per CU if the occupancy query fails: correct, with fewer groups.)
+template <int W, int T>
+static int tile_slots_wt(int cus) {
+  int a = 0, b = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_spread3_tile<W, T, IN_USER_F32_DINV>, 256,
+                                                   tile_form_lds(W, T, true)) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_interp3_tile<W, T, IN_USER_F32, OUT_USER_LS>,
+                                                   256, tile_form_lds(W, T, false)) != hipSuccess) {
+    (void)hipGetLastError();
+    return cus;
+  }
+  return cus * std::max(1, std::min(a, b));
+}
+
+int tile_group_slots(const nfl_plan *P) {
+  if (P->d != 3) return 0;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0) {
+    (void)hipGetLastError();
+    cus = 1;
+  }
+  const int T = 1 << P->tshift;
+  switch (T * 100 + 2 * P->m) {
+    case 404: return tile_slots_wt<4, 4>(cus);
+    case 406: return tile_slots_wt<6, 4>(cus);
+    case 408: return tile_slots_wt<8, 4>(cus);
+    case 410: return tile_slots_wt<10, 4>(cus);
+    case 412: return tile_slots_wt<12, 4>(cus);
+    case 804: return tile_slots_wt<4, 8>(cus);
+    case 806: return tile_slots_wt<6, 8>(cus);
+    case 808: return tile_slots_wt<8, 8>(cus);
+    default: return 0;
+  }
 }
 
 template <int W, int IN>

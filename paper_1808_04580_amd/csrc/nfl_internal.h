@@ -131,6 +131,13 @@ struct nfl_plan {
   nfl::DBuf<nfl::Item> items;
   int nitems = 0;
   int max_item_len = 0;
+  // the tile-stationary forms' work: the sorted nodes cut into ngroups groups
+  // of near-equal cost, at most one per workgroup the GPU holds at once; group
+  // g is the segments gitems[goff[g] .. goff[g + 1]), each the nodes of one
+  // tile inside the group (contiguous in the sort)
+  nfl::DBuf<nfl::Item> gitems;
+  nfl::DBuf<int> goff;
+  int ngroups = 0;
 
   // FFT / filter
   nfl::DBuf<float> wcoef;       // window polynomials, WIN_MAXW x WIN_NC
@@ -270,6 +277,9 @@ int spread(nfl_plan *P, int in_mode, const VecArgs &a, float *grid, bool clear =
 // zero_in: the r2c pass sets the input grid to 0 as it reads it
 // support: the grids are the plan's own (spread and interpolation of its nodes):
 // the d = 3 passes then take only the z-line support
+// workgroups of the tile-stationary forms that the GPU holds at once for the
+// plan's window and tile (0 where those forms do not apply)
+int tile_group_slots(const nfl_plan *P);
 int convolve(nfl_plan *P, const float *gin, float *gout, bool zero_in = false, bool support = false);
 int interp(nfl_plan *P, const float *grid, int in_mode, int out_mode, const VecArgs &a);
 // whole fast summation with the given input/output modes (grid = plan grid)

@@ -354,6 +354,55 @@ __global__ __launch_bounds__(256) void k_tile_ends(const uint32_t *__restrict__ 
   if (i + 1 == n || (keys[i + 1] >> shift) != t) end[t] = (uint32_t)(i + 1);
 }
 
+// The tile-stationary forms' work: the sorted nodes in at most G groups of
+// near-equal cost, G the workgroups the GPU holds at once, so that all groups
+// run in one round and end together (work items of a fixed size leave the
+// CUs of the last round partly idle, and a second round of smaller groups
+// measured slower).  A segment (the nodes of one tile inside a group,
+// contiguous in the sort) costs its nodes plus kSegCost node-equivalents:
+// the interpolation stages the tile's padded grid block and the spread
+// flushes it whatever the number of nodes, each a chain of dependent memory
+// accesses, so a group's time grows with its segments even where the CU has
+// other work (at the benchmark workload a product took 261, 233, 215, 202,
+// 196 and 200 us with 64, 96, 128, 192, 256 and 384).  A tile's nodes in one
+// group form one segment, so they are staged and flushed once.
+static void cost_groups(const std::vector<uint32_t> &hc, int64_t n, int G, std::vector<Item> &gi,
+                        std::vector<int> &goff) {
+  constexpr double kSegCost = 256.0;
+  constexpr int64_t kMinTake = 32;
+  int64_t nocc = 0;
+  for (uint32_t c : hc) nocc += c > 0;
+  const double target = ((double)n + kSegCost * (double)(nocc + G)) / G;
+  gi.clear();
+  goff.assign(1, 0);
+  double gc = 0.0;
+  int64_t start = 0;
+  for (size_t t = 0; t < hc.size(); ++t) {
+    int64_t pos = start, rem = hc[t];
+    start += hc[t];
+    while (rem > 0) {
+      const bool last = (int)goff.size() == G;   // the last group takes the rest
+      const double room = target - gc - kSegCost;
+      if (!last && gc > 0.0 && room < (double)kMinTake) {
+        goff.push_back((int)gi.size());
+        gc = 0.0;
+        continue;
+      }
+      const int64_t take =
+          last ? rem : std::min<int64_t>(rem, std::max<int64_t>(kMinTake, (int64_t)std::ceil(room)));
+      gi.push_back(Item{(int)t, (int)pos, (int)(pos + take), 0});
+      gc += kSegCost + (double)take;
+      pos += take;
+      rem -= take;
+      if (!last && gc >= target) {
+        goff.push_back((int)gi.size());
+        gc = 0.0;
+      }
+    }
+  }
+  if (goff.back() != (int)gi.size()) goff.push_back((int)gi.size());
+}
+
 int build_sorted_nodes(nfl_plan *P) {
   const int64_t n = P->n;
   const int d = P->d;
@@ -471,6 +520,20 @@ int build_sorted_nodes(nfl_plan *P) {
   NFL_TRY(P->items.ensure(items.size()));
   NFL_HIP(hipMemcpyAsync(P->items.p, items.data(), items.size() * sizeof(Item),
                          hipMemcpyHostToDevice, P->stream));
+  P->ngroups = 0;
+  if (const int slots = tile_group_slots(P); slots > 0 && n > 0) {
+    std::vector<Item> gi;
+    std::vector<int> goff;
+    cost_groups(hc, n, slots, gi, goff);
+    NFL_TRY(P->gitems.ensure(gi.size()));
+    NFL_TRY(P->goff.ensure(goff.size()));
+    NFL_HIP(hipMemcpyAsync(P->gitems.p, gi.data(), gi.size() * sizeof(Item),
+                           hipMemcpyHostToDevice, P->stream));
+    NFL_HIP(hipMemcpyAsync(P->goff.p, goff.data(), goff.size() * sizeof(int),
+                           hipMemcpyHostToDevice, P->stream));
+    NFL_HIP(hipStreamSynchronize(P->stream));   // the host vectors go out of scope
+    P->ngroups = (int)goff.size() - 1;
+  }
   // d = 3: the z-lines some node's window touches.  A node of cell c spreads
   // into cells c - m + 1 .. c + m (mod nos) along each axis, so the lines of an
   // occupied tile with origin o lie in [o - m + 1, o + T + m) along x and y.

@@ -126,6 +126,32 @@ def test_spread_matches_cpu_gridding(nfl, d, n, N, m, tile, chunk, kernel):
     assert err < 2e-6, err
 
 
+@pytest.mark.parametrize("n_sparse,n_dense,N,m,tile", [
+    (2500, 0, 64, 4, 4), (2000, 6000, 64, 6, 4), (1500, 9000, 32, 4, 8), (3000, 3000, 64, 2, 8)])
+def test_tile_forms_on_mixed_clouds(nfl, n_sparse, n_dense, N, m, tile):
+    """A sparse uniform ball (most tiles hold a node or two) plus one dense
+    cluster: the tile forms' workgroups then take several tiles one after the
+    other (each reusing the LDS of the one before) and the dense tiles are
+    split over several workgroups.  Spread element-wise against the FP64
+    gridding, interpolation on sampled nodes against its transpose."""
+    rng = np.random.default_rng(42)
+    dense = rng.normal(size=(n_dense, 3)) * 0.004 + np.array([0.05, 0.02, -0.03])
+    v = np.concatenate([synth.uniform_ball(n_sparse, d=3, seed=41), dense]).astype(np.float32)
+    n = len(v)
+    P = make(nfl, v, 0.08, N, m, 0.0, tile)
+    x = synth.normal_vectors(n, seed=5)
+    g = host(P.spread(tt(x)))
+    u = grid_coords(v, P.info()["rho"], 0.0, 2 * N)
+    ref = cpu_spread(u, x.astype(np.float64), m, 2 * N)
+    assert np.abs(g - ref).max() <= 2e-6 * np.abs(ref).max()
+    rng = np.random.default_rng(3)
+    G = rng.standard_normal((2 * N) ** 3).astype(np.float32)
+    f = host(P.interp(tt(G)))
+    rows = np.arange(0, n, 37)
+    ref_f = np.array([cpu_spread(u[i:i + 1], np.ones(1), m, 2 * N) @ G for i in rows])
+    np.testing.assert_allclose(f[rows], ref_f, rtol=0, atol=3e-6 * np.abs(ref_f).max())
+
+
 @pytest.mark.parametrize("d,N", [(1, 64), (1, 256), (2, 32), (2, 128), (3, 16), (3, 32), (3, 64)])
 def test_convolve_matches_numpy_fft(nfl, d, N):
     v = synth.gmm(500, d=d, k=3, seed=2)
