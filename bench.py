@@ -71,10 +71,11 @@ def golden_degree(v):
 
 
 def kernel_src_sha1():
-    """SHA-1 of the sources of the spread / FFT / interpolation kernels."""
+    """SHA-1 of the sources of the spread / FFT / interpolation kernels and
+    of the plan set-up that divides their work among workgroups."""
     import hashlib
     h = hashlib.sha1()
-    for f in ("nfft.hip", "nfft_device.h"):
+    for f in ("nfft.hip", "nfft_device.h", "setup.hip"):
         h.update(open(os.path.join(ROOT, "paper_1808_04580_amd", "csrc", f), "rb").read())
     return h.hexdigest()
 

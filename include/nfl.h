@@ -54,7 +54,9 @@ typedef struct nfl_mlp *nfl_mlp_handle;
 /* Options for nfl_set_option (take effect at the next nfl_set_kernel). */
 #define NFL_OPT_P          1   /* regularisation smoothness p of K_R (Fig. tab:fastsum_param); default p = m */
 #define NFL_OPT_TILE       2   /* grid tile edge T for spread/interp (power of 2, 4..32); default 4 */
-#define NFL_OPT_CHUNK      3   /* max nodes per spread/interp work item; default 512 */
+#define NFL_OPT_CHUNK      3   /* max nodes per work item of the per-cell, d <= 2, near-field and FP64
+                                  kernels; default 512 (the tile-stationary d = 3 forms divide their
+                                  work into one round of cost-balanced groups instead) */
 #define NFL_OPT_EPS_B_DEFAULT 4 /* if value != 0, nfl_set_kernel with eps_B < 0 uses eps_B = p/N (the paper's default) */
 #define NFL_OPT_KERNEL     5   /* d = 3 spread/interp: 0 = matrix-core (MFMA) kernels (default; tile-stationary
                                    where tile + 2m - 1 <= 16, else per-cell runs), 1 = vector-ALU kernels,
