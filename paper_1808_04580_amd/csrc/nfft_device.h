@@ -867,7 +867,11 @@ __device__ __forceinline__ void spread3_tile_body(const Item it, const float4 *_
   const int len = it.end - it.start, per = (len + NW - 1) / NW;
   const int s = it.start + min(len, wave * per), e = it.start + min(len, (wave + 1) * per);
 
-  // window coefficients (rows 2m..15 are 0) after the weight tables
+  // the first batch loads while the window coefficients (rows 2m..15 are 0)
+  // are staged after the weight tables
+  float4 qb, qn;
+  float xb, xn;
+  load_batch<IN, true>(pts, ka, s, e, lane, qb, xb);
   float *cft = lds + NW * 16 * TS_PITCH;
   for (int q = threadIdx.x; q < WIN_MAXW * WIN_NC; q += NW * 64) cft[q] = wcoef[q];
   __syncthreads();
@@ -875,9 +879,6 @@ __device__ __forceinline__ void spread3_tile_body(const Item it, const float4 *_
 #pragma unroll
   for (int z = 0; z < P; ++z) acc[z] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  float4 qb, qn;
-  float xb, xn;
-  load_batch<IN, true>(pts, ka, s, e, lane, qb, xb);
   for (int b0 = s; b0 < e; b0 += 64) {
     load_batch<IN, true>(pts, ka, b0 + 64, e, lane, qn, xn);  // prefetch the next batch
     const int bcnt = min(64, e - b0);
@@ -920,21 +921,31 @@ __device__ __forceinline__ void spread3_tile_body(const Item it, const float4 *_
     }
     __syncthreads();
   }
-  // into the grid: each wave takes rows (px, py), four at a time, z along lanes
+  // into the grid: each wave takes rows (px, py), four at a time, z along
+  // lanes; all its LDS reads are issued before the first global add
   const int mask = nos - 1;
   const double fx = fx_of(ka);
   const int pz = lane & 15, rsub = lane >> 4;
-  for (int row0 = wave * 4; row0 < P * P; row0 += NW * 4) {
-    const int row = row0 + rsub;
+  constexpr int NRG = (P * P + NW * 4 - 1) / (NW * 4);   // row groups per wave
+  float fv[NRG];
+#pragma unroll
+  for (int k = 0; k < NRG; ++k) {
+    const int row = wave * 4 + k * (NW * 4) + rsub;
+    fv[k] = 0.f;
     if (row < P * P && pz < P) {
       const int px = row / P, py = row - px * P;
       const int o = px * XS + pz * TS_SZS + py;
-      const float v = NC == 2 ? lds[o] + lds[16 * XS + o] : lds[o];
-      if (v != 0.f) {
-        const int gx = (ox - (M - 1) + px) & mask, gy = (oy - (M - 1) + py) & mask,
-                  gz = (oz - (M - 1) + pz) & mask;
-        grid_add(grid, ((size_t)gx * nos + gy) * nos + gz, v, fx);
-      }
+      fv[k] = NC == 2 ? lds[o] + lds[16 * XS + o] : lds[o];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NRG; ++k) {
+    const int row = wave * 4 + k * (NW * 4) + rsub;
+    if (fv[k] != 0.f) {   // (rows past P * P and z past P hold 0)
+      const int px = row / P, py = row - px * P;
+      const int gx = (ox - (M - 1) + px) & mask, gy = (oy - (M - 1) + py) & mask,
+                gz = (oz - (M - 1) + pz) & mask;
+      grid_add(grid, ((size_t)gx * nos + gy) * nos + gz, fv[k], fx);
     }
   }
 }
@@ -957,26 +968,22 @@ __device__ __forceinline__ void interp3_tile_body(const Item *__restrict__ items
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int c16 = lane & 15, p4 = lane >> 4;
-  {
-    // stage the padded tile, z padded to 16 with zeros
-    for (int row0 = wave * 4; row0 < P * P; row0 += NW * 4) {
-      const int row = row0 + p4;
-      if (row < P * P) {
-        const int px = row / P, py = row - px * P;
-        float v = 0.f;
-        if (c16 < P) {
-          const int gx = (ox - (M - 1) + px) & mask, gy = (oy - (M - 1) + py) & mask,
-                    gz = (oz - (M - 1) + c16) & mask;
-          v = grid[((size_t)gx * nos + gy) * nos + gz];
-        }
-        tile[px * XS + py * 16 + c16] = v;
-      }
+  // Stage the padded tile (z padded to 16 with zeros): the wave issues all its
+  // loads before its first LDS store, so they wait once, not once per row
+  // group, and the first batch's records load before the barrier.
+  constexpr int NRG = (P * P + NW * 4 - 1) / (NW * 4);   // row groups per wave
+  float stg[NRG];
+#pragma unroll
+  for (int k = 0; k < NRG; ++k) {
+    const int row = wave * 4 + k * (NW * 4) + p4;
+    stg[k] = 0.f;
+    if (row < P * P && c16 < P) {
+      const int px = row / P, py = row - px * P;
+      const int gx = (ox - (M - 1) + px) & mask, gy = (oy - (M - 1) + py) & mask,
+                gz = (oz - (M - 1) + c16) & mask;
+      stg[k] = grid[((size_t)gx * nos + gy) * nos + gz];
     }
-    // window coefficients (rows 2m..15 are 0) after the tables
-    float *cfs = lds + P * XS + NW * 16 * TS_PITCH_I;
-    for (int q = threadIdx.x; q < WIN_MAXW * WIN_NC; q += NW * 64) cfs[q] = wcoef[q];
   }
-  __syncthreads();
   // Nodes are taken in runs of <= 16 that share their cell's z inside the tile
   // (the sort orders a tile's nodes z-major, so a run is usually 16 long):
   // their z windows coincide, so K = (padded y, z window) needs ZQ = W/4
@@ -989,7 +996,7 @@ __device__ __forceinline__ void interp3_tile_body(const Item *__restrict__ items
   int cur_lz = -1;
 
   float *wt = lds + P * XS + wave * (16 * TS_PITCH_I);
-  const float *cft = lds + P * XS + NW * 16 * TS_PITCH_I;   // staged with the tile
+  float *cft = lds + P * XS + NW * 16 * TS_PITCH_I;   // window coefficients after the tables
   const int len = it.end - it.start, per = (len + NW - 1) / NW;
   const int s = it.start + min(len, wave * per), e = it.start + min(len, (wave + 1) * per);
   float4 qb, qn;
@@ -997,6 +1004,17 @@ __device__ __forceinline__ void interp3_tile_body(const Item *__restrict__ items
   OutPre ob, on;
   load_batch<IN, false>(pts, ka, s, e, lane, qb, xb);
   pre_index<OUT>(ka, s + lane, s + lane < e, ob);
+#pragma unroll
+  for (int k = 0; k < NRG; ++k) {
+    const int row = wave * 4 + k * (NW * 4) + p4;
+    if (row < P * P) {
+      const int px = row / P, py = row - px * P;
+      tile[px * XS + py * 16 + c16] = stg[k];
+    }
+  }
+  // (rows 2m..15 of the coefficient table are 0)
+  for (int q = threadIdx.x; q < WIN_MAXW * WIN_NC; q += NW * 64) cft[q] = wcoef[q];
+  __syncthreads();
   pre_gather<OUT>(ka, s + lane < e, ob);
   for (int b0 = s; b0 < e; b0 += 64) {
     // prefetch the next batch: records, permutation entries, d^{-1/2}
