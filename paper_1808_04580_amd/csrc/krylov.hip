@@ -326,12 +326,13 @@ static int apply_A64(nfl_plan *P, const double *q, double *w) {
 // w = (I + tau L_s) q; fx_ready: q's bound for the deterministic spread is in
 // the plan's fx_max word already (the CG direction kernels write it)
 static int apply_SSL64(nfl_plan *P, double tau, const double *q, double *w,
-                       bool fx_ready = false) {
+                       bool fx_ready = false, double *dot = nullptr) {
   VecArgs a;
   a.x64 = q;
   a.y64 = w;
   a.tau = tau;
   a.fx_ready = fx_ready;
+  a.dot = dot;
   return fastsum(P, IN_SORTED_F64_DINV, OUT_SORTED_F64_SSL, a);
 }
 
@@ -977,15 +978,18 @@ __global__ __launch_bounds__(VT) void k_cg_pq(const double *__restrict__ p,
 }
 
 // step k: alpha = r.r / p.q; u += alpha p; r -= alpha q; partials of the new r.r
+// p.q is the sum of the npq partials pqp (of k_cg_pq, or of the product's
+// interpolation)
 __global__ __launch_bounds__(VT) void k_cg_step(double *__restrict__ u, double *__restrict__ r,
                                                 const double *__restrict__ p,
                                                 const double *__restrict__ q, int64_t n, int k,
                                                 const double *__restrict__ sc,
                                                 int *__restrict__ st,
+                                                const double *__restrict__ pqp, int npq,
                                                 double *__restrict__ part) {
   if (cg_stopped(st)) return;
   __shared__ double sh[VT / 64];
-  const double pq = sum_partials(part, (int)gridDim.x, sh);
+  const double pq = sum_partials(pqp, npq, sh);
   if (!(pq > 0.0) || !isfinite(pq)) {   // M is not positive definite on p: stop
     if (blockIdx.x == 0 && threadIdx.x == 0) st[0] = 2;
     return;
@@ -1117,10 +1121,11 @@ __global__ __launch_bounds__(VT) void k_krr_combine(const float *__restrict__ t,
 
 struct KrrOp {
   static constexpr bool fx_feed = false;
+  static constexpr bool dot_feed = false;
   nfl_plan *P;
   double beta;
   float *x32, *t32;
-  int operator()(const double *x, double *q, bool = false) const {
+  int operator()(const double *x, double *q, bool = false, double * = nullptr) const {
     const int gb = grid_for(P->n);
     hipLaunchKernelGGL(k_to_f32, dim3(gb), dim3(VT), 0, P->stream, x, P->n, x32);
     VecArgs a;
@@ -1136,10 +1141,11 @@ struct KrrOp {
 
 struct SslOp {
   static constexpr bool fx_feed = true;   // products take the input bound from the CG kernels
+  static constexpr bool dot_feed = true;  // products can form the partials of x . Mx
   nfl_plan *P;
   double tau;
-  int operator()(const double *x, double *q, bool fx_ready = false) const {
-    return apply_SSL64(P, tau, x, q, fx_ready);
+  int operator()(const double *x, double *q, bool fx_ready = false, double *dot = nullptr) const {
+    return apply_SSL64(P, tau, x, q, fx_ready, dot);
   }
 };
 
@@ -1154,6 +1160,7 @@ struct SslOp {
 struct CgWork {
   double *r, *p, *q;   // n each
   double *part;        // 2 * CG_NB
+  double *dot;         // DOT_PARTS_MAX: the product's partials of p.q
   double *sc;          // 8
   int *st;             // 2
   int *host_st = nullptr;          // pinned status words (iterations, converged), device-visible
@@ -1187,12 +1194,21 @@ static int cg_core(nfl_plan *P, const Op &op, const CgWork &W, const double *f, 
     ~StopGuard() { P->stop = nullptr; }
   } guard{P};
   P->stop = W.st;   // every product kernel of the loop returns once the flag is set
+  // the product's interpolation forms the partials of p.q where it can (one
+  // kernel fewer per iteration), else k_cg_pq does
+  int ndot = 0;
+  if constexpr (Op::dot_feed) ndot = product_dot_parts(P);
   constexpr int check = 4;
   for (int k = 0; k < maxit; ++k) {
-    NFL_TRY(op(W.p, W.q, fxw != nullptr));
-    hipLaunchKernelGGL(k_cg_pq, dim3(nb), dim3(VT), 0, s, W.p, W.q, n, W.st, W.part);
+    if (ndot > 0) {
+      NFL_TRY(op(W.p, W.q, fxw != nullptr, W.dot));
+    } else {
+      NFL_TRY(op(W.p, W.q, fxw != nullptr));
+      hipLaunchKernelGGL(k_cg_pq, dim3(nb), dim3(VT), 0, s, W.p, W.q, n, W.st, W.part);
+    }
     hipLaunchKernelGGL(k_cg_step, dim3(nb), dim3(VT), 0, s, u, W.r, W.p, W.q, n, k, W.sc, W.st,
-                       W.part);
+                       ndot > 0 ? (const double *)W.dot : (const double *)W.part,
+                       ndot > 0 ? ndot : nb, W.part);
     hipLaunchKernelGGL(k_cg_dir, dim3(nb), dim3(VT), 0, s, W.p, W.r, n, k, W.sc, W.st, W.part,
                        W.host_st, fxw);
     NFL_HIP(hipGetLastError());
@@ -1245,7 +1261,7 @@ static int cg_core(nfl_plan *P, const Op &op, const CgWork &W, const double *f, 
 // pinned status words; allocated by the first solve and kept with the plan.
 static int plan_cg_work(nfl_plan *P, CgWork &W, double **f_sorted, double **u_sorted) {
   const size_t n = (size_t)P->n;
-  NFL_TRY(P->cg_vec.ensure(5 * n + 2 * CG_NB + 8));
+  NFL_TRY(P->cg_vec.ensure(5 * n + 2 * CG_NB + 8 + DOT_PARTS_MAX));
   NFL_TRY(P->cg_st.ensure(2));
   if (!P->cg_host) {
     void *h = nullptr;
@@ -1260,6 +1276,7 @@ static int plan_cg_work(nfl_plan *P, CgWork &W, double **f_sorted, double **u_so
   W.q = b + 2 * n;
   W.part = b + 5 * n;
   W.sc = W.part + 2 * CG_NB;
+  W.dot = W.sc + 8;
   W.st = P->cg_st.p;
   W.host_st = P->cg_host;
   W.ev = P->cg_ev;
@@ -1314,7 +1331,8 @@ static int cg_sorted(nfl_plan *P, const CgWork &W, double tau, const double *f_d
 // taken once per device with hipGetSymbolAddress and kept here.  All calls
 // on one GPU share that GPU's array, so calls that overlap on one GPU race.
 // ---------------------------------------------------------------------------
-constexpr size_t CG_SCRATCH_DOUBLES = 5 * (size_t)NFL_CG_NOALLOC_MAX_N + 2 * CG_NB + 8 + 2;
+constexpr size_t CG_SCRATCH_DOUBLES =
+    5 * (size_t)NFL_CG_NOALLOC_MAX_N + 2 * CG_NB + 8 + 2 + DOT_PARTS_MAX;
 static __device__ __align__(256) double scratch[CG_SCRATCH_DOUBLES];
 
 constexpr int SCRATCH_MAX_DEVICES = 64;
@@ -1362,6 +1380,7 @@ int cg_noalloc(nfl_plan *P, double tau, const double *f_dev, double *u_dev, int 
   W.part = b + 5 * n;
   W.sc = W.part + 2 * CG_NB;
   W.st = reinterpret_cast<int *>(W.sc + 8);
+  W.dot = W.sc + 10;
   W.host_st = nullptr;   // status read by a copy every few iterations
   W.ev = nullptr;
   return cg_sorted(P, W, tau, f_dev, u_dev, b + 3 * n, b + 4 * n, warm, tol, maxit, iters,

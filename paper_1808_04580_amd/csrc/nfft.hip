@@ -273,9 +273,20 @@ void k_interp3_tile(const Item *__restrict__ items, const int *__restrict__ goff
                     int nos, const float *__restrict__ wcoef) {
   if (stopped(ka.stop)) return;
   const int g0 = goff[blockIdx.x], g1 = goff[blockIdx.x + 1];
+  double dsum = 0.0;
   for (int it = g0; it < g1; ++it) {
     if (it > g0) __syncthreads();
-    interp3_tile_body<W, T, IN, OUT>(items, it, pts, ka, grid, nos, wcoef);
+    interp3_tile_body<W, T, IN, OUT>(items, it, pts, ka, grid, nos, wcoef, &dsum);
+  }
+  if constexpr (OUT == OUT_SORTED_F64_SSL) {
+    if (ka.dot) {   // the workgroup's partial of x64 . y64, summed in a fixed order
+      __shared__ double wsum[4];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) dsum += __shfl_xor(dsum, o);
+      if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = dsum;
+      __syncthreads();
+      if (threadIdx.x == 0) ka.dot[blockIdx.x] = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
+    }
   }
 }
 
@@ -571,6 +582,7 @@ static KArgs make_kargs(nfl_plan *P, const VecArgs &a) {
   k.fx_max = nullptr;
   k.fx_mult = 0.f;
   k.xs = a.xs;
+  k.dot = a.dot;
   return k;
 }
 
@@ -915,6 +927,12 @@ int convolve(nfl_plan *P, const float *gin_c, float *gout, bool zero_in, bool su
 static bool tile_forms(const nfl_plan *P) {
   const int T = 1 << P->tshift, W = 2 * P->m;
   return P->d == 3 && P->opt_kernel == 0 && ((T == 4 && W + 3 <= 16) || (T == 8 && W + 7 <= 16));
+}
+
+int product_dot_parts(const nfl_plan *P) {
+  return P->prec == 32 && tile_forms(P) && P->ngroups > 0 && P->ngroups <= DOT_PARTS_MAX
+             ? P->ngroups
+             : 0;
 }
 
 int fastsum(nfl_plan *P, int in_mode, int out_mode, const VecArgs &a_in) {

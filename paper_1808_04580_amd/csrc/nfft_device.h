@@ -52,6 +52,9 @@ struct KArgs {
   // here (xs[i] = x[perm[i]]), and the tile interpolation's output step reads
   // it back instead of gathering x through the permutation again
   float *xs;
+  // non-null (OUT_SORTED_F64_SSL, tile interpolation): one partial sum of
+  // x64_i y64_i per workgroup, over its nodes in a fixed order (the CG's p.q)
+  double *dot;
 };
 
 // Deterministic spread: the plan's grid holds int64 fixed-point values
@@ -196,8 +199,10 @@ __device__ __forceinline__ OutPre pre_from(const OutPre &p, int src) {
   return q;
 }
 
+// Returns x64_i y64_i for OUT_SORTED_F64_SSL (the term of the CG's p.q),
+// else 0.
 template <int OUT>
-__device__ __forceinline__ void store_pre(const KArgs &a, int i, float f, const OutPre &p) {
+__device__ __forceinline__ double store_pre(const KArgs &a, int i, float f, const OutPre &p) {
   if constexpr (OUT == OUT_USER_RAW) {
     a.y32[p.j] = f;
   } else if constexpr (OUT == OUT_USER_W) {
@@ -221,8 +226,11 @@ __device__ __forceinline__ void store_pre(const KArgs &a, int i, float f, const 
     const double xv = p.xd;
     const float xt = (float)(di * xv);
     const double av = di * ((double)f - (double)xt);
-    a.y64[i] = xv + a.tau * (xv - av);
+    const double yv = xv + a.tau * (xv - av);
+    a.y64[i] = yv;
+    return xv * yv;
   }
+  return 0.0;
 }
 
 // v[l] + v[l ^ 16] + v[l ^ 32] + v[l ^ 48] on every lane, summed in the
@@ -955,7 +963,8 @@ __device__ __forceinline__ void interp3_tile_body(const Item *__restrict__ items
                                                   const float4 *__restrict__ pts,
                                                   const KArgs ka,
                                                   const float *__restrict__ grid, int nos,
-                                                  const float *__restrict__ wcoef) {
+                                                  const float *__restrict__ wcoef,
+                                                  double *dot_acc = nullptr) {
   constexpr int M = W / 2, P = T + W - 1, XS = ts_xs(P);
   static_assert(P <= 16, "tile-stationary form needs T + W - 1 <= 16");
   extern __shared__ float lds[];
@@ -1073,7 +1082,11 @@ __device__ __forceinline__ void interp3_tile_body(const Item *__restrict__ items
 #pragma unroll
       for (int r = 0; r < 4; ++r) part = fmaf(w[4 * p4 + r], d[0][r] + d[1][r], part);
       part = sum_rows4(part);
-      if (p4 == 0 && c16 < cnt) store_pre<OUT>(ka, i0 + c16, part, op);
+      if (p4 == 0 && c16 < cnt) {
+        const double t = store_pre<OUT>(ka, i0 + c16, part, op);
+        if constexpr (OUT == OUT_SORTED_F64_SSL)
+          if (dot_acc) *dot_acc += t;   // this lane's nodes, in the order they come
+      }
       wave_sync_lds();
     }
     qb = qn;

@@ -271,15 +271,24 @@ struct VecArgs {
   const double *x64 = nullptr;  // sorted order
   double *y64 = nullptr;        // sorted order
   double tau = 0;
+  // OUT_SORTED_F64_SSL: per-workgroup partials of x64 . y64, written by the
+  // tile interpolation (product_dot_parts of them); null: not formed
+  double *dot = nullptr;
 };
 
 int spread(nfl_plan *P, int in_mode, const VecArgs &a, float *grid, bool clear = true);
-// zero_in: the r2c pass sets the input grid to 0 as it reads it
-// support: the grids are the plan's own (spread and interpolation of its nodes):
-// the d = 3 passes then take only the z-line support
 // workgroups of the tile-stationary forms that the GPU holds at once for the
 // plan's window and tile (0 where those forms do not apply)
 int tile_group_slots(const nfl_plan *P);
+// most partials a product writes into VecArgs::dot
+constexpr int DOT_PARTS_MAX = 4096;
+// partials of x64 . y64 that the plan's SSL product writes into VecArgs::dot
+// (one per workgroup of the tile interpolation), or 0 where its kernels do
+// not form them
+int product_dot_parts(const nfl_plan *P);
+// zero_in: the r2c pass sets the input grid to 0 as it reads it
+// support: the grids are the plan's own (spread and interpolation of its nodes):
+// the d = 3 passes then take only the z-line support
 int convolve(nfl_plan *P, const float *gin, float *gout, bool zero_in = false, bool support = false);
 int interp(nfl_plan *P, const float *grid, int in_mode, int out_mode, const VecArgs &a);
 // whole fast summation with the given input/output modes (grid = plan grid)
