@@ -75,7 +75,7 @@ def kernel_src_sha1():
     of the plan set-up that divides their work among workgroups."""
     import hashlib
     h = hashlib.sha1()
-    for f in ("nfft.hip", "nfft_device.h", "setup.hip"):
+    for f in ("nfft.hip", "nfft_device.h", "setup.hip", "workdiv.h"):
         h.update(open(os.path.join(ROOT, "paper_1808_04580_amd", "csrc", f), "rb").read())
     return h.hexdigest()
 

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "nfl_internal.h"
+#include "workdiv.h"
 
 namespace nfl {
 
@@ -354,59 +355,6 @@ __global__ __launch_bounds__(256) void k_tile_ends(const uint32_t *__restrict__ 
   if (i + 1 == n || (keys[i + 1] >> shift) != t) end[t] = (uint32_t)(i + 1);
 }
 
-// The tile-stationary forms' work: the sorted nodes in at most G groups of
-// near-equal cost, G the workgroups the GPU holds at once, so that all groups
-// run in one round and end together (work items of a fixed size leave the
-// CUs of the last round partly idle, and a second round of smaller groups
-// measured slower).  A segment (the nodes of one tile inside a group,
-// contiguous in the sort) costs its nodes plus kSegCost node-equivalents:
-// the interpolation stages the tile's padded grid block and the spread
-// flushes it whatever the number of nodes, each a chain of dependent memory
-// accesses, so a group's time grows with its segments even where the CU has
-// other work (at the benchmark workload a product took 261, 233, 215, 202,
-// 196 and 200 us with 64, 96, 128, 192, 256 and 384).  A tile's nodes in one
-// group form one segment, so they are staged and flushed once.  Small
-// problems get fewer, larger groups: none costs less than a segment of 512
-// nodes (many groups of ~100 nodes in a few dense tiles flush into the same
-// cells at once: on the 316 x 316 RGB image, 1e5 nodes, 88 against 77 us).
-static void cost_groups(const std::vector<uint32_t> &hc, int64_t n, int G, std::vector<Item> &gi,
-                        std::vector<int> &goff) {
-  constexpr double kSegCost = 256.0, kMinGroupCost = 512.0 + kSegCost;
-  constexpr int64_t kMinTake = 32;
-  int64_t nocc = 0;
-  for (uint32_t c : hc) nocc += c > 0;
-  const double target =
-      std::max(kMinGroupCost, ((double)n + kSegCost * (double)(nocc + G)) / G);
-  gi.clear();
-  goff.assign(1, 0);
-  double gc = 0.0;
-  int64_t start = 0;
-  for (size_t t = 0; t < hc.size(); ++t) {
-    int64_t pos = start, rem = hc[t];
-    start += hc[t];
-    while (rem > 0) {
-      const bool last = (int)goff.size() == G;   // the last group takes the rest
-      const double room = target - gc - kSegCost;
-      if (!last && gc > 0.0 && room < (double)kMinTake) {
-        goff.push_back((int)gi.size());
-        gc = 0.0;
-        continue;
-      }
-      const int64_t take =
-          last ? rem : std::min<int64_t>(rem, std::max<int64_t>(kMinTake, (int64_t)std::ceil(room)));
-      gi.push_back(Item{(int)t, (int)pos, (int)(pos + take), 0});
-      gc += kSegCost + (double)take;
-      pos += take;
-      rem -= take;
-      if (!last && gc >= target) {
-        goff.push_back((int)gi.size());
-        gc = 0.0;
-      }
-    }
-  }
-  if (goff.back() != (int)gi.size()) goff.push_back((int)gi.size());
-}
-
 int build_sorted_nodes(nfl_plan *P) {
   const int64_t n = P->n;
   const int d = P->d;
@@ -526,9 +474,11 @@ int build_sorted_nodes(nfl_plan *P) {
                          hipMemcpyHostToDevice, P->stream));
   P->ngroups = 0;
   if (const int slots = tile_group_slots(P); slots > 0 && n > 0) {
-    std::vector<Item> gi;
+    std::vector<GroupSeg> segs;
     std::vector<int> goff;
-    cost_groups(hc, n, slots, gi, goff);
+    cost_groups(hc, n, slots, segs, goff);
+    std::vector<Item> gi(segs.size());
+    for (size_t k = 0; k < segs.size(); ++k) gi[k] = Item{segs[k].tile, segs[k].start, segs[k].end, 0};
     NFL_TRY(P->gitems.ensure(gi.size()));
     NFL_TRY(P->goff.ensure(goff.size()));
     NFL_HIP(hipMemcpyAsync(P->gitems.p, gi.data(), gi.size() * sizeof(Item),
