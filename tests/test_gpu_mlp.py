@@ -166,8 +166,11 @@ def test_cg_with_learned_warm_start_reaches_same_solution(nfl):
 
 def test_trained_network_reduces_cg_iterations(nfl):
     """The committed network (trained by paper_1808_04580_amd.train_warmstart on
-    clouds 1..100) on a held-out cloud: fewer CG iterations to 1e-6 than u0 = 0,
-    same solution."""
+    clouds 1..100) on a held-out cloud: its start leaves a relative residual
+    of at most 0.2 of u0 = 0's (measured ~0.11), CG from it needs fewer
+    iterations to 1e-6 in total (measured about one in 17 per right-hand
+    side: the network's error lies in slowly converging directions), and
+    reaches the same solution."""
     import os
     import torch
     import synth
@@ -180,6 +183,10 @@ def test_trained_network_reduces_cg_iterations(nfl):
     for c in range(3):
         f = torch.as_tensor(synth.ssl_rhs(lab, c, frac=0.02, seed=300 + c), device="cuda")
         r0 = P.cg_solve(f, tau=10.0, tol=1e-6, maxit=300)
+        u_net = W.predict(P, f, c)
+        Mu = u_net + 10.0 * P.apply_Ls(u_net.float()).double()
+        rel0 = (torch.linalg.vector_norm(f - Mu) / torch.linalg.vector_norm(f)).item()
+        assert rel0 <= 0.2, rel0
         W.attach(P, c)
         r1 = P.cg_solve(f, tau=10.0, tol=1e-6, maxit=300, warm=nfl.WARM_MLP)
         assert r0["converged"] and r1["converged"] and r1["relres"] <= 2e-6
@@ -188,4 +195,4 @@ def test_trained_network_reduces_cg_iterations(nfl):
         plain.append(r0["iters"])
         warm.append(r1["iters"])
     print("CG iterations plain", plain, "learned", warm)
-    assert np.mean(warm) < np.mean(plain), (plain, warm)
+    assert sum(plain) - sum(warm) >= 1, (plain, warm)
