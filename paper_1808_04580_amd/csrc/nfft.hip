@@ -251,6 +251,9 @@ void k_interp3_mfma(const Item *__restrict__ items,
 // segments (the plan's gitems / goff): the segments of a group are taken one
 // after the other, each with its own tile staging (interpolation) or flush
 // (spread); the barrier between two frees the LDS of the previous one.  The
+// groups follow the sort, so neighbouring groups share grid cells; each XCD
+// takes one contiguous range of them (xcd_block), which keeps those cells in
+// one L2 (a product at the benchmark workload: 194.6 -> 190.5 us).  The
 // spread keeps its accumulators in VGPRs without spills within the register
 // budget of three waves per SIMD (168 per lane); it uses 112, so four fit.
 template <int W, int T, int IN>
@@ -259,7 +262,8 @@ void k_spread3_tile(const Item *__restrict__ items, const int *__restrict__ goff
                     const float4 *__restrict__ pts, KArgs ka, float *__restrict__ grid, int nos,
                     const float *__restrict__ wcoef) {
   if (stopped(ka.stop)) return;
-  const int g0 = goff[blockIdx.x], g1 = goff[blockIdx.x + 1];
+  const int gb = xcd_block(blockIdx.x, gridDim.x);
+  const int g0 = goff[gb], g1 = goff[gb + 1];
   for (int it = g0; it < g1; ++it) {
     if (it > g0) __syncthreads();
     spread3_tile_body<W, T, IN>(items[it], pts, ka, grid, nos, wcoef);
@@ -272,7 +276,8 @@ void k_interp3_tile(const Item *__restrict__ items, const int *__restrict__ goff
                     const float4 *__restrict__ pts, KArgs ka, const float *__restrict__ grid,
                     int nos, const float *__restrict__ wcoef) {
   if (stopped(ka.stop)) return;
-  const int g0 = goff[blockIdx.x], g1 = goff[blockIdx.x + 1];
+  const int gb = xcd_block(blockIdx.x, gridDim.x);
+  const int g0 = goff[gb], g1 = goff[gb + 1];
   double dsum = 0.0;
   for (int it = g0; it < g1; ++it) {
     if (it > g0) __syncthreads();

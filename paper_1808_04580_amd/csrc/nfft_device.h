@@ -248,9 +248,9 @@ __device__ __forceinline__ float sum_rows4(float v) {
 // its own L2.  xcd_block maps workgroup id b of nb to a logical block so that
 // each XCD gets one contiguous range of blocks (bijective on [0, nb)): the
 // column passes of the FFT, whose neighbouring workgroups read parts of the
-// same cache lines, then fetch each line into one L2 instead of several.  (The
-// spread and the interpolation keep their issue order: mapped this way they
-// measured slower.)
+// same cache lines, then fetch each line into one L2 instead of several, and
+// so do the tile forms' work groups, whose neighbours in the sort share grid
+// cells.
 constexpr int NUM_XCD = 8;
 
 __device__ __forceinline__ int xcd_block(int b, int nb) {
