@@ -255,7 +255,8 @@ void k_interp3_mfma(const Item *__restrict__ items,
 // takes one contiguous range of them (xcd_block), which keeps those cells in
 // one L2 (a product at the benchmark workload: 194.6 -> 190.5 us).  The
 // spread keeps its accumulators in VGPRs without spills within the register
-// budget of three waves per SIMD (168 per lane); it uses 112, so four fit.
+// budget of three waves per SIMD (168 per lane); it uses at most 127 (m = 6),
+// so four fit.
 template <int W, int T, int IN>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 void k_spread3_tile(const Item *__restrict__ items, const int *__restrict__ goff,
@@ -676,9 +677,8 @@ static int tile_slots_wt(int cus) {
 
 int tile_group_slots(const nfl_plan *P) {
   if (P->d != 3) return 0;
-  int dev = 0, cus = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P->device) != hipSuccess ||
       cus <= 0) {
     (void)hipGetLastError();
     cus = 1;
