@@ -1186,24 +1186,35 @@ __host__ __device__ __forceinline__ size_t fft_lds_bytes(int lpb, int L) {
   return ((size_t)2 * lpb * L + L) * 8;
 }
 
-// Lines per workgroup of each pass for lines of length L, N = L/2:
-//   z passes (r2c / c2r): FFT_ELEMS / L lines;
+// Lines per workgroup of each pass for lines of length L, N = L/2, with at
+// most `elems` complex values per workgroup:
+//   z passes (r2c / c2r): elems / L lines;
 //   y passes: the Hz = N/2 + 1 columns split into equal groups of at most
-//     FFT_ELEMS / L;
+//     elems / L;
 //   x pass: enough workgroups (>= 1024) for the (N+1)(N/2+1) columns.
-__host__ __device__ __forceinline__ int fft_lpb_z(int L) { return L >= FFT_ELEMS ? 1 : FFT_ELEMS / L; }
+// The single-plan product uses FFT_ELEMS_PLAN: its passes are latency bound
+// and gain from more, smaller workgroups (at the benchmark workload 190.6 ->
+// 189.0 us per product with 256 instead of 512; 195.6 with 128, 195.6 with
+// 1024); the batched launch, whose passes cover hundreds of grids, keeps
+// FFT_ELEMS (4.32 ms per batch; 4.92 with 256).
+constexpr int FFT_ELEMS_PLAN = 256;
+__host__ __device__ __forceinline__ int fft_lpb_z(int L, int elems = FFT_ELEMS) {
+  return L >= elems ? 1 : elems / L;
+}
 // real lines per workgroup of the r2c / c2r passes (two per complex line)
-__host__ __device__ __forceinline__ int fft_lpb_zr(int L) { return 2 * fft_lpb_z(L); }
-__host__ __device__ __forceinline__ int fft_lpb_y(int L) {
-  const int Hz = L / 4 + 1, mx = fft_lpb_z(L);
+__host__ __device__ __forceinline__ int fft_lpb_zr(int L, int elems = FFT_ELEMS) {
+  return 2 * fft_lpb_z(L, elems);
+}
+__host__ __device__ __forceinline__ int fft_lpb_y(int L, int elems = FFT_ELEMS) {
+  const int Hz = L / 4 + 1, mx = fft_lpb_z(L, elems);
   const int groups = (Hz + mx - 1) / mx;
   return (Hz + groups - 1) / groups;
 }
-__host__ __device__ __forceinline__ int fft_lpb_x(int L) {
+__host__ __device__ __forceinline__ int fft_lpb_x(int L, int elems = FFT_ELEMS) {
   const int C = (L / 2 + 1) * (L / 4 + 1);
   int l = C / 1024;
   if (l < 1) l = 1;
-  const int mx = fft_lpb_z(L);
+  const int mx = fft_lpb_z(L, elems);
   return l > mx ? mx : l;
 }
 
