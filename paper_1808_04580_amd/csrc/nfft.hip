@@ -872,7 +872,10 @@ int convolve(nfl_plan *P, const float *gin_c, float *gout, bool zero_in, bool su
   const int L = P->nos, N = P->N, Hz = N / 2 + 1, F = N + 1;
   int logL = 0;
   while ((1 << logL) < L) ++logL;
-  const int lpz = fft_lpb_zr(L, FFT_ELEMS_PLAN);   // real lines per workgroup, two per FFT
+  // values per workgroup: FFT_ELEMS_PLAN up to L = 128 (longer lines: two per
+  // workgroup at least, as with FFT_ELEMS)
+  const int fe = L <= 128 ? FFT_ELEMS_PLAN : FFT_ELEMS;
+  const int lpz = fft_lpb_zr(L, fe);   // real lines per workgroup, two per FFT
   const size_t ldz = fft_lds_bytes(lpz / 2, L);
   const float2 *tw = P->tw.p;
   if (P->d == 1) {
@@ -908,11 +911,11 @@ int convolve(nfl_plan *P, const float *gin_c, float *gout, bool zero_in, bool su
     const int nb = (nlines + lpz - 1) / lpz;
     hipLaunchKernelGGL(r2c, dim3(nb), dim3(FFT_THREADS), ldz, P->stream, gin, P->spec1.p,
                        nlines, L, logL, lpz, Hz, tw, P->stop, fxm, fxu, zl);
-    const int lpy = fft_lpb_y(L, FFT_ELEMS_PLAN), ngroups = (Hz + lpy - 1) / lpy;
+    const int lpy = fft_lpb_y(L, fe), ngroups = (Hz + lpy - 1) / lpy;
     const size_t ldy = fft_lds_bytes(lpy, L);
     hipLaunchKernelGGL(k_y_fwd, dim3(nxs * ngroups), dim3(FFT_THREADS), ldy, P->stream, P->spec1.p,
                        P->spec2.p, L, logL, lpy, Hz, N, tw, P->stop, zx);
-    const int C = F * Hz, lpx = fft_lpb_x(L, FFT_ELEMS_PLAN);
+    const int C = F * Hz, lpx = fft_lpb_x(L, fe);
     hipLaunchKernelGGL(k_x_filter, dim3((C + lpx - 1) / lpx), dim3(FFT_THREADS),
                        fft_lds_bytes(lpx, L), P->stream, P->spec2.p, P->filt.p, C, L, logL, lpx,
                        N, tw, P->stop, zxin);

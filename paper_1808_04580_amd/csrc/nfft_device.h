@@ -1192,11 +1192,12 @@ __host__ __device__ __forceinline__ size_t fft_lds_bytes(int lpb, int L) {
 //   y passes: the Hz = N/2 + 1 columns split into equal groups of at most
 //     elems / L;
 //   x pass: enough workgroups (>= 1024) for the (N+1)(N/2+1) columns.
-// The single-plan product uses FFT_ELEMS_PLAN: its passes are latency bound
-// and gain from more, smaller workgroups (at the benchmark workload 190.6 ->
-// 189.0 us per product with 256 instead of 512; 195.6 with 128, 195.6 with
-// 1024); the batched launch, whose passes cover hundreds of grids, keeps
-// FFT_ELEMS (4.32 ms per batch; 4.92 with 256).
+// The single-plan product uses FFT_ELEMS_PLAN for lines of up to 128: its
+// passes are latency bound and gain from more, smaller workgroups (at the
+// benchmark workload 190.6 -> 189.0 us per product with 256 instead of 512;
+// 195.6 with 128, 195.6 with 1024; at L = 256 the five passes took 92
+// instead of 74 us); the batched launch, whose passes cover hundreds of
+// grids, keeps FFT_ELEMS (4.32 ms per batch; 4.92 with 256).
 constexpr int FFT_ELEMS_PLAN = 256;
 __host__ __device__ __forceinline__ int fft_lpb_z(int L, int elems = FFT_ELEMS) {
   return L >= elems ? 1 : elems / L;
