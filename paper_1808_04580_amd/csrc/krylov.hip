@@ -878,10 +878,18 @@ int lanczos(nfl_plan *P, int k, int block, double tol, int maxit, double *evals_
 constexpr int CG_NB = 1024;    // reduction blocks of the CG vector kernels (partials per sum)
 
 // sum of the nb partials in a fixed tree, valid in every thread of the block
+// (each thread adds its partials i, i + VT, ... in order; their loads are
+// issued four at a time, so a thread waits once per four, not once per load)
 __device__ __forceinline__ double sum_partials(const double *__restrict__ part, int nb,
                                                double *sh) {
   double v = 0.0;
-  for (int i = threadIdx.x; i < nb; i += VT) v += part[i];
+  for (int i0 = threadIdx.x; i0 < nb; i0 += 4 * VT) {
+    double t[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) t[u] = i0 + u * VT < nb ? part[i0 + u * VT] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v += t[u];
+  }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   const int w = threadIdx.x >> 6;
@@ -996,11 +1004,30 @@ __global__ __launch_bounds__(VT) void k_cg_step(double *__restrict__ u, double *
   }
   const double a = sc[k & 1] / pq;
   double s = 0.0;
-  for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT) {
-    u[i] += a * p[i];
-    const double ri = r[i] - a * q[i];
-    r[i] = ri;
-    s += ri * ri;
+  // four elements per thread at a time (stride apart, in the order a plain
+  // grid-stride loop takes them), their loads issued together
+  const int64_t stride = (int64_t)gridDim.x * VT;
+  for (int64_t i0 = blockIdx.x * (int64_t)VT + threadIdx.x; i0 < n; i0 += 4 * stride) {
+    double uu[4], pp[4], rr[4], qq[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t i = i0 + v * stride;
+      const bool ok = i < n;
+      uu[v] = ok ? u[i] : 0.0;
+      pp[v] = ok ? p[i] : 0.0;
+      rr[v] = ok ? r[i] : 0.0;
+      qq[v] = ok ? q[i] : 0.0;
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t i = i0 + v * stride;
+      if (i < n) {
+        u[i] = uu[v] + a * pp[v];
+        const double ri = rr[v] - a * qq[v];
+        r[i] = ri;
+        s += ri * ri;
+      }
+    }
   }
   s = block_sum(s, sh);
   if (threadIdx.x == 0) part[CG_NB + blockIdx.x] = s;
@@ -1021,10 +1048,25 @@ __global__ __launch_bounds__(VT) void k_cg_dir(double *__restrict__ p,
   const double rn = sum_partials(part + CG_NB, (int)gridDim.x, sh);
   const double b = rn / sc[k & 1];
   float mx = 0.f;
-  for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT) {
-    const double pi = r[i] + b * p[i];
-    p[i] = pi;
-    mx = fmaxf(mx, (float)fabs(pi));
+  // four elements per thread at a time, loads issued together (as in k_cg_step)
+  const int64_t stride = (int64_t)gridDim.x * VT;
+  for (int64_t i0 = blockIdx.x * (int64_t)VT + threadIdx.x; i0 < n; i0 += 4 * stride) {
+    double rr[4], pp[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t i = i0 + v * stride;
+      rr[v] = i < n ? r[i] : 0.0;
+      pp[v] = i < n ? p[i] : 0.0;
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t i = i0 + v * stride;
+      if (i < n) {
+        const double pi = rr[v] + b * pp[v];
+        p[i] = pi;
+        mx = fmaxf(mx, (float)fabs(pi));
+      }
+    }
   }
   if (fx_max) block_absmax_to(mx, fx_max);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
