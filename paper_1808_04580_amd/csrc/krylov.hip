@@ -111,17 +111,37 @@ __global__ __launch_bounds__(VT) void k_lanczos_sub(double *__restrict__ w,
     w[i] -= a * q[i] + (qp ? b * qp[i] : 0.0);
 }
 
-// part[b*J + j] = sum over this block's rows of Q[j*ld + i] w[i]
+// part[b*J + j] = sum over this block's rows of Q[j*ld + i] w[i].  The columns
+// are taken GT_COLS at a time, so that one load of w[i] serves all of them;
+// each column still sums its rows in the grid-stride order.
+constexpr int GT_COLS = 8;
+
 __global__ __launch_bounds__(VT) void k_gemv_t_partial(const double *__restrict__ Q, int64_t ld,
                                                        int J, const double *__restrict__ w,
                                                        int64_t n, double *__restrict__ part) {
   __shared__ double sh[VT / 64];
-  for (int j = 0; j < J; ++j) {
-    double s = 0.0;
-    for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT)
-      s += Q[j * ld + i] * w[i];
-    s = block_sum(s, sh);
-    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * J + j] = s;
+  for (int j0 = 0; j0 < J; j0 += GT_COLS) {
+    const int cnt = min(GT_COLS, J - j0);
+    const double *Qj = Q + (int64_t)j0 * ld;
+    double s[GT_COLS];
+#pragma unroll
+    for (int q = 0; q < GT_COLS; ++q) s[q] = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * VT) {
+      const double wi = w[i];
+      double qv[GT_COLS];
+#pragma unroll
+      for (int q = 0; q < GT_COLS; ++q) qv[q] = q < cnt ? Qj[q * ld + i] : 0.0;
+#pragma unroll
+      for (int q = 0; q < GT_COLS; ++q) s[q] += qv[q] * wi;
+    }
+#pragma unroll
+    for (int q = 0; q < GT_COLS; ++q) {
+      if (q < cnt) {   // cnt is the same in every thread: the barriers below match
+        const double t = block_sum(s[q], sh);
+        if (threadIdx.x == 0) part[(int64_t)blockIdx.x * J + j0 + q] = t;
+      }
+    }
   }
 }
 
@@ -150,13 +170,23 @@ __global__ __launch_bounds__(VT) void k_colsum(const double *__restrict__ part, 
   }
 }
 
-// w[i] -= sum_j Q[j*ld + i] c[j]
+// w[i] -= sum_j Q[j*ld + i] c[j], the terms added in the order of j; the
+// loads of GT_COLS columns are issued before their products are added.
 __global__ __launch_bounds__(VT) void k_gemv_n_sub(const double *__restrict__ Q, int64_t ld,
                                                    int J, const double *__restrict__ c,
                                                    double *__restrict__ w, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT) {
     double s = 0.0;
-    for (int j = 0; j < J; ++j) s += Q[j * ld + i] * c[j];
+    for (int j0 = 0; j0 < J; j0 += GT_COLS) {
+      const int cnt = min(GT_COLS, J - j0);
+      double qv[GT_COLS];
+#pragma unroll
+      for (int q = 0; q < GT_COLS; ++q)
+        qv[q] = q < cnt ? Q[(int64_t)(j0 + q) * ld + i] : 0.0;
+#pragma unroll
+      for (int q = 0; q < GT_COLS; ++q)
+        if (q < cnt) s += qv[q] * c[j0 + q];
+    }
     w[i] -= s;
   }
 }
