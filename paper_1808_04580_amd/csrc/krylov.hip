@@ -191,6 +191,97 @@ __global__ __launch_bounds__(VT) void k_gemv_n_sub(const double *__restrict__ Q,
   }
 }
 
+// Block forms of the two kernels above for nb <= BT_VECS vectors w_c = W[c*ldw
+// + i]: one pass over the rows of GT_COLS basis columns serves all nb vectors.
+// part[b*(J*nb) + c*J + j] = sum over this block's rows of Q[j*ld + i] w_c[i];
+// each (j, c) sums its rows in the grid-stride order, as k_gemv_t_partial.
+constexpr int BT_VECS = 4;
+
+__global__ __launch_bounds__(VT) void k_gemm_tn_partial(const double *__restrict__ Q, int64_t ld,
+                                                        int J, const double *__restrict__ W,
+                                                        int64_t ldw, int nb, int64_t n,
+                                                        double *__restrict__ part) {
+  constexpr int NS = GT_COLS * BT_VECS;
+  __shared__ double sh[VT / 64][NS];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int j0 = 0; j0 < J; j0 += GT_COLS) {
+    const int cnt = min(GT_COLS, J - j0);
+    const double *Qj = Q + (int64_t)j0 * ld;
+    double s[GT_COLS][BT_VECS];
+#pragma unroll
+    for (int q = 0; q < GT_COLS; ++q)
+#pragma unroll
+      for (int c = 0; c < BT_VECS; ++c) s[q][c] = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * VT) {
+      double wv[BT_VECS], qv[GT_COLS];
+#pragma unroll
+      for (int c = 0; c < BT_VECS; ++c) wv[c] = c < nb ? W[c * ldw + i] : 0.0;
+#pragma unroll
+      for (int q = 0; q < GT_COLS; ++q) qv[q] = q < cnt ? Qj[q * ld + i] : 0.0;
+#pragma unroll
+      for (int q = 0; q < GT_COLS; ++q)
+#pragma unroll
+        for (int c = 0; c < BT_VECS; ++c) s[q][c] += qv[q] * wv[c];
+    }
+#pragma unroll
+    for (int q = 0; q < GT_COLS; ++q)
+#pragma unroll
+      for (int c = 0; c < BT_VECS; ++c) {
+        double v = s[q][c];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        s[q][c] = v;
+      }
+    __syncthreads();   // the previous group's sums have been read
+    if (lane == 0) {
+#pragma unroll
+      for (int q = 0; q < GT_COLS; ++q)
+#pragma unroll
+        for (int c = 0; c < BT_VECS; ++c) sh[wave][q * BT_VECS + c] = s[q][c];
+    }
+    __syncthreads();
+    if (threadIdx.x < NS) {
+      const int q = threadIdx.x / BT_VECS, c = threadIdx.x % BT_VECS;
+      if (q < cnt && c < nb) {
+        double t = 0.0;
+        for (int k = 0; k < VT / 64; ++k) t += sh[k][threadIdx.x];
+        part[(int64_t)blockIdx.x * J * nb + (int64_t)c * J + j0 + q] = t;
+      }
+    }
+  }
+}
+
+// w_c[i] -= sum_j Q[j*ld + i] C[c*ldc + j] for c < nb <= BT_VECS, the terms of
+// each vector added in the order of j, as k_gemv_n_sub.
+__global__ __launch_bounds__(VT) void k_gemm_n_sub(const double *__restrict__ Q, int64_t ld,
+                                                   int J, const double *__restrict__ C, int ldc,
+                                                   double *__restrict__ W, int64_t ldw, int nb,
+                                                   int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT) {
+    double s[BT_VECS];
+#pragma unroll
+    for (int c = 0; c < BT_VECS; ++c) s[c] = 0.0;
+    for (int j0 = 0; j0 < J; j0 += GT_COLS) {
+      const int cnt = min(GT_COLS, J - j0);
+      double qv[GT_COLS];
+#pragma unroll
+      for (int q = 0; q < GT_COLS; ++q)
+        qv[q] = q < cnt ? Q[(int64_t)(j0 + q) * ld + i] : 0.0;
+#pragma unroll
+      for (int q = 0; q < GT_COLS; ++q)
+        if (q < cnt) {
+#pragma unroll
+          for (int c = 0; c < BT_VECS; ++c)
+            if (c < nb) s[c] += qv[q] * C[c * ldc + j0 + q];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < BT_VECS; ++c)
+      if (c < nb) W[c * ldw + i] -= s[c];
+  }
+}
+
 // out[c*n + i] = sum_j Q[j*ld + i] Z[sel[c]*J + j]   (Ritz vectors, sorted order)
 __global__ __launch_bounds__(VT) void k_ritz(const double *__restrict__ Q, int64_t ld, int J,
                                              const double *__restrict__ Z,
@@ -614,10 +705,10 @@ static int block_lanczos(nfl_plan *P, int k, int b, double tol, int maxit, int r
   NFL_TRY(Q.ensure((size_t)ld * (mcols + b)));
   NFL_TRY(W.ensure((size_t)n * b));
   NFL_TRY(H.ensure((size_t)ldH * ldH));
-  NFL_TRY(cvec.ensure(mcols + b));
+  NFL_TRY(cvec.ensure((size_t)BT_VECS * (mcols + b)));
   Reducer R;
   NFL_TRY(R.init(n));
-  NFL_TRY(part.ensure((size_t)R.nb * (mcols + b)));
+  NFL_TRY(part.ensure((size_t)R.nb * BT_VECS * (mcols + b)));
   NFL_TRY(Aw.ensure((size_t)mcols * mcols));
   NFL_TRY(Vw.ensure((size_t)mcols * mcols));
   NFL_TRY(ev.ensure(mcols));
@@ -633,23 +724,43 @@ static int block_lanczos(nfl_plan *P, int k, int b, double tol, int maxit, int r
   hipStream_t s = P->stream;
   hipLaunchKernelGGL(k_fill64, dim3(256), dim3(VT), 0, s, H.p, (int64_t)(ldH * ldH), 0.0);
 
-  // orthogonalise w twice against the first ncol columns, adding the
-  // coefficients to hcol (may be null); then normalise into column ncol,
-  // its norm written to *nrm_dev
-  auto orth_next = [&](double *w, int ncol, double *hcol, double *nrm_dev) -> int {
-    for (int pass = 0; pass < 2 && ncol > 0; ++pass) {
-      hipLaunchKernelGGL(k_gemv_t_partial, dim3(R.nb), dim3(VT), 0, s, Q.p, ld, ncol, w, n,
+  // orthogonalise w twice against the cnt columns from column `first` on,
+  // adding the coefficients to hcol[first..] (hcol may be null); then
+  // normalise into column first + cnt, its norm written to *nrm_dev
+  auto orth_next = [&](double *w, int first, int cnt, double *hcol, double *nrm_dev) -> int {
+    const double *Qf = Q.p + (int64_t)first * ld;
+    for (int pass = 0; pass < 2 && cnt > 0; ++pass) {
+      hipLaunchKernelGGL(k_gemv_t_partial, dim3(R.nb), dim3(VT), 0, s, Qf, ld, cnt, w, n,
                          part.p);
-      hipLaunchKernelGGL(k_colsum, dim3((ncol + CS_E - 1) / CS_E), dim3(VT), 0, s, part.p, R.nb,
-                         ncol, cvec.p);
+      hipLaunchKernelGGL(k_colsum, dim3((cnt + CS_E - 1) / CS_E), dim3(VT), 0, s, part.p, R.nb,
+                         cnt, cvec.p);
       if (hcol)
-        hipLaunchKernelGGL(k_add_col, dim3((ncol + VT - 1) / VT), dim3(VT), 0, s, hcol, cvec.p,
-                           ncol);
-      hipLaunchKernelGGL(k_gemv_n_sub, dim3(gb), dim3(VT), 0, s, Q.p, ld, ncol, cvec.p, w, n);
+        hipLaunchKernelGGL(k_add_col, dim3((cnt + VT - 1) / VT), dim3(VT), 0, s, hcol + first,
+                           cvec.p, cnt);
+      hipLaunchKernelGGL(k_gemv_n_sub, dim3(gb), dim3(VT), 0, s, Qf, ld, cnt, cvec.p, w, n);
     }
     NFL_TRY(dot(P, R, w, w, nrm_dev, 1));
     hipLaunchKernelGGL(k_scale_inv, dim3(gb), dim3(VT), 0, s, w, nrm_dev, n,
-                       Q.p + (int64_t)ncol * ld);
+                       Q.p + (int64_t)(first + cnt) * ld);
+    NFL_HIP(hipGetLastError());
+    return NFL_OK;
+  };
+
+  // orthogonalise the products W[:, c0..c0+nv) twice against the first ncol
+  // columns, BT_VECS vectors per pass over the basis, adding the coefficients
+  // of vector c to column hfirst + c of H
+  auto orth_block = [&](int c0, int nv, int ncol, int hfirst) -> int {
+    for (int pass = 0; pass < 2; ++pass) {
+      hipLaunchKernelGGL(k_gemm_tn_partial, dim3(R.nb), dim3(VT), 0, s, Q.p, ld, ncol,
+                         W.p + (int64_t)c0 * n, (int64_t)n, nv, n, part.p);
+      hipLaunchKernelGGL(k_colsum, dim3((ncol * nv + CS_E - 1) / CS_E), dim3(VT), 0, s, part.p,
+                         R.nb, ncol * nv, cvec.p);
+      for (int c = 0; c < nv; ++c)
+        hipLaunchKernelGGL(k_add_col, dim3((ncol + VT - 1) / VT), dim3(VT), 0, s,
+                           H.p + (int64_t)(hfirst + c) * ldH, cvec.p + (int64_t)c * ncol, ncol);
+      hipLaunchKernelGGL(k_gemm_n_sub, dim3(gb), dim3(VT), 0, s, Q.p, ld, ncol, cvec.p, ncol,
+                         W.p + (int64_t)c0 * n, (int64_t)n, nv, n);
+    }
     NFL_HIP(hipGetLastError());
     return NFL_OK;
   };
@@ -658,7 +769,7 @@ static int block_lanczos(nfl_plan *P, int k, int b, double tol, int maxit, int r
   for (int c = 0; c < b; ++c) {
     hipLaunchKernelGGL(k_start_vector, dim3(gb), dim3(VT), 0, s, W.p, P->perm.p, n,
                        (uint64_t)(c + 1));
-    NFL_TRY(orth_next(W.p, c, nullptr, cvec.p + mcols + b - 1));
+    NFL_TRY(orth_next(W.p, 0, c, nullptr, cvec.p + (size_t)BT_VECS * (mcols + b) - 1));
   }
 
   std::vector<double> h_eval, h_V, h_R((size_t)b * b);
@@ -670,10 +781,13 @@ static int block_lanczos(nfl_plan *P, int k, int b, double tol, int maxit, int r
   while (Jc + b <= mcols) {
     const int J0 = Jc;
     for (int c = 0; c < b; ++c) NFL_TRY(apply_A64(P, Q.p + (int64_t)(J0 + c) * ld, W.p + (int64_t)c * n));
+    // against the basis so far (the current block included), then within
+    // the new block: together the two give the new block's QR factor
+    for (int c0 = 0; c0 < b; c0 += BT_VECS)
+      NFL_TRY(orth_block(c0, std::min(BT_VECS, b - c0), J0 + b, J0 + c0));
     for (int c = 0; c < b; ++c) {
-      const int ncol = J0 + b + c;
       double *hcol = H.p + (int64_t)(J0 + c) * ldH;
-      NFL_TRY(orth_next(W.p + (int64_t)c * n, ncol, hcol, hcol + ncol));
+      NFL_TRY(orth_next(W.p + (int64_t)c * n, J0 + b, c, hcol, hcol + J0 + b + c));
     }
     nprod += b;
     ++since;

@@ -280,10 +280,11 @@ def test_invariants_of_the_approximate_operator(nfl):
     assert np.abs(Y[1] - Lb).max() <= 1e-6 * np.abs(Lb).max()
 
 
-@pytest.mark.parametrize("block", [1, 3, 4])
+@pytest.mark.parametrize("block", [1, 3, 4, 6])
 def test_lanczos_matches_dense_eigh(nfl, block):
     """10 smallest eigenpairs of L_s on the n = 5000 blob workload (N = 64),
-    single-vector and block Lanczos: eigenvalues within 1e-6 of LAPACK on the
+    single-vector and block Lanczos (block 6: two passes of four and two
+    vectors over the basis): eigenvalues within 1e-6 of LAPACK on the
     dense FP64 matrix; residuals of the returned vectors against the dense
     matrix small."""
     v = synth.blobs2d(5000, seed=0)
