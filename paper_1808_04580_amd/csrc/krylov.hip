@@ -664,9 +664,10 @@ __global__ __launch_bounds__(VT) void k_add_col(double *__restrict__ h,
 
 // Block Lanczos with full reorthogonalisation for the k largest eigenvalues of
 // A_E (Section 4 with blocks of b vectors).  Column J0 + c of the basis is
-// multiplied by A_E; the product is orthogonalised twice against every
-// column built so far (which also forms the QR factor of the new block) and
-// normalised into the next column.  H holds the coefficients: column J0 + c
+// multiplied by A_E; the block's products are orthogonalised together, twice,
+// against every column built so far, then each twice against the block's
+// earlier new columns, and normalised into the next column (which also forms
+// the QR factor of the new block).  H holds the coefficients: column J0 + c
 // gets the projections in rows < J0 + b + c and the norm in row J0 + b + c,
 // so the leading J x J part of H is the projection Q^T A_E Q and the b x b
 // block below it the R factor of the next block.  Ritz residual of (theta, s):
