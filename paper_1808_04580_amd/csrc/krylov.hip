@@ -482,18 +482,20 @@ __device__ double jac_block_sum(double v, double *sh) {
   return t;  // valid in every thread
 }
 
-// IN_LDS (m <= JAC_LDS_MAXM): A and V live in dynamic LDS (2 m^2 doubles)
-// during the sweeps and V is copied to Vg at the end; otherwise both are the
-// global work arrays.
-constexpr int JAC_LDS_MAXM = 64;
+// KSC > 0 (m <= KSC): A and V live in dynamic LDS (2 m^2 doubles) during the
+// sweeps and V is copied to Vg at the end; KSC = 0: both are the global work
+// arrays.  The LDS forms: KSC = 64, and KSC = 96 (144 KiB of the 160 KiB of
+// LDS a workgroup may hold).
+constexpr int JAC_LDS_MAXM = 64, JAC_LDS_MAXM2 = 96;
 
-template <bool IN_LDS>
+template <int KSC>
 __global__ __launch_bounds__(JAC_THREADS) void k_sym_jacobi(const double *__restrict__ H,
                                                             int64_t ldH, int m,
                                                             double *__restrict__ Ag,
                                                             double *__restrict__ Vg,
                                                             double *__restrict__ eval,
                                                             int *__restrict__ status) {
+  constexpr bool IN_LDS = KSC > 0;
   extern __shared__ double jac_dyn[];
   double *A = IN_LDS ? jac_dyn : Ag;
   double *V = IN_LDS ? jac_dyn + (size_t)m * m : Vg;
@@ -511,9 +513,9 @@ __global__ __launch_bounds__(JAC_THREADS) void k_sym_jacobi(const double *__rest
   for (int64_t idx = tid; idx < (int64_t)m * m; idx += JAC_THREADS) nn += A[idx] * A[idx];
   const double nrm = sqrt(jac_block_sum(nn, sh));
   const int M = m + (m & 1), npair = M / 2;
-  // (pair or row, column) index spaces use the stride KS; for small orders it
-  // is the constant 64, so that splitting an index needs no division
-  const int KS = IN_LDS ? JAC_LDS_MAXM : m;
+  // (pair or row, column) index spaces use the stride KS; in the LDS forms it
+  // is a constant, so that splitting an index needs no division
+  const int KS = IN_LDS ? KSC : m;
   int st = 1;
   for (int sweep = 0; sweep < 40; ++sweep) {
     double off = 0.0;
@@ -641,16 +643,30 @@ int sym_eig(hipStream_t s, const double *H, int64_t ldH, int m, double *A_work, 
     set_error("symmetric eigensolver: order outside 1..1024");
     return NFL_ERR_UNSUPPORTED;
   }
+  // the larger LDS form only where the device grants its LDS (else the
+  // global form)
+  static const bool lds96 = [] {
+    const bool ok = hipFuncSetAttribute((const void *)k_sym_jacobi<JAC_LDS_MAXM2>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        2 * JAC_LDS_MAXM2 * JAC_LDS_MAXM2 *
+                                            (int)sizeof(double)) == hipSuccess;
+    if (!ok) (void)hipGetLastError();
+    return ok;
+  }();
+  const size_t dyn = (size_t)2 * m * m * sizeof(double);
   if (m <= JAC_LDS_MAXM) {
     static const hipError_t attr = hipFuncSetAttribute(
-        (const void *)k_sym_jacobi<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        (const void *)k_sym_jacobi<JAC_LDS_MAXM>, hipFuncAttributeMaxDynamicSharedMemorySize,
         2 * JAC_LDS_MAXM * JAC_LDS_MAXM * (int)sizeof(double));
     NFL_HIP(attr);
-    hipLaunchKernelGGL(k_sym_jacobi<true>, dim3(1), dim3(JAC_THREADS),
-                       (size_t)2 * m * m * sizeof(double), s, H, ldH, m, A_work, V, eval, status);
+    hipLaunchKernelGGL(k_sym_jacobi<JAC_LDS_MAXM>, dim3(1), dim3(JAC_THREADS), dyn, s, H, ldH, m,
+                       A_work, V, eval, status);
+  } else if (m <= JAC_LDS_MAXM2 && lds96) {
+    hipLaunchKernelGGL(k_sym_jacobi<JAC_LDS_MAXM2>, dim3(1), dim3(JAC_THREADS), dyn, s, H, ldH,
+                       m, A_work, V, eval, status);
   } else {
-    hipLaunchKernelGGL(k_sym_jacobi<false>, dim3(1), dim3(JAC_THREADS), 0, s, H, ldH, m, A_work,
-                       V, eval, status);
+    hipLaunchKernelGGL(k_sym_jacobi<0>, dim3(1), dim3(JAC_THREADS), 0, s, H, ldH, m, A_work, V,
+                       eval, status);
   }
   NFL_HIP(hipGetLastError());
   return NFL_OK;
