@@ -202,6 +202,7 @@ __global__ __launch_bounds__(VT) void k_gemm_tn_partial(const double *__restrict
                                                         int64_t ldw, int nb, int64_t n,
                                                         double *__restrict__ part) {
   constexpr int NS = GT_COLS * BT_VECS;
+  static_assert(NS == 32, "the halving exchanges below take 32 values to one per lane pair");
   __shared__ double sh[VT / 64][NS];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int j0 = 0; j0 < J; j0 += GT_COLS) {
@@ -224,22 +225,29 @@ __global__ __launch_bounds__(VT) void k_gemm_tn_partial(const double *__restrict
 #pragma unroll
         for (int c = 0; c < BT_VECS; ++c) s[q][c] += qv[q] * wv[c];
     }
+    // wave sums of the NS = 32 values by halving exchanges: at offset o
+    // (32, 16, .., 2) a lane keeps the half of its values selected by lane
+    // bit o and adds the partner's copy of it, so after five steps lane l
+    // holds value l >> 1 summed over its 32 partners; offset 1 adds the pair.
+    // 32 shuffles per lane instead of 6 per value.
+    double v[NS];
 #pragma unroll
     for (int q = 0; q < GT_COLS; ++q)
 #pragma unroll
-      for (int c = 0; c < BT_VECS; ++c) {
-        double v = s[q][c];
+      for (int c = 0; c < BT_VECS; ++c) v[q * BT_VECS + c] = s[q][c];
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-        s[q][c] = v;
+    for (int h = NS / 2, o = 32; h >= 1; h >>= 1, o >>= 1) {
+      const bool up = (lane & o) != 0;
+#pragma unroll
+      for (int k = 0; k < h; ++k) {
+        const double mine = up ? v[h + k] : v[k];
+        const double give = up ? v[k] : v[h + k];
+        v[k] = mine + __shfl_xor(give, o);
       }
-    __syncthreads();   // the previous group's sums have been read
-    if (lane == 0) {
-#pragma unroll
-      for (int q = 0; q < GT_COLS; ++q)
-#pragma unroll
-        for (int c = 0; c < BT_VECS; ++c) sh[wave][q * BT_VECS + c] = s[q][c];
     }
+    v[0] += __shfl_xor(v[0], 1);
+    __syncthreads();   // the previous group's sums have been read
+    if ((lane & 1) == 0) sh[wave][lane >> 1] = v[0];
     __syncthreads();
     if (threadIdx.x < NS) {
       const int q = threadIdx.x / BT_VECS, c = threadIdx.x % BT_VECS;
